@@ -1,0 +1,202 @@
+"""FP64 oracle for Anderson acceleration (Section "Anderson acceleration" and
+Section "Method").  TEST INFRASTRUCTURE ONLY.
+
+* Algorithm 1, alpha form: min ||F_k alpha|| subject to sum(alpha) = 1
+  (eq. AAopt), update with damping beta (eq. AAupdate0).
+* gamma form: gamma = argmin ||A_k gamma - f_k|| with A_k the consecutive
+  residual differences (eq. Ak, eq. AAopt2, eq. solveGamma) and, for
+  beta = 1, p_{k+1} = G(p_k) - sum_i gamma_i [G(p_{i+1}) - G(p_i)]
+  (eq. AA2_update).
+* For steepest descent G(p) = p - eta grad J(p) (eq. GD) the residual is
+  f_k = -eta grad J(p_k).
+* Algorithm 2: pbar = G(p_k), ptilde from the gamma form, and the new
+  iterate lambda ptilde + (1 - lambda) pbar with lambda from a backtracking
+  test on J.
+
+Readings taken where the paper leaves a choice (each listed in the design
+notes): the least-squares solve here is numpy's SVD-based lstsq on A_k
+itself; columns are dropped oldest first while cond_2(A_k) exceeds
+``cond_max``; lambda is tried in {1, 1/2, 1/4, 1/8} with the Armijo test
+J(p) <= J(p_k) + c1 <g_k, p - p_k>, falling back to lambda = 0 untested.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+COND_MAX = 1e5
+LAMBDAS = (1.0, 0.5, 0.25, 0.125)
+ARMIJO_C1 = 1e-4
+
+
+# ----------------------------------------------------------------------------
+# Algorithm 1 (generic fixed-point form)
+# ----------------------------------------------------------------------------
+
+def alpha_weights(F: np.ndarray) -> np.ndarray:
+    """argmin ||F alpha||_2 subject to sum(alpha) = 1, via the KKT system."""
+    k = F.shape[1]
+    kkt = np.zeros((k + 1, k + 1))
+    kkt[:k, :k] = 2.0 * F.T @ F
+    kkt[:k, k] = 1.0
+    kkt[k, :k] = 1.0
+    rhs = np.zeros(k + 1)
+    rhs[k] = 1.0
+    sol = np.linalg.lstsq(kkt, rhs, rcond=None)[0]
+    return sol[:k]
+
+
+def alpha_update(P: np.ndarray, GP: np.ndarray, alpha: np.ndarray, beta: float = 1.0):
+    """(1 - beta) sum alpha_i p_i + beta sum alpha_i G(p_i)."""
+    return (1.0 - beta) * (P @ alpha) + beta * (GP @ alpha)
+
+
+def gamma_weights(A: np.ndarray, f: np.ndarray) -> np.ndarray:
+    """Minimum-norm least-squares gamma = argmin ||A gamma - f||_2."""
+    if A.shape[1] == 0:
+        return np.zeros(0)
+    return np.linalg.lstsq(A, f, rcond=None)[0]
+
+
+def gamma_to_alpha(gamma: np.ndarray) -> np.ndarray:
+    """The change of variables gamma_i = alpha_0 + ... + alpha_i, inverted."""
+    mk = gamma.shape[0]
+    alpha = np.zeros(mk + 1)
+    prev = 0.0
+    for i in range(mk):
+        alpha[i] = gamma[i] - prev
+        prev = gamma[i]
+    alpha[mk] = 1.0 - prev
+    return alpha
+
+
+def anderson_alg1(G, p0, M, iters, beta=1.0):
+    """Algorithm 1 with the alpha form; returns the iterate list p_0..p_iters."""
+    ps = [np.asarray(p0, np.float64)]
+    gs = [G(ps[0])]
+    ps.append(gs[0].copy())
+    for k in range(1, iters):
+        gs.append(G(ps[k]))
+        mk = min(M, k)
+        P = np.stack(ps[k - mk:k + 1], axis=1)
+        GP = np.stack(gs[k - mk:k + 1], axis=1)
+        alpha = alpha_weights(GP - P)
+        ps.append(alpha_update(P, GP, alpha, beta))
+    return ps
+
+
+# ----------------------------------------------------------------------------
+# gamma form with an explicit history window (what the GPU step computes)
+# ----------------------------------------------------------------------------
+
+class AAHistory:
+    """Window of the most recent accepted iterates p_i and gradients g_i.
+
+    ``step`` appends (p_k, g_k) and returns pbar = G(p_k), ptilde
+    (eq. AA2_update), gamma and M_k.  The window holds at most M+1 entries;
+    while cond_2(A_k) > cond_max the oldest entry is dropped for good.
+    """
+
+    def __init__(self, M: int, cond_max: float = COND_MAX):
+        self.M = M
+        self.cond_max = cond_max
+        self.p = []
+        self.g = []
+
+    def reset(self):
+        self.p.clear()
+        self.g.clear()
+
+    def _matrices(self, eta):
+        f = [-eta * g for g in self.g]
+        Gp = [p + fi for p, fi in zip(self.p, f)]
+        A = np.stack([f[i + 1] - f[i] for i in range(len(f) - 1)], axis=1) \
+            if len(f) > 1 else np.zeros((f[0].size, 0))
+        dG = np.stack([Gp[i + 1] - Gp[i] for i in range(len(Gp) - 1)], axis=1) \
+            if len(Gp) > 1 else np.zeros((Gp[0].size, 0))
+        return f, Gp, A, dG
+
+    def step(self, p_k, g_k, eta):
+        self.p.append(np.asarray(p_k, np.float64).ravel().copy())
+        self.g.append(np.asarray(g_k, np.float64).ravel().copy())
+        while len(self.p) > self.M + 1:
+            self.p.pop(0)
+            self.g.pop(0)
+        eta = float(eta)
+        while True:
+            f, Gp, A, dG = self._matrices(eta)
+            if A.shape[1] == 0:
+                break
+            sv = np.linalg.svd(A, compute_uv=False)
+            cond = np.inf if sv[-1] <= 0.0 else sv[0] / sv[-1]
+            if cond <= self.cond_max:
+                break
+            self.p.pop(0)
+            self.g.pop(0)
+        gamma = gamma_weights(A, f[-1])
+        pbar = Gp[-1]
+        ptilde = pbar - dG @ gamma if gamma.size else pbar.copy()
+        return pbar, ptilde, gamma, A.shape[1]
+
+
+def multisecant_matrix(P: np.ndarray, D: np.ndarray) -> np.ndarray:
+    """S = argmin ||S + I||_F subject to S D = P (eq. aaFnorm, eq. multisecant):
+    S = -I + (P + D)(D^T D)^{-1} D^T."""
+    n = P.shape[0]
+    return -np.eye(n) + (P + D) @ np.linalg.solve(D.T @ D, D.T)
+
+
+# ----------------------------------------------------------------------------
+# Algorithm 2 driver
+# ----------------------------------------------------------------------------
+
+def alg2(grad_fn, misfit_fn, p0, eta, M, iters, cond_max=COND_MAX, lambdas=LAMBDAS,
+         c1=ARMIJO_C1, linesearch=True):
+    """Run Algorithm 2 for ``iters`` AA iterations after p_1 = G(p_0).
+
+    grad_fn(p) -> (J, g); misfit_fn(p) -> J.  Returns a dict with the
+    accepted iterates, misfits, chosen lambdas and evaluation counts.
+    """
+    hist = AAHistory(M, cond_max)
+    p = np.asarray(p0, np.float64).ravel().copy()
+    J0, g0 = grad_fn(p)
+    g0 = np.asarray(g0, np.float64).ravel()
+    hist.step(p, g0, eta)
+    iterates, misfits, lams, gammas = [p.copy()], [J0], [], []
+    n_grad, n_fwd = 1, 0
+    p = p - eta * g0
+    iterates.append(p.copy())
+    for _ in range(iters):
+        J, g = grad_fn(p)
+        g = np.asarray(g, np.float64).ravel()
+        n_grad += 1
+        misfits.append(J)
+        pbar, ptilde, gamma, mk = hist.step(p, g, eta)
+        gammas.append(gamma)
+        lam_acc = 0.0
+        new = pbar
+        if linesearch:
+            for lam in lambdas:
+                trial = lam * ptilde + (1.0 - lam) * pbar
+                Jt = misfit_fn(trial)
+                n_fwd += 1
+                if Jt <= J + c1 * float(np.dot(g, trial - p)):
+                    lam_acc, new = lam, trial
+                    break
+        else:
+            lam_acc, new = 1.0, ptilde
+        lams.append(lam_acc)
+        p = new.copy()
+        iterates.append(p.copy())
+    return dict(iterates=iterates, misfits=misfits, lambdas=lams, gammas=gammas,
+                n_grad=n_grad, n_fwd=n_fwd)
+
+
+def picard(grad_fn, p0, eta, iters):
+    """Steepest descent with a fixed step = AA with M = 0."""
+    p = np.asarray(p0, np.float64).ravel().copy()
+    out = [p.copy()]
+    for _ in range(iters):
+        _, g = grad_fn(p)
+        p = p - eta * np.asarray(g, np.float64).ravel()
+        out.append(p.copy())
+    return out
