@@ -1,0 +1,205 @@
+/*
+ * aafwi — Anderson-accelerated acoustic FWI / LSRTM hot path for MI355X (gfx950).
+ *
+ * C ABI of libaafwi.so.  Every entry point takes plain pointers and sizes.
+ * Pointers documented as "device" are HIP device pointers the caller owns
+ * (contiguous, 4-byte aligned, at least 16-byte aligned recommended); "host"
+ * pointers are read synchronously during the call.  Work is enqueued on the
+ * stream given at creation and is asynchronous with respect to the host
+ * unless stated otherwise: the caller keeps device buffers alive until that
+ * stream has drained.  Outputs are overwritten, never accumulated.
+ *
+ * Errors: every function returns 0 (AAFWI_OK) or a negative code below;
+ * aafwi_last_error() returns a thread-local message for the last failure.
+ * Argument validation is synchronous; asynchronous HIP failures surface at
+ * the next call.  No C++ exception crosses this boundary.
+ *
+ * Discretisation (shared by all wave-equation calls; the paper's Section
+ * "FWI and LSRTM", eq. FWD, eq. FWI, eq. Born, eq. FWI_adj, eq. adj_grad1):
+ *   - model m = 1/c^2 [s^2/m^2] on an interior grid nz x nx, row-major with x
+ *     fastest, spacing h (dx = dz); extended by edge replication into nb
+ *     sponge cells on all four sides (padded grid nz+2nb by nx+2nb);
+ *   - centred 8th-order Laplacian, field zero outside the padded grid;
+ *   - sponge: sigma = smax*(xi_x^2 + xi_z^2), xi = depth into the layer in
+ *     cells / nb, smax = 3 vref ln(1/refl) / (2 nb h); st = sigma dt/2,
+ *     A = 1/(1+st), B = (1-st)/(1+st);
+ *   - leapfrog u^{n+1} = 2A u^n - B u^{n-1} + A dt^2/m (Lap u^n + s^n),
+ *     u^0 = u^{-1} = 0, n = 0..nt-1;
+ *   - point source s^n = wavelet[n] / h^2 at (src_iz+nb, src_ix+nb);
+ *   - data d[s][n][r] = u_s^{n+1} at (rec_iz+nb, rec_ix+nb), layout [S][nt][R];
+ *   - misfit J = 1/2 sum (d - d_obs)^2 (plain Euclidean sum);
+ *   - gradient: the exact discrete adjoint of the above, imaged with
+ *     q^n = (Lap u^n + s^n)/m and folded back onto the interior (transpose of
+ *     the edge replication).
+ */
+#ifndef AAFWI_H
+#define AAFWI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define AAFWI_OK            0
+#define AAFWI_E_INVALID    (-1) /* bad argument or geometry                        */
+#define AAFWI_E_CFL        (-2) /* vmax_bound*dt/h above the 2D stability limit    */
+#define AAFWI_E_NOMEM      (-3) /* device allocation failed                        */
+#define AAFWI_E_HIP        (-4) /* HIP runtime error                               */
+#define AAFWI_E_NONFINITE  (-5) /* a model value was non-positive or non-finite    */
+#define AAFWI_E_STATE      (-6) /* call order violated (e.g. no kept checkpoints)  */
+
+typedef struct aafwi_ctx aafwi_ctx;
+typedef struct aafwi_aa aafwi_aa;
+/* hipStream_t passed opaquely; NULL is the null stream. */
+typedef void* aafwi_stream;
+
+/* Acquisition and grid description.  All array pointers are host memory,
+ * copied by aafwi_create. */
+typedef struct aafwi_geometry {
+    int32_t nz, nx;        /* interior grid (rows = depth, columns = x)           */
+    int32_t nb;            /* sponge width in cells (each side), >= 4            */
+    float h;               /* grid spacing dx = dz [m]                            */
+    float dt;              /* time step [s]                                       */
+    int32_t nt;            /* number of time steps = samples per trace            */
+    float vref;            /* velocity used for the sponge strength [m/s]         */
+    float refl;            /* nominal sponge reflection coefficient; >= 1 = off   */
+    float vmax_bound;      /* largest velocity the model may take (CFL check)     */
+    int32_t nshots;        /* S                                                   */
+    int32_t nrec;          /* R receivers per shot                                */
+    const int32_t* src_iz; /* [S] interior row of each shot's source node         */
+    const int32_t* src_ix; /* [S] interior column                                 */
+    const int32_t* rec_iz; /* [S*R] receiver rows, shot-major                     */
+    const int32_t* rec_ix; /* [S*R] receiver columns                              */
+    const float* wavelet;  /* [nt] source time function sampled at n*dt           */
+    int32_t ckpt_every;    /* checkpoint interval in steps; 0 = library default   */
+} aafwi_geometry;
+
+/* ---- context -------------------------------------------------------------- */
+
+/* Validate and copy the geometry, allocate all device scratch (wavefields,
+ * checkpoints, segment buffer, per-shot images).  Fails with AAFWI_E_CFL if
+ * vmax_bound*dt/h > 0.55 (the 2D limit of this scheme is 0.5547). */
+int aafwi_create(const aafwi_geometry* g, aafwi_stream stream, aafwi_ctx** out);
+
+/* Synchronise the context's stream and free everything it owns. */
+int aafwi_destroy(aafwi_ctx* ctx);
+
+/* Bytes of device memory the context holds. */
+int aafwi_device_bytes(const aafwi_ctx* ctx, int64_t* bytes);
+
+/* Synchronise the stream and report a model-validity flag raised by an
+ * earlier call (AAFWI_E_NONFINITE if some m was <= 0 or not finite; the flag
+ * is then cleared). */
+int aafwi_sync(aafwi_ctx* ctx);
+
+/* ---- forward modelling: f(m) = R F(m)  (eq. FWD, eq. FWI) ------------------ */
+
+/* m: device [nz][nx]; d: device [S][nt][R], overwritten.  If keep_ckpt != 0,
+ * wavefield checkpoints are kept so that aafwi_adjoint_from_residual can run
+ * the backward pass without a second forward. */
+int aafwi_forward_model(aafwi_ctx* ctx, const float* m, float* d, int keep_ckpt);
+
+/* r = d - d_obs (device [S][nt][R]; r may alias d) and J = 1/2 sum r^2 written
+ * as one double to device memory J (FP64 accumulation, deterministic order). */
+int aafwi_residual_misfit(aafwi_ctx* ctx, const float* d, const float* d_obs, float* r,
+                          double* J);
+
+/* ---- adjoint-state gradient (eq. FWI_adj, eq. adj_grad1) ------------------- */
+
+/* Forward (with checkpoints) + residual + adjoint + zero-lag imaging + fold.
+ * m, d_obs: device inputs; grad: device [nz][nx] = dJ/dm; J: device double. */
+int aafwi_adjoint_gradient(aafwi_ctx* ctx, const float* m, const float* d_obs, float* grad,
+                           double* J);
+
+/* Backward pass only, after aafwi_forward_model(..., keep_ckpt=1) with the
+ * model that is still in the context: grad = J'(m)^T r for a data-space
+ * vector r [S][nt][R].  AAFWI_E_STATE if no checkpoints are kept. */
+int aafwi_adjoint_from_residual(aafwi_ctx* ctx, const float* r, float* grad);
+
+/* ---- Born modelling and its adjoint (eq. Born, eq. LSRTM) ------------------ */
+
+/* d_scat = L dm at background m0 (device [nz][nx] each; d_scat [S][nt][R]). */
+int aafwi_born(aafwi_ctx* ctx, const float* m0, const float* dm, float* d_scat);
+
+/* image = L^T y at background m0 (y device [S][nt][R]; image device [nz][nx]).
+ * The RTM image of the LSRTM section is aafwi_born_adjoint(m0, d_r). */
+int aafwi_born_adjoint(aafwi_ctx* ctx, const float* m0, const float* y, float* image);
+
+/* ---- Anderson acceleration for gradient descent (Algorithm 2, Steps 1-3) --- */
+
+/* State for vectors of n FP32 values with memory parameter M (1 <= M <= 31):
+ * a device ring of the last M+1 accepted iterates and gradients, the FP64
+ * Gram matrix of consecutive gradient differences, and gamma.  cond_max is
+ * the largest 2-norm condition number of A_k kept: older columns are
+ * dropped (for good) while cond_2(A_k) > cond_max. */
+int aafwi_aa_create(int64_t n, int32_t M, double cond_max, aafwi_stream stream, aafwi_aa** out);
+int aafwi_aa_reset(aafwi_aa* aa);
+int aafwi_aa_destroy(aafwi_aa* aa);
+
+/* Push the accepted iterate p_k (device [n]) and its gradient g_k (device
+ * [n]) and compute, with f_i = -eta g_i and G(p) = p - eta grad J(p) (eq. GD):
+ *   p_bar   = G(p_k)                                  (Step 1)
+ *   gamma   = argmin ||A_k gamma - f_k||_2            (Step 2, eq. AAopt2),
+ *             A_k = [f_{i+1} - f_i] over the window, solved in FP64 from the
+ *             Gram matrix by a Jacobi eigen-decomposition
+ *   p_tilde = G(p_k) - sum_i gamma_i [G(p_{i+1}) - G(p_i)]   (Step 3, eq. AA2_update)
+ * p_bar and p_tilde are device [n] outputs.  gamma (device double [M]) and
+ * mk (device int32) receive gamma and M_k if non-NULL.  On the first call
+ * after create/reset, p_tilde = p_bar = G(p_0). */
+int aafwi_aa_step(aafwi_aa* aa, const float* p_k, const float* g_k, float eta, float* p_bar,
+                  float* p_tilde, double* gamma, int32_t* mk);
+
+/* Condition number of A_k found by the last step (device double), for logs. */
+int aafwi_aa_last_cond(aafwi_aa* aa, double* cond_dev);
+
+/* out = lambda*p_tilde + (1-lambda)*p_bar (Algorithm 2, Step 5); device [n]. */
+int aafwi_blend(aafwi_stream stream, int64_t n, float lambda, const float* p_tilde,
+                const float* p_bar, float* out);
+
+/* Number of doubles of device workspace the reductions below need. */
+#define AAFWI_DOT_WORKSPACE 1024
+
+/* *out = sum_i x_i y_i in FP64 (device [n] inputs, device double output),
+ * summed in a fixed order (bitwise reproducible).  workspace: device memory
+ * of AAFWI_DOT_WORKSPACE doubles owned by the caller; calls that may overlap
+ * must use different workspaces. */
+int aafwi_dot(aafwi_stream stream, int64_t n, const float* x, const float* y, double* out,
+              double* workspace);
+
+/* *out = sum_i g_i (a_i - b_i) in FP64 with a_i - b_i formed exactly; the
+ * Armijo test of the line search.  workspace as for aafwi_dot. */
+int aafwi_dot_diff(aafwi_stream stream, int64_t n, const float* g, const float* a,
+                   const float* b, double* out, double* workspace);
+
+/* y = a*x + y in FP32 (device [n]). */
+int aafwi_axpy(aafwi_stream stream, int64_t n, float a, const float* x, float* y);
+
+/* ---- instrumentation ------------------------------------------------------- */
+
+/* Kernel ids for aafwi_kernel_timing. */
+#define AAFWI_K_FWD_STEP   0 /* forward time step (with injection and sampling)   */
+#define AAFWI_K_REC_STEP   1 /* recompute step that stores q for imaging          */
+#define AAFWI_K_ADJ_STEP   2 /* adjoint step with imaging                         */
+#define AAFWI_K_BORN_STEP  3 /* background + scattered pair step                  */
+
+/* Enable (every > 0) or disable (0) event timing of every `every`-th launch
+ * of each stepping kernel on the context's stream; the counters are reset. */
+int aafwi_kernel_timing(aafwi_ctx* ctx, int every);
+
+/* Synchronise and return the mean duration in ms and the number of timed
+ * launches of kernel `kernel_id`. */
+int aafwi_kernel_timing_read(aafwi_ctx* ctx, int kernel_id, double* mean_ms, int64_t* count);
+
+/* Set the z-strip height (rows per wave) of the stepping kernels; 0 picks the
+ * default.  Used by the tile autotuner. */
+int aafwi_set_tile(aafwi_ctx* ctx, int32_t rows_per_wave);
+
+/* Thread-local message for the last non-zero return on this thread. */
+const char* aafwi_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AAFWI_H */

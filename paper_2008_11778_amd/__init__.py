@@ -1,0 +1,10 @@
+"""MI355X (gfx950) hot path of Anderson-accelerated seismic inversion.
+
+The wave-equation calls (forward modelling, adjoint-state gradient, Born
+and its adjoint) and the Anderson step run in hand-written HIP kernels
+behind the C ABI of ``libaafwi.so`` (declared in ``include/aafwi.h``);
+``_lib`` is the ctypes binding and ``inversion`` drives Algorithm 2 and
+its comparators on top of it.
+"""
+from ._lib import (AA, AafwiError, Context, Reducer, axpy, blend,  # noqa: F401
+                   K_ADJ_STEP, K_BORN_STEP, K_FWD_STEP, K_REC_STEP, LIB_PATH)

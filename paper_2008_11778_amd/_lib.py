@@ -1,0 +1,317 @@
+"""ctypes binding of libaafwi.so (argument marshalling only).
+
+Every computation runs in the HIP library; this module checks tensor
+shapes, dtypes and devices, passes raw device pointers and the HIP stream,
+and turns status codes into exceptions.  PyTorch provides device memory and
+streams.  Importing fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libaafwi.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'` "
+        "or `python -m paper_2008_11778_amd.build` (the HIP path has no CPU fallback)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+AAFWI_OK = 0
+ERRORS = {-1: "E_INVALID", -2: "E_CFL", -3: "E_NOMEM", -4: "E_HIP", -5: "E_NONFINITE", -6: "E_STATE"}
+K_FWD_STEP, K_REC_STEP, K_ADJ_STEP, K_BORN_STEP = 0, 1, 2, 3
+DOT_WORKSPACE = 1024
+
+
+class AafwiError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"aafwi {ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _Geometry(ctypes.Structure):
+    _fields_ = [
+        ("nz", ctypes.c_int32), ("nx", ctypes.c_int32), ("nb", ctypes.c_int32),
+        ("h", ctypes.c_float), ("dt", ctypes.c_float), ("nt", ctypes.c_int32),
+        ("vref", ctypes.c_float), ("refl", ctypes.c_float), ("vmax_bound", ctypes.c_float),
+        ("nshots", ctypes.c_int32), ("nrec", ctypes.c_int32),
+        ("src_iz", ctypes.POINTER(ctypes.c_int32)), ("src_ix", ctypes.POINTER(ctypes.c_int32)),
+        ("rec_iz", ctypes.POINTER(ctypes.c_int32)), ("rec_ix", ctypes.POINTER(ctypes.c_int32)),
+        ("wavelet", ctypes.POINTER(ctypes.c_float)), ("ckpt_every", ctypes.c_int32),
+    ]
+
+
+_vp, _i32, _i64, _f32, _f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_double
+
+
+def _sig(name, *args):
+    fn = getattr(_lib, name)
+    fn.argtypes = list(args)
+    fn.restype = ctypes.c_int
+    return fn
+
+
+_sig("aafwi_create", ctypes.POINTER(_Geometry), _vp, ctypes.POINTER(_vp))
+_sig("aafwi_destroy", _vp)
+_sig("aafwi_device_bytes", _vp, ctypes.POINTER(_i64))
+_sig("aafwi_sync", _vp)
+_sig("aafwi_forward_model", _vp, _vp, _vp, ctypes.c_int)
+_sig("aafwi_residual_misfit", _vp, _vp, _vp, _vp, _vp)
+_sig("aafwi_adjoint_gradient", _vp, _vp, _vp, _vp, _vp)
+_sig("aafwi_adjoint_from_residual", _vp, _vp, _vp)
+_sig("aafwi_born", _vp, _vp, _vp, _vp)
+_sig("aafwi_born_adjoint", _vp, _vp, _vp, _vp)
+_sig("aafwi_aa_create", _i64, _i32, _f64, _vp, ctypes.POINTER(_vp))
+_sig("aafwi_aa_reset", _vp)
+_sig("aafwi_aa_destroy", _vp)
+_sig("aafwi_aa_step", _vp, _vp, _vp, _f32, _vp, _vp, _vp, _vp)
+_sig("aafwi_aa_last_cond", _vp, _vp)
+_sig("aafwi_blend", _vp, _i64, _f32, _vp, _vp, _vp)
+_sig("aafwi_dot", _vp, _i64, _vp, _vp, _vp, _vp)
+_sig("aafwi_dot_diff", _vp, _i64, _vp, _vp, _vp, _vp, _vp)
+_sig("aafwi_axpy", _vp, _i64, _f32, _vp, _vp)
+_sig("aafwi_kernel_timing", _vp, ctypes.c_int)
+_sig("aafwi_kernel_timing_read", _vp, ctypes.c_int, ctypes.POINTER(_f64), ctypes.POINTER(_i64))
+_sig("aafwi_set_tile", _vp, _i32)
+_lib.aafwi_last_error.argtypes = []
+_lib.aafwi_last_error.restype = ctypes.c_char_p
+
+
+def _check(code: int):
+    if code != AAFWI_OK:
+        raise AafwiError(code, (_lib.aafwi_last_error() or b"").decode())
+
+
+def _ptr(t: torch.Tensor, dtype=torch.float32, numel=None, name="tensor") -> int:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must live on a GPU (got {t.device})")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype} (got {t.dtype})")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements (got {t.numel()})")
+    return t.data_ptr()
+
+
+def _stream_handle(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+def make_geometry_struct(geom, ckpt_every=0):
+    """Pack a geometry description (any object with the documented fields)."""
+    keep = dict(
+        src_iz=np.ascontiguousarray(geom.src_iz, dtype=np.int32).ravel(),
+        src_ix=np.ascontiguousarray(geom.src_ix, dtype=np.int32).ravel(),
+        rec_iz=np.ascontiguousarray(geom.rec_iz, dtype=np.int32).ravel(),
+        rec_ix=np.ascontiguousarray(geom.rec_ix, dtype=np.int32).ravel(),
+        wavelet=np.ascontiguousarray(geom.wavelet, dtype=np.float32).ravel(),
+    )
+    ip = ctypes.POINTER(ctypes.c_int32)
+    s = _Geometry(
+        nz=int(geom.nz), nx=int(geom.nx), nb=int(geom.nb), h=float(geom.h), dt=float(geom.dt),
+        nt=int(geom.nt), vref=float(geom.vref), refl=float(geom.refl),
+        vmax_bound=float(geom.vmax_bound), nshots=int(keep["src_iz"].size),
+        nrec=int(keep["rec_iz"].size // max(1, keep["src_iz"].size)),
+        src_iz=keep["src_iz"].ctypes.data_as(ip), src_ix=keep["src_ix"].ctypes.data_as(ip),
+        rec_iz=keep["rec_iz"].ctypes.data_as(ip), rec_ix=keep["rec_ix"].ctypes.data_as(ip),
+        wavelet=keep["wavelet"].ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+        ckpt_every=int(ckpt_every))
+    return s, keep
+
+
+class Context:
+    """One acquisition geometry on one GPU (all shots batched in every launch)."""
+
+    def __init__(self, geom, stream=None, ckpt_every=0, device=None):
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.current_stream()
+            self.nz, self.nx, self.nt = int(geom.nz), int(geom.nx), int(geom.nt)
+            self.nshots = int(np.asarray(geom.src_iz).size)
+            self.nrec = int(np.asarray(geom.rec_iz).size // self.nshots)
+            s, self._keep = make_geometry_struct(geom, ckpt_every)
+            h = _vp()
+            _check(_lib.aafwi_create(ctypes.byref(s), _stream_handle(self.stream), ctypes.byref(h)))
+            self._h = h
+        self.n = self.nz * self.nx
+        self.data_shape = (self.nshots, self.nt, self.nrec)
+
+    # -- lifetime -------------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(_lib.aafwi_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- helpers --------------------------------------------------------------
+    def _new(self, shape, dtype=torch.float32):
+        return torch.empty(shape, dtype=dtype, device=self.device)
+
+    def device_bytes(self) -> int:
+        v = _i64()
+        _check(_lib.aafwi_device_bytes(self._h, ctypes.byref(v)))
+        return int(v.value)
+
+    def sync(self):
+        _check(_lib.aafwi_sync(self._h))
+
+    # -- the calls -------------------------------------------------------------
+    def forward_model(self, m, d=None, keep_ckpt=False):
+        d = self._new(self.data_shape) if d is None else d
+        _check(_lib.aafwi_forward_model(self._h, _ptr(m, numel=self.n, name="m"),
+                                        _ptr(d, numel=self.nshots * self.nt * self.nrec, name="d"),
+                                        int(bool(keep_ckpt))))
+        return d
+
+    def residual_misfit(self, d, d_obs, r=None, J=None):
+        N = self.nshots * self.nt * self.nrec
+        r = self._new(self.data_shape) if r is None else r
+        J = self._new((1,), torch.float64) if J is None else J
+        _check(_lib.aafwi_residual_misfit(self._h, _ptr(d, numel=N, name="d"), _ptr(d_obs, numel=N, name="d_obs"),
+                                          _ptr(r, numel=N, name="r"), _ptr(J, torch.float64, 1, "J")))
+        return r, J
+
+    def adjoint_gradient(self, m, d_obs, grad=None, J=None):
+        grad = self._new((self.nz, self.nx)) if grad is None else grad
+        J = self._new((1,), torch.float64) if J is None else J
+        _check(_lib.aafwi_adjoint_gradient(self._h, _ptr(m, numel=self.n, name="m"),
+                                           _ptr(d_obs, numel=self.nshots * self.nt * self.nrec, name="d_obs"),
+                                           _ptr(grad, numel=self.n, name="grad"), _ptr(J, torch.float64, 1, "J")))
+        return grad, J
+
+    def adjoint_from_residual(self, r, grad=None):
+        grad = self._new((self.nz, self.nx)) if grad is None else grad
+        _check(_lib.aafwi_adjoint_from_residual(self._h, _ptr(r, numel=self.nshots * self.nt * self.nrec, name="r"),
+                                                _ptr(grad, numel=self.n, name="grad")))
+        return grad
+
+    def born(self, m0, dm, d=None):
+        d = self._new(self.data_shape) if d is None else d
+        _check(_lib.aafwi_born(self._h, _ptr(m0, numel=self.n, name="m0"), _ptr(dm, numel=self.n, name="dm"),
+                               _ptr(d, numel=self.nshots * self.nt * self.nrec, name="d")))
+        return d
+
+    def born_adjoint(self, m0, y, image=None):
+        image = self._new((self.nz, self.nx)) if image is None else image
+        _check(_lib.aafwi_born_adjoint(self._h, _ptr(m0, numel=self.n, name="m0"),
+                                       _ptr(y, numel=self.nshots * self.nt * self.nrec, name="y"),
+                                       _ptr(image, numel=self.n, name="image")))
+        return image
+
+    # -- instrumentation -------------------------------------------------------
+    def kernel_timing(self, every: int):
+        _check(_lib.aafwi_kernel_timing(self._h, int(every)))
+
+    def kernel_timing_read(self, kernel_id: int):
+        ms, cnt = _f64(), _i64()
+        _check(_lib.aafwi_kernel_timing_read(self._h, int(kernel_id), ctypes.byref(ms), ctypes.byref(cnt)))
+        return float(ms.value), int(cnt.value)
+
+    def set_tile(self, rows_per_wave: int):
+        _check(_lib.aafwi_set_tile(self._h, int(rows_per_wave)))
+
+
+class AA:
+    """Device state of Algorithm 2 (Steps 1-3) for vectors of n values."""
+
+    def __init__(self, n: int, M: int, cond_max: float = 1e5, stream=None):
+        self.n, self.M = int(n), int(M)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        h = _vp()
+        _check(_lib.aafwi_aa_create(self.n, self.M, float(cond_max), _stream_handle(self.stream), ctypes.byref(h)))
+        self._h = h
+        self.gamma = torch.zeros(self.M, dtype=torch.float64, device=self.device)
+        self.mk = torch.zeros(1, dtype=torch.int32, device=self.device)
+        self.cond = torch.zeros(1, dtype=torch.float64, device=self.device)
+
+    def reset(self):
+        _check(_lib.aafwi_aa_reset(self._h))
+
+    def step(self, p, g, eta, p_bar=None, p_tilde=None):
+        p_bar = torch.empty_like(p) if p_bar is None else p_bar
+        p_tilde = torch.empty_like(p) if p_tilde is None else p_tilde
+        _check(_lib.aafwi_aa_step(self._h, _ptr(p, numel=self.n, name="p"), _ptr(g, numel=self.n, name="g"),
+                                  float(eta), _ptr(p_bar, numel=self.n, name="p_bar"),
+                                  _ptr(p_tilde, numel=self.n, name="p_tilde"),
+                                  _ptr(self.gamma, torch.float64, self.M, "gamma"),
+                                  _ptr(self.mk, torch.int32, 1, "mk")))
+        return p_bar, p_tilde
+
+    def last_cond(self):
+        _check(_lib.aafwi_aa_last_cond(self._h, _ptr(self.cond, torch.float64, 1, "cond")))
+        return self.cond
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(_lib.aafwi_aa_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Reducer:
+    """FP64 dot products with a private device workspace (one per instance)."""
+
+    def __init__(self, stream=None, device=None):
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self.ws = torch.empty(DOT_WORKSPACE, dtype=torch.float64, device=dev)
+
+    def dot(self, x, y, out=None):
+        out = torch.empty(1, dtype=torch.float64, device=x.device) if out is None else out
+        n = x.numel()
+        _check(_lib.aafwi_dot(_stream_handle(self.stream), n, _ptr(x, numel=n, name="x"),
+                              _ptr(y, numel=n, name="y"), _ptr(out, torch.float64, 1, "out"),
+                              _ptr(self.ws, torch.float64, DOT_WORKSPACE, "workspace")))
+        return out
+
+    def dot_diff(self, g, a, b, out=None):
+        out = torch.empty(1, dtype=torch.float64, device=g.device) if out is None else out
+        n = g.numel()
+        _check(_lib.aafwi_dot_diff(_stream_handle(self.stream), n, _ptr(g, numel=n, name="g"),
+                                   _ptr(a, numel=n, name="a"), _ptr(b, numel=n, name="b"),
+                                   _ptr(out, torch.float64, 1, "out"),
+                                   _ptr(self.ws, torch.float64, DOT_WORKSPACE, "workspace")))
+        return out
+
+
+def blend(lam, p_tilde, p_bar, out=None, stream=None):
+    out = torch.empty_like(p_bar) if out is None else out
+    n = p_bar.numel()
+    _check(_lib.aafwi_blend(_stream_handle(stream), n, float(lam), _ptr(p_tilde, numel=n, name="p_tilde"),
+                            _ptr(p_bar, numel=n, name="p_bar"), _ptr(out, numel=n, name="out")))
+    return out
+
+
+def axpy(a, x, y, stream=None):
+    n = y.numel()
+    _check(_lib.aafwi_axpy(_stream_handle(stream), n, float(a), _ptr(x, numel=n, name="x"),
+                           _ptr(y, numel=n, name="y")))
+    return y

@@ -1,0 +1,501 @@
+// Anderson-acceleration step for gradient descent (Algorithm 2, Steps 1-3,
+// eq. Ak, eq. AAopt2, eq. solveGamma, eq. AA2_update) and the FP64 vector
+// reductions used by the line search.
+//
+// With f_i = -eta g_i the least-squares problem min ||A_k gamma - f_k|| has
+// A_k = -eta [g_{i+1} - g_i], so gamma = argmin ||dG gamma - g_k|| with
+// dG = [g_{i+1} - g_i] does not depend on eta.  The device keeps a ring of
+// the last M+1 accepted (p_i, g_i) in FP32, the FP64 Gram matrix of the
+// consecutive gradient differences (each difference formed exactly in FP64
+// from two FP32 values) and the right-hand side dG^T g_k.  Each step adds
+// one Gram row/column in a single pass over the window, then one workgroup
+// decomposes the Gram matrix (cyclic Jacobi, FP64): the oldest columns are
+// dropped while cond_2(A_k) = sqrt(lmax/lmin) exceeds cond_max, and
+// gamma = V diag(1/l) V^T rhs.  The mixing pass forms, per element in FP64,
+//   p_bar   = p_k - eta g_k
+//   p_tilde = p_bar - sum_i gamma_i [(p_{i+1} - p_i) - eta (g_{i+1} - g_i)].
+#include <cmath>
+#include <new>
+
+#include "common.hpp"
+
+namespace aafwi {
+
+constexpr int kAACap = 32;  // ring capacity bound: M + 1 <= 32
+
+struct AAState {
+    int head, count, slot_new, mk;
+    double cond;
+    double gram[kAACap * kAACap];
+    double rhs[kAACap];
+    double gamma[kAACap];
+};
+
+namespace {
+
+__device__ __forceinline__ double wave_reduce(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__global__ void k_aa_prepare(AAState* s, int cap) {
+    if (threadIdx.x != 0) return;
+    if (s->count == cap) {
+        // drop the oldest iterate and its gradient difference
+        const int ndg = s->count - 1;
+        for (int i = 0; i + 1 < ndg; ++i)
+            for (int j = 0; j + 1 < ndg; ++j) s->gram[i * kAACap + j] = s->gram[(i + 1) * kAACap + j + 1];
+        s->head = (s->head + 1) % cap;
+        s->count -= 1;
+    }
+    s->slot_new = (s->head + s->count) % cap;
+}
+
+// One pass: copy (p_new, g_new) into the ring and accumulate, per block,
+//   cross[i] = dnew . dG_i (i < cnt-1), cross[cnt-1] = dnew . dnew,
+//   rhs[i]   = dG_i . g_new (i < cnt-1), rhs[cnt-1] = dnew . g_new,
+// with dnew = g_new - g_{cnt-1}.
+template <int CAP>
+__global__ __launch_bounds__(kReduceThreads) void k_aa_dots(long long n, const float* __restrict__ p_new,
+                                                            const float* __restrict__ g_new,
+                                                            float* __restrict__ ring_p,
+                                                            float* __restrict__ ring_g, int cap,
+                                                            const AAState* __restrict__ s,
+                                                            double* __restrict__ part) {
+    const int cnt = s->count, head = s->head, slot_new = s->slot_new;
+    double cross[CAP], rhs[CAP];
+#pragma unroll
+    for (int i = 0; i < CAP; ++i) cross[i] = rhs[i] = 0.0;
+    for (long long e = (long long)blockIdx.x * kReduceThreads + threadIdx.x; e < n;
+         e += (long long)kReduceBlocks * kReduceThreads) {
+        const float gn = g_new[e];
+        ring_p[(long long)slot_new * n + e] = p_new[e];
+        ring_g[(long long)slot_new * n + e] = gn;
+        if (cnt == 0) continue;
+        float gv[CAP];
+#pragma unroll
+        for (int i = 0; i < CAP; ++i)
+            gv[i] = (i < cnt) ? ring_g[(long long)((head + i) % cap) * n + e] : 0.0f;
+        double glast = 0.0;
+#pragma unroll
+        for (int i = 0; i < CAP; ++i)
+            if (i == cnt - 1) glast = (double)gv[i];
+        const double dnew = (double)gn - glast;
+#pragma unroll
+        for (int i = 0; i + 1 < CAP; ++i) {
+            if (i + 1 < cnt) {
+                const double dg = (double)gv[i + 1] - (double)gv[i];
+                cross[i] += dnew * dg;
+                rhs[i] += dg * (double)gn;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < CAP; ++i) {
+            if (i == cnt - 1) {
+                cross[i] += dnew * dnew;
+                rhs[i] += dnew * (double)gn;
+            }
+        }
+    }
+    __shared__ double sh[kReduceThreads / 64][2 * CAP];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < CAP; ++i) {
+        const double a = wave_reduce(cross[i]);
+        const double b = wave_reduce(rhs[i]);
+        if (lane == 0) {
+            sh[wv][i] = a;
+            sh[wv][CAP + i] = b;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * CAP) {
+        double t = 0.0;
+        for (int w = 0; w < kReduceThreads / 64; ++w) t += sh[w][threadIdx.x];
+        part[(long long)blockIdx.x * 2 * CAP + threadIdx.x] = t;
+    }
+}
+
+// Cyclic Jacobi eigen-decomposition of the symmetric n x n matrix S (row
+// stride kAACap), overwritten by its diagonalisation; V receives the vectors.
+__device__ void jacobi_eig(double* S, double* V, int n) {
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) V[i * kAACap + j] = (i == j) ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        double off = 0.0, diag = 0.0;
+        for (int i = 0; i < n; ++i) {
+            diag += S[i * kAACap + i] * S[i * kAACap + i];
+            for (int j = i + 1; j < n; ++j) off += S[i * kAACap + j] * S[i * kAACap + j];
+        }
+        if (off <= 1e-32 * diag || off == 0.0) break;
+        for (int p = 0; p < n; ++p) {
+            for (int q = p + 1; q < n; ++q) {
+                const double apq = S[p * kAACap + q];
+                if (apq == 0.0) continue;
+                const double app = S[p * kAACap + p], aqq = S[q * kAACap + q];
+                const double theta = (aqq - app) / (2.0 * apq);
+                const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                const double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
+                for (int k = 0; k < n; ++k) {  // columns p, q
+                    const double skp = S[k * kAACap + p], skq = S[k * kAACap + q];
+                    S[k * kAACap + p] = c * skp - sn * skq;
+                    S[k * kAACap + q] = sn * skp + c * skq;
+                }
+                for (int k = 0; k < n; ++k) {  // rows p, q
+                    const double spk = S[p * kAACap + k], sqk = S[q * kAACap + k];
+                    S[p * kAACap + k] = c * spk - sn * sqk;
+                    S[q * kAACap + k] = sn * spk + c * sqk;
+                }
+                S[p * kAACap + q] = S[q * kAACap + p] = 0.0;
+                for (int k = 0; k < n; ++k) {
+                    const double vkp = V[k * kAACap + p], vkq = V[k * kAACap + q];
+                    V[k * kAACap + p] = c * vkp - sn * vkq;
+                    V[k * kAACap + q] = sn * vkp + c * vkq;
+                }
+            }
+        }
+    }
+}
+
+template <int CAP>
+__global__ __launch_bounds__(64) void k_aa_solve(AAState* s, const double* __restrict__ part, int cap,
+                                                 double cond_max) {
+    __shared__ double sums[2 * CAP];
+    __shared__ double S[kAACap * kAACap];
+    __shared__ double V[kAACap * kAACap];
+    const int t = threadIdx.x;
+    if (t < 2 * CAP) {
+        double acc = 0.0;
+        for (int b = 0; b < kReduceBlocks; ++b) acc += part[(long long)b * 2 * CAP + t];
+        sums[t] = acc;
+    }
+    __syncthreads();
+    if (t != 0) return;
+    const int cnt = s->count;  // before the push
+    if (cnt >= 1) {
+        const int k = cnt - 1;  // index of the new difference column
+        for (int i = 0; i < k; ++i) {
+            s->gram[k * kAACap + i] = sums[i];
+            s->gram[i * kAACap + k] = sums[i];
+        }
+        s->gram[k * kAACap + k] = sums[k];
+        for (int i = 0; i <= k; ++i) s->rhs[i] = sums[CAP + i];
+    }
+    s->count = cnt + 1;
+    int ndg = s->count - 1;
+    double cond = 1.0;
+    while (ndg > 0) {
+        for (int i = 0; i < ndg; ++i)
+            for (int j = 0; j < ndg; ++j) S[i * kAACap + j] = s->gram[i * kAACap + j];
+        jacobi_eig(S, V, ndg);
+        double lmax = 0.0, lmin = INFINITY;
+        for (int i = 0; i < ndg; ++i) {
+            lmax = fmax(lmax, S[i * kAACap + i]);
+            lmin = fmin(lmin, S[i * kAACap + i]);
+        }
+        cond = (lmin > 0.0) ? sqrt(lmax / lmin) : INFINITY;
+        if (cond <= cond_max) {
+            for (int i = 0; i < ndg; ++i) {
+                double acc = 0.0;
+                for (int j = 0; j < ndg; ++j) {
+                    double vr = 0.0;
+                    for (int k = 0; k < ndg; ++k) vr += V[k * kAACap + j] * s->rhs[k];
+                    acc += V[i * kAACap + j] * vr / S[j * kAACap + j];
+                }
+                s->gamma[i] = acc;
+            }
+            break;
+        }
+        // drop the oldest column for good
+        for (int i = 0; i + 1 < ndg; ++i) {
+            for (int j = 0; j + 1 < ndg; ++j) s->gram[i * kAACap + j] = s->gram[(i + 1) * kAACap + j + 1];
+            s->rhs[i] = s->rhs[i + 1];
+        }
+        s->head = (s->head + 1) % cap;
+        s->count -= 1;
+        ndg -= 1;
+        cond = 1.0;
+    }
+    s->mk = ndg;
+    s->cond = (ndg > 0) ? cond : 0.0;
+}
+
+template <int CAP>
+__global__ __launch_bounds__(256) void k_aa_mix(long long n, const float* __restrict__ p_k,
+                                                const float* __restrict__ g_k, float eta,
+                                                const float* __restrict__ ring_p,
+                                                const float* __restrict__ ring_g, int cap,
+                                                const AAState* __restrict__ s, float* __restrict__ p_bar,
+                                                float* __restrict__ p_tilde) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const int mk = s->mk, head = s->head;
+    const double et = (double)eta;
+    const double pb = (double)p_k[e] - et * (double)g_k[e];
+    double pt = pb;
+    if (mk > 0) {
+        float pv[CAP], gv[CAP];
+#pragma unroll
+        for (int i = 0; i < CAP; ++i) {
+            const bool ok = i <= mk;
+            const long long o = (long long)((head + i) % cap) * n + e;
+            pv[i] = ok ? ring_p[o] : 0.0f;
+            gv[i] = ok ? ring_g[o] : 0.0f;
+        }
+#pragma unroll
+        for (int i = 0; i + 1 < CAP; ++i) {
+            if (i < mk) {
+                const double dGi = ((double)pv[i + 1] - (double)pv[i]) - et * ((double)gv[i + 1] - (double)gv[i]);
+                pt -= s->gamma[i] * dGi;
+            }
+        }
+    }
+    p_bar[e] = (float)pb;
+    p_tilde[e] = (float)pt;
+}
+
+__global__ __launch_bounds__(kReduceThreads) void k_dot(long long n, const float* __restrict__ x,
+                                                        const float* __restrict__ y,
+                                                        const float* __restrict__ z,
+                                                        double* __restrict__ part) {
+    double acc = 0.0;
+    for (long long i = (long long)blockIdx.x * kReduceThreads + threadIdx.x; i < n;
+         i += (long long)kReduceBlocks * kReduceThreads) {
+        const double yv = z ? ((double)y[i] - (double)z[i]) : (double)y[i];
+        acc += (double)x[i] * yv;
+    }
+    __shared__ double sh[kReduceThreads / 64];
+    const double w = wave_reduce(acc);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = w;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int i = 0; i < kReduceThreads / 64; ++i) t += sh[i];
+        part[blockIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(kReduceThreads) void k_sum_partials(const double* __restrict__ part,
+                                                                 double* __restrict__ out) {
+    __shared__ double sh[kReduceThreads / 64];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < kReduceBlocks; i += kReduceThreads) acc += part[i];
+    const double w = wave_reduce(acc);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = w;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int i = 0; i < kReduceThreads / 64; ++i) t += sh[i];
+        out[0] = t;
+    }
+}
+
+__global__ void k_blend(long long n, float lam, const float* __restrict__ pt, const float* __restrict__ pb,
+                        float* __restrict__ out) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double l = (double)lam;
+    out[i] = (float)(l * (double)pt[i] + (1.0 - l) * (double)pb[i]);
+}
+
+__global__ void k_axpy(long long n, float a, const float* __restrict__ x, float* __restrict__ y) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    y[i] = fmaf(a, x[i], y[i]);
+}
+
+template <int CAP>
+void aa_launch(hipStream_t st, long long n, const float* p, const float* g, float eta, float* ring_p,
+               float* ring_g, int cap, AAState* s, double* part, double cond_max, float* pbar,
+               float* ptilde) {
+    hipLaunchKernelGGL(k_aa_prepare, dim3(1), dim3(64), 0, st, s, cap);
+    AAFWI_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_aa_dots<CAP>, dim3(kReduceBlocks), dim3(kReduceThreads), 0, st, n, p, g, ring_p,
+                       ring_g, cap, (const AAState*)s, part);
+    AAFWI_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_aa_solve<CAP>, dim3(1), dim3(64), 0, st, s, (const double*)part, cap, cond_max);
+    AAFWI_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_aa_mix<CAP>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, p, g, eta,
+                       (const float*)ring_p, (const float*)ring_g, cap, (const AAState*)s, pbar, ptilde);
+    AAFWI_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+void launch_dot(hipStream_t st, long long n, const float* x, const float* y, const float* z,
+                double* partials, double* out) {
+    hipLaunchKernelGGL(k_dot, dim3(kReduceBlocks), dim3(kReduceThreads), 0, st, n, x, y, z, partials);
+    AAFWI_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kReduceThreads), 0, st, (const double*)partials, out);
+    AAFWI_HIP(hipGetLastError());
+}
+
+void launch_blend(hipStream_t st, long long n, float lam, const float* pt, const float* pb, float* out) {
+    hipLaunchKernelGGL(k_blend, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, lam, pt, pb, out);
+    AAFWI_HIP(hipGetLastError());
+}
+
+void launch_axpy(hipStream_t st, long long n, float a, const float* x, float* y) {
+    hipLaunchKernelGGL(k_axpy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, a, x, y);
+    AAFWI_HIP(hipGetLastError());
+}
+
+}  // namespace aafwi
+
+// ---------------------------------------------------------------------------
+// C ABI: AA state and vector helpers
+// ---------------------------------------------------------------------------
+struct aafwi_aa {
+    long long n;
+    int M, cap, capT;  // cap = M + 1 slots; capT = kernel template bound
+    double cond_max;
+    hipStream_t stream;
+    float* ring_p;
+    float* ring_g;
+    aafwi::AAState* state;
+    double* part;
+};
+
+namespace {
+
+template <typename F>
+int guarded(F&& f) {
+    try {
+        return f();
+    } catch (const aafwi::Error& e) {
+        aafwi::set_last_error(e.msg);
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        aafwi::set_last_error("host allocation failed");
+        return AAFWI_E_NOMEM;
+    } catch (...) {
+        aafwi::set_last_error("unknown error");
+        return AAFWI_E_INVALID;
+    }
+}
+
+void aa_free(aafwi_aa* a) {
+    if (!a) return;
+    if (a->ring_p) (void)hipFree(a->ring_p);
+    if (a->ring_g) (void)hipFree(a->ring_g);
+    if (a->state) (void)hipFree(a->state);
+    if (a->part) (void)hipFree(a->part);
+    delete a;
+}
+
+}  // namespace
+
+extern "C" int aafwi_aa_create(int64_t n, int32_t M, double cond_max, aafwi_stream stream, aafwi_aa** out) {
+    return guarded([&]() -> int {
+        AAFWI_REQUIRE(out != nullptr, "aa_create: out is NULL");
+        *out = nullptr;
+        AAFWI_REQUIRE(n > 0, "aa_create: n must be positive");
+        AAFWI_REQUIRE(M >= 1 && M + 1 <= aafwi::kAACap, "aa_create: M must be in [1, 31]");
+        AAFWI_REQUIRE(cond_max >= 1.0, "aa_create: cond_max must be >= 1");
+        aafwi_aa* a = new aafwi_aa{};
+        a->n = n;
+        a->M = M;
+        a->cap = M + 1;
+        a->capT = a->cap <= 4 ? 4 : a->cap <= 8 ? 8 : a->cap <= 16 ? 16 : 32;
+        a->cond_max = cond_max;
+        a->stream = (hipStream_t)stream;
+        try {
+            auto alloc = [&](void** p, size_t bytes) {
+                if (hipMalloc(p, bytes) != hipSuccess)
+                    throw aafwi::Error{AAFWI_E_NOMEM, "aa_create: device allocation failed"};
+            };
+            alloc((void**)&a->ring_p, sizeof(float) * (size_t)n * a->cap);
+            alloc((void**)&a->ring_g, sizeof(float) * (size_t)n * a->cap);
+            alloc((void**)&a->state, sizeof(aafwi::AAState));
+            alloc((void**)&a->part, sizeof(double) * aafwi::kReduceBlocks * 2 * aafwi::kAACap);
+            AAFWI_HIP(hipMemsetAsync(a->state, 0, sizeof(aafwi::AAState), a->stream));
+        } catch (...) {
+            aa_free(a);
+            throw;
+        }
+        *out = a;
+        return AAFWI_OK;
+    });
+}
+
+extern "C" int aafwi_aa_reset(aafwi_aa* a) {
+    return guarded([&]() -> int {
+        AAFWI_REQUIRE(a != nullptr, "aa_reset: NULL state");
+        AAFWI_HIP(hipMemsetAsync(a->state, 0, sizeof(aafwi::AAState), a->stream));
+        return AAFWI_OK;
+    });
+}
+
+extern "C" int aafwi_aa_destroy(aafwi_aa* a) {
+    return guarded([&]() -> int {
+        if (!a) return AAFWI_OK;
+        (void)hipStreamSynchronize(a->stream);
+        aa_free(a);
+        return AAFWI_OK;
+    });
+}
+
+extern "C" int aafwi_aa_step(aafwi_aa* a, const float* p_k, const float* g_k, float eta, float* p_bar,
+                             float* p_tilde, double* gamma, int32_t* mk) {
+    return guarded([&]() -> int {
+        AAFWI_REQUIRE(a != nullptr, "aa_step: NULL state");
+        AAFWI_REQUIRE(p_k && g_k && p_bar && p_tilde, "aa_step: NULL vector");
+        AAFWI_REQUIRE(std::isfinite(eta) && eta >= 0.0f, "aa_step: eta must be finite and >= 0");
+        switch (a->capT) {
+            case 4: aafwi::aa_launch<4>(a->stream, a->n, p_k, g_k, eta, a->ring_p, a->ring_g, a->cap, a->state, a->part, a->cond_max, p_bar, p_tilde); break;
+            case 8: aafwi::aa_launch<8>(a->stream, a->n, p_k, g_k, eta, a->ring_p, a->ring_g, a->cap, a->state, a->part, a->cond_max, p_bar, p_tilde); break;
+            case 16: aafwi::aa_launch<16>(a->stream, a->n, p_k, g_k, eta, a->ring_p, a->ring_g, a->cap, a->state, a->part, a->cond_max, p_bar, p_tilde); break;
+            default: aafwi::aa_launch<32>(a->stream, a->n, p_k, g_k, eta, a->ring_p, a->ring_g, a->cap, a->state, a->part, a->cond_max, p_bar, p_tilde); break;
+        }
+        if (gamma)
+            AAFWI_HIP(hipMemcpyAsync(gamma, a->state->gamma, sizeof(double) * a->M, hipMemcpyDeviceToDevice,
+                                     a->stream));
+        if (mk)
+            AAFWI_HIP(hipMemcpyAsync(mk, &a->state->mk, sizeof(int32_t), hipMemcpyDeviceToDevice, a->stream));
+        return AAFWI_OK;
+    });
+}
+
+extern "C" int aafwi_aa_last_cond(aafwi_aa* a, double* cond_dev) {
+    return guarded([&]() -> int {
+        AAFWI_REQUIRE(a && cond_dev, "aa_last_cond: NULL argument");
+        AAFWI_HIP(hipMemcpyAsync(cond_dev, &a->state->cond, sizeof(double), hipMemcpyDeviceToDevice, a->stream));
+        return AAFWI_OK;
+    });
+}
+
+
+extern "C" int aafwi_blend(aafwi_stream stream, int64_t n, float lambda, const float* p_tilde, const float* p_bar,
+                           float* out) {
+    return guarded([&]() -> int {
+        AAFWI_REQUIRE(n > 0 && p_tilde && p_bar && out, "blend: bad argument");
+        aafwi::launch_blend((hipStream_t)stream, n, lambda, p_tilde, p_bar, out);
+        return AAFWI_OK;
+    });
+}
+
+extern "C" int aafwi_dot(aafwi_stream stream, int64_t n, const float* x, const float* y, double* out,
+                         double* workspace) {
+    return guarded([&]() -> int {
+        AAFWI_REQUIRE(n > 0 && x && y && out && workspace, "dot: bad argument");
+        aafwi::launch_dot((hipStream_t)stream, n, x, y, nullptr, workspace, out);
+        return AAFWI_OK;
+    });
+}
+
+extern "C" int aafwi_dot_diff(aafwi_stream stream, int64_t n, const float* g, const float* a, const float* b,
+                              double* out, double* workspace) {
+    return guarded([&]() -> int {
+        AAFWI_REQUIRE(n > 0 && g && a && b && out && workspace, "dot_diff: bad argument");
+        aafwi::launch_dot((hipStream_t)stream, n, g, a, b, workspace, out);
+        return AAFWI_OK;
+    });
+}
+
+extern "C" int aafwi_axpy(aafwi_stream stream, int64_t n, float a, const float* x, float* y) {
+    return guarded([&]() -> int {
+        AAFWI_REQUIRE(n > 0 && x && y, "axpy: bad argument");
+        aafwi::launch_axpy((hipStream_t)stream, n, a, x, y);
+        return AAFWI_OK;
+    });
+}
