@@ -1,0 +1,178 @@
+#!/usr/bin/env python
+"""Throughput of Anderson-accelerated FWI on one MI355X.
+
+A step is one iteration of Algorithm 2 on the full FWI-gradient workload:
+768 x 256 interior grid (nx x nz), dx = 12.5 m, 20-cell sponge, dt = 1 ms,
+4000 time steps, 64 shots batched in every launch, 384 receivers per shot,
+wavefield checkpoints every 50 steps, AA depth M = 10.  Each iteration runs
+the backward pass of the gradient (recompute + adjoint + imaging + fold) on
+the forward run kept from the accepted line-search trial, the Anderson step,
+and the line-search forward run(s).
+
+value = (forward + adjoint point-updates of one gradient, per iteration) /
+wall time, in G point-updates/s; a point-update advances one padded cell one
+time step.  Recompute updates and extra line-search forwards are not
+credited.  The roofline object is for the stepping kernel with the largest
+total time, timed live with HIP events on the library's stream.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "FD Gpt-updates/s (fwd+adj) & %HBM roofline; time to misfit target, AA vs +learned"
+HBM_PEAK_GBS = 8000.0
+BYTES = {0: 16, 1: 20, 2: 28, 3: 32}  # algorithmic bytes per point-update, per kernel id
+NAMES = {0: "fwd_step", 1: "rec_step", 2: "adj_step", 3: "born_step"}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(nt_sample: int = 300):
+    """The FP64 oracle on one shot of the same grid, nt_sample steps,
+    forward + adjoint gradient; returns G point-updates/s."""
+    import numpy as np
+
+    import synth
+    from oracle import fd
+    g, m_true, m0 = synth.config2(nshots=64, nt=nt_sample)
+    g1 = g.subset_shots([0])
+    d_obs = np.zeros((1, nt_sample, g1.nrec), np.float32)
+    t0 = time.perf_counter()
+    fd.adjoint_gradient(g1, m0, d_obs)
+    dt = time.perf_counter() - t0
+    updates = 2.0 * g1.nz_p * g1.nx_p * nt_sample
+    return dict(value=updates / dt / 1e9, unit="Gpt-updates/s", cores=1, kind="oracle",
+                sample=f"1 of 64 shots, {nt_sample} of 4000 steps, forward + adjoint gradient "
+                       f"(FP64 NumPy, single thread), {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=6)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--time-every", type=int, default=16, help="event-time every n-th stepping launch")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tile", type=int, default=-1,
+                    help="rows per wave for every stepping kernel (-1 = autotune, 0 = library default)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the shot-sharded multi-GPU "
+              "design is described in DESIGN.md and not built", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2008_11778_amd import Context
+    from paper_2008_11778_amd.inversion import AADescent, FWIProblem
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    g, m_true, m0 = synth.config2()
+    log(f"workload: {g.nx}x{g.nz} grid, {g.nshots} shots, {g.nt} steps, {g.nrec} receivers")
+    ctx = Context(g, ckpt_every=50)
+    m0t = torch.from_numpy(m0).to(dev)
+    if args.tile >= 0:
+        ctx.set_tile(args.tile)
+        tiles = {k: ctx.get_tile(k) for k in range(4)}
+    else:
+        from paper_2008_11778_amd import autotune
+        tiles = autotune.tune(g, m0t, verbose=True)
+        autotune.apply(ctx, tiles)
+    log(f"rows per wave (fwd, rec, adj, born): {[tiles[k] for k in range(4)]}")
+    log(f"device memory held by the context: {ctx.device_bytes() / 2**30:.1f} GiB")
+    cells = g.nz_p * g.nx_p
+    upd_fwd = float(cells) * g.nt * g.nshots
+
+    mt = torch.from_numpy(m_true).to(dev)
+    d_obs = ctx.forward_model(mt)  # synthetic observed data from the true model
+    torch.cuda.synchronize()
+    prob = FWIProblem(ctx, d_obs)
+    run = AADescent(prob, m0t, None, M=10)
+    rec = run.first()
+    log(f"k=0 J={rec.J:.6e} eta={run.eta:.3e}")
+    for _ in range(args.warmup):
+        rec = run.iterate()
+        log(f"warmup k={rec.k} J={rec.J:.6e} lam={rec.lam} mk={rec.mk}")
+
+    ctx.kernel_timing(args.time_every)
+    torch.cuda.synchronize()
+    n_adj0, n_fwd0 = prob.n_adj, prob.n_fwd
+    t0 = time.perf_counter()
+    recs = []
+    for _ in range(args.steps):
+        rec = run.iterate()
+        recs.append(rec)
+        log(f"step k={rec.k} J={rec.J:.6e} lam={rec.lam} mk={rec.mk} fwd={rec.n_fwd} t={rec.wall:.2f}s")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    n_adj, n_fwd = prob.n_adj - n_adj0, prob.n_fwd - n_fwd0
+    credited = 2.0 * upd_fwd * n_adj  # one forward and one adjoint per gradient
+    value = credited / elapsed / 1e9
+
+    # kernel timing
+    kt = {}
+    for kid in (0, 1, 2):
+        mean_ms, cnt = ctx.kernel_timing_read(kid)
+        kt[kid] = (mean_ms, cnt)
+    launches = {0: n_fwd * g.nt, 1: n_adj * g.nt, 2: n_adj * g.nt}
+    totals = {k: kt[k][0] * launches[k] for k in kt}
+    dom = max(totals, key=totals.get)
+    mean_s = kt[dom][0] / 1e3
+    per_launch_bytes = BYTES[dom] * cells * g.nshots
+    achieved = per_launch_bytes / mean_s / 1e9
+    roofline = dict(kernel=NAMES[dom], bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
+                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                    mean_launch_us=round(kt[dom][0] * 1e3, 2), timed_launches=kt[dom][1],
+                    bytes_per_launch=per_launch_bytes)
+    kernels = {NAMES[k]: dict(mean_us=round(kt[k][0] * 1e3, 2), timed=kt[k][1],
+                              gbs=round(BYTES[k] * cells * g.nshots / (kt[k][0] / 1e3) / 1e9, 1) if kt[k][0] else None)
+               for k in kt}
+    it_bytes = upd_fwd * (16 * n_fwd + 20 * n_adj + 28 * n_adj)
+    out = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "Gpt-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "AA-FWI iteration on the FWI-gradient case: 768x256 (nx x nz) grid, dx 12.5 m, "
+                        "20-cell sponge, dt 1 ms, 4000 steps, 64 shots in one launch, 384 receivers, "
+                        "checkpoints every 50 steps, AA M=10",
+            "global_batch": g.nshots, "seq_len": g.nt, "parallelism": "single GPU",
+            "rows_per_wave": {NAMES[k]: tiles[k] for k in range(4)},
+        },
+        "roofline": roofline,
+        "kernels": kernels,
+        "iteration": {"gradients": n_adj, "forward_runs": n_fwd,
+                      "hbm_frac_all_kernels": round(it_bytes / elapsed / 1e9 / HBM_PEAK_GBS, 4),
+                      "misfits": [r.J for r in recs], "lambdas": [r.lam for r in recs]},
+    }
+    if not args.no_cpu_baseline:
+        log("timing the FP64 oracle on a bounded sample ...")
+        out["cpu_baseline"] = cpu_baseline()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -191,9 +191,13 @@ int aafwi_kernel_timing(aafwi_ctx* ctx, int every);
  * launches of kernel `kernel_id`. */
 int aafwi_kernel_timing_read(aafwi_ctx* ctx, int kernel_id, double* mean_ms, int64_t* count);
 
-/* Set the z-strip height (rows per wave) of the stepping kernels; 0 picks the
- * default.  Used by the tile autotuner. */
-int aafwi_set_tile(aafwi_ctx* ctx, int32_t rows_per_wave);
+/* Set the z-strip height (rows per wave, 0..64; 0 picks the default) of
+ * stepping kernel kernel_id (an AAFWI_K_* id, or -1 for all of them).  Used
+ * by the tile autotuner; results do not depend on it (bitwise). */
+int aafwi_set_tile(aafwi_ctx* ctx, int32_t kernel_id, int32_t rows_per_wave);
+
+/* Current strip height of stepping kernel kernel_id. */
+int aafwi_get_tile(const aafwi_ctx* ctx, int32_t kernel_id, int32_t* rows_per_wave);
 
 /* Thread-local message for the last non-zero return on this thread. */
 const char* aafwi_last_error(void);

@@ -78,7 +78,8 @@ _sig("aafwi_dot_diff", _vp, _i64, _vp, _vp, _vp, _vp, _vp)
 _sig("aafwi_axpy", _vp, _i64, _f32, _vp, _vp)
 _sig("aafwi_kernel_timing", _vp, ctypes.c_int)
 _sig("aafwi_kernel_timing_read", _vp, ctypes.c_int, ctypes.POINTER(_f64), ctypes.POINTER(_i64))
-_sig("aafwi_set_tile", _vp, _i32)
+_sig("aafwi_set_tile", _vp, _i32, _i32)
+_sig("aafwi_get_tile", _vp, _i32, ctypes.POINTER(_i32))
 _lib.aafwi_last_error.argtypes = []
 _lib.aafwi_last_error.restype = ctypes.c_char_p
 
@@ -229,8 +230,13 @@ class Context:
         _check(_lib.aafwi_kernel_timing_read(self._h, int(kernel_id), ctypes.byref(ms), ctypes.byref(cnt)))
         return float(ms.value), int(cnt.value)
 
-    def set_tile(self, rows_per_wave: int):
-        _check(_lib.aafwi_set_tile(self._h, int(rows_per_wave)))
+    def set_tile(self, rows_per_wave: int, kernel_id: int = -1):
+        _check(_lib.aafwi_set_tile(self._h, int(kernel_id), int(rows_per_wave)))
+
+    def get_tile(self, kernel_id: int) -> int:
+        v = _i32()
+        _check(_lib.aafwi_get_tile(self._h, int(kernel_id), ctypes.byref(v)))
+        return int(v.value)
 
 
 class AA:

@@ -1,0 +1,92 @@
+"""Strip-height autotuner for the stepping kernels.
+
+For a grid class (padded rows, padded columns, shot count) every candidate
+rows-per-wave value is timed with the library's event timer on a short
+record (same grid and shots, few time steps), separately for the forward,
+recompute, adjoint and Born steps; the fastest value per kernel is kept and
+cached in a JSON file.  Results are bitwise independent of the choice.
+"""
+from __future__ import annotations
+
+import json
+import os
+import types
+
+import numpy as np
+
+CANDIDATES = (8, 12, 16, 20, 24, 28, 32, 40, 48, 64)
+KERNELS = (0, 1, 2, 3)  # forward, recompute, adjoint, Born
+
+
+def _short(geom, nt):
+    g = types.SimpleNamespace(**{k: getattr(geom, k) for k in (
+        "nz", "nx", "nb", "h", "dt", "vref", "refl", "vmax_bound", "src_iz", "src_ix", "rec_iz", "rec_ix")})
+    g.nt = nt
+    g.wavelet = np.asarray(geom.wavelet, np.float32)[:nt].copy()
+    return g
+
+
+def grid_key(geom) -> str:
+    S = int(np.asarray(geom.src_iz).size)
+    return f"{geom.nz + 2 * geom.nb}x{geom.nx + 2 * geom.nb}x{S}"
+
+
+def cache_path() -> str:
+    base = os.environ.get("AAFWI_TUNE_CACHE") or os.path.join(os.path.expanduser("~"), ".cache", "aafwi")
+    return os.path.join(base, "tiles.json")
+
+
+def tune(geom, m, candidates=CANDIDATES, nt=48, use_cache=True, verbose=False) -> dict:
+    """Return {kernel_id: rows_per_wave} for this grid class (m: device model)."""
+    import torch
+
+    from ._lib import Context
+    key = grid_key(geom)
+    path = cache_path()
+    if use_cache and os.path.exists(path):
+        with open(path) as f:
+            cached = json.load(f)
+        if key in cached:
+            return {int(k): int(v) for k, v in cached[key].items()}
+    g = _short(geom, nt)
+    best = {k: (float("inf"), 0) for k in KERNELS}
+    table = {}
+    with Context(g, ckpt_every=nt) as ctx:
+        r = torch.zeros(ctx.data_shape, device=m.device)
+        dm = torch.zeros_like(m)
+        for rows in candidates:
+            if rows > g.nz + 2 * g.nb:
+                continue
+            ctx.set_tile(rows)
+            ctx.forward_model(m, keep_ckpt=True)  # warm
+            ctx.kernel_timing(1)
+            ctx.forward_model(m, keep_ckpt=True)
+            ctx.adjoint_from_residual(r)
+            ctx.born(m, dm)
+            for k in KERNELS:
+                ms, cnt = ctx.kernel_timing_read(k)
+                table[(rows, k)] = ms
+                if cnt and ms < best[k][0]:
+                    best[k] = (ms, rows)
+            ctx.kernel_timing(0)
+    if verbose:
+        for k in KERNELS:
+            row = " ".join(f"{rows}:{table.get((rows, k), float('nan')) * 1e3:.1f}us" for rows in candidates
+                           if (rows, k) in table)
+            print(f"autotune {key} kernel {k}: {row} -> {best[k][1]}", flush=True)
+    out = {k: best[k][1] for k in KERNELS}
+    if use_cache:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        cached = {}
+        if os.path.exists(path):
+            with open(path) as f:
+                cached = json.load(f)
+        cached[key] = out
+        with open(path, "w") as f:
+            json.dump(cached, f, indent=1)
+    return out
+
+
+def apply(ctx, tiles: dict):
+    for k, rows in tiles.items():
+        ctx.set_tile(int(rows), int(k))

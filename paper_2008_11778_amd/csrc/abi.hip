@@ -29,6 +29,7 @@ struct aafwi_ctx {
     float h = 0, dt = 0, vref = 0, refl = 0, vmax = 0;
     std::vector<float> wavelet;
     aafwi::WaveGrid g{};
+    aafwi::WaveGrid gk[4];  // per stepping kernel (tile height may differ)
     hipStream_t stream = nullptr;
     long long field = 0;  // S * plane floats
 
@@ -106,6 +107,15 @@ void free_ctx(aafwi_ctx* c) {
     delete c;
 }
 
+// Strip height: rows per wave; 0 picks about 8 strips per column of tiles.
+void apply_tile(aafwi::WaveGrid& g, int rows) {
+    int tz = rows;
+    if (tz == 0) tz = std::max(16, std::min((g.nzp + 7) / 8, 64));
+    g.tz = std::min(tz, g.nzp);
+    g.nzs = (g.nzp + g.tz - 1) / g.tz;
+    g.ntiles = g.ntx * g.nzs * g.S;
+}
+
 aafwi::RecMaps maps(const aafwi_ctx* c) { return {c->rowmap, c->xmap, c->rnext, c->nrr, c->R}; }
 aafwi::SrcNodes srcs(const aafwi_ctx* c) { return {c->src}; }
 
@@ -159,7 +169,7 @@ void run_forward(aafwi_ctx* c, const float* m, float* d, bool keep) {
         }
         {
             Timed t(c, AAFWI_K_FWD_STEP);
-            aafwi::launch_fwd_step(c->stream, c->g, c->K, cur, prev, prev, c->wavelet[n], srcs(c), maps(c), d, n,
+            aafwi::launch_fwd_step(c->stream, c->gk[AAFWI_K_FWD_STEP], c->K, cur, prev, prev, c->wavelet[n], srcs(c), maps(c), d, n,
                                    c->nt, cu, cum);
         }
         std::swap(cur, prev);
@@ -193,7 +203,7 @@ void run_backward(aafwi_ctx* c, const float* r, float* grad) {
             }
             {
                 Timed t(c, AAFWI_K_REC_STEP);
-                aafwi::launch_rec_step(c->stream, c->g, c->K, cur, prev, out, c->wavelet[n], srcs(c),
+                aafwi::launch_rec_step(c->stream, c->gk[AAFWI_K_REC_STEP], c->K, cur, prev, out, c->wavelet[n], srcs(c),
                                        c->qseg + (long long)(n - n0) * c->field);
             }
             prev_is_ck = (cur == ckpt_slot(c, j, 0) || cur == ckpt_slot(c, j, 1));
@@ -204,7 +214,7 @@ void run_backward(aafwi_ctx* c, const float* r, float* grad) {
         for (int n = n1 - 1; n >= n0; --n) {
             {
                 Timed t(c, AAFWI_K_ADJ_STEP);
-                aafwi::launch_adj_step(c->stream, c->g, c->K, lam1, lam2, lam2, maps(c), r, n, c->nt, h2,
+                aafwi::launch_adj_step(c->stream, c->gk[AAFWI_K_ADJ_STEP], c->K, lam1, lam2, lam2, maps(c), r, n, c->nt, h2,
                                        c->qseg + (long long)(n - n0) * c->field, c->GI);
             }
             std::swap(lam1, lam2);
@@ -238,7 +248,8 @@ extern "C" int aafwi_create(const aafwi_geometry* gp, aafwi_stream stream, aafwi
         if (cfl > 0.55)
             throw Error{AAFWI_E_CFL, "create: vmax_bound*dt/h = " + std::to_string(cfl) + " exceeds 0.55"};
         const long long nzp = (long long)G.nz + 2LL * G.nb, nxp = (long long)G.nx + 2LL * G.nb;
-        AAFWI_REQUIRE(nzp * ((nxp + 63) / 64 * 64) < (1LL << 31), "create: padded plane too large");
+        // byte offsets of a plane (plus 16 rows of slack) must stay below 2^31
+        AAFWI_REQUIRE(4LL * (nzp + 16) * ((nxp + 63) / 64 * 64) < (1LL << 31), "create: padded plane too large");
         for (int s = 0; s < G.nshots; ++s) {
             AAFWI_REQUIRE(G.src_iz[s] >= 0 && G.src_iz[s] < G.nz && G.src_ix[s] >= 0 && G.src_ix[s] < G.nx,
                           "create: source index outside the interior grid");
@@ -273,14 +284,8 @@ extern "C" int aafwi_create(const aafwi_geometry* gp, aafwi_stream stream, aafwi
             g.scoef = (float)(smax * G.dt / 2.0);
             g.inv_nb = (float)(1.0 / G.nb);
             c->field = (long long)g.S * g.plane;
-            // default strip height: about 8 strips of rows per column of tiles
-            {
-                int tz = (g.nzp + 7) / 8;
-                tz = std::max(16, std::min(tz, 64));
-                g.tz = tz;
-                g.nzs = (g.nzp + tz - 1) / tz;
-                g.ntiles = g.ntx * g.nzs * g.S;
-            }
+            apply_tile(g, 0);
+            for (auto& gk : c->gk) gk = g;
 
             // receiver maps
             std::vector<int> rowmap((size_t)g.S * g.nzp, -1);
@@ -426,7 +431,7 @@ extern "C" int aafwi_born(aafwi_ctx* c, const float* m0, const float* dm, float*
         for (int n = 0; n < c->nt; ++n) {
             {
                 Timed t(c, AAFWI_K_BORN_STEP);
-                aafwi::launch_born_step(c->stream, c->g, c->K, c->E, u, up, up, du, dup, dup, c->wavelet[n], srcs(c),
+                aafwi::launch_born_step(c->stream, c->gk[AAFWI_K_BORN_STEP], c->K, c->E, u, up, up, du, dup, dup, c->wavelet[n], srcs(c),
                                         maps(c), d_scat, n, c->nt);
             }
             std::swap(u, up);
@@ -483,15 +488,20 @@ extern "C" int aafwi_kernel_timing_read(aafwi_ctx* c, int id, double* mean_ms, i
     });
 }
 
-extern "C" int aafwi_set_tile(aafwi_ctx* c, int32_t rows) {
+extern "C" int aafwi_set_tile(aafwi_ctx* c, int32_t kernel_id, int32_t rows) {
     return guarded([&]() -> int {
         AAFWI_REQUIRE(c && rows >= 0 && rows <= 64, "set_tile: rows per wave must be in [0, 64]");
-        aafwi::WaveGrid& g = c->g;
-        int tz = rows;
-        if (tz == 0) tz = std::max(16, std::min((g.nzp + 7) / 8, 64));
-        g.tz = std::min(tz, g.nzp);
-        g.nzs = (g.nzp + g.tz - 1) / g.tz;
-        g.ntiles = g.ntx * g.nzs * g.S;
+        AAFWI_REQUIRE(kernel_id >= -1 && kernel_id < 4, "set_tile: kernel_id must be -1 or a kernel id");
+        for (int k = 0; k < 4; ++k)
+            if (kernel_id == -1 || kernel_id == k) apply_tile(c->gk[k], rows);
+        return AAFWI_OK;
+    });
+}
+
+extern "C" int aafwi_get_tile(const aafwi_ctx* c, int32_t kernel_id, int32_t* rows) {
+    return guarded([&]() -> int {
+        AAFWI_REQUIRE(c && rows && kernel_id >= 0 && kernel_id < 4, "get_tile: bad argument");
+        *rows = c->gk[kernel_id].tz;
         return AAFWI_OK;
     });
 }

@@ -22,6 +22,9 @@ namespace aafwi {
 namespace {
 
 constexpr int kWaves = 4;
+constexpr int kUFwd = 4;   // rows per register block: forward / recompute
+constexpr int kUAdj = 4;   // adjoint + imaging
+constexpr int kUBorn = 2;  // Born pair (two fields)
 constexpr float kC0 = -205.0f / 72.0f;
 constexpr float kC1 = 8.0f / 5.0f;
 constexpr float kC2 = -1.0f / 5.0f;
@@ -71,67 +74,84 @@ __device__ __forceinline__ Tile decode_tile(const WaveGrid& g) {
     return t;
 }
 
-// Column state of one field for a wave.  At the top of the iteration for row
-// z the lane holds u at rows z-4 .. z+5 (q0..q9); the load of row z+6 is
-// issued during the iteration and lands in q9 two iterations later, so each
-// global load has two row-iterations of latency cover.
-struct Column {
-    float q0, q1, q2, q3, q4, q5, q6, q7, q8, q9;
+// Buffer views.  Every field plane of one shot is addressed through a raw
+// buffer resource (base in SGPRs, 32-bit byte offset per lane).  The hardware
+// range check returns 0 for loads, and drops stores, at offsets at or beyond
+// the plane size; lanes outside the grid carry an offset with bit 31 set, so
+// they read zeros and write nothing.  That is also the zero field outside the
+// padded grid that the stencil assumes (rows above and below the plane).
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+constexpr unsigned kOut = 0x80000000u;
+
+__device__ __forceinline__ Rsrc view(const float* base, long long plane) {
+    return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)(plane * 4), 0x00020000);
+}
+// The b32 builtins move raw 32-bit patterns: reinterpret, never convert.
+__device__ __forceinline__ float bld(Rsrc r, unsigned off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ __forceinline__ void bst(Rsrc r, unsigned off, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
+}
+
+// Register blocking along z.  A lane advances U rows per block.  At the
+// start of the block for rows zb .. zb+U-1 it holds the z-queue q[0..U+8) =
+// u at rows zb-4 .. zb+U+3 and the per-row streams (u^{n-1}, Kp, halo, ...)
+// of those U rows; it then issues every load of the next block (U new queue
+// rows and U rows of each stream) before computing the current one, so a
+// wave keeps U rows of loads in flight behind U rows of arithmetic.  The U
+// rows are staged to LDS together (U x 72 floats per wave) behind one
+// wave-level ordering point.
+template <int U>
+struct Queue {
+    float q[U + 8];
 };
 
-// Branch-free guarded load: the address is clamped to the plane origin when
-// the element is outside the grid, and the value replaced by zero.
-__device__ __forceinline__ float ld_sel(const float* P, int off, bool ok) {
-    const float v = P[ok ? off : 0];
-    return ok ? v : 0.0f;
+template <int U>
+__device__ __forceinline__ void queue_prime(Queue<U>& c, Rsrc R, unsigned o, unsigned rb) {
+#pragma unroll
+    for (int i = 0; i < U + 8; ++i) c.q[i] = bld(R, o + (unsigned)(i - 4) * rb);
 }
 
-// Prime the queue with rows z0-4 .. z0+5 (o0 = z0*pitch + x).
-__device__ __forceinline__ void prime(Column& c, const float* U, const WaveGrid& g, int z0, int o0, bool xin) {
-    const int p = g.pitch;
-    c.q0 = ld_sel(U, o0 - 4 * p, xin && z0 - 4 >= 0);
-    c.q1 = ld_sel(U, o0 - 3 * p, xin && z0 - 3 >= 0);
-    c.q2 = ld_sel(U, o0 - 2 * p, xin && z0 - 2 >= 0);
-    c.q3 = ld_sel(U, o0 - 1 * p, xin && z0 - 1 >= 0);
-    c.q4 = ld_sel(U, o0, xin && z0 < g.nzp);
-    c.q5 = ld_sel(U, o0 + 1 * p, xin && z0 + 1 < g.nzp);
-    c.q6 = ld_sel(U, o0 + 2 * p, xin && z0 + 2 < g.nzp);
-    c.q7 = ld_sel(U, o0 + 3 * p, xin && z0 + 3 < g.nzp);
-    c.q8 = ld_sel(U, o0 + 4 * p, xin && z0 + 4 < g.nzp);
-    c.q9 = ld_sel(U, o0 + 5 * p, xin && z0 + 5 < g.nzp);
+// rows zb+U+4 .. zb+2U+3 (the queue's incoming rows for the next block)
+template <int U>
+__device__ __forceinline__ void queue_fetch(float (&nq)[U], Rsrc R, unsigned o, unsigned rb) {
+#pragma unroll
+    for (int i = 0; i < U; ++i) nq[i] = bld(R, o + (unsigned)(U + 4 + i) * rb);
 }
 
-// Advance one row; `incoming` is u at row z+6.
-__device__ __forceinline__ void shift(Column& c, float incoming) {
-    c.q0 = c.q1; c.q1 = c.q2; c.q2 = c.q3; c.q3 = c.q4; c.q4 = c.q5;
-    c.q5 = c.q6; c.q6 = c.q7; c.q7 = c.q8; c.q8 = c.q9; c.q9 = incoming;
+template <int U>
+__device__ __forceinline__ void queue_advance(Queue<U>& c, const float (&nq)[U]) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) c.q[i] = c.q[i + U];
+#pragma unroll
+    for (int i = 0; i < U; ++i) c.q[8 + i] = nq[i];
 }
 
-// Per-row stream (one value per row of the strip) with two rows of prefetch.
-struct Pipe {
-    float v0, v1;  // rows z, z+1
-};
-
-__device__ __forceinline__ void pipe_init(Pipe& p, const float* P, const WaveGrid& g, int z0, int z1, int o0,
-                                          bool ok) {
-    p.v0 = ld_sel(P, o0, ok && z0 < z1);
-    p.v1 = ld_sel(P, o0 + g.pitch, ok && z0 + 1 < z1);
+// U rows of a per-row stream starting at byte offset o.
+template <int U>
+__device__ __forceinline__ void rows_fetch(float (&v)[U], Rsrc R, unsigned o, unsigned rb) {
+#pragma unroll
+    for (int i = 0; i < U; ++i) v[i] = bld(R, o + (unsigned)i * rb);
 }
 
-__device__ __forceinline__ void pipe_shift(Pipe& p, float incoming) {
-    p.v0 = p.v1;
-    p.v1 = incoming;
+template <int U>
+__device__ __forceinline__ void rows_copy(float (&dst)[U], const float (&src)[U]) {
+#pragma unroll
+    for (int i = 0; i < U; ++i) dst[i] = src[i];
 }
 
-// Unscaled 8th-order Laplacian at the lane's node: z-pairs from the queue,
-// x-pairs from the LDS row (centre of lane l at row[4 + l]).
-__device__ __forceinline__ float lap8(const Column& c, const float* row, int lane) {
+// Unscaled 8th-order Laplacian of row j of the block: z-pairs from the
+// queue, x-pairs from LDS row j (centre of lane l at row[4 + l]).
+template <int U>
+__device__ __forceinline__ float lap8(const Queue<U>& c, int j, const float* row, int lane) {
     const float* r = row + 4 + lane;
-    const float s1 = (c.q3 + c.q5) + (r[-1] + r[1]);
-    const float s2 = (c.q2 + c.q6) + (r[-2] + r[2]);
-    const float s3 = (c.q1 + c.q7) + (r[-3] + r[3]);
-    const float s4 = (c.q0 + c.q8) + (r[-4] + r[4]);
-    float acc = (2.0f * kC0) * c.q4;
+    const float* q = c.q + j + 4;
+    const float s1 = (q[-1] + q[1]) + (r[-1] + r[1]);
+    const float s2 = (q[-2] + q[2]) + (r[-2] + r[2]);
+    const float s3 = (q[-3] + q[3]) + (r[-3] + r[3]);
+    const float s4 = (q[-4] + q[4]) + (r[-4] + r[4]);
+    float acc = (2.0f * kC0) * q[0];
     acc = fmaf(kC1, s1, acc);
     acc = fmaf(kC2, s2, acc);
     acc = fmaf(kC3, s3, acc);
@@ -139,27 +159,58 @@ __device__ __forceinline__ float lap8(const Column& c, const float* row, int lan
     return acc;
 }
 
-// Halo column of lane l < 8 (lanes 0-3 left, 4-7 right) and its LDS slot.
-struct Halo {
-    int hx, slot;
-    bool ok;
+// Per-lane addressing of a wave tile: node offset (bytes, row z0) and halo
+// offset for lanes 0-7 (lanes 0-3 left halo, 4-7 right halo), with out-of-grid
+// lanes pushed out of the buffer.
+struct Lanes {
+    int x;
+    unsigned o, oh, rb;
+    int hslot;
+    bool xin, interior_x;
+    float sx;
 };
 
-__device__ __forceinline__ Halo halo_cfg(int lane, int x0, int nxp) {
-    Halo h;
-    h.hx = (lane < 4) ? (x0 - 4 + lane) : (x0 + 60 + lane);
-    h.ok = (lane < 8) && h.hx >= 0 && h.hx < nxp;
-    h.slot = (lane < 4) ? lane : (64 + lane);
-    return h;
+__device__ __forceinline__ Lanes lanes(const WaveGrid& g, const Tile& t) {
+    Lanes L;
+    L.x = t.x0 + t.lane;
+    L.xin = L.x < g.nxp;
+    L.rb = (unsigned)g.pitch * 4u;
+    L.o = L.xin ? (unsigned)(t.z0 * g.pitch + L.x) * 4u : kOut;
+    const int hx = (t.lane < 4) ? (t.x0 - 4 + t.lane) : (t.x0 + 60 + t.lane);
+    const bool hok = (t.lane < 8) && hx >= 0 && hx < g.nxp;
+    L.oh = hok ? (unsigned)(t.z0 * g.pitch + hx) * 4u : kOut;
+    L.hslot = (t.lane < 4) ? t.lane : (64 + t.lane);
+    // the whole 64-column tile lies inside the undamped interior columns
+    L.interior_x = (t.x0 >= g.nb) && (t.x0 + 64 <= g.nb + g.nx);
+    L.sx = sponge_st(L.x, g.nx, g.nb, g.inv_nb, g.scoef);
+    return L;
 }
 
-// Stage row z of a field into LDS: centre values from the queue, halo value
-// hv (prefetched) from lanes 0-7.
-__device__ __forceinline__ void stage(float* row, const Column& c, float hv, int lane, const Halo& h) {
+// Stage the U rows of a block into LDS: centre values from the queue, halo
+// values (prefetched) from lanes 0-7.
+template <int U>
+__device__ __forceinline__ void stage(float* rows, const Queue<U>& c, const float (&hv)[U], int lane, int hslot) {
     wave_sync();
-    row[4 + lane] = c.q4;
-    if (lane < 8) row[h.slot] = hv;
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+        rows[j * 72 + 4 + lane] = c.q[j + 4];
+        if (lane < 8) rows[j * 72 + hslot] = hv[j];
+    }
     wave_sync();
+}
+
+// Sponge factors (A, B) of row z for this lane; exactly (1, 1) when the whole
+// tile row is in the undamped interior (a wave-uniform branch).
+__device__ __forceinline__ void sponge_ab(const WaveGrid& g, const Lanes& L, int z, float& A, float& B) {
+    const bool interior = L.interior_x && z >= g.nb && z < g.nb + g.nz;
+    if (interior) {
+        A = 1.0f;
+        B = 1.0f;
+    } else {
+        const float st = L.sx + sponge_st(z, g.nz, g.nb, g.inv_nb, g.scoef);
+        A = __builtin_amdgcn_rcpf(1.0f + st);
+        B = fmaf(2.0f, A, -1.0f);
+    }
 }
 
 // Receiver-row slots of the strip's rows, one per lane (strips are at most
@@ -174,7 +225,7 @@ __device__ __forceinline__ int strip_rowmap(const RecMaps& rm, const WaveGrid& g
 // ---------------------------------------------------------------------------
 // forward step (sampling, optional checkpoint copy) and recompute step (q out)
 // ---------------------------------------------------------------------------
-template <bool kRecompute>
+template <int U, bool kRecompute>
 __global__ __launch_bounds__(256) void k_fwd_step(WaveGrid g, const float* __restrict__ K,
                                                   const float* __restrict__ u, const float* uprev,
                                                   float* out, float w, SrcNodes src, RecMaps rm,
@@ -182,146 +233,146 @@ __global__ __launch_bounds__(256) void k_fwd_step(WaveGrid g, const float* __res
                                                   float* __restrict__ ck_u,
                                                   float* __restrict__ ck_um,
                                                   float* __restrict__ q) {
-    __shared__ float lds[kWaves][2][72];
+    __shared__ float lds[kWaves][U * 72];
     const Tile t = decode_tile(g);
     if (!t.live) return;
     const int lane = t.lane;
-    float* rowbuf = &lds[threadIdx.x >> 6][0][0];
-    const int x = t.x0 + lane;
-    const bool xin = x < g.nxp;
+    float* rows = &lds[threadIdx.x >> 6][0];
     const long long off0 = (long long)t.s * g.plane;
-    const float* U = u + off0;
-    const float* UP = uprev + off0;
-    float* O = out + off0;
-    float* CU = ck_u ? ck_u + off0 : nullptr;
-    float* CUM = ck_um ? ck_um + off0 : nullptr;
-    float* Q = kRecompute ? q + off0 : nullptr;
-    const Halo hc = halo_cfg(lane, t.x0, g.nxp);
-    const float sx = sponge_st(x, g.nx, g.nb, g.inv_nb, g.scoef);
+    const Rsrc UR = view(u + off0, g.plane);
+    const Rsrc UP = view(uprev + off0, g.plane);
+    const Rsrc O = view(out + off0, g.plane);
+    const Rsrc KR = view(K, g.plane);
+    const bool ck = ck_u != nullptr;
+    const Rsrc CU = view(ck ? ck_u + off0 : u, g.plane);
+    const Rsrc CUM = view(ck ? ck_um + off0 : u, g.plane);
+    const Rsrc QR = view(kRecompute ? q + off0 : u, g.plane);
+    const Lanes L = lanes(g, t);
     const int2 sn = src.node[t.s];
     const int my_rm = kRecompute ? -1 : strip_rowmap(rm, g, t);
-    const int p = g.pitch;
+    const unsigned rb = L.rb;
 
-    Column c;
-    int o = t.z0 * p + x;             // this lane's node
-    int oh = t.z0 * p + hc.hx;        // this lane's halo node (lanes 0-7)
-    prime(c, U, g, t.z0, o, xin);
-    Pipe pv, kv, hv;
-    pipe_init(pv, UP, g, t.z0, t.z1, o, xin);
-    pipe_init(kv, K, g, t.z0, t.z1, o, xin);
-    pipe_init(hv, U, g, t.z0, t.z1, oh, hc.ok);
-    for (int z = t.z0; z < t.z1; ++z, o += p, oh += p) {
-        const float nq = ld_sel(U, o + 6 * p, xin && z + 6 < g.nzp);
-        const bool more = z + 2 < t.z1;
-        const float npv = ld_sel(UP, o + 2 * p, xin && more);
-        const float nkv = ld_sel(K, o + 2 * p, xin && more);
-        const float nhv = ld_sel(U, oh + 2 * p, hc.ok && more);
-        float* row = rowbuf + (z & 1) * 72;
-        stage(row, c, hv.v0, lane, hc);
-        float acc = lap8(c, row, lane);
-        if (z == sn.x && x == sn.y) acc += w;
-        const float st = sx + sponge_st(z, g.nz, g.nb, g.inv_nb, g.scoef);
-        const float A = __builtin_amdgcn_rcpf(1.0f + st);
-        const float B = fmaf(2.0f, A, -1.0f);
-        const float qh = kv.v0 * acc;
-        const float un = fmaf(2.0f * A, c.q4, fmaf(-B, pv.v0, qh));
-        if (xin) {
-            if (CU) {
-                CU[o] = c.q4;
-                CUM[o] = pv.v0;
+    unsigned o = L.o, oh = L.oh;
+    Queue<U> c;
+    queue_prime(c, UR, o, rb);
+    float pv[U], kv[U], hv[U];
+    rows_fetch(pv, UP, o, rb);
+    rows_fetch(kv, KR, o, rb);
+    rows_fetch(hv, UR, oh, rb);
+    for (int zb = t.z0; zb < t.z1; zb += U, o += U * rb, oh += U * rb) {
+        float nq[U], npv[U], nkv[U], nhv[U];
+        queue_fetch(nq, UR, o, rb);
+        rows_fetch(npv, UP, o + U * rb, rb);
+        rows_fetch(nkv, KR, o + U * rb, rb);
+        rows_fetch(nhv, UR, oh + U * rb, rb);
+        stage(rows, c, hv, lane, L.hslot);
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const int z = zb + j;
+            if (z >= t.z1) break;
+            const unsigned oz = o + (unsigned)j * rb;
+            float acc = lap8(c, j, rows + j * 72, lane);
+            if (z == sn.x && L.x == sn.y) acc += w;
+            float A, B;
+            sponge_ab(g, L, z, A, B);
+            const float qh = kv[j] * acc;
+            const float un = fmaf(2.0f * A, c.q[j + 4], fmaf(-B, pv[j], qh));
+            if (ck) {
+                bst(CU, oz, c.q[j + 4]);
+                bst(CUM, oz, pv[j]);
             }
-            O[o] = un;
-            if (kRecompute) Q[o] = qh;
-        }
-        if (!kRecompute) {
-            const int slot = __builtin_amdgcn_readlane(my_rm, z - t.z0);
-            if (slot >= 0 && xin) {
-                int ri = rm.xmap[((long long)t.s * rm.nrr + slot) * p + x];
-                while (ri >= 0) {
-                    d[((long long)t.s * nt + n) * rm.R + ri] = un;
-                    ri = rm.next[t.s * rm.R + ri];
+            bst(O, oz, un);
+            if (kRecompute) bst(QR, oz, qh);
+            if (!kRecompute) {
+                const int slot = __builtin_amdgcn_readlane(my_rm, z - t.z0);
+                if (slot >= 0 && L.xin) {
+                    int ri = rm.xmap[((long long)t.s * rm.nrr + slot) * g.pitch + L.x];
+                    while (ri >= 0) {
+                        d[((long long)t.s * nt + n) * rm.R + ri] = un;
+                        ri = rm.next[t.s * rm.R + ri];
+                    }
                 }
             }
         }
-        shift(c, nq);
-        pipe_shift(pv, npv);
-        pipe_shift(kv, nkv);
-        pipe_shift(hv, nhv);
+        queue_advance(c, nq);
+        rows_copy(pv, npv);
+        rows_copy(kv, nkv);
+        rows_copy(hv, nhv);
     }
 }
 
 // ---------------------------------------------------------------------------
 // adjoint step with receiver injection and zero-lag imaging g += lam^n * q^n
 // ---------------------------------------------------------------------------
+template <int U>
 __global__ __launch_bounds__(256) void k_adj_step(WaveGrid g, const float* __restrict__ K,
                                                   const float* __restrict__ l, const float* lprev,
                                                   float* out, RecMaps rm,
                                                   const float* __restrict__ r, int n, int nt,
                                                   float h2, const float* __restrict__ q,
                                                   float* __restrict__ gimg) {
-    __shared__ float lds[kWaves][2][72];
+    __shared__ float lds[kWaves][U * 72];
     const Tile t = decode_tile(g);
     if (!t.live) return;
     const int lane = t.lane;
-    float* rowbuf = &lds[threadIdx.x >> 6][0][0];
-    const int x = t.x0 + lane;
-    const bool xin = x < g.nxp;
+    float* rows = &lds[threadIdx.x >> 6][0];
     const long long off0 = (long long)t.s * g.plane;
-    const float* U = l + off0;
-    const float* UP = lprev + off0;
-    float* O = out + off0;
-    const float* Q = q + off0;
-    float* GI = gimg + off0;
-    const Halo hc = halo_cfg(lane, t.x0, g.nxp);
-    const float sx = sponge_st(x, g.nx, g.nb, g.inv_nb, g.scoef);
+    const Rsrc UR = view(l + off0, g.plane);
+    const Rsrc UP = view(lprev + off0, g.plane);
+    const Rsrc O = view(out + off0, g.plane);
+    const Rsrc KR = view(K, g.plane);
+    const Rsrc QR = view(q + off0, g.plane);
+    const Rsrc GI = view(gimg + off0, g.plane);
+    const Lanes L = lanes(g, t);
     const int my_rm = strip_rowmap(rm, g, t);
-    const int p = g.pitch;
+    const unsigned rb = L.rb;
 
-    Column c;
-    int o = t.z0 * p + x;
-    int oh = t.z0 * p + hc.hx;
-    prime(c, U, g, t.z0, o, xin);
-    Pipe pv, kv, hv, qv, gv;
-    pipe_init(pv, UP, g, t.z0, t.z1, o, xin);
-    pipe_init(kv, K, g, t.z0, t.z1, o, xin);
-    pipe_init(hv, U, g, t.z0, t.z1, oh, hc.ok);
-    pipe_init(qv, Q, g, t.z0, t.z1, o, xin);
-    pipe_init(gv, GI, g, t.z0, t.z1, o, xin);
-    for (int z = t.z0; z < t.z1; ++z, o += p, oh += p) {
-        const float nq = ld_sel(U, o + 6 * p, xin && z + 6 < g.nzp);
-        const bool more = xin && (z + 2 < t.z1);
-        const float npv = ld_sel(UP, o + 2 * p, more);
-        const float nkv = ld_sel(K, o + 2 * p, more);
-        const float nhv = ld_sel(U, oh + 2 * p, hc.ok && z + 2 < t.z1);
-        const float nqv = ld_sel(Q, o + 2 * p, more);
-        const float ngv = ld_sel(GI, o + 2 * p, more);
-        float* row = rowbuf + (z & 1) * 72;
-        stage(row, c, hv.v0, lane, hc);
-        float acc = lap8(c, row, lane);
-        const int slot = __builtin_amdgcn_readlane(my_rm, z - t.z0);
-        if (slot >= 0 && xin) {
-            int ri = rm.xmap[((long long)t.s * rm.nrr + slot) * p + x];
-            float rs = 0.0f;
-            while (ri >= 0) {
-                rs += r[((long long)t.s * nt + n) * rm.R + ri];
-                ri = rm.next[t.s * rm.R + ri];
+    unsigned o = L.o, oh = L.oh;
+    Queue<U> c;
+    queue_prime(c, UR, o, rb);
+    float pv[U], kv[U], hv[U], qv[U], gv[U];
+    rows_fetch(pv, UP, o, rb);
+    rows_fetch(kv, KR, o, rb);
+    rows_fetch(hv, UR, oh, rb);
+    rows_fetch(qv, QR, o, rb);
+    rows_fetch(gv, GI, o, rb);
+    for (int zb = t.z0; zb < t.z1; zb += U, o += U * rb, oh += U * rb) {
+        float nq[U], npv[U], nkv[U], nhv[U], nqv[U], ngv[U];
+        queue_fetch(nq, UR, o, rb);
+        rows_fetch(npv, UP, o + U * rb, rb);
+        rows_fetch(nkv, KR, o + U * rb, rb);
+        rows_fetch(nhv, UR, oh + U * rb, rb);
+        rows_fetch(nqv, QR, o + U * rb, rb);
+        rows_fetch(ngv, GI, o + U * rb, rb);
+        stage(rows, c, hv, lane, L.hslot);
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const int z = zb + j;
+            if (z >= t.z1) break;
+            const unsigned oz = o + (unsigned)j * rb;
+            float acc = lap8(c, j, rows + j * 72, lane);
+            const int slot = __builtin_amdgcn_readlane(my_rm, z - t.z0);
+            if (slot >= 0 && L.xin) {
+                int ri = rm.xmap[((long long)t.s * rm.nrr + slot) * g.pitch + L.x];
+                float rs = 0.0f;
+                while (ri >= 0) {
+                    rs += r[((long long)t.s * nt + n) * rm.R + ri];
+                    ri = rm.next[t.s * rm.R + ri];
+                }
+                acc = fmaf(-h2, rs, acc);
             }
-            acc = fmaf(-h2, rs, acc);
+            float A, B;
+            sponge_ab(g, L, z, A, B);
+            const float ln = fmaf(2.0f * A, c.q[j + 4], fmaf(-B, pv[j], kv[j] * acc));
+            bst(O, oz, ln);
+            bst(GI, oz, fmaf(ln, qv[j], gv[j]));
         }
-        const float st = sx + sponge_st(z, g.nz, g.nb, g.inv_nb, g.scoef);
-        const float A = __builtin_amdgcn_rcpf(1.0f + st);
-        const float B = fmaf(2.0f, A, -1.0f);
-        const float ln = fmaf(2.0f * A, c.q4, fmaf(-B, pv.v0, kv.v0 * acc));
-        if (xin) {
-            O[o] = ln;
-            GI[o] = fmaf(ln, qv.v0, gv.v0);
-        }
-        shift(c, nq);
-        pipe_shift(pv, npv);
-        pipe_shift(kv, nkv);
-        pipe_shift(hv, nhv);
-        pipe_shift(qv, nqv);
-        pipe_shift(gv, ngv);
+        queue_advance(c, nq);
+        rows_copy(pv, npv);
+        rows_copy(kv, nkv);
+        rows_copy(hv, nhv);
+        rows_copy(qv, nqv);
+        rows_copy(gv, ngv);
     }
 }
 
@@ -329,6 +380,7 @@ __global__ __launch_bounds__(256) void k_adj_step(WaveGrid g, const float* __res
 // Born pair step: background u0 and scattered du with source -E * qhat0,
 // E = dm_pad / m0_pad (eq. Born: -m_r d^2u0/dt^2), sampling du.
 // ---------------------------------------------------------------------------
+template <int U>
 __global__ __launch_bounds__(256) void k_born_step(WaveGrid g, const float* __restrict__ K,
                                                    const float* __restrict__ E,
                                                    const float* __restrict__ u,
@@ -337,83 +389,80 @@ __global__ __launch_bounds__(256) void k_born_step(WaveGrid g, const float* __re
                                                    const float* duprev, float* duout, float w,
                                                    SrcNodes src, RecMaps rm,
                                                    float* __restrict__ d, int n, int nt) {
-    __shared__ float lds[kWaves][2][2][72];
+    __shared__ float lds[kWaves][2][U * 72];
     const Tile t = decode_tile(g);
     if (!t.live) return;
     const int lane = t.lane;
     const int wv = threadIdx.x >> 6;
-    const int x = t.x0 + lane;
-    const bool xin = x < g.nxp;
     const long long off0 = (long long)t.s * g.plane;
-    const float* U = u + off0;
-    const float* UP = uprev + off0;
-    float* UO = uout + off0;
-    const float* D = du + off0;
-    const float* DP = duprev + off0;
-    float* DO = duout + off0;
-    const Halo hc = halo_cfg(lane, t.x0, g.nxp);
-    const float sx = sponge_st(x, g.nx, g.nb, g.inv_nb, g.scoef);
+    const Rsrc UR = view(u + off0, g.plane);
+    const Rsrc UP = view(uprev + off0, g.plane);
+    const Rsrc UO = view(uout + off0, g.plane);
+    const Rsrc DR = view(du + off0, g.plane);
+    const Rsrc DP = view(duprev + off0, g.plane);
+    const Rsrc DO = view(duout + off0, g.plane);
+    const Rsrc KR = view(K, g.plane);
+    const Rsrc ER = view(E, g.plane);
+    const Lanes L = lanes(g, t);
     const int2 sn = src.node[t.s];
     const int my_rm = strip_rowmap(rm, g, t);
-    const int p = g.pitch;
+    const unsigned rb = L.rb;
 
-    Column c, e;
-    int o = t.z0 * p + x;
-    int oh = t.z0 * p + hc.hx;
-    prime(c, U, g, t.z0, o, xin);
-    prime(e, D, g, t.z0, o, xin);
-    Pipe pv, dpv, kv, ev, hv, dhv;
-    pipe_init(pv, UP, g, t.z0, t.z1, o, xin);
-    pipe_init(dpv, DP, g, t.z0, t.z1, o, xin);
-    pipe_init(kv, K, g, t.z0, t.z1, o, xin);
-    pipe_init(ev, E, g, t.z0, t.z1, o, xin);
-    pipe_init(hv, U, g, t.z0, t.z1, oh, hc.ok);
-    pipe_init(dhv, D, g, t.z0, t.z1, oh, hc.ok);
-    for (int z = t.z0; z < t.z1; ++z, o += p, oh += p) {
-        const bool ahead = xin && z + 6 < g.nzp;
-        const float nq = ld_sel(U, o + 6 * p, ahead);
-        const float ne = ld_sel(D, o + 6 * p, ahead);
-        const bool more = xin && (z + 2 < t.z1);
-        const bool hmore = hc.ok && (z + 2 < t.z1);
-        const float npv = ld_sel(UP, o + 2 * p, more);
-        const float ndpv = ld_sel(DP, o + 2 * p, more);
-        const float nkv = ld_sel(K, o + 2 * p, more);
-        const float nev = ld_sel(E, o + 2 * p, more);
-        const float nhv = ld_sel(U, oh + 2 * p, hmore);
-        const float ndhv = ld_sel(D, oh + 2 * p, hmore);
-        float* row0 = &lds[wv][z & 1][0][0];
-        float* row1 = &lds[wv][z & 1][1][0];
-        stage(row0, c, hv.v0, lane, hc);
-        stage(row1, e, dhv.v0, lane, hc);
-        float acc0 = lap8(c, row0, lane);
-        const float acc1 = lap8(e, row1, lane);
-        if (z == sn.x && x == sn.y) acc0 += w;
-        const float st = sx + sponge_st(z, g.nz, g.nb, g.inv_nb, g.scoef);
-        const float A = __builtin_amdgcn_rcpf(1.0f + st);
-        const float B = fmaf(2.0f, A, -1.0f);
-        const float qh0 = kv.v0 * acc0;
-        const float un = fmaf(2.0f * A, c.q4, fmaf(-B, pv.v0, qh0));
-        const float dn = fmaf(2.0f * A, e.q4, fmaf(-B, dpv.v0, fmaf(kv.v0, acc1, -ev.v0 * qh0)));
-        if (xin) {
-            UO[o] = un;
-            DO[o] = dn;
-        }
-        const int slot = __builtin_amdgcn_readlane(my_rm, z - t.z0);
-        if (slot >= 0 && xin) {
-            int ri = rm.xmap[((long long)t.s * rm.nrr + slot) * p + x];
-            while (ri >= 0) {
-                d[((long long)t.s * nt + n) * rm.R + ri] = dn;
-                ri = rm.next[t.s * rm.R + ri];
+    unsigned o = L.o, oh = L.oh;
+    Queue<U> c, e;
+    queue_prime(c, UR, o, rb);
+    queue_prime(e, DR, o, rb);
+    float pv[U], dpv[U], kv[U], ev[U], hv[U], dhv[U];
+    rows_fetch(pv, UP, o, rb);
+    rows_fetch(dpv, DP, o, rb);
+    rows_fetch(kv, KR, o, rb);
+    rows_fetch(ev, ER, o, rb);
+    rows_fetch(hv, UR, oh, rb);
+    rows_fetch(dhv, DR, oh, rb);
+    for (int zb = t.z0; zb < t.z1; zb += U, o += U * rb, oh += U * rb) {
+        float nq[U], ne[U], npv[U], ndpv[U], nkv[U], nev[U], nhv[U], ndhv[U];
+        queue_fetch(nq, UR, o, rb);
+        queue_fetch(ne, DR, o, rb);
+        rows_fetch(npv, UP, o + U * rb, rb);
+        rows_fetch(ndpv, DP, o + U * rb, rb);
+        rows_fetch(nkv, KR, o + U * rb, rb);
+        rows_fetch(nev, ER, o + U * rb, rb);
+        rows_fetch(nhv, UR, oh + U * rb, rb);
+        rows_fetch(ndhv, DR, oh + U * rb, rb);
+        stage(&lds[wv][0][0], c, hv, lane, L.hslot);
+        stage(&lds[wv][1][0], e, dhv, lane, L.hslot);
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const int z = zb + j;
+            if (z >= t.z1) break;
+            const unsigned oz = o + (unsigned)j * rb;
+            float acc0 = lap8(c, j, &lds[wv][0][j * 72], lane);
+            const float acc1 = lap8(e, j, &lds[wv][1][j * 72], lane);
+            if (z == sn.x && L.x == sn.y) acc0 += w;
+            float A, B;
+            sponge_ab(g, L, z, A, B);
+            const float qh0 = kv[j] * acc0;
+            const float un = fmaf(2.0f * A, c.q[j + 4], fmaf(-B, pv[j], qh0));
+            const float dn = fmaf(2.0f * A, e.q[j + 4], fmaf(-B, dpv[j], fmaf(kv[j], acc1, -ev[j] * qh0)));
+            bst(UO, oz, un);
+            bst(DO, oz, dn);
+            const int slot = __builtin_amdgcn_readlane(my_rm, z - t.z0);
+            if (slot >= 0 && L.xin) {
+                int ri = rm.xmap[((long long)t.s * rm.nrr + slot) * g.pitch + L.x];
+                while (ri >= 0) {
+                    d[((long long)t.s * nt + n) * rm.R + ri] = dn;
+                    ri = rm.next[t.s * rm.R + ri];
+                }
             }
         }
-        shift(c, nq);
-        shift(e, ne);
-        pipe_shift(pv, npv);
-        pipe_shift(dpv, ndpv);
-        pipe_shift(kv, nkv);
-        pipe_shift(ev, nev);
-        pipe_shift(hv, nhv);
-        pipe_shift(dhv, ndhv);
+        queue_advance(c, nq);
+        queue_advance(e, ne);
+        rows_copy(pv, npv);
+        rows_copy(dpv, ndpv);
+        rows_copy(kv, nkv);
+        rows_copy(ev, nev);
+        rows_copy(hv, nhv);
+        rows_copy(dhv, ndhv);
     }
 }
 
@@ -548,7 +597,7 @@ void launch_zero(hipStream_t st, float* p, long long n) {
 void launch_fwd_step(hipStream_t st, const WaveGrid& g, const float* K, const float* u,
                      const float* uprev, float* out, float w, SrcNodes src, RecMaps rm, float* d,
                      int n, int nt, float* ck_u, float* ck_um) {
-    hipLaunchKernelGGL(k_fwd_step<false>, dim3(step_blocks(g)), dim3(64 * kWaves), 0, st, g, K, u,
+    hipLaunchKernelGGL((k_fwd_step<kUFwd, false>), dim3(step_blocks(g)), dim3(64 * kWaves), 0, st, g, K, u,
                        uprev, out, w, src, rm, d, n, nt, ck_u, ck_um, (float*)nullptr);
     AAFWI_HIP(hipGetLastError());
 }
@@ -556,7 +605,7 @@ void launch_fwd_step(hipStream_t st, const WaveGrid& g, const float* K, const fl
 void launch_rec_step(hipStream_t st, const WaveGrid& g, const float* K, const float* u,
                      const float* uprev, float* out, float w, SrcNodes src, float* q) {
     RecMaps none{nullptr, nullptr, nullptr, 0, 0};
-    hipLaunchKernelGGL(k_fwd_step<true>, dim3(step_blocks(g)), dim3(64 * kWaves), 0, st, g, K, u,
+    hipLaunchKernelGGL((k_fwd_step<kUFwd, true>), dim3(step_blocks(g)), dim3(64 * kWaves), 0, st, g, K, u,
                        uprev, out, w, src, none, (float*)nullptr, 0, 0, (float*)nullptr,
                        (float*)nullptr, q);
     AAFWI_HIP(hipGetLastError());
@@ -565,7 +614,7 @@ void launch_rec_step(hipStream_t st, const WaveGrid& g, const float* K, const fl
 void launch_adj_step(hipStream_t st, const WaveGrid& g, const float* K, const float* l,
                      const float* lprev, float* out, RecMaps rm, const float* r, int n, int nt,
                      float h2, const float* q, float* gimg) {
-    hipLaunchKernelGGL(k_adj_step, dim3(step_blocks(g)), dim3(64 * kWaves), 0, st, g, K, l, lprev,
+    hipLaunchKernelGGL(k_adj_step<kUAdj>, dim3(step_blocks(g)), dim3(64 * kWaves), 0, st, g, K, l, lprev,
                        out, rm, r, n, nt, h2, q, gimg);
     AAFWI_HIP(hipGetLastError());
 }
@@ -574,7 +623,7 @@ void launch_born_step(hipStream_t st, const WaveGrid& g, const float* K, const f
                       const float* u, const float* uprev, float* uout, const float* du,
                       const float* duprev, float* duout, float w, SrcNodes src, RecMaps rm,
                       float* d, int n, int nt) {
-    hipLaunchKernelGGL(k_born_step, dim3(step_blocks(g)), dim3(64 * kWaves), 0, st, g, K, E, u,
+    hipLaunchKernelGGL(k_born_step<kUBorn>, dim3(step_blocks(g)), dim3(64 * kWaves), 0, st, g, K, E, u,
                        uprev, uout, du, duprev, duout, w, src, rm, d, n, nt);
     AAFWI_HIP(hipGetLastError());
 }

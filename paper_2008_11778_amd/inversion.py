@@ -1,0 +1,220 @@
+"""Algorithm 2 (l2-based Anderson acceleration for gradient descent) on the
+HIP path, plus the problem wrappers it drives.
+
+Every vector operation and every wave simulation runs in libaafwi.so; the
+host only sequences the calls and reads the scalar misfits that the line
+search compares (the one device-to-host synchronisation per trial).
+
+Readings of the paper used here (Section "Method", Algorithm 2):
+  * G(p) = p - eta dJ/dp with a fixed eta (eq. GD); f_k = -eta g_k.
+  * p_1 = G(p_0); for k >= 1: pbar = G(p_k) (Step 1), gamma from the
+    least-squares problem over the last M_k = min(M, k) differences (Step 2),
+    ptilde from eq. AA2_update (Step 3), then the backtracking search over
+    lambda in {1, 1/2, 1/4, 1/8} with the sufficient-decrease test
+    J(p) <= J(p_k) + c1 <g_k, p - p_k> (Step 4), falling back to lambda = 0,
+    and p_{k+1} = lambda ptilde + (1 - lambda) pbar (Step 5).
+  * The accepted trial's forward run keeps its wavefield checkpoints, so the
+    next gradient needs only the backward pass (no second forward).
+"""
+from __future__ import annotations
+
+import dataclasses
+import json
+import time
+
+import torch
+
+from ._lib import AA, Context, Reducer, axpy, blend
+
+LAMBDAS = (1.0, 0.5, 0.25, 0.125)
+ARMIJO_C1 = 1e-4
+
+
+class FWIProblem:
+    """J(m) = 1/2 ||R F(m) - d_obs||^2 and its gradient on one Context."""
+
+    def __init__(self, ctx: Context, d_obs: torch.Tensor):
+        self.ctx = ctx
+        self.d_obs = d_obs
+        self.d = ctx._new(ctx.data_shape)
+        self.r = ctx._new(ctx.data_shape)
+        self.J = ctx._new((1,), torch.float64)
+        self.kept = None  # the model whose forward run (and residual) is kept
+        self.n_fwd = 0
+        self.n_adj = 0
+
+    def misfit_keep(self, m: torch.Tensor) -> float:
+        """Forward with checkpoints kept (for the tensor object m); returns J
+        (host sync)."""
+        self.ctx.forward_model(m, self.d, keep_ckpt=True)
+        self.ctx.residual_misfit(self.d, self.d_obs, self.r, self.J)
+        self.kept = m
+        self.n_fwd += 1
+        return float(self.J.item())
+
+    def gradient(self, m: torch.Tensor, grad: torch.Tensor):
+        """(J, grad) at m, reusing the kept forward run when it was at m."""
+        if self.kept is not m:
+            self.misfit_keep(m)
+        J = float(self.J.item())
+        self.ctx.adjoint_from_residual(self.r, grad)
+        self.n_adj += 1
+        return J
+
+
+class LSRTMProblem:
+    """J(x) = 1/2 ||L x - d_r||^2 at a fixed background m0 (eq. LSRTM)."""
+
+    def __init__(self, ctx: Context, m0: torch.Tensor, d_r: torch.Tensor):
+        self.ctx, self.m0, self.d_r = ctx, m0, d_r
+        self.d = ctx._new(ctx.data_shape)
+        self.r = ctx._new(ctx.data_shape)
+        self.J = ctx._new((1,), torch.float64)
+        self.kept = None
+        self.n_fwd = 0
+        self.n_adj = 0
+
+    def misfit_keep(self, x: torch.Tensor) -> float:
+        self.ctx.born(self.m0, x, self.d)
+        self.ctx.residual_misfit(self.d, self.d_r, self.r, self.J)
+        self.kept = x
+        self.n_fwd += 1
+        return float(self.J.item())
+
+    def gradient(self, x: torch.Tensor, grad: torch.Tensor):
+        if self.kept is not x:
+            self.misfit_keep(x)
+        J = float(self.J.item())
+        self.ctx.born_adjoint(self.m0, self.r, grad)
+        self.n_adj += 1
+        return J
+
+    def normal_op(self, x: torch.Tensor, out: torch.Tensor):
+        """out = L^T L x (one Born and one Born adjoint)."""
+        self.ctx.born(self.m0, x, self.d)
+        self.ctx.born_adjoint(self.m0, self.d, out)
+        self.n_fwd += 1
+        self.n_adj += 1
+        return out
+
+
+@dataclasses.dataclass
+class IterLog:
+    k: int
+    J: float
+    lam: float
+    mk: int
+    n_grad: int
+    n_fwd: int
+    wall: float
+
+
+class AADescent:
+    """Algorithm 2 as a stepper: ``first()`` evaluates g_0 and sets p_1 = G(p_0);
+    each ``iterate()`` performs one iteration k >= 1.
+
+    M = 0 is steepest descent with the fixed step (the Picard iteration of G).
+    The problem sees flat tensors; the accepted trial buffer becomes the new
+    iterate itself, so the problem recognises (by object identity) that its
+    kept forward run is at that iterate.
+    """
+
+    def __init__(self, problem, p0: torch.Tensor, eta: float | None, M: int, cond_max: float = 1e5,
+                 lambdas=LAMBDAS, c1: float = ARMIJO_C1, linesearch: bool = True,
+                 eta_frac: float = 0.02):
+        self.problem, self.M, self.eta = problem, M, eta
+        self.lambdas, self.c1, self.linesearch, self.eta_frac = lambdas, c1, linesearch, eta_frac
+        self.shape = p0.shape
+        self.aa = AA(p0.numel(), max(M, 1), cond_max) if M > 0 else None
+        self.red = Reducer()
+        self.p = p0.detach().clone().reshape(-1)
+        self.g = torch.empty_like(self.p)
+        self.pbar = torch.empty_like(self.p)
+        self.ptilde = torch.empty_like(self.p)
+        self.trials = [torch.empty_like(self.p) for _ in range(2)]
+        self.k = 0
+        self.t0 = time.perf_counter()
+
+    def _G(self):
+        if self.aa is not None:
+            self.aa.step(self.p, self.g, self.eta, self.pbar, self.ptilde)
+        else:
+            _gd_step(self.p, self.g, self.eta, self.pbar)
+            self.ptilde.copy_(self.pbar)
+
+    def first(self) -> IterLog:
+        J = self.problem.gradient(self.p, self.g)
+        if self.eta is None:
+            self.eta = step_size(self.p, self.g, self.eta_frac)
+        self._G()
+        self.p = self.pbar.clone()
+        return IterLog(0, J, 0.0, 0, self.problem.n_adj, self.problem.n_fwd, time.perf_counter() - self.t0)
+
+    def iterate(self) -> IterLog:
+        self.k += 1
+        p, g = self.p, self.g
+        J = self.problem.gradient(p, g)
+        self._G()
+        lam_acc, p_next = 0.0, None
+        if self.linesearch:
+            for i, lam in enumerate(self.lambdas):
+                trial = self.trials[i % 2]
+                blend(lam, self.ptilde, self.pbar, trial)
+                Jt = self.problem.misfit_keep(trial)
+                slope = float(self.red.dot_diff(g, trial, p).item())
+                if Jt <= J + self.c1 * slope:
+                    lam_acc, p_next = lam, trial
+                    self.trials[i % 2] = torch.empty_like(p)
+                    break
+        else:
+            lam_acc, p_next = 1.0, self.ptilde
+            self.ptilde = torch.empty_like(p)
+        if p_next is None:
+            p_next = self.pbar
+            self.pbar = torch.empty_like(p)
+        self.p = p_next
+        mk = int(self.aa.mk.item()) if self.aa is not None else 0
+        return IterLog(self.k, J, lam_acc, mk, self.problem.n_adj, self.problem.n_fwd,
+                       time.perf_counter() - self.t0)
+
+    def close(self):
+        if self.aa is not None:
+            self.aa.close()
+            self.aa = None
+
+
+def aa_descent(problem, p0: torch.Tensor, eta: float | None, M: int, iters: int, cond_max: float = 1e5,
+               lambdas=LAMBDAS, c1: float = ARMIJO_C1, linesearch: bool = True,
+               keep_iterates: bool = True, log_path: str | None = None, callback=None):
+    """Run Algorithm 2 for ``iters`` iterations after p_1 = G(p_0).
+    Returns (iterates p_0..p_{iters+1}, history of IterLog, final p)."""
+    run = AADescent(problem, p0, eta, M, cond_max, lambdas, c1, linesearch)
+    iterates = [run.p.clone()] if keep_iterates else []
+    hist = []
+    out = open(log_path, "a") if log_path else None
+    try:
+        for i in range(iters + 1):
+            rec = run.first() if i == 0 else run.iterate()
+            if keep_iterates:
+                iterates.append(run.p.clone())
+            hist.append(rec)
+            if out:
+                out.write(json.dumps(dataclasses.asdict(rec)) + "\n")
+            if callback:
+                callback(rec)
+    finally:
+        if out:
+            out.close()
+        run.close()
+    return iterates, hist, run.p.view(p0.shape)
+
+
+def _gd_step(p, g, eta, out):
+    """out = p - eta g (the map G of eq. GD)."""
+    blend(1.0, p, p, out)
+    axpy(-eta, g, out)
+
+
+def step_size(m0: torch.Tensor, g0: torch.Tensor, frac: float = 0.02) -> float:
+    """eta = frac * max(m0) / max|g0| (fixed for the whole run)."""
+    return float(frac * m0.abs().max().item() / g0.abs().max().item())
