@@ -62,6 +62,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--time-every", type=int, default=16, help="event-time every n-th stepping launch")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="after the run, copy this many MiB device-to-device (counter calibration)")
     ap.add_argument("--tile", type=int, default=-1,
                     help="rows per wave for every stepping kernel (-1 = autotune, 0 = library default)")
     args = ap.parse_args()
@@ -167,6 +169,19 @@ def main():
                       "hbm_frac_all_kernels": round(it_bytes / elapsed / 1e9 / HBM_PEAK_GBS, 4),
                       "misfits": [r.J for r in recs], "lambdas": [r.lam for r in recs]},
     }
+    if args.copy_probe:
+        n = args.copy_probe * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        gbs = 5 * 2 * n * 4 / (time.perf_counter() - t2) / 1e9
+        out["copy_probe"] = {"mib": args.copy_probe, "gbs_read_plus_write": round(gbs, 1)}
+        log(f"copy probe: {args.copy_probe} MiB x5, {gbs:.1f} GB/s (read + write)")
+        del a, b
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline()

@@ -112,9 +112,9 @@ int aafwi_residual_misfit(aafwi_ctx* ctx, const float* d, const float* d_obs, fl
 int aafwi_adjoint_gradient(aafwi_ctx* ctx, const float* m, const float* d_obs, float* grad,
                            double* J);
 
-/* Backward pass only, after aafwi_forward_model(..., keep_ckpt=1) with the
- * model that is still in the context: grad = J'(m)^T r for a data-space
- * vector r [S][nt][R].  AAFWI_E_STATE if no checkpoints are kept. */
+/* Backward pass only: grad = J'(m)^T r for a data-space vector r [S][nt][R],
+ * where m is the model of the last forward run with kept checkpoints (the
+ * context holds a copy of it).  AAFWI_E_STATE if no checkpoints are kept. */
 int aafwi_adjoint_from_residual(aafwi_ctx* ctx, const float* r, float* grad);
 
 /* ---- Born modelling and its adjoint (eq. Born, eq. LSRTM) ------------------ */
@@ -123,7 +123,11 @@ int aafwi_adjoint_from_residual(aafwi_ctx* ctx, const float* r, float* grad);
 int aafwi_born(aafwi_ctx* ctx, const float* m0, const float* dm, float* d_scat);
 
 /* image = L^T y at background m0 (y device [S][nt][R]; image device [nz][nx]).
- * The RTM image of the LSRTM section is aafwi_born_adjoint(m0, d_r). */
+ * The RTM image of the LSRTM section is aafwi_born_adjoint(m0, d_r).  When
+ * the context keeps checkpoints of a forward run whose model is bitwise m0
+ * (checked on the device, one host synchronisation), the background forward
+ * is not repeated; otherwise it runs with checkpoints kept.  aafwi_born does
+ * not discard kept checkpoints. */
 int aafwi_born_adjoint(aafwi_ctx* ctx, const float* m0, const float* y, float* image);
 
 /* ---- Anderson acceleration for gradient descent (Algorithm 2, Steps 1-3) --- */
@@ -153,7 +157,8 @@ int aafwi_aa_step(aafwi_aa* aa, const float* p_k, const float* g_k, float eta, f
 /* Condition number of A_k found by the last step (device double), for logs. */
 int aafwi_aa_last_cond(aafwi_aa* aa, double* cond_dev);
 
-/* out = lambda*p_tilde + (1-lambda)*p_bar (Algorithm 2, Step 5); device [n]. */
+/* out = lambda*p_tilde + (1-lambda)*p_bar (Algorithm 2, Step 5), formed in
+ * FP64 and rounded once; device [n]; out may alias either input. */
 int aafwi_blend(aafwi_stream stream, int64_t n, float lambda, const float* p_tilde,
                 const float* p_bar, float* out);
 
@@ -172,8 +177,11 @@ int aafwi_dot(aafwi_stream stream, int64_t n, const float* x, const float* y, do
 int aafwi_dot_diff(aafwi_stream stream, int64_t n, const float* g, const float* a,
                    const float* b, double* out, double* workspace);
 
-/* y = a*x + y in FP32 (device [n]). */
+/* y = a*x + y in FP32 (device [n]); x may alias y. */
 int aafwi_axpy(aafwi_stream stream, int64_t n, float a, const float* x, float* y);
+
+/* out = a*x in FP32 (device [n]); out may alias x. */
+int aafwi_scale(aafwi_stream stream, int64_t n, float a, const float* x, float* out);
 
 /* ---- instrumentation ------------------------------------------------------- */
 

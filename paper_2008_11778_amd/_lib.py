@@ -76,6 +76,7 @@ _sig("aafwi_blend", _vp, _i64, _f32, _vp, _vp, _vp)
 _sig("aafwi_dot", _vp, _i64, _vp, _vp, _vp, _vp)
 _sig("aafwi_dot_diff", _vp, _i64, _vp, _vp, _vp, _vp, _vp)
 _sig("aafwi_axpy", _vp, _i64, _f32, _vp, _vp)
+_sig("aafwi_scale", _vp, _i64, _f32, _vp, _vp)
 _sig("aafwi_kernel_timing", _vp, ctypes.c_int)
 _sig("aafwi_kernel_timing_read", _vp, ctypes.c_int, ctypes.POINTER(_f64), ctypes.POINTER(_i64))
 _sig("aafwi_set_tile", _vp, _i32, _i32)
@@ -147,6 +148,8 @@ class Context:
             self._h = h
         self.n = self.nz * self.nx
         self.data_shape = (self.nshots, self.nt, self.nrec)
+        # incremented by every call that replaces the kept checkpoints / model
+        self.generation = 0
 
     # -- lifetime -------------------------------------------------------------
     def close(self):
@@ -181,6 +184,7 @@ class Context:
     # -- the calls -------------------------------------------------------------
     def forward_model(self, m, d=None, keep_ckpt=False):
         d = self._new(self.data_shape) if d is None else d
+        self.generation += 1
         _check(_lib.aafwi_forward_model(self._h, _ptr(m, numel=self.n, name="m"),
                                         _ptr(d, numel=self.nshots * self.nt * self.nrec, name="d"),
                                         int(bool(keep_ckpt))))
@@ -197,6 +201,7 @@ class Context:
     def adjoint_gradient(self, m, d_obs, grad=None, J=None):
         grad = self._new((self.nz, self.nx)) if grad is None else grad
         J = self._new((1,), torch.float64) if J is None else J
+        self.generation += 1
         _check(_lib.aafwi_adjoint_gradient(self._h, _ptr(m, numel=self.n, name="m"),
                                            _ptr(d_obs, numel=self.nshots * self.nt * self.nrec, name="d_obs"),
                                            _ptr(grad, numel=self.n, name="grad"), _ptr(J, torch.float64, 1, "J")))
@@ -210,12 +215,14 @@ class Context:
 
     def born(self, m0, dm, d=None):
         d = self._new(self.data_shape) if d is None else d
+        self.generation += 1
         _check(_lib.aafwi_born(self._h, _ptr(m0, numel=self.n, name="m0"), _ptr(dm, numel=self.n, name="dm"),
                                _ptr(d, numel=self.nshots * self.nt * self.nrec, name="d")))
         return d
 
     def born_adjoint(self, m0, y, image=None):
         image = self._new((self.nz, self.nx)) if image is None else image
+        self.generation += 1
         _check(_lib.aafwi_born_adjoint(self._h, _ptr(m0, numel=self.n, name="m0"),
                                        _ptr(y, numel=self.nshots * self.nt * self.nrec, name="y"),
                                        _ptr(image, numel=self.n, name="image")))
@@ -313,6 +320,15 @@ def blend(lam, p_tilde, p_bar, out=None, stream=None):
     n = p_bar.numel()
     _check(_lib.aafwi_blend(_stream_handle(stream), n, float(lam), _ptr(p_tilde, numel=n, name="p_tilde"),
                             _ptr(p_bar, numel=n, name="p_bar"), _ptr(out, numel=n, name="out")))
+    return out
+
+
+def scale(a, x, out=None, stream=None):
+    """out = a * x (out may be x)."""
+    out = torch.empty_like(x) if out is None else out
+    n = x.numel()
+    _check(_lib.aafwi_scale(_stream_handle(stream), n, float(a), _ptr(x, numel=n, name="x"),
+                            _ptr(out, numel=n, name="out")))
     return out
 
 

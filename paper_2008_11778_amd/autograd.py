@@ -1,0 +1,43 @@
+"""torch.autograd.Function around the forward map f(m) = R F(m).
+
+forward() runs the HIP forward pass keeping wavefield checkpoints (every
+``ckpt_every`` steps of the Context); backward() maps the incoming data-space
+gradient through the exact discrete adjoint (recompute each segment from its
+checkpoint, adjoint steps with zero-lag imaging, fold), so a long record's
+memory is O(nt/k + k) wavefields and no second full forward is run.
+
+If another forward run has used the same Context in between (the kept
+checkpoints belong to a different model), backward() first re-runs the
+forward for the saved model, so the result is always J'(m)^T grad_d.
+"""
+from __future__ import annotations
+
+import torch
+
+from ._lib import Context
+
+
+class SeismicForward(torch.autograd.Function):
+    @staticmethod
+    def forward(fctx, m: torch.Tensor, context: Context):
+        m_c = m.detach().contiguous()
+        d = context.forward_model(m_c, keep_ckpt=True)
+        fctx.context = context
+        fctx.gen = context.generation
+        fctx.save_for_backward(m_c)
+        return d
+
+    @staticmethod
+    def backward(fctx, grad_d: torch.Tensor):
+        (m_c,) = fctx.saved_tensors
+        context = fctx.context
+        if context.generation != fctx.gen:
+            context.forward_model(m_c, keep_ckpt=True)
+            fctx.gen = context.generation
+        grad_m = context.adjoint_from_residual(grad_d.detach().contiguous())
+        return grad_m, None
+
+
+def seismic_forward(m: torch.Tensor, context: Context) -> torch.Tensor:
+    """Differentiable f(m): [S][nt][R] seismograms from the model m [nz][nx]."""
+    return SeismicForward.apply(m, context)

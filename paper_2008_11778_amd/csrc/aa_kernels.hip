@@ -290,15 +290,21 @@ __global__ __launch_bounds__(kReduceThreads) void k_sum_partials(const double* _
     }
 }
 
-__global__ void k_blend(long long n, float lam, const float* __restrict__ pt, const float* __restrict__ pb,
-                        float* __restrict__ out) {
+// Element-wise kernels: outputs may alias inputs (same index only).
+__global__ void k_blend(long long n, float lam, const float* pt, const float* pb, float* out) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double l = (double)lam;
     out[i] = (float)(l * (double)pt[i] + (1.0 - l) * (double)pb[i]);
 }
 
-__global__ void k_axpy(long long n, float a, const float* __restrict__ x, float* __restrict__ y) {
+__global__ void k_scale(long long n, float a, const float* x, float* out) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    out[i] = a * x[i];
+}
+
+__global__ void k_axpy(long long n, float a, const float* x, float* y) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     y[i] = fmaf(a, x[i], y[i]);
@@ -332,6 +338,11 @@ void launch_dot(hipStream_t st, long long n, const float* x, const float* y, con
 
 void launch_blend(hipStream_t st, long long n, float lam, const float* pt, const float* pb, float* out) {
     hipLaunchKernelGGL(k_blend, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, lam, pt, pb, out);
+    AAFWI_HIP(hipGetLastError());
+}
+
+void launch_scale(hipStream_t st, long long n, float a, const float* x, float* out) {
+    hipLaunchKernelGGL(k_scale, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, a, x, out);
     AAFWI_HIP(hipGetLastError());
 }
 
@@ -488,6 +499,14 @@ extern "C" int aafwi_dot_diff(aafwi_stream stream, int64_t n, const float* g, co
     return guarded([&]() -> int {
         AAFWI_REQUIRE(n > 0 && g && a && b && out && workspace, "dot_diff: bad argument");
         aafwi::launch_dot((hipStream_t)stream, n, g, a, b, workspace, out);
+        return AAFWI_OK;
+    });
+}
+
+extern "C" int aafwi_scale(aafwi_stream stream, int64_t n, float a, const float* x, float* out) {
+    return guarded([&]() -> int {
+        AAFWI_REQUIRE(n > 0 && x && out, "scale: bad argument");
+        aafwi::launch_scale((hipStream_t)stream, n, a, x, out);
         return AAFWI_OK;
     });
 }

@@ -46,6 +46,8 @@ struct aafwi_ctx {
     float* dwork = nullptr;  // [S][nt][R]
     double* part = nullptr;  // reduction partials
     int* flag = nullptr;     // model-validity flag
+    float* mkeep = nullptr;  // model of the kept checkpoints [nz][nx]
+    int* same = nullptr;     // comparison flag
     int2* src = nullptr;     // [S]
     int* rowmap = nullptr;   // [S][nzp]
     int* xmap = nullptr;     // [S][nrr][pitch]
@@ -92,7 +94,7 @@ void dalloc(aafwi_ctx* c, void** p, size_t bytes) {
 void free_ctx(aafwi_ctx* c) {
     if (!c) return;
     void* ps[] = {c->K, c->E, c->F0, c->F1, c->L0, c->L1, c->GI, c->ckpt, c->qseg,
-                  c->dwork, c->part, c->flag, c->src, c->rowmap, c->xmap, c->rnext};
+                  c->dwork, c->part, c->flag, c->src, c->rowmap, c->xmap, c->rnext, c->mkeep, c->same};
     for (void* p : ps)
         if (p) (void)hipFree(p);
     for (auto& v : c->ev)
@@ -175,6 +177,19 @@ void run_forward(aafwi_ctx* c, const float* m, float* d, bool keep) {
         std::swap(cur, prev);
     }
     c->have_ckpt = keep;
+    if (keep)
+        AAFWI_HIP(hipMemcpyAsync(c->mkeep, m, sizeof(float) * (size_t)c->nz * c->nx, hipMemcpyDeviceToDevice,
+                                 c->stream));
+}
+
+// True when m is bitwise the model of the kept checkpoints (synchronises).
+bool kept_model_is(aafwi_ctx* c, const float* m) {
+    if (!c->have_ckpt) return false;
+    aafwi::launch_compare(c->stream, (long long)c->nz * c->nx, m, c->mkeep, c->same);
+    int v = 0;
+    AAFWI_HIP(hipMemcpyAsync(&v, c->same, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    AAFWI_HIP(hipStreamSynchronize(c->stream));
+    return v == 1;
 }
 
 // Checkpointed backward pass for the residual r (the model is already in K).
@@ -323,6 +338,8 @@ extern "C" int aafwi_create(const aafwi_geometry* gp, aafwi_stream stream, aafwi
             dalloc(c, (void**)&c->dwork, sizeof(float) * (size_t)g.S * G.nt * G.nrec);
             dalloc(c, (void**)&c->part, sizeof(double) * aafwi::kReduceBlocks);
             dalloc(c, (void**)&c->flag, sizeof(int));
+            dalloc(c, (void**)&c->mkeep, sizeof(float) * (size_t)G.nz * G.nx);
+            dalloc(c, (void**)&c->same, sizeof(int));
             dalloc(c, (void**)&c->src, sizeof(int2) * g.S);
             dalloc(c, (void**)&c->rowmap, sizeof(int) * rowmap.size());
             dalloc(c, (void**)&c->xmap, sizeof(int) * xmap.size());
@@ -412,6 +429,7 @@ extern "C" int aafwi_adjoint_from_residual(aafwi_ctx* c, const float* r, float* 
         AAFWI_REQUIRE(c && r && grad, "adjoint_from_residual: NULL argument");
         if (!c->have_ckpt)
             throw Error{AAFWI_E_STATE, "adjoint_from_residual: no kept checkpoints (call forward_model with keep_ckpt=1)"};
+        model_prep(c, c->mkeep);  // Kp of the kept run (a Born call may have replaced it)
         run_backward(c, r, grad);
         return AAFWI_OK;
     });
@@ -420,7 +438,7 @@ extern "C" int aafwi_adjoint_from_residual(aafwi_ctx* c, const float* r, float* 
 extern "C" int aafwi_born(aafwi_ctx* c, const float* m0, const float* dm, float* d_scat) {
     return guarded([&]() -> int {
         AAFWI_REQUIRE(c && m0 && dm && d_scat, "born: NULL argument");
-        c->have_ckpt = false;
+        // the kept checkpoints are untouched; Kp is rebuilt before any backward pass
         model_prep(c, m0);
         aafwi::launch_born_prep(c->stream, c->g, m0, dm, c->E);
         aafwi::launch_zero(c->stream, c->F0, c->field);
@@ -444,7 +462,11 @@ extern "C" int aafwi_born(aafwi_ctx* c, const float* m0, const float* dm, float*
 extern "C" int aafwi_born_adjoint(aafwi_ctx* c, const float* m0, const float* y, float* image) {
     return guarded([&]() -> int {
         AAFWI_REQUIRE(c && m0 && y && image, "born_adjoint: NULL argument");
-        run_forward(c, m0, c->dwork, true);
+        if (kept_model_is(c, m0)) {
+            model_prep(c, m0);  // background forward already checkpointed
+        } else {
+            run_forward(c, m0, c->dwork, true);
+        }
         run_backward(c, y, image);
         return AAFWI_OK;
     });

@@ -68,6 +68,7 @@ void launch_model_prep(hipStream_t st, const WaveGrid& g, float c2, const float*
 void launch_born_prep(hipStream_t st, const WaveGrid& g, const float* m0, const float* dm,
                       float* E);
 void launch_zero(hipStream_t st, float* p, long long n);
+void launch_compare(hipStream_t st, long long n, const float* a, const float* b, int* same);
 void launch_fwd_step(hipStream_t st, const WaveGrid& g, const float* K, const float* u,
                      const float* uprev, float* out, float w, SrcNodes src, RecMaps rm,
                      float* d, int n, int nt, float* ck_u, float* ck_um);
@@ -90,6 +91,7 @@ void launch_dot(hipStream_t st, long long n, const float* x, const float* y, con
 void launch_blend(hipStream_t st, long long n, float lam, const float* pt, const float* pb,
                   float* out);
 void launch_axpy(hipStream_t st, long long n, float a, const float* x, float* y);
+void launch_scale(hipStream_t st, long long n, float a, const float* x, float* out);
 
 constexpr int kReduceBlocks = 1024;  // fixed partial count: deterministic reductions
 constexpr int kReduceThreads = 256;

@@ -570,6 +570,20 @@ __global__ __launch_bounds__(kReduceThreads) void k_finish_sum(const double* __r
     if (threadIdx.x == 0) out[0] = s * scale;
 }
 
+// same[0] = 1 iff a and b are bitwise equal (n elements).
+__global__ void k_compare(long long n, const float* __restrict__ a, const float* __restrict__ b,
+                          int* __restrict__ same) {
+    __shared__ int diff;
+    if (threadIdx.x == 0) diff = 0;
+    __syncthreads();
+    int local = 0;
+    for (long long i = threadIdx.x; i < n; i += blockDim.x)
+        local |= (__builtin_bit_cast(unsigned, a[i]) != __builtin_bit_cast(unsigned, b[i]));
+    if (local) diff = 1;
+    __syncthreads();
+    if (threadIdx.x == 0) same[0] = diff ? 0 : 1;
+}
+
 inline int step_blocks(const WaveGrid& g) { return (g.ntiles + kWaves - 1) / kWaves; }
 
 }  // namespace
@@ -583,6 +597,11 @@ void launch_model_prep(hipStream_t st, const WaveGrid& g, float c2, const float*
 void launch_born_prep(hipStream_t st, const WaveGrid& g, const float* m0, const float* dm, float* E) {
     const int blocks = (int)((g.plane + 255) / 256);
     hipLaunchKernelGGL(k_born_prep, dim3(blocks), dim3(256), 0, st, g, m0, dm, E);
+    AAFWI_HIP(hipGetLastError());
+}
+
+void launch_compare(hipStream_t st, long long n, const float* a, const float* b, int* same) {
+    hipLaunchKernelGGL(k_compare, dim3(1), dim3(1024), 0, st, n, a, b, same);
     AAFWI_HIP(hipGetLastError());
 }
 

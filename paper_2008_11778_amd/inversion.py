@@ -40,6 +40,7 @@ class FWIProblem:
         self.r = ctx._new(ctx.data_shape)
         self.J = ctx._new((1,), torch.float64)
         self.kept = None  # the model whose forward run (and residual) is kept
+        self.kept_gen = -1
         self.n_fwd = 0
         self.n_adj = 0
 
@@ -48,13 +49,14 @@ class FWIProblem:
         (host sync)."""
         self.ctx.forward_model(m, self.d, keep_ckpt=True)
         self.ctx.residual_misfit(self.d, self.d_obs, self.r, self.J)
-        self.kept = m
+        self.kept, self.kept_gen = m, self.ctx.generation
         self.n_fwd += 1
         return float(self.J.item())
 
     def gradient(self, m: torch.Tensor, grad: torch.Tensor):
-        """(J, grad) at m, reusing the kept forward run when it was at m."""
-        if self.kept is not m:
+        """(J, grad) at m, reusing the kept forward run when it was at m (and
+        no other run has replaced it on the Context since)."""
+        if self.kept is not m or self.kept_gen != self.ctx.generation:
             self.misfit_keep(m)
         J = float(self.J.item())
         self.ctx.adjoint_from_residual(self.r, grad)
