@@ -183,6 +183,57 @@ int aafwi_axpy(aafwi_stream stream, int64_t n, float a, const float* x, float* y
 /* out = a*x in FP32 (device [n]); out may alias x. */
 int aafwi_scale(aafwi_stream stream, int64_t n, float a, const float* x, float* out);
 
+/* ---- batches of uneven inversion instances ---------------------------------- */
+
+/* N independent instances (each its own grid, spacing, time step, record
+ * length, shots and receivers) advanced together: every stepping launch covers
+ * the tiles of all active instances, and each instance derives its own time
+ * step, buffer parity and checkpoint slot from the launch's step counter.
+ * Each instance reads its model and observed data from, and writes its
+ * residual and gradient to, caller-owned device buffers fixed at creation
+ * (kept alive until the batch is destroyed), so its launch sequences can be
+ * captured once as HIP graphs and replayed (aafwi_batch_use_graphs).
+ * geoms, io: host arrays of ninst entries; ckpt_every: checkpoint interval
+ * shared by all instances (0 = 50).  Memory is the sum of the instances'
+ * needs. */
+typedef struct aafwi_batch aafwi_batch;
+typedef struct aafwi_batch_io {
+    float* m;            /* [nz][nx] model, read by aafwi_batch_forward           */
+    const float* d_obs;  /* [S][nt][R] observed data                               */
+    float* r;            /* [S][nt][R] residual f(m) - d_obs, written by forward   */
+    float* grad;         /* [nz][nx] gradient, written by aafwi_batch_backward      */
+} aafwi_batch_io;
+int aafwi_batch_create(const aafwi_geometry* geoms, const aafwi_batch_io* io, int32_t ninst,
+                       int32_t ckpt_every, aafwi_stream stream, aafwi_batch** out);
+int aafwi_batch_destroy(aafwi_batch* b);
+
+/* Copy the misfit J of each instance's last forward run into J (device, N
+ * doubles), stream-ordered. */
+int aafwi_batch_misfits(aafwi_batch* b, double* J);
+
+/* Host mask of N bytes (NULL = all active).  Masked instances are skipped by
+ * every following call; their kept checkpoints, residuals and gradients stay
+ * as they were.  Synchronises the batch stream. */
+int aafwi_batch_set_active(aafwi_batch* b, const uint8_t* active);
+
+/* For every active instance: r = f(m) - d_obs and J = 1/2 |r|^2 (eq. FWI),
+ * keeping wavefield checkpoints when keep_ckpt != 0. */
+int aafwi_batch_forward(aafwi_batch* b, int keep_ckpt);
+
+/* For every active instance: grad = J'(m)^T r from its kept checkpoints
+ * (eq. FWI_adj, eq. adj_grad1).  AAFWI_E_STATE if one has none. */
+int aafwi_batch_backward(aafwi_batch* b);
+
+/* Capture each launch sequence (forward with/without checkpoints, backward)
+ * as a HIP graph on first use and replay it afterwards (needs a non-NULL
+ * stream).  Masks are read on the device, so replays honour them. */
+int aafwi_batch_use_graphs(aafwi_batch* b, int enable);
+
+int aafwi_batch_device_bytes(const aafwi_batch* b, int64_t* bytes);
+int aafwi_batch_set_tile(aafwi_batch* b, int32_t kernel_id, int32_t rows_per_wave);
+int aafwi_batch_kernel_timing(aafwi_batch* b, int every);
+int aafwi_batch_kernel_timing_read(aafwi_batch* b, int kernel_id, double* mean_ms, int64_t* count);
+
 /* ---- instrumentation ------------------------------------------------------- */
 
 /* Kernel ids for aafwi_kernel_timing. */

@@ -81,6 +81,16 @@ _sig("aafwi_kernel_timing", _vp, ctypes.c_int)
 _sig("aafwi_kernel_timing_read", _vp, ctypes.c_int, ctypes.POINTER(_f64), ctypes.POINTER(_i64))
 _sig("aafwi_set_tile", _vp, _i32, _i32)
 _sig("aafwi_get_tile", _vp, _i32, ctypes.POINTER(_i32))
+_sig("aafwi_batch_destroy", _vp)
+_sig("aafwi_batch_misfits", _vp, _vp)
+_sig("aafwi_batch_set_active", _vp, _vp)
+_sig("aafwi_batch_forward", _vp, ctypes.c_int)
+_sig("aafwi_batch_backward", _vp)
+_sig("aafwi_batch_use_graphs", _vp, ctypes.c_int)
+_sig("aafwi_batch_device_bytes", _vp, ctypes.POINTER(_i64))
+_sig("aafwi_batch_set_tile", _vp, _i32, _i32)
+_sig("aafwi_batch_kernel_timing", _vp, ctypes.c_int)
+_sig("aafwi_batch_kernel_timing_read", _vp, ctypes.c_int, ctypes.POINTER(_f64), ctypes.POINTER(_i64))
 _lib.aafwi_last_error.argtypes = []
 _lib.aafwi_last_error.restype = ctypes.c_char_p
 
@@ -244,6 +254,115 @@ class Context:
         v = _i32()
         _check(_lib.aafwi_get_tile(self._h, int(kernel_id), ctypes.byref(v)))
         return int(v.value)
+
+
+class _BatchIO(ctypes.Structure):
+    _fields_ = [("m", _vp), ("d_obs", _vp), ("r", _vp), ("grad", _vp)]
+
+
+_sig("aafwi_batch_create", ctypes.POINTER(_Geometry), ctypes.POINTER(_BatchIO), _i32, _i32, _vp,
+     ctypes.POINTER(_vp))
+
+
+class Batch:
+    """N uneven inversion instances advanced together (one launch per step).
+
+    The batch owns torch buffers per instance: ``m[i]`` (model, read by
+    forward), ``d_obs[i]`` (observed data), ``r[i]`` (residual, written by
+    forward) and ``grad[i]`` (written by backward).  A non-default stream is
+    created for it (graph capture cannot use the null stream); run torch work
+    that touches these buffers under ``with torch.cuda.stream(batch.stream)``.
+    """
+
+    def __init__(self, geoms, d_obs, ckpt_every=0, use_graphs=True, stream=None):
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        self.N = len(geoms)
+        self.geoms = list(geoms)
+        self.shapes, self.data_shapes = [], []
+        structs, self._keep = [], []
+        for g in geoms:
+            s, keep = make_geometry_struct(g, 0)
+            structs.append(s)
+            self._keep.append(keep)
+            S = int(np.asarray(g.src_iz).size)
+            R = int(np.asarray(g.rec_iz).size // S)
+            self.shapes.append((int(g.nz), int(g.nx)))
+            self.data_shapes.append((S, int(g.nt), R))
+        with torch.cuda.stream(self.stream):
+            self.m = [torch.zeros(sh, dtype=torch.float32, device=self.device) for sh in self.shapes]
+            self.grad = [torch.zeros(sh, dtype=torch.float32, device=self.device) for sh in self.shapes]
+            self.r = [torch.zeros(ds, dtype=torch.float32, device=self.device) for ds in self.data_shapes]
+            self.d_obs = []
+            for i, x in enumerate(d_obs):
+                t = torch.as_tensor(x, dtype=torch.float32, device=self.device).contiguous().clone()
+                if tuple(t.shape) != self.data_shapes[i]:
+                    t = t.reshape(self.data_shapes[i])
+                self.d_obs.append(t)
+            self.J = torch.zeros(self.N, dtype=torch.float64, device=self.device)
+        self.stream.synchronize()
+        garr = (_Geometry * self.N)(*structs)
+        ioarr = (_BatchIO * self.N)(*[_BatchIO(self.m[i].data_ptr(), self.d_obs[i].data_ptr(),
+                                               self.r[i].data_ptr(), self.grad[i].data_ptr())
+                                      for i in range(self.N)])
+        h = _vp()
+        _check(_lib.aafwi_batch_create(garr, ioarr, self.N, int(ckpt_every), _stream_handle(self.stream),
+                                       ctypes.byref(h)))
+        self._h = h
+        if use_graphs:
+            _check(_lib.aafwi_batch_use_graphs(self._h, 1))
+        self.active = np.ones(self.N, dtype=np.uint8)
+
+    def set_active(self, mask):
+        self.active = np.ascontiguousarray(mask, dtype=np.uint8)
+        _check(_lib.aafwi_batch_set_active(self._h, self.active.ctypes.data))
+
+    def forward(self, keep_ckpt=True):
+        _check(_lib.aafwi_batch_forward(self._h, int(bool(keep_ckpt))))
+
+    def backward(self):
+        _check(_lib.aafwi_batch_backward(self._h))
+
+    def misfits(self):
+        _check(_lib.aafwi_batch_misfits(self._h, _ptr(self.J, torch.float64, self.N, "J")))
+        self.stream.synchronize()
+        return self.J.cpu().numpy()
+
+    def use_graphs(self, enable):
+        _check(_lib.aafwi_batch_use_graphs(self._h, int(bool(enable))))
+
+    def set_tile(self, rows_per_wave: int, kernel_id: int = -1):
+        _check(_lib.aafwi_batch_set_tile(self._h, int(kernel_id), int(rows_per_wave)))
+
+    def device_bytes(self) -> int:
+        v = _i64()
+        _check(_lib.aafwi_batch_device_bytes(self._h, ctypes.byref(v)))
+        return int(v.value)
+
+    def kernel_timing(self, every: int):
+        _check(_lib.aafwi_batch_kernel_timing(self._h, int(every)))
+
+    def kernel_timing_read(self, kernel_id: int):
+        ms, cnt = _f64(), _i64()
+        _check(_lib.aafwi_batch_kernel_timing_read(self._h, int(kernel_id), ctypes.byref(ms), ctypes.byref(cnt)))
+        return float(ms.value), int(cnt.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(_lib.aafwi_batch_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
 
 
 class AA:

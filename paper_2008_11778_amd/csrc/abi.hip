@@ -1,10 +1,26 @@
-// Host runtime and C ABI of the wave-equation calls: context creation
-// (geometry validation, receiver maps, device scratch), the forward pass with
-// checkpoints, the checkpointed backward pass (recompute + adjoint + imaging),
-// Born modelling and its adjoint, and event timing of the stepping kernels.
+// Host runtime and C ABI of the wave-equation calls.
+//
+// An Engine holds one or more inversion instances (each a geometry with all
+// of its shots) and advances all of them together: every stepping launch
+// covers the tiles of every active instance (a device tile table), and each
+// instance derives its own time step, buffer parity and checkpoint slot from
+// the launch's step counter, so instances with different grids, shot counts
+// and record lengths share launches.  aafwi_ctx is an Engine with one
+// instance whose inputs and outputs are caller buffers; aafwi_batch is an
+// Engine with N instances that owns its model, data and gradient buffers (so
+// the launch sequence can be captured once in a hipGraph and replayed).
+//
+// Forward pass: u^{n+1} = 2A u^n - B u^{n-1} + Kp (Lt u^n + src) for
+// n = 0..nt-1 with (u^n, u^{n-1}) copied to checkpoint slot n/k when n % k == 0.
+// Backward pass, segment by segment from the end of each record: recompute
+// the segment's steps from its checkpoint storing q-hat^n, then run the
+// adjoint steps of the segment backwards, imaging into per-shot
+// accumulators; finally fold (sum over shots, transpose of the edge
+// replication, scaling by 1/(A dt^2)).
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <new>
 #include <string>
 #include <vector>
@@ -12,59 +28,61 @@
 #include "common.hpp"
 
 namespace aafwi {
-
 namespace {
 thread_local std::string g_last_error;
 }
-
 void set_last_error(const std::string& msg) { g_last_error = msg; }
-
 }  // namespace aafwi
 
 using aafwi::Error;
 
-struct aafwi_ctx {
-    // geometry (host copy)
-    int nz = 0, nx = 0, nb = 0, nt = 0, S = 0, R = 0, k = 0, nseg = 0;
-    float h = 0, dt = 0, vref = 0, refl = 0, vmax = 0;
-    std::vector<float> wavelet;
+namespace {
+
+// Host view of one instance.
+struct InstHost {
+    int nz = 0, nx = 0, nb = 0, nt = 0, S = 0, R = 0, nseg = 0;
+    float h = 0, dt = 0;
     aafwi::WaveGrid g{};
-    aafwi::WaveGrid gk[4];  // per stepping kernel (tile height may differ)
-    hipStream_t stream = nullptr;
-    long long field = 0;  // S * plane floats
-
-    // device scratch
-    float* K = nullptr;      // Kp on the padded grid [plane]
-    float* E = nullptr;      // Born dm/m0 [plane]
-    float* F0 = nullptr;     // forward wavefields [S][plane] x 2
-    float* F1 = nullptr;
-    float* L0 = nullptr;     // adjoint (or scattered) wavefields [S][plane] x 2
-    float* L1 = nullptr;
-    float* GI = nullptr;     // per-shot image accumulators [S][plane]
-    float* ckpt = nullptr;   // [nseg][2][S][plane]
-    float* qseg = nullptr;   // [k][S][plane]
-    float* dwork = nullptr;  // [S][nt][R]
-    double* part = nullptr;  // reduction partials
-    int* flag = nullptr;     // model-validity flag
-    float* mkeep = nullptr;  // model of the kept checkpoints [nz][nx]
-    int* same = nullptr;     // comparison flag
-    int2* src = nullptr;     // [S]
-    int* rowmap = nullptr;   // [S][nzp]
-    int* xmap = nullptr;     // [S][nrr][pitch]
-    int* rnext = nullptr;    // [S*R]
+    long long field = 0;
     int nrr = 0;
-    long long bytes = 0;
-
+    std::vector<float> wavelet;
+    // device memory
+    float *K = nullptr, *E = nullptr, *F0 = nullptr, *F1 = nullptr, *L0 = nullptr, *L1 = nullptr;
+    float *GI = nullptr, *ckpt = nullptr, *qseg = nullptr, *d = nullptr, *wav = nullptr, *mkeep = nullptr;
+    float *m = nullptr, *grad = nullptr;  // caller buffers of batch instances
+    const float* dobs = nullptr;
+    int2* src = nullptr;
+    int *rowmap = nullptr, *xmap = nullptr, *rnext = nullptr;
     bool have_ckpt = false;
+};
 
+struct Engine {
+    hipStream_t stream = nullptr;
+    int k = 0;
+    bool is_batch = false;  // per-instance masks, caller buffers fixed at creation
+    std::vector<InstHost> in;
+    aafwi::Inst* dinst = nullptr;
+    aafwi::TileRec* dtiles[4] = {nullptr, nullptr, nullptr, nullptr};
+    int ntiles[4] = {0, 0, 0, 0};
+    int tz[4] = {0, 0, 0, 0};
+    int* active = nullptr;  // device [N], batches only
+    std::vector<int> active_host;
+    double* J = nullptr;    // device [N]
+    double* part = nullptr;
+    int* flag = nullptr;
+    int* same = nullptr;
+    long long bytes = 0;
+    std::vector<void*> allocs;
     // timing
     int time_every = 0;
     long long launches[4] = {0, 0, 0, 0};
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[4];
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
+    // graphs (batches)
+    bool use_graphs = false;
+    bool capturing = false;
+    std::map<int, hipGraphExec_t> graphs;
 };
-
-namespace {
 
 template <typename F>
 int guarded(F&& f) {
@@ -82,164 +100,405 @@ int guarded(F&& f) {
     }
 }
 
-void dalloc(aafwi_ctx* c, void** p, size_t bytes) {
-    if (bytes == 0) bytes = 4;
-    if (hipMalloc(p, bytes) != hipSuccess) {
+template <typename T>
+T* dalloc(Engine* e, size_t count) {
+    size_t bytes = sizeof(T) * (count ? count : 1);
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
         (void)hipGetLastError();
         throw Error{AAFWI_E_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed"};
     }
-    c->bytes += (long long)bytes;
+    e->allocs.push_back(p);
+    e->bytes += (long long)bytes;
+    return (T*)p;
 }
 
-void free_ctx(aafwi_ctx* c) {
-    if (!c) return;
-    void* ps[] = {c->K, c->E, c->F0, c->F1, c->L0, c->L1, c->GI, c->ckpt, c->qseg,
-                  c->dwork, c->part, c->flag, c->src, c->rowmap, c->xmap, c->rnext, c->mkeep, c->same};
-    for (void* p : ps)
-        if (p) (void)hipFree(p);
-    for (auto& v : c->ev)
-        for (auto& e : v) {
-            (void)hipEventDestroy(e.first);
-            (void)hipEventDestroy(e.second);
+void free_engine(Engine* e) {
+    if (!e) return;
+    for (auto& kv : e->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (void* p : e->allocs) (void)hipFree(p);
+    for (auto& v : e->ev)
+        for (auto& x : v) {
+            (void)hipEventDestroy(x.first);
+            (void)hipEventDestroy(x.second);
         }
-    for (auto& e : c->ev_pool) {
-        (void)hipEventDestroy(e.first);
-        (void)hipEventDestroy(e.second);
+    for (auto& x : e->ev_pool) {
+        (void)hipEventDestroy(x.first);
+        (void)hipEventDestroy(x.second);
     }
-    delete c;
+    delete e;
 }
 
 // Strip height: rows per wave; 0 picks about 8 strips per column of tiles.
-void apply_tile(aafwi::WaveGrid& g, int rows) {
-    int tz = rows;
-    if (tz == 0) tz = std::max(16, std::min((g.nzp + 7) / 8, 64));
-    g.tz = std::min(tz, g.nzp);
-    g.nzs = (g.nzp + g.tz - 1) / g.tz;
-    g.ntiles = g.ntx * g.nzs * g.S;
+int default_tz(int nzp) { return std::max(16, std::min((nzp + 7) / 8, 64)); }
+
+void validate_geometry(const aafwi_geometry& G) {
+    AAFWI_REQUIRE(G.nz >= 1 && G.nx >= 1, "create: nz and nx must be >= 1");
+    AAFWI_REQUIRE(G.nb >= 1 && G.nb <= 4096, "create: nb must be in [1, 4096]");
+    AAFWI_REQUIRE(G.nt >= 1, "create: nt must be >= 1");
+    AAFWI_REQUIRE(G.nshots >= 1 && G.nrec >= 1, "create: nshots and nrec must be >= 1");
+    AAFWI_REQUIRE(std::isfinite(G.h) && G.h > 0 && std::isfinite(G.dt) && G.dt > 0,
+                  "create: h and dt must be positive");
+    AAFWI_REQUIRE(std::isfinite(G.vref) && G.vref > 0, "create: vref must be positive");
+    AAFWI_REQUIRE(std::isfinite(G.refl) && G.refl > 0, "create: refl must be positive");
+    AAFWI_REQUIRE(std::isfinite(G.vmax_bound) && G.vmax_bound > 0, "create: vmax_bound must be positive");
+    AAFWI_REQUIRE(G.src_iz && G.src_ix && G.rec_iz && G.rec_ix && G.wavelet, "create: NULL geometry array");
+    AAFWI_REQUIRE(G.ckpt_every >= 0, "create: ckpt_every must be >= 0");
+    const double cfl = (double)G.vmax_bound * G.dt / G.h;
+    if (cfl > 0.55) throw Error{AAFWI_E_CFL, "create: vmax_bound*dt/h = " + std::to_string(cfl) + " exceeds 0.55"};
+    const long long nzp = (long long)G.nz + 2LL * G.nb, nxp = (long long)G.nx + 2LL * G.nb;
+    // byte offsets inside a plane (plus 16 rows of slack) must stay below 2^31
+    AAFWI_REQUIRE(4LL * (nzp + 16) * ((nxp + 63) / 64 * 64) < (1LL << 31), "create: padded plane too large");
+    AAFWI_REQUIRE(nzp < 65536, "create: too many padded rows");
+    for (int s = 0; s < G.nshots; ++s)
+        AAFWI_REQUIRE(G.src_iz[s] >= 0 && G.src_iz[s] < G.nz && G.src_ix[s] >= 0 && G.src_ix[s] < G.nx,
+                      "create: source index outside the interior grid");
+    for (long long i = 0; i < (long long)G.nshots * G.nrec; ++i)
+        AAFWI_REQUIRE(G.rec_iz[i] >= 0 && G.rec_iz[i] < G.nz && G.rec_ix[i] >= 0 && G.rec_ix[i] < G.nx,
+                      "create: receiver index outside the interior grid");
+    for (int n = 0; n < G.nt; ++n) AAFWI_REQUIRE(std::isfinite(G.wavelet[n]), "create: wavelet must be finite");
 }
 
-aafwi::RecMaps maps(const aafwi_ctx* c) { return {c->rowmap, c->xmap, c->rnext, c->nrr, c->R}; }
-aafwi::SrcNodes srcs(const aafwi_ctx* c) { return {c->src}; }
+void add_instance(Engine* e, const aafwi_geometry& G, const aafwi_batch_io* io) {
+    validate_geometry(G);
+    InstHost I;
+    I.nz = G.nz; I.nx = G.nx; I.nb = G.nb; I.nt = G.nt; I.S = G.nshots; I.R = G.nrec;
+    I.h = G.h; I.dt = G.dt;
+    I.nseg = (G.nt + e->k - 1) / e->k;
+    I.wavelet.assign(G.wavelet, G.wavelet + G.nt);
+    aafwi::WaveGrid& g = I.g;
+    g.nz = G.nz; g.nx = G.nx; g.nb = G.nb;
+    g.nzp = G.nz + 2 * G.nb;
+    g.nxp = G.nx + 2 * G.nb;
+    g.pitch = (g.nxp + 63) / 64 * 64;
+    g.plane = (long long)g.nzp * g.pitch;
+    g.S = G.nshots;
+    g.ntx = g.pitch / 64;
+    const double smax = (G.refl >= 1.0f) ? 0.0 : 3.0 * G.vref * std::log(1.0 / (double)G.refl) / (2.0 * G.nb * G.h);
+    g.scoef = (float)(smax * G.dt / 2.0);
+    g.inv_nb = (float)(1.0 / G.nb);
+    I.field = (long long)g.S * g.plane;
 
-// Event pair around a launch of kernel `id` when sampling is on.
-struct Timed {
-    aafwi_ctx* c;
-    int id;
-    std::pair<hipEvent_t, hipEvent_t> e{nullptr, nullptr};
-    Timed(aafwi_ctx* c_, int id_) : c(c_), id(id_) {
-        if (c->time_every > 0 && (c->launches[id] % c->time_every) == 0 && !c->ev_pool.empty()) {
-            e = c->ev_pool.back();
-            c->ev_pool.pop_back();
-            AAFWI_HIP(hipEventRecord(e.first, c->stream));
+    // receiver maps
+    std::vector<int> rowmap((size_t)g.S * g.nzp, -1);
+    std::vector<int> nrows(g.S, 0);
+    for (int s = 0; s < g.S; ++s)
+        for (int r = 0; r < G.nrec; ++r) {
+            const int zp = G.rec_iz[(long long)s * G.nrec + r] + G.nb;
+            int& slot = rowmap[(size_t)s * g.nzp + zp];
+            if (slot < 0) slot = nrows[s]++;
         }
-        c->launches[id] += 1;
+    I.nrr = *std::max_element(nrows.begin(), nrows.end());
+    std::vector<int> xmap((size_t)g.S * I.nrr * g.pitch, -1);
+    std::vector<int> rnext((size_t)g.S * G.nrec, -1);
+    for (int s = 0; s < g.S; ++s)
+        for (int r = G.nrec - 1; r >= 0; --r) {
+            const long long i = (long long)s * G.nrec + r;
+            const int zp = G.rec_iz[i] + G.nb, xp = G.rec_ix[i] + G.nb;
+            const int slot = rowmap[(size_t)s * g.nzp + zp];
+            int& head = xmap[((size_t)s * I.nrr + slot) * g.pitch + xp];
+            rnext[i] = head;  // chain in ascending receiver order
+            head = r;
+        }
+    std::vector<int2> src(g.S);
+    for (int s = 0; s < g.S; ++s) src[s] = make_int2(G.src_iz[s] + G.nb, G.src_ix[s] + G.nb);
+
+    const size_t ndata = (size_t)g.S * G.nt * G.nrec;
+    I.K = dalloc<float>(e, g.plane);
+    I.E = dalloc<float>(e, g.plane);
+    I.F0 = dalloc<float>(e, I.field);
+    I.F1 = dalloc<float>(e, I.field);
+    I.L0 = dalloc<float>(e, I.field);
+    I.L1 = dalloc<float>(e, I.field);
+    I.GI = dalloc<float>(e, I.field);
+    I.ckpt = dalloc<float>(e, (size_t)I.field * 2 * I.nseg);
+    I.qseg = dalloc<float>(e, (size_t)I.field * e->k);
+    I.d = (io && io->r) ? io->r : dalloc<float>(e, ndata);
+    I.wav = dalloc<float>(e, G.nt);
+    I.mkeep = dalloc<float>(e, (size_t)G.nz * G.nx);
+    if (io) {
+        I.m = io->m;
+        I.dobs = io->d_obs;
+        I.grad = io->grad;
+    }
+    I.src = dalloc<int2>(e, g.S);
+    I.rowmap = dalloc<int>(e, rowmap.size());
+    I.xmap = dalloc<int>(e, xmap.size());
+    I.rnext = dalloc<int>(e, rnext.size());
+    AAFWI_HIP(hipMemcpy(I.src, src.data(), sizeof(int2) * g.S, hipMemcpyHostToDevice));
+    AAFWI_HIP(hipMemcpy(I.rowmap, rowmap.data(), sizeof(int) * rowmap.size(), hipMemcpyHostToDevice));
+    AAFWI_HIP(hipMemcpy(I.xmap, xmap.data(), sizeof(int) * xmap.size(), hipMemcpyHostToDevice));
+    AAFWI_HIP(hipMemcpy(I.rnext, rnext.data(), sizeof(int) * rnext.size(), hipMemcpyHostToDevice));
+    AAFWI_HIP(hipMemcpy(I.wav, I.wavelet.data(), sizeof(float) * G.nt, hipMemcpyHostToDevice));
+    // padding columns of every field read as zero forever (stores never reach them)
+    AAFWI_HIP(hipMemset(I.F0, 0, sizeof(float) * I.field));
+    AAFWI_HIP(hipMemset(I.F1, 0, sizeof(float) * I.field));
+    AAFWI_HIP(hipMemset(I.L0, 0, sizeof(float) * I.field));
+    AAFWI_HIP(hipMemset(I.L1, 0, sizeof(float) * I.field));
+    e->in.push_back(std::move(I));
+}
+
+void build_tiles(Engine* e, int kid) {
+    std::vector<aafwi::TileRec> t;
+    for (int i = 0; i < (int)e->in.size(); ++i) {
+        const aafwi::WaveGrid& g = e->in[i].g;
+        const int tz = std::min(e->tz[kid] ? e->tz[kid] : default_tz(g.nzp), g.nzp);
+        for (int s = 0; s < g.S; ++s)
+            for (int z0 = 0; z0 < g.nzp; z0 += tz)
+                for (int tx = 0; tx < g.ntx; ++tx) {
+                    const int z1 = std::min(z0 + tz, g.nzp);
+                    t.push_back({i, s, tx * 64, (z0 << 16) | z1});
+                }
+    }
+    if (e->dtiles[kid]) {
+        (void)hipFree(e->dtiles[kid]);
+        e->allocs.erase(std::remove(e->allocs.begin(), e->allocs.end(), (void*)e->dtiles[kid]), e->allocs.end());
+    }
+    e->dtiles[kid] = dalloc<aafwi::TileRec>(e, t.size());
+    AAFWI_HIP(hipMemcpy(e->dtiles[kid], t.data(), sizeof(aafwi::TileRec) * t.size(), hipMemcpyHostToDevice));
+    e->ntiles[kid] = (int)t.size();
+}
+
+void finalize(Engine* e) {
+    const int N = (int)e->in.size();
+    std::vector<aafwi::Inst> tab(N);
+    for (int i = 0; i < N; ++i) {
+        const InstHost& I = e->in[i];
+        aafwi::Inst& D = tab[i];
+        D.g = I.g;
+        D.K = I.K; D.E = I.E;
+        D.F0 = I.F0; D.F1 = I.F1; D.L0 = I.L0; D.L1 = I.L1; D.GI = I.GI;
+        D.ckpt = I.ckpt; D.qseg = I.qseg; D.d = I.d; D.r = I.d; D.wav = I.wav;
+        D.src = {I.src};
+        D.rm = {I.rowmap, I.xmap, I.rnext, I.nrr, I.R};
+        D.nt = I.nt; D.nseg = I.nseg; D.k = e->k;
+        D.h2 = I.h * I.h;
+        D.field = I.field;
+    }
+    e->dinst = dalloc<aafwi::Inst>(e, N);
+    AAFWI_HIP(hipMemcpy(e->dinst, tab.data(), sizeof(aafwi::Inst) * N, hipMemcpyHostToDevice));
+    for (int kid = 0; kid < 4; ++kid) build_tiles(e, kid);
+    e->J = dalloc<double>(e, N);
+    e->part = dalloc<double>(e, aafwi::kReduceBlocks);
+    e->flag = dalloc<int>(e, 1);
+    e->same = dalloc<int>(e, 1);
+    AAFWI_HIP(hipMemset(e->flag, 0, sizeof(int)));
+    AAFWI_HIP(hipMemset(e->J, 0, sizeof(double) * N));
+    if (e->is_batch) {
+        e->active = dalloc<int>(e, N);
+        e->active_host.assign(N, 1);
+        AAFWI_HIP(hipMemcpy(e->active, e->active_host.data(), sizeof(int) * N, hipMemcpyHostToDevice));
+    }
+    AAFWI_HIP(hipDeviceSynchronize());
+}
+
+// Event pair around a stepping launch when sampling is on (not inside captures).
+struct Timed {
+    Engine* e;
+    int id;
+    std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+    Timed(Engine* e_, int id_) : e(e_), id(id_) {
+        if (!e->capturing && e->time_every > 0 && (e->launches[id] % e->time_every) == 0 && !e->ev_pool.empty()) {
+            ev = e->ev_pool.back();
+            e->ev_pool.pop_back();
+            AAFWI_HIP(hipEventRecord(ev.first, e->stream));
+        }
+        e->launches[id] += 1;
     }
     ~Timed() {
-        if (e.first) {
-            (void)hipEventRecord(e.second, c->stream);
-            c->ev[id].push_back(e);
+        if (ev.first) {
+            (void)hipEventRecord(ev.second, e->stream);
+            e->ev[id].push_back(ev);
         }
     }
 };
 
-void check_m(const aafwi_ctx* c, const void* p, const char* what) {
-    if (!p) throw Error{AAFWI_E_INVALID, std::string(what) + " is NULL"};
+void step(Engine* e, int kid, const aafwi::StepArgs& a) {
+    Timed t(e, kid);
+    aafwi::launch_step(kid, e->stream, e->dtiles[kid], e->ntiles[kid], e->dinst, a);
 }
 
-void model_prep(aafwi_ctx* c, const float* m) {
-    const double c2 = ((double)c->dt / (double)c->h) * ((double)c->dt / (double)c->h);
-    aafwi::launch_model_prep(c->stream, c->g, (float)c2, m, c->K, c->flag);
+void model_prep(Engine* e, int i, const float* m) {
+    const InstHost& I = e->in[i];
+    const double c2 = ((double)I.dt / (double)I.h) * ((double)I.dt / (double)I.h);
+    aafwi::launch_model_prep(e->stream, I.g, (float)c2, m, I.K, e->flag, e->active, i);
 }
 
-float* ckpt_slot(aafwi_ctx* c, int j, int which) {
-    return c->ckpt + ((long long)j * 2 + which) * c->field;
-}
-
-// Forward pass over all shots; samples into d (may be dwork).
-void run_forward(aafwi_ctx* c, const float* m, float* d, bool keep) {
-    model_prep(c, m);
-    aafwi::launch_zero(c->stream, c->F0, c->field);
-    aafwi::launch_zero(c->stream, c->F1, c->field);
-    float* cur = c->F0;  // u^n
-    float* prev = c->F1; // u^{n-1}
-    for (int n = 0; n < c->nt; ++n) {
-        float* cu = nullptr;
-        float* cum = nullptr;
-        if (keep && n % c->k == 0) {
-            cu = ckpt_slot(c, n / c->k, 0);
-            cum = ckpt_slot(c, n / c->k, 1);
-        }
-        {
-            Timed t(c, AAFWI_K_FWD_STEP);
-            aafwi::launch_fwd_step(c->stream, c->gk[AAFWI_K_FWD_STEP], c->K, cur, prev, prev, c->wavelet[n], srcs(c), maps(c), d, n,
-                                   c->nt, cu, cum);
-        }
-        std::swap(cur, prev);
-    }
-    c->have_ckpt = keep;
-    if (keep)
-        AAFWI_HIP(hipMemcpyAsync(c->mkeep, m, sizeof(float) * (size_t)c->nz * c->nx, hipMemcpyDeviceToDevice,
-                                 c->stream));
-}
-
-// True when m is bitwise the model of the kept checkpoints (synchronises).
-bool kept_model_is(aafwi_ctx* c, const float* m) {
-    if (!c->have_ckpt) return false;
-    aafwi::launch_compare(c->stream, (long long)c->nz * c->nx, m, c->mkeep, c->same);
+int max_nt(const Engine* e) {
     int v = 0;
-    AAFWI_HIP(hipMemcpyAsync(&v, c->same, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-    AAFWI_HIP(hipStreamSynchronize(c->stream));
+    for (auto& I : e->in) v = std::max(v, I.nt);
+    return v;
+}
+
+// Forward pass of every (active) instance; models m[i], samples into d_ovr (if
+// set) or the instances' own data buffers.
+void run_forward(Engine* e, const std::vector<const float*>& m, float* d_ovr, bool keep) {
+    const int N = (int)e->in.size();
+    for (int i = 0; i < N; ++i) {
+        model_prep(e, i, m[i]);
+        aafwi::launch_zero(e->stream, e->in[i].F0, e->in[i].field);
+        aafwi::launch_zero(e->stream, e->in[i].F1, e->in[i].field);
+    }
+    aafwi::StepArgs a{0, 0, keep ? 1 : 0, d_ovr, nullptr, e->active};
+    const int T = max_nt(e);
+    for (int n = 0; n < T; ++n) {
+        a.n = n;
+        step(e, AAFWI_K_FWD_STEP, a);
+    }
+    if (keep)
+        for (int i = 0; i < N; ++i)
+            aafwi::launch_copy(e->stream, (long long)e->in[i].nz * e->in[i].nx, m[i], e->in[i].mkeep, e->active, i);
+    for (int i = 0; i < N; ++i)
+        if (e->active_host.empty() || e->active_host[i]) e->in[i].have_ckpt = keep;
+}
+
+int seg_len(const Engine* e, const InstHost& I, int J) {
+    const int j = I.nseg - 1 - J;
+    if (j < 0) return 0;
+    return std::min(e->k, I.nt - j * e->k);
+}
+
+// Backward pass of every (active) instance from its kept checkpoints; the
+// adjoint source is r_ovr (if set) or the instances' own residual buffers.
+void run_backward(Engine* e, const float* r_ovr, const std::vector<float*>& grad) {
+    const int N = (int)e->in.size();
+    int maxseg = 0;
+    for (int i = 0; i < N; ++i) {
+        InstHost& I = e->in[i];
+        model_prep(e, i, I.mkeep);  // Kp of the kept run (a Born call may have replaced it)
+        aafwi::launch_zero(e->stream, I.L0, I.field);
+        aafwi::launch_zero(e->stream, I.L1, I.field);
+        aafwi::launch_zero(e->stream, I.GI, I.field);
+        maxseg = std::max(maxseg, I.nseg);
+    }
+    aafwi::StepArgs a{0, 0, 0, nullptr, r_ovr, e->active};
+    for (int J = 0; J < maxseg; ++J) {
+        int len = 0;
+        for (auto& I : e->in) len = std::max(len, seg_len(e, I, J));
+        a.seg = J;
+        for (int tt = 0; tt < len; ++tt) {
+            a.n = tt;
+            step(e, AAFWI_K_REC_STEP, a);
+        }
+        for (int tt = len - 1; tt >= 0; --tt) {
+            a.n = tt;
+            step(e, AAFWI_K_ADJ_STEP, a);
+        }
+    }
+    for (int i = 0; i < N; ++i) {
+        const InstHost& I = e->in[i];
+        const double inv_dt2 = 1.0 / ((double)I.dt * (double)I.dt);
+        aafwi::launch_fold(e->stream, I.g, (float)inv_dt2, I.GI, grad[i], e->active, i);
+    }
+}
+
+void residuals(Engine* e, const std::vector<const float*>& d, const std::vector<const float*>& dobs,
+               const std::vector<float*>& r) {
+    for (int i = 0; i < (int)e->in.size(); ++i) {
+        const InstHost& I = e->in[i];
+        aafwi::launch_residual_misfit(e->stream, (long long)I.S * I.nt * I.R, d[i], dobs[i], r[i], e->part, e->J + i,
+                                      e->active, i);
+    }
+}
+
+// True when m is bitwise the model of instance 0's kept checkpoints (synchronises).
+bool kept_model_is(Engine* e, const float* m) {
+    InstHost& I = e->in[0];
+    if (!I.have_ckpt) return false;
+    aafwi::launch_compare(e->stream, (long long)I.nz * I.nx, m, I.mkeep, e->same);
+    int v = 0;
+    AAFWI_HIP(hipMemcpyAsync(&v, e->same, sizeof(int), hipMemcpyDeviceToHost, e->stream));
+    AAFWI_HIP(hipStreamSynchronize(e->stream));
     return v == 1;
 }
 
-// Checkpointed backward pass for the residual r (the model is already in K).
-void run_backward(aafwi_ctx* c, const float* r, float* grad) {
-    aafwi::launch_zero(c->stream, c->L0, c->field);
-    aafwi::launch_zero(c->stream, c->L1, c->field);
-    aafwi::launch_zero(c->stream, c->GI, c->field);
-    float* lam1 = c->L0;  // lam^{n+1}
-    float* lam2 = c->L1;  // lam^{n+2}
-    const float h2 = c->h * c->h;
-    for (int j = c->nseg - 1; j >= 0; --j) {
-        const int n0 = j * c->k, n1 = std::min(n0 + c->k, c->nt);
-        // recompute u^{n0} .. u^{n1-1} from the checkpoint, storing q-hat^n
-        const float* cur = ckpt_slot(c, j, 0);
-        const float* prev = ckpt_slot(c, j, 1);
-        bool prev_is_ck = true;
-        float* work[2] = {c->F0, c->F1};
-        int wi = 0;
-        for (int n = n0; n < n1; ++n) {
-            float* out;
-            if (prev_is_ck) {
-                out = work[wi];
-                wi ^= 1;
-            } else {
-                out = const_cast<float*>(prev);
-            }
-            {
-                Timed t(c, AAFWI_K_REC_STEP);
-                aafwi::launch_rec_step(c->stream, c->gk[AAFWI_K_REC_STEP], c->K, cur, prev, out, c->wavelet[n], srcs(c),
-                                       c->qseg + (long long)(n - n0) * c->field);
-            }
-            prev_is_ck = (cur == ckpt_slot(c, j, 0) || cur == ckpt_slot(c, j, 1));
-            prev = cur;
-            cur = out;
-        }
-        // adjoint steps n1-1 .. n0 with imaging
-        for (int n = n1 - 1; n >= n0; --n) {
-            {
-                Timed t(c, AAFWI_K_ADJ_STEP);
-                aafwi::launch_adj_step(c->stream, c->gk[AAFWI_K_ADJ_STEP], c->K, lam1, lam2, lam2, maps(c), r, n, c->nt, h2,
-                                       c->qseg + (long long)(n - n0) * c->field, c->GI);
-            }
-            std::swap(lam1, lam2);
+int timing_enable(Engine* e, int every) {
+    AAFWI_HIP(hipStreamSynchronize(e->stream));
+    for (auto& v : e->ev) {
+        for (auto& x : v) e->ev_pool.push_back(x);
+        v.clear();
+    }
+    for (auto& l : e->launches) l = 0;
+    e->time_every = every;
+    if (every > 0) {
+        while (e->ev_pool.size() < 8192) {
+            hipEvent_t a, b;
+            AAFWI_HIP(hipEventCreate(&a));
+            AAFWI_HIP(hipEventCreate(&b));
+            e->ev_pool.emplace_back(a, b);
         }
     }
-    const double inv_dt2 = 1.0 / ((double)c->dt * (double)c->dt);
-    aafwi::launch_fold(c->stream, c->g, (float)inv_dt2, c->GI, grad);
+    return AAFWI_OK;
+}
+
+int timing_read(Engine* e, int id, double* mean_ms, int64_t* count) {
+    AAFWI_REQUIRE(mean_ms && count && id >= 0 && id < 4, "kernel_timing_read: bad argument");
+    AAFWI_HIP(hipStreamSynchronize(e->stream));
+    double tot = 0.0;
+    for (auto& x : e->ev[id]) {
+        float ms = 0.0f;
+        AAFWI_HIP(hipEventElapsedTime(&ms, x.first, x.second));
+        tot += ms;
+    }
+    *count = (int64_t)e->ev[id].size();
+    *mean_ms = e->ev[id].empty() ? 0.0 : tot / (double)e->ev[id].size();
+    return AAFWI_OK;
+}
+
+int set_tile(Engine* e, int kernel_id, int rows) {
+    AAFWI_REQUIRE(rows >= 0 && rows <= 64, "set_tile: rows per wave must be in [0, 64]");
+    AAFWI_REQUIRE(kernel_id >= -1 && kernel_id < 4, "set_tile: kernel_id must be -1 or a kernel id");
+    AAFWI_HIP(hipStreamSynchronize(e->stream));
+    for (int k = 0; k < 4; ++k)
+        if (kernel_id == -1 || kernel_id == k) {
+            e->tz[k] = rows;
+            build_tiles(e, k);
+        }
+    for (auto& kv : e->graphs) (void)hipGraphExecDestroy(kv.second);
+    e->graphs.clear();
+    return AAFWI_OK;
+}
+
+// Run `body` directly, or (graphs on) capture it once under `key` and replay.
+template <typename F>
+void maybe_graph(Engine* e, int key, F&& body) {
+    if (!e->use_graphs) {
+        body();
+        return;
+    }
+    auto it = e->graphs.find(key);
+    if (it == e->graphs.end()) {
+        hipGraph_t graph = nullptr;
+        AAFWI_HIP(hipStreamBeginCapture(e->stream, hipStreamCaptureModeThreadLocal));
+        e->capturing = true;
+        try {
+            body();
+        } catch (...) {
+            e->capturing = false;
+            hipGraph_t g2 = nullptr;
+            (void)hipStreamEndCapture(e->stream, &g2);
+            if (g2) (void)hipGraphDestroy(g2);
+            throw;
+        }
+        e->capturing = false;
+        AAFWI_HIP(hipStreamEndCapture(e->stream, &graph));
+        hipGraphExec_t exec = nullptr;
+        const hipError_t err = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        AAFWI_HIP(err);
+        it = e->graphs.emplace(key, exec).first;
+    }
+    AAFWI_HIP(hipGraphLaunch(it->second, e->stream));
 }
 
 }  // namespace
+
+// ---------------------------------------------------------------------------
+// single context
+// ---------------------------------------------------------------------------
+struct aafwi_ctx {
+    Engine* e = nullptr;
+};
 
 extern "C" const char* aafwi_last_error(void) { return aafwi::g_last_error.c_str(); }
 
@@ -247,119 +506,18 @@ extern "C" int aafwi_create(const aafwi_geometry* gp, aafwi_stream stream, aafwi
     return guarded([&]() -> int {
         AAFWI_REQUIRE(gp != nullptr && out != nullptr, "create: NULL argument");
         *out = nullptr;
-        const aafwi_geometry& G = *gp;
-        AAFWI_REQUIRE(G.nz >= 1 && G.nx >= 1, "create: nz and nx must be >= 1");
-        AAFWI_REQUIRE(G.nb >= 1 && G.nb <= 4096, "create: nb must be in [1, 4096]");
-        AAFWI_REQUIRE(G.nt >= 1, "create: nt must be >= 1");
-        AAFWI_REQUIRE(G.nshots >= 1 && G.nrec >= 1, "create: nshots and nrec must be >= 1");
-        AAFWI_REQUIRE(std::isfinite(G.h) && G.h > 0 && std::isfinite(G.dt) && G.dt > 0,
-                      "create: h and dt must be positive");
-        AAFWI_REQUIRE(std::isfinite(G.vref) && G.vref > 0, "create: vref must be positive");
-        AAFWI_REQUIRE(std::isfinite(G.refl) && G.refl > 0, "create: refl must be positive");
-        AAFWI_REQUIRE(std::isfinite(G.vmax_bound) && G.vmax_bound > 0, "create: vmax_bound must be positive");
-        AAFWI_REQUIRE(G.src_iz && G.src_ix && G.rec_iz && G.rec_ix && G.wavelet, "create: NULL geometry array");
-        AAFWI_REQUIRE(G.ckpt_every >= 0, "create: ckpt_every must be >= 0");
-        const double cfl = (double)G.vmax_bound * G.dt / G.h;
-        if (cfl > 0.55)
-            throw Error{AAFWI_E_CFL, "create: vmax_bound*dt/h = " + std::to_string(cfl) + " exceeds 0.55"};
-        const long long nzp = (long long)G.nz + 2LL * G.nb, nxp = (long long)G.nx + 2LL * G.nb;
-        // byte offsets of a plane (plus 16 rows of slack) must stay below 2^31
-        AAFWI_REQUIRE(4LL * (nzp + 16) * ((nxp + 63) / 64 * 64) < (1LL << 31), "create: padded plane too large");
-        for (int s = 0; s < G.nshots; ++s) {
-            AAFWI_REQUIRE(G.src_iz[s] >= 0 && G.src_iz[s] < G.nz && G.src_ix[s] >= 0 && G.src_ix[s] < G.nx,
-                          "create: source index outside the interior grid");
-        }
-        for (long long i = 0; i < (long long)G.nshots * G.nrec; ++i) {
-            AAFWI_REQUIRE(G.rec_iz[i] >= 0 && G.rec_iz[i] < G.nz && G.rec_ix[i] >= 0 && G.rec_ix[i] < G.nx,
-                          "create: receiver index outside the interior grid");
-        }
-        for (int n = 0; n < G.nt; ++n)
-            AAFWI_REQUIRE(std::isfinite(G.wavelet[n]), "create: wavelet must be finite");
-
-        aafwi_ctx* c = new aafwi_ctx{};
+        validate_geometry(*gp);
+        Engine* e = new Engine{};
         try {
-            c->nz = G.nz; c->nx = G.nx; c->nb = G.nb; c->nt = G.nt;
-            c->S = G.nshots; c->R = G.nrec;
-            c->h = G.h; c->dt = G.dt; c->vref = G.vref; c->refl = G.refl; c->vmax = G.vmax_bound;
-            c->k = G.ckpt_every > 0 ? std::min(G.ckpt_every, G.nt) : std::min(50, G.nt);
-            c->nseg = (G.nt + c->k - 1) / c->k;
-            c->wavelet.assign(G.wavelet, G.wavelet + G.nt);
-            c->stream = (hipStream_t)stream;
-
-            aafwi::WaveGrid& g = c->g;
-            g.nz = G.nz; g.nx = G.nx; g.nb = G.nb;
-            g.nzp = (int)nzp; g.nxp = (int)nxp;
-            g.pitch = (int)((nxp + 63) / 64 * 64);
-            g.plane = (long long)g.nzp * g.pitch;
-            g.S = G.nshots;
-            g.ntx = g.pitch / 64;
-            g.tz = 0;
-            const double smax = (G.refl >= 1.0f) ? 0.0
-                                                  : 3.0 * G.vref * std::log(1.0 / (double)G.refl) / (2.0 * G.nb * G.h);
-            g.scoef = (float)(smax * G.dt / 2.0);
-            g.inv_nb = (float)(1.0 / G.nb);
-            c->field = (long long)g.S * g.plane;
-            apply_tile(g, 0);
-            for (auto& gk : c->gk) gk = g;
-
-            // receiver maps
-            std::vector<int> rowmap((size_t)g.S * g.nzp, -1);
-            std::vector<int> nrows(g.S, 0);
-            for (int s = 0; s < g.S; ++s)
-                for (int r = 0; r < G.nrec; ++r) {
-                    const int zp = G.rec_iz[(long long)s * G.nrec + r] + G.nb;
-                    int& slot = rowmap[(size_t)s * g.nzp + zp];
-                    if (slot < 0) slot = nrows[s]++;
-                }
-            c->nrr = *std::max_element(nrows.begin(), nrows.end());
-            std::vector<int> xmap((size_t)g.S * c->nrr * g.pitch, -1);
-            std::vector<int> rnext((size_t)g.S * G.nrec, -1);
-            for (int s = 0; s < g.S; ++s)
-                for (int r = G.nrec - 1; r >= 0; --r) {
-                    const long long i = (long long)s * G.nrec + r;
-                    const int zp = G.rec_iz[i] + G.nb, xp = G.rec_ix[i] + G.nb;
-                    const int slot = rowmap[(size_t)s * g.nzp + zp];
-                    int& head = xmap[((size_t)s * c->nrr + slot) * g.pitch + xp];
-                    rnext[i] = head;  // chain (ascending receiver order)
-                    head = r;
-                }
-            std::vector<int2> src(g.S);
-            for (int s = 0; s < g.S; ++s) src[s] = make_int2(G.src_iz[s] + G.nb, G.src_ix[s] + G.nb);
-
-            dalloc(c, (void**)&c->K, sizeof(float) * g.plane);
-            dalloc(c, (void**)&c->E, sizeof(float) * g.plane);
-            dalloc(c, (void**)&c->F0, sizeof(float) * c->field);
-            dalloc(c, (void**)&c->F1, sizeof(float) * c->field);
-            dalloc(c, (void**)&c->L0, sizeof(float) * c->field);
-            dalloc(c, (void**)&c->L1, sizeof(float) * c->field);
-            dalloc(c, (void**)&c->GI, sizeof(float) * c->field);
-            dalloc(c, (void**)&c->ckpt, sizeof(float) * (size_t)c->field * 2 * c->nseg);
-            dalloc(c, (void**)&c->qseg, sizeof(float) * (size_t)c->field * c->k);
-            dalloc(c, (void**)&c->dwork, sizeof(float) * (size_t)g.S * G.nt * G.nrec);
-            dalloc(c, (void**)&c->part, sizeof(double) * aafwi::kReduceBlocks);
-            dalloc(c, (void**)&c->flag, sizeof(int));
-            dalloc(c, (void**)&c->mkeep, sizeof(float) * (size_t)G.nz * G.nx);
-            dalloc(c, (void**)&c->same, sizeof(int));
-            dalloc(c, (void**)&c->src, sizeof(int2) * g.S);
-            dalloc(c, (void**)&c->rowmap, sizeof(int) * rowmap.size());
-            dalloc(c, (void**)&c->xmap, sizeof(int) * xmap.size());
-            dalloc(c, (void**)&c->rnext, sizeof(int) * rnext.size());
-            AAFWI_HIP(hipMemcpy(c->src, src.data(), sizeof(int2) * g.S, hipMemcpyHostToDevice));
-            AAFWI_HIP(hipMemcpy(c->rowmap, rowmap.data(), sizeof(int) * rowmap.size(), hipMemcpyHostToDevice));
-            AAFWI_HIP(hipMemcpy(c->xmap, xmap.data(), sizeof(int) * xmap.size(), hipMemcpyHostToDevice));
-            AAFWI_HIP(hipMemcpy(c->rnext, rnext.data(), sizeof(int) * rnext.size(), hipMemcpyHostToDevice));
-            AAFWI_HIP(hipMemset(c->flag, 0, sizeof(int)));
-            // padding columns of every field stay zero forever
-            AAFWI_HIP(hipMemset(c->F0, 0, sizeof(float) * c->field));
-            AAFWI_HIP(hipMemset(c->F1, 0, sizeof(float) * c->field));
-            AAFWI_HIP(hipMemset(c->L0, 0, sizeof(float) * c->field));
-            AAFWI_HIP(hipMemset(c->L1, 0, sizeof(float) * c->field));
-            AAFWI_HIP(hipDeviceSynchronize());
+            e->stream = (hipStream_t)stream;
+            e->k = gp->ckpt_every > 0 ? std::min(gp->ckpt_every, gp->nt) : std::min(50, gp->nt);
+            add_instance(e, *gp, nullptr);
+            finalize(e);
         } catch (...) {
-            free_ctx(c);
+            free_engine(e);
             throw;
         }
-        *out = c;
+        *out = new aafwi_ctx{e};
         return AAFWI_OK;
     });
 }
@@ -367,8 +525,9 @@ extern "C" int aafwi_create(const aafwi_geometry* gp, aafwi_stream stream, aafwi
 extern "C" int aafwi_destroy(aafwi_ctx* c) {
     return guarded([&]() -> int {
         if (!c) return AAFWI_OK;
-        (void)hipStreamSynchronize(c->stream);
-        free_ctx(c);
+        (void)hipStreamSynchronize(c->e->stream);
+        free_engine(c->e);
+        delete c;
         return AAFWI_OK;
     });
 }
@@ -376,7 +535,7 @@ extern "C" int aafwi_destroy(aafwi_ctx* c) {
 extern "C" int aafwi_device_bytes(const aafwi_ctx* c, int64_t* bytes) {
     return guarded([&]() -> int {
         AAFWI_REQUIRE(c && bytes, "device_bytes: NULL argument");
-        *bytes = c->bytes;
+        *bytes = c->e->bytes;
         return AAFWI_OK;
     });
 }
@@ -384,11 +543,12 @@ extern "C" int aafwi_device_bytes(const aafwi_ctx* c, int64_t* bytes) {
 extern "C" int aafwi_sync(aafwi_ctx* c) {
     return guarded([&]() -> int {
         AAFWI_REQUIRE(c, "sync: NULL context");
-        AAFWI_HIP(hipStreamSynchronize(c->stream));
+        Engine* e = c->e;
+        AAFWI_HIP(hipStreamSynchronize(e->stream));
         int f = 0;
-        AAFWI_HIP(hipMemcpy(&f, c->flag, sizeof(int), hipMemcpyDeviceToHost));
+        AAFWI_HIP(hipMemcpy(&f, e->flag, sizeof(int), hipMemcpyDeviceToHost));
         if (f) {
-            AAFWI_HIP(hipMemset(c->flag, 0, sizeof(int)));
+            AAFWI_HIP(hipMemset(e->flag, 0, sizeof(int)));
             throw Error{AAFWI_E_NONFINITE, "a model value was non-positive or non-finite"};
         }
         return AAFWI_OK;
@@ -397,10 +557,8 @@ extern "C" int aafwi_sync(aafwi_ctx* c) {
 
 extern "C" int aafwi_forward_model(aafwi_ctx* c, const float* m, float* d, int keep_ckpt) {
     return guarded([&]() -> int {
-        AAFWI_REQUIRE(c, "forward_model: NULL context");
-        check_m(c, m, "forward_model: m");
-        check_m(c, d, "forward_model: d");
-        run_forward(c, m, d, keep_ckpt != 0);
+        AAFWI_REQUIRE(c && m && d, "forward_model: NULL argument");
+        run_forward(c->e, {m}, d, keep_ckpt != 0);
         return AAFWI_OK;
     });
 }
@@ -408,7 +566,9 @@ extern "C" int aafwi_forward_model(aafwi_ctx* c, const float* m, float* d, int k
 extern "C" int aafwi_residual_misfit(aafwi_ctx* c, const float* d, const float* d_obs, float* r, double* J) {
     return guarded([&]() -> int {
         AAFWI_REQUIRE(c && d && d_obs && r && J, "residual_misfit: NULL argument");
-        aafwi::launch_residual_misfit(c->stream, (long long)c->S * c->nt * c->R, d, d_obs, r, c->part, J);
+        const InstHost& I = c->e->in[0];
+        aafwi::launch_residual_misfit(c->e->stream, (long long)I.S * I.nt * I.R, d, d_obs, r, c->e->part, J, nullptr,
+                                      0);
         return AAFWI_OK;
     });
 }
@@ -416,10 +576,11 @@ extern "C" int aafwi_residual_misfit(aafwi_ctx* c, const float* d, const float* 
 extern "C" int aafwi_adjoint_gradient(aafwi_ctx* c, const float* m, const float* d_obs, float* grad, double* J) {
     return guarded([&]() -> int {
         AAFWI_REQUIRE(c && m && d_obs && grad && J, "adjoint_gradient: NULL argument");
-        run_forward(c, m, c->dwork, true);
-        aafwi::launch_residual_misfit(c->stream, (long long)c->S * c->nt * c->R, c->dwork, d_obs, c->dwork, c->part,
-                                      J);
-        run_backward(c, c->dwork, grad);
+        Engine* e = c->e;
+        InstHost& I = e->in[0];
+        run_forward(e, {m}, I.d, true);
+        aafwi::launch_residual_misfit(e->stream, (long long)I.S * I.nt * I.R, I.d, d_obs, I.d, e->part, J, nullptr, 0);
+        run_backward(e, I.d, {grad});
         return AAFWI_OK;
     });
 }
@@ -427,10 +588,9 @@ extern "C" int aafwi_adjoint_gradient(aafwi_ctx* c, const float* m, const float*
 extern "C" int aafwi_adjoint_from_residual(aafwi_ctx* c, const float* r, float* grad) {
     return guarded([&]() -> int {
         AAFWI_REQUIRE(c && r && grad, "adjoint_from_residual: NULL argument");
-        if (!c->have_ckpt)
+        if (!c->e->in[0].have_ckpt)
             throw Error{AAFWI_E_STATE, "adjoint_from_residual: no kept checkpoints (call forward_model with keep_ckpt=1)"};
-        model_prep(c, c->mkeep);  // Kp of the kept run (a Born call may have replaced it)
-        run_backward(c, r, grad);
+        run_backward(c->e, r, {grad});
         return AAFWI_OK;
     });
 }
@@ -438,22 +598,19 @@ extern "C" int aafwi_adjoint_from_residual(aafwi_ctx* c, const float* r, float* 
 extern "C" int aafwi_born(aafwi_ctx* c, const float* m0, const float* dm, float* d_scat) {
     return guarded([&]() -> int {
         AAFWI_REQUIRE(c && m0 && dm && d_scat, "born: NULL argument");
+        Engine* e = c->e;
+        InstHost& I = e->in[0];
         // the kept checkpoints are untouched; Kp is rebuilt before any backward pass
-        model_prep(c, m0);
-        aafwi::launch_born_prep(c->stream, c->g, m0, dm, c->E);
-        aafwi::launch_zero(c->stream, c->F0, c->field);
-        aafwi::launch_zero(c->stream, c->F1, c->field);
-        aafwi::launch_zero(c->stream, c->L0, c->field);
-        aafwi::launch_zero(c->stream, c->L1, c->field);
-        float *u = c->F0, *up = c->F1, *du = c->L0, *dup = c->L1;
-        for (int n = 0; n < c->nt; ++n) {
-            {
-                Timed t(c, AAFWI_K_BORN_STEP);
-                aafwi::launch_born_step(c->stream, c->gk[AAFWI_K_BORN_STEP], c->K, c->E, u, up, up, du, dup, dup, c->wavelet[n], srcs(c),
-                                        maps(c), d_scat, n, c->nt);
-            }
-            std::swap(u, up);
-            std::swap(du, dup);
+        model_prep(e, 0, m0);
+        aafwi::launch_born_prep(e->stream, I.g, m0, dm, I.E);
+        aafwi::launch_zero(e->stream, I.F0, I.field);
+        aafwi::launch_zero(e->stream, I.F1, I.field);
+        aafwi::launch_zero(e->stream, I.L0, I.field);
+        aafwi::launch_zero(e->stream, I.L1, I.field);
+        aafwi::StepArgs a{0, 0, 0, d_scat, nullptr, nullptr};
+        for (int n = 0; n < I.nt; ++n) {
+            a.n = n;
+            step(e, AAFWI_K_BORN_STEP, a);
         }
         return AAFWI_OK;
     });
@@ -462,12 +619,9 @@ extern "C" int aafwi_born(aafwi_ctx* c, const float* m0, const float* dm, float*
 extern "C" int aafwi_born_adjoint(aafwi_ctx* c, const float* m0, const float* y, float* image) {
     return guarded([&]() -> int {
         AAFWI_REQUIRE(c && m0 && y && image, "born_adjoint: NULL argument");
-        if (kept_model_is(c, m0)) {
-            model_prep(c, m0);  // background forward already checkpointed
-        } else {
-            run_forward(c, m0, c->dwork, true);
-        }
-        run_backward(c, y, image);
+        Engine* e = c->e;
+        if (!kept_model_is(e, m0)) run_forward(e, {m0}, e->in[0].d, true);
+        run_backward(e, y, {image});
         return AAFWI_OK;
     });
 }
@@ -475,55 +629,179 @@ extern "C" int aafwi_born_adjoint(aafwi_ctx* c, const float* m0, const float* y,
 extern "C" int aafwi_kernel_timing(aafwi_ctx* c, int every) {
     return guarded([&]() -> int {
         AAFWI_REQUIRE(c && every >= 0, "kernel_timing: bad argument");
-        AAFWI_HIP(hipStreamSynchronize(c->stream));
-        for (auto& v : c->ev) {
-            for (auto& e : v) c->ev_pool.push_back(e);
-            v.clear();
-        }
-        for (auto& l : c->launches) l = 0;
-        c->time_every = every;
-        if (every > 0) {
-            while (c->ev_pool.size() < 8192) {
-                hipEvent_t a, b;
-                AAFWI_HIP(hipEventCreate(&a));
-                AAFWI_HIP(hipEventCreate(&b));
-                c->ev_pool.emplace_back(a, b);
-            }
-        }
-        return AAFWI_OK;
+        return timing_enable(c->e, every);
     });
 }
 
 extern "C" int aafwi_kernel_timing_read(aafwi_ctx* c, int id, double* mean_ms, int64_t* count) {
     return guarded([&]() -> int {
-        AAFWI_REQUIRE(c && mean_ms && count && id >= 0 && id < 4, "kernel_timing_read: bad argument");
-        AAFWI_HIP(hipStreamSynchronize(c->stream));
-        double tot = 0.0;
-        for (auto& e : c->ev[id]) {
-            float ms = 0.0f;
-            AAFWI_HIP(hipEventElapsedTime(&ms, e.first, e.second));
-            tot += ms;
-        }
-        *count = (int64_t)c->ev[id].size();
-        *mean_ms = c->ev[id].empty() ? 0.0 : tot / (double)c->ev[id].size();
-        return AAFWI_OK;
+        AAFWI_REQUIRE(c, "kernel_timing_read: NULL context");
+        return timing_read(c->e, id, mean_ms, count);
     });
 }
 
 extern "C" int aafwi_set_tile(aafwi_ctx* c, int32_t kernel_id, int32_t rows) {
     return guarded([&]() -> int {
-        AAFWI_REQUIRE(c && rows >= 0 && rows <= 64, "set_tile: rows per wave must be in [0, 64]");
-        AAFWI_REQUIRE(kernel_id >= -1 && kernel_id < 4, "set_tile: kernel_id must be -1 or a kernel id");
-        for (int k = 0; k < 4; ++k)
-            if (kernel_id == -1 || kernel_id == k) apply_tile(c->gk[k], rows);
-        return AAFWI_OK;
+        AAFWI_REQUIRE(c, "set_tile: NULL context");
+        return set_tile(c->e, kernel_id, rows);
     });
 }
 
 extern "C" int aafwi_get_tile(const aafwi_ctx* c, int32_t kernel_id, int32_t* rows) {
     return guarded([&]() -> int {
         AAFWI_REQUIRE(c && rows && kernel_id >= 0 && kernel_id < 4, "get_tile: bad argument");
-        *rows = c->gk[kernel_id].tz;
+        const int tz = c->e->tz[kernel_id];
+        *rows = std::min(tz ? tz : default_tz(c->e->in[0].g.nzp), c->e->in[0].g.nzp);
         return AAFWI_OK;
+    });
+}
+
+// ---------------------------------------------------------------------------
+// batches of uneven instances
+// ---------------------------------------------------------------------------
+struct aafwi_batch {
+    Engine* e = nullptr;
+};
+
+namespace {
+std::vector<const float*> batch_m(Engine* e) {
+    std::vector<const float*> v;
+    for (auto& I : e->in) v.push_back(I.m);
+    return v;
+}
+}  // namespace
+
+extern "C" int aafwi_batch_create(const aafwi_geometry* geoms, const aafwi_batch_io* io, int32_t ninst,
+                                  int32_t ckpt_every, aafwi_stream stream, aafwi_batch** out) {
+    return guarded([&]() -> int {
+        AAFWI_REQUIRE(geoms && io && out && ninst >= 1, "batch_create: bad argument");
+        for (int i = 0; i < ninst; ++i)
+            AAFWI_REQUIRE(io[i].m && io[i].d_obs && io[i].r && io[i].grad, "batch_create: NULL instance buffer");
+        AAFWI_REQUIRE(ckpt_every >= 0, "batch_create: ckpt_every must be >= 0");
+        *out = nullptr;
+        int ntmax = 0;
+        for (int i = 0; i < ninst; ++i) {
+            validate_geometry(geoms[i]);
+            ntmax = std::max(ntmax, geoms[i].nt);
+        }
+        Engine* e = new Engine{};
+        try {
+            e->stream = (hipStream_t)stream;
+            e->is_batch = true;
+            e->k = ckpt_every > 0 ? std::min(ckpt_every, ntmax) : std::min(50, ntmax);
+            for (int i = 0; i < ninst; ++i) add_instance(e, geoms[i], &io[i]);
+            finalize(e);
+        } catch (...) {
+            free_engine(e);
+            throw;
+        }
+        *out = new aafwi_batch{e};
+        return AAFWI_OK;
+    });
+}
+
+extern "C" int aafwi_batch_destroy(aafwi_batch* b) {
+    return guarded([&]() -> int {
+        if (!b) return AAFWI_OK;
+        (void)hipStreamSynchronize(b->e->stream);
+        free_engine(b->e);
+        delete b;
+        return AAFWI_OK;
+    });
+}
+
+extern "C" int aafwi_batch_misfits(aafwi_batch* b, double* J) {
+    return guarded([&]() -> int {
+        AAFWI_REQUIRE(b && J, "batch_misfits: NULL argument");
+        AAFWI_HIP(hipMemcpyAsync(J, b->e->J, sizeof(double) * b->e->in.size(), hipMemcpyDeviceToDevice, b->e->stream));
+        return AAFWI_OK;
+    });
+}
+
+extern "C" int aafwi_batch_set_active(aafwi_batch* b, const uint8_t* active) {
+    return guarded([&]() -> int {
+        AAFWI_REQUIRE(b, "batch_set_active: NULL batch");
+        const int N = (int)b->e->in.size();
+        std::vector<int> v(N, 1);
+        if (active)
+            for (int i = 0; i < N; ++i) v[i] = active[i] ? 1 : 0;
+        AAFWI_HIP(hipStreamSynchronize(b->e->stream));
+        AAFWI_HIP(hipMemcpy(b->e->active, v.data(), sizeof(int) * N, hipMemcpyHostToDevice));
+        b->e->active_host = v;
+        return AAFWI_OK;
+    });
+}
+
+extern "C" int aafwi_batch_forward(aafwi_batch* b, int keep_ckpt) {
+    return guarded([&]() -> int {
+        AAFWI_REQUIRE(b, "batch_forward: NULL batch");
+        Engine* e = b->e;
+        maybe_graph(e, keep_ckpt ? 1 : 0, [&]() {
+            run_forward(e, batch_m(e), nullptr, keep_ckpt != 0);
+            std::vector<const float*> d, dobs;
+            std::vector<float*> r;
+            for (auto& I : e->in) {
+                d.push_back(I.d);
+                dobs.push_back(I.dobs);
+                r.push_back(I.d);
+            }
+            residuals(e, d, dobs, r);
+        });
+        return AAFWI_OK;
+    });
+}
+
+extern "C" int aafwi_batch_backward(aafwi_batch* b) {
+    return guarded([&]() -> int {
+        AAFWI_REQUIRE(b, "batch_backward: NULL batch");
+        Engine* e = b->e;
+        for (int i = 0; i < (int)e->in.size(); ++i)
+            if (e->active_host[i] && !e->in[i].have_ckpt)
+                throw Error{AAFWI_E_STATE, "batch_backward: an active instance has no kept checkpoints"};
+        maybe_graph(e, 2, [&]() {
+            std::vector<float*> grad;
+            for (auto& I : e->in) grad.push_back(I.grad);
+            run_backward(e, nullptr, grad);
+        });
+        return AAFWI_OK;
+    });
+}
+
+extern "C" int aafwi_batch_use_graphs(aafwi_batch* b, int enable) {
+    return guarded([&]() -> int {
+        AAFWI_REQUIRE(b, "batch_use_graphs: NULL batch");
+        AAFWI_REQUIRE(!enable || b->e->stream != nullptr, "batch_use_graphs: graph capture needs a non-null stream");
+        AAFWI_HIP(hipStreamSynchronize(b->e->stream));
+        b->e->use_graphs = enable != 0;
+        return AAFWI_OK;
+    });
+}
+
+extern "C" int aafwi_batch_device_bytes(const aafwi_batch* b, int64_t* bytes) {
+    return guarded([&]() -> int {
+        AAFWI_REQUIRE(b && bytes, "batch_device_bytes: NULL argument");
+        *bytes = b->e->bytes;
+        return AAFWI_OK;
+    });
+}
+
+extern "C" int aafwi_batch_set_tile(aafwi_batch* b, int32_t kernel_id, int32_t rows) {
+    return guarded([&]() -> int {
+        AAFWI_REQUIRE(b, "batch_set_tile: NULL batch");
+        return set_tile(b->e, kernel_id, rows);
+    });
+}
+
+extern "C" int aafwi_batch_kernel_timing(aafwi_batch* b, int every) {
+    return guarded([&]() -> int {
+        AAFWI_REQUIRE(b && every >= 0, "batch_kernel_timing: bad argument");
+        return timing_enable(b->e, every);
+    });
+}
+
+extern "C" int aafwi_batch_kernel_timing_read(aafwi_batch* b, int id, double* mean_ms, int64_t* count) {
+    return guarded([&]() -> int {
+        AAFWI_REQUIRE(b, "batch_kernel_timing_read: NULL batch");
+        return timing_read(b->e, id, mean_ms, count);
     });
 }

@@ -62,28 +62,65 @@ struct SrcNodes {
     const int2* node;
 };
 
+// One inversion instance (one geometry, all of its shots) as the stepping
+// kernels see it: a device-resident table entry read with scalar loads.
+struct Inst {
+    WaveGrid g;
+    const float* K;        // Kp on the padded grid [plane]
+    const float* E;        // Born perturbation dm/m0 [plane]
+    float* F0;             // forward (or background) pair [S][plane]
+    float* F1;
+    float* L0;             // adjoint (or scattered) pair [S][plane]
+    float* L1;
+    float* GI;             // image accumulators [S][plane]
+    float* ckpt;           // [nseg][2][S][plane]
+    float* qseg;           // [k][S][plane]
+    float* d;              // sampling target [S][nt][R] (instance-owned)
+    const float* r;        // adjoint source [S][nt][R] (instance-owned)
+    const float* wav;      // source wavelet [nt]
+    SrcNodes src;
+    RecMaps rm;
+    int nt, nseg, k;
+    float h2;
+    long long field;       // S * plane floats
+};
+
+// One wave's work: 64 columns from x0, rows [z0, z1) of shot s of instance
+// inst.  z01 packs z0 << 16 | z1.
+struct TileRec {
+    int inst, s, x0, z01;
+};
+
+// Per-launch step selection.  Forward and Born: n is the time step.
+// Recompute and adjoint: seg counts segments from the end of each instance's
+// record and n is the step inside the segment.  Instances derive their own
+// step index, buffer parity and checkpoint slot from these, so instances with
+// different record lengths share one launch.
+struct StepArgs {
+    int n;
+    int seg;
+    int keep;              // forward: copy (u^n, u^{n-1}) to the checkpoint slot
+    float* d_ovr;          // if set: sampling target for every instance (single context)
+    const float* r_ovr;    // if set: adjoint source for every instance (single context)
+    const int* active;     // per-instance mask (NULL = all active)
+};
+
 // Launchers (wave_kernels.hip).
 void launch_model_prep(hipStream_t st, const WaveGrid& g, float c2, const float* m, float* K,
-                       int* flag);
+                       int* flag, const int* active, int inst);
 void launch_born_prep(hipStream_t st, const WaveGrid& g, const float* m0, const float* dm,
                       float* E);
 void launch_zero(hipStream_t st, float* p, long long n);
 void launch_compare(hipStream_t st, long long n, const float* a, const float* b, int* same);
-void launch_fwd_step(hipStream_t st, const WaveGrid& g, const float* K, const float* u,
-                     const float* uprev, float* out, float w, SrcNodes src, RecMaps rm,
-                     float* d, int n, int nt, float* ck_u, float* ck_um);
-void launch_rec_step(hipStream_t st, const WaveGrid& g, const float* K, const float* u,
-                     const float* uprev, float* out, float w, SrcNodes src, float* q);
-void launch_adj_step(hipStream_t st, const WaveGrid& g, const float* K, const float* l,
-                     const float* lprev, float* out, RecMaps rm, const float* r, int n, int nt,
-                     float h2, const float* q, float* gimg);
-void launch_born_step(hipStream_t st, const WaveGrid& g, const float* K, const float* E,
-                      const float* u, const float* uprev, float* uout, const float* du,
-                      const float* duprev, float* duout, float w, SrcNodes src, RecMaps rm,
-                      float* d, int n, int nt);
-void launch_fold(hipStream_t st, const WaveGrid& g, float inv_dt2, const float* gimg, float* grad);
+// Stepping kernels over a tile table (kernel ids as AAFWI_K_*).
+void launch_step(int kernel_id, hipStream_t st, const TileRec* tiles, int ntiles, const Inst* insts,
+                 const StepArgs& a);
+// Per-instance kernels; `active`/`inst` make them no-ops for masked instances.
+void launch_fold(hipStream_t st, const WaveGrid& g, float inv_dt2, const float* gimg, float* grad,
+                 const int* active, int inst);
 void launch_residual_misfit(hipStream_t st, long long n, const float* d, const float* dobs,
-                            float* r, double* partials, double* J);
+                            float* r, double* partials, double* J, const int* active, int inst);
+void launch_copy(hipStream_t st, long long n, const float* src, float* dst, const int* active, int inst);
 
 // Vector kernels (aa_kernels.hip).
 void launch_dot(hipStream_t st, long long n, const float* x, const float* y, const float* z,

@@ -52,25 +52,26 @@ __device__ __forceinline__ float sponge_st(int i, int n_int, int nb, float inv_n
 }
 
 struct Tile {
-    int s, x0, z0, z1, lane;
+    int inst, s, x0, z0, z1, lane;
     bool live;
 };
 
-__device__ __forceinline__ Tile decode_tile(const WaveGrid& g) {
+// The wave's entry of the tile table (wave-uniform, read with scalar loads).
+__device__ __forceinline__ Tile decode_tile(const TileRec* __restrict__ tiles, int ntiles) {
     Tile t;
-    const int lane = threadIdx.x & 63;
+    t.lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const int tile = __builtin_amdgcn_readfirstlane(blk * kWaves + wave);
-    t.live = tile < g.ntiles;
-    const int tx = tile % g.ntx;
-    const int rest = tile / g.ntx;
-    const int zs = rest % g.nzs;
-    t.s = rest / g.nzs;
-    t.x0 = tx * 64;
-    t.z0 = zs * g.tz;
-    t.z1 = min(t.z0 + g.tz, g.nzp);
-    t.lane = lane;
+    t.live = tile < ntiles;
+    if (!t.live) return t;
+    const TileRec r = tiles[tile];
+    t.inst = __builtin_amdgcn_readfirstlane(r.inst);
+    t.s = __builtin_amdgcn_readfirstlane(r.s);
+    t.x0 = __builtin_amdgcn_readfirstlane(r.x0);
+    const int z01 = __builtin_amdgcn_readfirstlane(r.z01);
+    t.z0 = z01 >> 16;
+    t.z1 = z01 & 0xffff;
     return t;
 }
 
@@ -226,29 +227,66 @@ __device__ __forceinline__ int strip_rowmap(const RecMaps& rm, const WaveGrid& g
 // forward step (sampling, optional checkpoint copy) and recompute step (q out)
 // ---------------------------------------------------------------------------
 template <int U, bool kRecompute>
-__global__ __launch_bounds__(256) void k_fwd_step(WaveGrid g, const float* __restrict__ K,
-                                                  const float* __restrict__ u, const float* uprev,
-                                                  float* out, float w, SrcNodes src, RecMaps rm,
-                                                  float* __restrict__ d, int n, int nt,
-                                                  float* __restrict__ ck_u,
-                                                  float* __restrict__ ck_um,
-                                                  float* __restrict__ q) {
+__global__ __launch_bounds__(256) void k_fwd_step(const TileRec* __restrict__ tiles, int ntiles,
+                                                  const Inst* __restrict__ insts, StepArgs a) {
     __shared__ float lds[kWaves][U * 72];
-    const Tile t = decode_tile(g);
+    const Tile t = decode_tile(tiles, ntiles);
     if (!t.live) return;
+    if (a.active && !a.active[t.inst]) return;
+    const Inst& I = insts[t.inst];
+    const WaveGrid g = I.g;
+    // step index, buffers and checkpoint slot of this instance
+    int n;
+    const float* u;
+    const float* uprev;
+    float* out;
+    float* ck_u = nullptr;
+    float* q = nullptr;
+    if (!kRecompute) {
+        n = a.n;
+        if (n >= I.nt) return;
+        u = (n & 1) ? I.F1 : I.F0;  // u^n
+        out = (n & 1) ? I.F0 : I.F1;  // u^{n-1}, overwritten by u^{n+1}
+        uprev = out;
+        if (a.keep && n % I.k == 0) ck_u = I.ckpt + (long long)(n / I.k) * 2 * I.field;
+    } else {
+        const int j = I.nseg - 1 - a.seg;  // segment being recomputed
+        const int tt = a.n;
+        n = j * I.k + tt;
+        if (j < 0 || n >= I.nt) return;
+        const float* c0 = I.ckpt + (long long)j * 2 * I.field;  // u^{jk}
+        if (tt == 0) {
+            u = c0;
+            uprev = c0 + I.field;
+            out = I.F0;
+        } else if (tt == 1) {
+            u = I.F0;
+            uprev = c0;
+            out = I.F1;
+        } else {
+            u = (tt & 1) ? I.F0 : I.F1;
+            out = (tt & 1) ? I.F1 : I.F0;
+            uprev = out;
+        }
+        q = I.qseg + (long long)tt * I.field;
+    }
+    const float w = I.wav[n];
+    const int nt = I.nt;
+    const RecMaps rm = I.rm;
+    float* d = a.d_ovr ? a.d_ovr : I.d;
     const int lane = t.lane;
     float* rows = &lds[threadIdx.x >> 6][0];
     const long long off0 = (long long)t.s * g.plane;
     const Rsrc UR = view(u + off0, g.plane);
     const Rsrc UP = view(uprev + off0, g.plane);
     const Rsrc O = view(out + off0, g.plane);
-    const Rsrc KR = view(K, g.plane);
+    const Rsrc KR = view(I.K, g.plane);
     const bool ck = ck_u != nullptr;
     const Rsrc CU = view(ck ? ck_u + off0 : u, g.plane);
-    const Rsrc CUM = view(ck ? ck_um + off0 : u, g.plane);
+    const Rsrc CUM = view(ck ? ck_u + I.field + off0 : u, g.plane);
     const Rsrc QR = view(kRecompute ? q + off0 : u, g.plane);
     const Lanes L = lanes(g, t);
-    const int2 sn = src.node[t.s];
+    const int2 sn = I.src.node[t.s];
     const int my_rm = kRecompute ? -1 : strip_rowmap(rm, g, t);
     const unsigned rb = L.rb;
 
@@ -305,24 +343,37 @@ __global__ __launch_bounds__(256) void k_fwd_step(WaveGrid g, const float* __res
 // adjoint step with receiver injection and zero-lag imaging g += lam^n * q^n
 // ---------------------------------------------------------------------------
 template <int U>
-__global__ __launch_bounds__(256) void k_adj_step(WaveGrid g, const float* __restrict__ K,
-                                                  const float* __restrict__ l, const float* lprev,
-                                                  float* out, RecMaps rm,
-                                                  const float* __restrict__ r, int n, int nt,
-                                                  float h2, const float* __restrict__ q,
-                                                  float* __restrict__ gimg) {
+__global__ __launch_bounds__(256) void k_adj_step(const TileRec* __restrict__ tiles, int ntiles,
+                                                  const Inst* __restrict__ insts, StepArgs a) {
     __shared__ float lds[kWaves][U * 72];
-    const Tile t = decode_tile(g);
+    const Tile t = decode_tile(tiles, ntiles);
     if (!t.live) return;
+    if (a.active && !a.active[t.inst]) return;
+    const Inst& I = insts[t.inst];
+    const WaveGrid g = I.g;
+    const int j = I.nseg - 1 - a.seg;
+    const int tt = a.n;
+    const int n = j * I.k + tt;
+    if (j < 0 || n >= I.nt) return;
+    // lam^{n+1} sits in L[(nt-1-n) & 1]; lam^n overwrites lam^{n+2} in the other
+    const bool par = ((I.nt - 1 - n) & 1) != 0;
+    const float* l = par ? I.L1 : I.L0;
+    float* out = par ? I.L0 : I.L1;
+    const float* lprev = out;
+    const float* r = a.r_ovr ? a.r_ovr : I.r;
+    const float* q = I.qseg + (long long)tt * I.field;
+    const int nt = I.nt;
+    const RecMaps rm = I.rm;
+    const float h2 = I.h2;
     const int lane = t.lane;
     float* rows = &lds[threadIdx.x >> 6][0];
     const long long off0 = (long long)t.s * g.plane;
     const Rsrc UR = view(l + off0, g.plane);
     const Rsrc UP = view(lprev + off0, g.plane);
     const Rsrc O = view(out + off0, g.plane);
-    const Rsrc KR = view(K, g.plane);
+    const Rsrc KR = view(I.K, g.plane);
     const Rsrc QR = view(q + off0, g.plane);
-    const Rsrc GI = view(gimg + off0, g.plane);
+    const Rsrc GI = view(I.GI + off0, g.plane);
     const Lanes L = lanes(g, t);
     const int my_rm = strip_rowmap(rm, g, t);
     const unsigned rb = L.rb;
@@ -381,17 +432,26 @@ __global__ __launch_bounds__(256) void k_adj_step(WaveGrid g, const float* __res
 // E = dm_pad / m0_pad (eq. Born: -m_r d^2u0/dt^2), sampling du.
 // ---------------------------------------------------------------------------
 template <int U>
-__global__ __launch_bounds__(256) void k_born_step(WaveGrid g, const float* __restrict__ K,
-                                                   const float* __restrict__ E,
-                                                   const float* __restrict__ u,
-                                                   const float* uprev, float* uout,
-                                                   const float* __restrict__ du,
-                                                   const float* duprev, float* duout, float w,
-                                                   SrcNodes src, RecMaps rm,
-                                                   float* __restrict__ d, int n, int nt) {
+__global__ __launch_bounds__(256) void k_born_step(const TileRec* __restrict__ tiles, int ntiles,
+                                                   const Inst* __restrict__ insts, StepArgs a) {
     __shared__ float lds[kWaves][2][U * 72];
-    const Tile t = decode_tile(g);
+    const Tile t = decode_tile(tiles, ntiles);
     if (!t.live) return;
+    if (a.active && !a.active[t.inst]) return;
+    const Inst& I = insts[t.inst];
+    const WaveGrid g = I.g;
+    const int n = a.n;
+    if (n >= I.nt) return;
+    const float* u = (n & 1) ? I.F1 : I.F0;
+    float* uout = (n & 1) ? I.F0 : I.F1;
+    const float* uprev = uout;
+    const float* du = (n & 1) ? I.L1 : I.L0;
+    float* duout = (n & 1) ? I.L0 : I.L1;
+    const float* duprev = duout;
+    const float w = I.wav[n];
+    const int nt = I.nt;
+    const RecMaps rm = I.rm;
+    float* d = a.d_ovr ? a.d_ovr : I.d;
     const int lane = t.lane;
     const int wv = threadIdx.x >> 6;
     const long long off0 = (long long)t.s * g.plane;
@@ -401,10 +461,10 @@ __global__ __launch_bounds__(256) void k_born_step(WaveGrid g, const float* __re
     const Rsrc DR = view(du + off0, g.plane);
     const Rsrc DP = view(duprev + off0, g.plane);
     const Rsrc DO = view(duout + off0, g.plane);
-    const Rsrc KR = view(K, g.plane);
-    const Rsrc ER = view(E, g.plane);
+    const Rsrc KR = view(I.K, g.plane);
+    const Rsrc ER = view(I.E, g.plane);
     const Lanes L = lanes(g, t);
-    const int2 sn = src.node[t.s];
+    const int2 sn = I.src.node[t.s];
     const int my_rm = strip_rowmap(rm, g, t);
     const unsigned rb = L.rb;
 
@@ -474,9 +534,9 @@ __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? l
 // Kp = A c2 / m_pad on every padded cell, 0 in the pitch padding; raises flag
 // for a non-positive or non-finite m.
 __global__ void k_model_prep(WaveGrid g, float c2, const float* __restrict__ m, float* __restrict__ K,
-                             int* __restrict__ flag) {
+                             int* __restrict__ flag, const int* __restrict__ active, int inst) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= g.plane) return;
+    if (i >= g.plane || (active && !active[inst])) return;
     const int zp = (int)(i / g.pitch), xp = (int)(i % g.pitch);
     if (xp >= g.nxp) {
         K[i] = 0.0f;
@@ -504,6 +564,14 @@ __global__ void k_born_prep(WaveGrid g, const float* __restrict__ m0, const floa
     E[i] = dm[j] / m0[j];
 }
 
+__global__ void k_copy(long long n, const float* __restrict__ src, float* __restrict__ dst,
+                       const int* __restrict__ active, int inst) {
+    if (active && !active[inst]) return;
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) dst[i] = src[i];
+}
+
 __global__ void k_zero(float* __restrict__ p, long long n) {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long stride = (long long)gridDim.x * blockDim.x;
@@ -513,9 +581,9 @@ __global__ void k_zero(float* __restrict__ p, long long n) {
 // grad[iz][ix] = sum_s sum over the padded cells copied from (iz, ix) of
 // gimg_s * (1 + st) / dt^2  (the image holds lam * A dt^2 q; 1/A = 1 + st).
 __global__ void k_fold(WaveGrid g, float inv_dt2, const float* __restrict__ gimg,
-                       float* __restrict__ grad) {
+                       float* __restrict__ grad, const int* __restrict__ active, int inst) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= g.nz * g.nx) return;
+    if (i >= g.nz * g.nx || (active && !active[inst])) return;
     const int iz = i / g.nx, ix = i % g.nx;
     const int za = (iz == 0) ? 0 : iz + g.nb;
     const int zb = (iz == g.nz - 1) ? g.nzp - 1 : iz + g.nb;
@@ -548,8 +616,10 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 
 __global__ __launch_bounds__(kReduceThreads) void k_residual(long long n, const float* d,
                                                              const float* __restrict__ dobs,
-                                                             float* r, double* __restrict__ part) {
+                                                             float* r, double* __restrict__ part,
+                                                             const int* __restrict__ active, int inst) {
     __shared__ double sh[kReduceThreads];
+    if (active && !active[inst]) return;
     double acc = 0.0;
     for (long long i = (long long)blockIdx.x * kReduceThreads + threadIdx.x; i < n;
          i += (long long)kReduceBlocks * kReduceThreads) {
@@ -562,8 +632,10 @@ __global__ __launch_bounds__(kReduceThreads) void k_residual(long long n, const 
 }
 
 __global__ __launch_bounds__(kReduceThreads) void k_finish_sum(const double* __restrict__ part,
-                                                               double scale, double* __restrict__ out) {
+                                                               double scale, double* __restrict__ out,
+                                                               const int* __restrict__ active, int inst) {
     __shared__ double sh[kReduceThreads];
+    if (active && !active[inst]) return;
     double acc = 0.0;
     for (int i = threadIdx.x; i < kReduceBlocks; i += kReduceThreads) acc += part[i];
     const double s = block_sum(acc, sh);
@@ -584,13 +656,12 @@ __global__ void k_compare(long long n, const float* __restrict__ a, const float*
     if (threadIdx.x == 0) same[0] = diff ? 0 : 1;
 }
 
-inline int step_blocks(const WaveGrid& g) { return (g.ntiles + kWaves - 1) / kWaves; }
-
 }  // namespace
 
-void launch_model_prep(hipStream_t st, const WaveGrid& g, float c2, const float* m, float* K, int* flag) {
+void launch_model_prep(hipStream_t st, const WaveGrid& g, float c2, const float* m, float* K, int* flag,
+                       const int* active, int inst) {
     const int blocks = (int)((g.plane + 255) / 256);
-    hipLaunchKernelGGL(k_model_prep, dim3(blocks), dim3(256), 0, st, g, c2, m, K, flag);
+    hipLaunchKernelGGL(k_model_prep, dim3(blocks), dim3(256), 0, st, g, c2, m, K, flag, active, inst);
     AAFWI_HIP(hipGetLastError());
 }
 
@@ -605,6 +676,13 @@ void launch_compare(hipStream_t st, long long n, const float* a, const float* b,
     AAFWI_HIP(hipGetLastError());
 }
 
+void launch_copy(hipStream_t st, long long n, const float* src, float* dst, const int* active, int inst) {
+    long long blocks = (n + 255) / 256;
+    blocks = blocks > 4096 ? 4096 : (blocks < 1 ? 1 : blocks);
+    hipLaunchKernelGGL(k_copy, dim3((int)blocks), dim3(256), 0, st, n, src, dst, active, inst);
+    AAFWI_HIP(hipGetLastError());
+}
+
 void launch_zero(hipStream_t st, float* p, long long n) {
     long long blocks = (n + 255) / 256;
     if (blocks > 8192) blocks = 8192;
@@ -613,53 +691,40 @@ void launch_zero(hipStream_t st, float* p, long long n) {
     AAFWI_HIP(hipGetLastError());
 }
 
-void launch_fwd_step(hipStream_t st, const WaveGrid& g, const float* K, const float* u,
-                     const float* uprev, float* out, float w, SrcNodes src, RecMaps rm, float* d,
-                     int n, int nt, float* ck_u, float* ck_um) {
-    hipLaunchKernelGGL((k_fwd_step<kUFwd, false>), dim3(step_blocks(g)), dim3(64 * kWaves), 0, st, g, K, u,
-                       uprev, out, w, src, rm, d, n, nt, ck_u, ck_um, (float*)nullptr);
+void launch_step(int kernel_id, hipStream_t st, const TileRec* tiles, int ntiles, const Inst* insts,
+                 const StepArgs& a) {
+    const dim3 grid((ntiles + kWaves - 1) / kWaves), block(64 * kWaves);
+    switch (kernel_id) {
+        case AAFWI_K_FWD_STEP:
+            hipLaunchKernelGGL((k_fwd_step<kUFwd, false>), grid, block, 0, st, tiles, ntiles, insts, a);
+            break;
+        case AAFWI_K_REC_STEP:
+            hipLaunchKernelGGL((k_fwd_step<kUFwd, true>), grid, block, 0, st, tiles, ntiles, insts, a);
+            break;
+        case AAFWI_K_ADJ_STEP:
+            hipLaunchKernelGGL(k_adj_step<kUAdj>, grid, block, 0, st, tiles, ntiles, insts, a);
+            break;
+        default:
+            hipLaunchKernelGGL(k_born_step<kUBorn>, grid, block, 0, st, tiles, ntiles, insts, a);
+            break;
+    }
     AAFWI_HIP(hipGetLastError());
 }
 
-void launch_rec_step(hipStream_t st, const WaveGrid& g, const float* K, const float* u,
-                     const float* uprev, float* out, float w, SrcNodes src, float* q) {
-    RecMaps none{nullptr, nullptr, nullptr, 0, 0};
-    hipLaunchKernelGGL((k_fwd_step<kUFwd, true>), dim3(step_blocks(g)), dim3(64 * kWaves), 0, st, g, K, u,
-                       uprev, out, w, src, none, (float*)nullptr, 0, 0, (float*)nullptr,
-                       (float*)nullptr, q);
-    AAFWI_HIP(hipGetLastError());
-}
-
-void launch_adj_step(hipStream_t st, const WaveGrid& g, const float* K, const float* l,
-                     const float* lprev, float* out, RecMaps rm, const float* r, int n, int nt,
-                     float h2, const float* q, float* gimg) {
-    hipLaunchKernelGGL(k_adj_step<kUAdj>, dim3(step_blocks(g)), dim3(64 * kWaves), 0, st, g, K, l, lprev,
-                       out, rm, r, n, nt, h2, q, gimg);
-    AAFWI_HIP(hipGetLastError());
-}
-
-void launch_born_step(hipStream_t st, const WaveGrid& g, const float* K, const float* E,
-                      const float* u, const float* uprev, float* uout, const float* du,
-                      const float* duprev, float* duout, float w, SrcNodes src, RecMaps rm,
-                      float* d, int n, int nt) {
-    hipLaunchKernelGGL(k_born_step<kUBorn>, dim3(step_blocks(g)), dim3(64 * kWaves), 0, st, g, K, E, u,
-                       uprev, uout, du, duprev, duout, w, src, rm, d, n, nt);
-    AAFWI_HIP(hipGetLastError());
-}
-
-void launch_fold(hipStream_t st, const WaveGrid& g, float inv_dt2, const float* gimg, float* grad) {
+void launch_fold(hipStream_t st, const WaveGrid& g, float inv_dt2, const float* gimg, float* grad,
+                 const int* active, int inst) {
     const int n = g.nz * g.nx;
-    hipLaunchKernelGGL(k_fold, dim3((n + 255) / 256), dim3(256), 0, st, g, inv_dt2, gimg, grad);
+    hipLaunchKernelGGL(k_fold, dim3((n + 255) / 256), dim3(256), 0, st, g, inv_dt2, gimg, grad, active, inst);
     AAFWI_HIP(hipGetLastError());
 }
 
 void launch_residual_misfit(hipStream_t st, long long n, const float* d, const float* dobs, float* r,
-                            double* partials, double* J) {
-    hipLaunchKernelGGL(k_residual, dim3(kReduceBlocks), dim3(kReduceThreads), 0, st, n, d, dobs, r,
-                       partials);
+                            double* partials, double* J, const int* active, int inst) {
+    hipLaunchKernelGGL(k_residual, dim3(kReduceBlocks), dim3(kReduceThreads), 0, st, n, d, dobs, r, partials,
+                       active, inst);
     AAFWI_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_finish_sum, dim3(1), dim3(kReduceThreads), 0, st, (const double*)partials, 0.5,
-                       J);
+    hipLaunchKernelGGL(k_finish_sum, dim3(1), dim3(kReduceThreads), 0, st, (const double*)partials, 0.5, J,
+                       active, inst);
     AAFWI_HIP(hipGetLastError());
 }
 
