@@ -98,7 +98,11 @@ class BatchedAADescent:
         return J
 
     def iterate(self):
-        """One iteration k >= 1 for every instance; returns (J(p_k), lambdas)."""
+        """One iteration k >= 1 for every instance.
+
+        Returns (J(p_k), lambdas, J(p_{k+1})), the last entry being the
+        accepted trial's misfit, or NaN where the search fell back to pbar
+        (whose misfit the next gradient evaluation computes)."""
         s = self.b.stream
         self.k += 1
         J = self._gradients()
@@ -106,6 +110,7 @@ class BatchedAADescent:
         pending = [True] * self.N
         lam = [0.0] * self.N
         new_p = [None] * self.N
+        J_next = np.full(self.N, np.nan)
         for lv in self.lambdas:
             idx = [i for i in range(self.N) if pending[i]]
             if not idx:
@@ -121,6 +126,7 @@ class BatchedAADescent:
                     with torch.cuda.stream(s):
                         new_p[i] = self._m(i).clone()
                     lam[i] = lv
+                    J_next[i] = Jt[i]
                     pending[i] = False
         for i in range(self.N):
             if pending[i]:
@@ -129,7 +135,7 @@ class BatchedAADescent:
                 self.kept_ok[i] = False
         self.b.set_active(np.ones(self.N, np.uint8))
         self.p = new_p
-        return J, lam
+        return J, lam, J_next
 
     def close(self):
         for a in self.aa:

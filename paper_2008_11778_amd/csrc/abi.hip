@@ -238,25 +238,43 @@ void add_instance(Engine* e, const aafwi_geometry& G, const aafwi_batch_io* io) 
     e->in.push_back(std::move(I));
 }
 
+// Tile table of one stepping kernel.  Workgroup i runs on XCD i % 8 and the
+// kernels remap workgroup ids so that XCD x receives the x-th contiguous
+// eighth of the table.  Each instance's tiles (shot-major, strip, x-tile) are
+// cut into 8 contiguous chunks and chunk c of every instance is placed in
+// region c, so every XCD holds the same share of every instance (instances
+// whose records end early leave every XCD equally); regions are padded to
+// equal length with no-op tiles (inst = -1).
 void build_tiles(Engine* e, int kid) {
-    std::vector<aafwi::TileRec> t;
+    constexpr int kX = 8, kWaves = 4;
+    std::vector<std::vector<aafwi::TileRec>> region(kX);
     for (int i = 0; i < (int)e->in.size(); ++i) {
         const aafwi::WaveGrid& g = e->in[i].g;
         const int tz = std::min(e->tz[kid] ? e->tz[kid] : default_tz(g.nzp), g.nzp);
+        std::vector<aafwi::TileRec> t;
         for (int s = 0; s < g.S; ++s)
             for (int z0 = 0; z0 < g.nzp; z0 += tz)
-                for (int tx = 0; tx < g.ntx; ++tx) {
-                    const int z1 = std::min(z0 + tz, g.nzp);
-                    t.push_back({i, s, tx * 64, (z0 << 16) | z1});
-                }
+                for (int tx = 0; tx < g.ntx; ++tx) t.push_back({i, s, tx * 64, (z0 << 16) | std::min(z0 + tz, g.nzp)});
+        const size_t n = t.size();
+        for (int c = 0; c < kX; ++c)
+            region[c].insert(region[c].end(), t.begin() + n * c / kX, t.begin() + n * (c + 1) / kX);
+    }
+    size_t L = 0;
+    for (auto& r : region) L = std::max(L, r.size());
+    L = (L + kWaves - 1) / kWaves * kWaves;
+    std::vector<aafwi::TileRec> all;
+    all.reserve(L * kX);
+    for (int c = 0; c < kX; ++c) {
+        all.insert(all.end(), region[c].begin(), region[c].end());
+        all.resize((size_t)(c + 1) * L, aafwi::TileRec{-1, 0, 0, 0});
     }
     if (e->dtiles[kid]) {
         (void)hipFree(e->dtiles[kid]);
         e->allocs.erase(std::remove(e->allocs.begin(), e->allocs.end(), (void*)e->dtiles[kid]), e->allocs.end());
     }
-    e->dtiles[kid] = dalloc<aafwi::TileRec>(e, t.size());
-    AAFWI_HIP(hipMemcpy(e->dtiles[kid], t.data(), sizeof(aafwi::TileRec) * t.size(), hipMemcpyHostToDevice));
-    e->ntiles[kid] = (int)t.size();
+    e->dtiles[kid] = dalloc<aafwi::TileRec>(e, all.size());
+    AAFWI_HIP(hipMemcpy(e->dtiles[kid], all.data(), sizeof(aafwi::TileRec) * all.size(), hipMemcpyHostToDevice));
+    e->ntiles[kid] = (int)all.size();
 }
 
 void finalize(Engine* e) {

@@ -67,6 +67,10 @@ __device__ __forceinline__ Tile decode_tile(const TileRec* __restrict__ tiles, i
     if (!t.live) return t;
     const TileRec r = tiles[tile];
     t.inst = __builtin_amdgcn_readfirstlane(r.inst);
+    if (t.inst < 0) {  // padding entry of the table
+        t.live = false;
+        return t;
+    }
     t.s = __builtin_amdgcn_readfirstlane(r.s);
     t.x0 = __builtin_amdgcn_readfirstlane(r.x0);
     const int z01 = __builtin_amdgcn_readfirstlane(r.z01);
