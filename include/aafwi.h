@@ -234,6 +234,50 @@ int aafwi_batch_set_tile(aafwi_batch* b, int32_t kernel_id, int32_t rows_per_wav
 int aafwi_batch_kernel_timing(aafwi_batch* b, int every);
 int aafwi_batch_kernel_timing_read(aafwi_batch* b, int kernel_id, double* mean_ms, int64_t* count);
 
+/* ---- learned preconditioner -------------------------------------------------
+ * A variant of the fixed-point map of the Method section, G(p) = p - eta g
+ * (eq. GD), with the gradient replaced by a learned direction
+ *   d = softplus(z) * g,   z = CNN([g / rms(g), (m - mean m) / std m]),
+ * so d = 0 exactly where g = 0 (G's fixed points are kept) and <d, g> > 0.
+ * CNN: four 3x3 zero-padded cross-correlations without bias, channels
+ * 2 -> 32 -> 32 -> 32 -> 1, ReLU after the first three; bf16 activations and
+ * weights, FP32 accumulation on the matrix cores, FP32 master weights.
+ * Weights (host, AAFWI_CNN_PARAMS floats): per layer [C_out][C_in][3][3],
+ * layers concatenated; w[co][ci][a][b] multiplies x[ci][i + a - 1][j + b - 1].
+ * Training loss of a batch of (g, m, s): mean over images of
+ * mean((d / rms(d) + s / rms(s))^2), s being a step p_{k+1} - p_k that an
+ * optimiser took; Adam (beta 0.9, 0.999, eps 1e-8) on it.
+ * All image arrays are device buffers of B images [B][nz][nx] FP32, on the
+ * stream given at creation.  The network owns its weights and activation
+ * buffers (about 196 bytes per pixel of max_batch images). */
+#define AAFWI_CNN_PARAMS 19296
+typedef struct aafwi_cnn aafwi_cnn;
+
+/* weights: host, AAFWI_CNN_PARAMS floats (copied).  max_batch * nz * nx must
+ * stay below 2^31. */
+int aafwi_cnn_create(int32_t nz, int32_t nx, int32_t max_batch, const float* weights, aafwi_stream stream,
+                     aafwi_cnn** out);
+int aafwi_cnn_destroy(aafwi_cnn* c);
+
+/* Replace the weights (host) and reset the Adam state; copy them out (host).
+ * Both synchronise the network's stream. */
+int aafwi_cnn_set_weights(aafwi_cnn* c, const float* weights);
+int aafwi_cnn_get_weights(aafwi_cnn* c, float* weights);
+
+/* Inference on B images (1 <= B <= max_batch): z (optional, may be NULL) the
+ * network output, d (optional) the direction softplus(z) * g. */
+int aafwi_cnn_forward(aafwi_cnn* c, int32_t B, const float* g, const float* m, float* z, float* d);
+
+/* Weight gradient (device, AAFWI_CNN_PARAMS floats, host weight layout) of
+ * the batch loss; loss: device double, optional.  Weights are unchanged. */
+int aafwi_cnn_gradients(aafwi_cnn* c, int32_t B, const float* g, const float* m, const float* s, float* grad,
+                        double* loss);
+
+/* One Adam step (learning rate lr > 0) on the batch loss; loss (device
+ * double, optional) receives the loss before the step. */
+int aafwi_cnn_train_step(aafwi_cnn* c, int32_t B, const float* g, const float* m, const float* s, float lr,
+                         double* loss);
+
 /* ---- instrumentation ------------------------------------------------------- */
 
 /* Kernel ids for aafwi_kernel_timing. */

@@ -456,3 +456,116 @@ def axpy(a, x, y, stream=None):
     _check(_lib.aafwi_axpy(_stream_handle(stream), n, float(a), _ptr(x, numel=n, name="x"),
                            _ptr(y, numel=n, name="y")))
     return y
+
+
+_sig("aafwi_cnn_create", _i32, _i32, _i32, _vp, _vp, ctypes.POINTER(_vp))
+_sig("aafwi_cnn_destroy", _vp)
+_sig("aafwi_cnn_set_weights", _vp, _vp)
+_sig("aafwi_cnn_get_weights", _vp, _vp)
+_sig("aafwi_cnn_forward", _vp, _i32, _vp, _vp, _vp, _vp)
+_sig("aafwi_cnn_gradients", _vp, _i32, _vp, _vp, _vp, _vp, _vp)
+_sig("aafwi_cnn_train_step", _vp, _i32, _vp, _vp, _vp, _f32, _vp)
+CNN_PARAMS = 19296
+CNN_SHAPES = ((32, 2, 3, 3), (32, 32, 3, 3), (32, 32, 3, 3), (1, 32, 3, 3))
+
+
+def cnn_flatten(ws) -> np.ndarray:
+    """Per-layer [C_out][C_in][3][3] arrays -> the flat FP32 host layout."""
+    flat = np.concatenate([np.asarray(w, np.float32).reshape(-1) for w in ws])
+    if flat.size != CNN_PARAMS:
+        raise ValueError(f"expected {CNN_PARAMS} weights, got {flat.size}")
+    return np.ascontiguousarray(flat)
+
+
+def cnn_unflatten(flat):
+    out, o = [], 0
+    for shp in CNN_SHAPES:
+        n = int(np.prod(shp))
+        out.append(np.asarray(flat[o:o + n]).reshape(shp))
+        o += n
+    return out
+
+
+class CNN:
+    """Learned direction network on [B][nz][nx] images (device tensors)."""
+
+    def __init__(self, nz: int, nx: int, max_batch: int, weights, stream=None):
+        self.nz, self.nx, self.max_batch = int(nz), int(nx), int(max_batch)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        w = cnn_flatten(weights) if isinstance(weights, (list, tuple)) else np.ascontiguousarray(weights, np.float32)
+        if w.size != CNN_PARAMS:
+            raise ValueError(f"expected {CNN_PARAMS} weights")
+        h = _vp()
+        _check(_lib.aafwi_cnn_create(self.nz, self.nx, self.max_batch, w.ctypes.data, _stream_handle(self.stream),
+                                     ctypes.byref(h)))
+        self._h = h
+        self.loss_dev = torch.zeros(1, dtype=torch.float64, device=self.device)
+
+    def _images(self, x, name):
+        if x.dim() == 2:
+            x = x.unsqueeze(0)
+        B = x.shape[0]
+        if not (1 <= B <= self.max_batch):
+            raise ValueError(f"batch of {B} images outside [1, {self.max_batch}]")
+        _ptr(x, numel=B * self.nz * self.nx, name=name)
+        return x, B
+
+    def set_weights(self, weights):
+        w = cnn_flatten(weights) if isinstance(weights, (list, tuple)) else np.ascontiguousarray(weights, np.float32)
+        _check(_lib.aafwi_cnn_set_weights(self._h, w.ctypes.data))
+
+    def get_weights(self) -> np.ndarray:
+        w = np.empty(CNN_PARAMS, np.float32)
+        _check(_lib.aafwi_cnn_get_weights(self._h, w.ctypes.data))
+        return w
+
+    def forward(self, g, m, z=None, d=None):
+        """(z, d) with d = softplus(z) * g; pass z=False or d=False to skip one."""
+        g, B = self._images(g, "g")
+        m, _ = self._images(m, "m")
+        with torch.cuda.stream(self.stream):
+            zt = torch.empty_like(g) if z is None else z
+            dt = torch.empty_like(g) if d is None else d
+        zp = 0 if zt is False else _ptr(zt, numel=g.numel(), name="z")
+        dp = 0 if dt is False else _ptr(dt, numel=g.numel(), name="d")
+        _check(_lib.aafwi_cnn_forward(self._h, B, g.data_ptr(), m.data_ptr(), zp or None, dp or None))
+        return (None if zt is False else zt), (None if dt is False else dt)
+
+    def gradients(self, g, m, s, grad=None):
+        """Weight gradient (flat, device) and the batch loss (device double)."""
+        g, B = self._images(g, "g")
+        m, _ = self._images(m, "m")
+        s, _ = self._images(s, "s")
+        with torch.cuda.stream(self.stream):
+            grad = torch.empty(CNN_PARAMS, dtype=torch.float32, device=self.device) if grad is None else grad
+        _check(_lib.aafwi_cnn_gradients(self._h, B, g.data_ptr(), m.data_ptr(), s.data_ptr(),
+                                        _ptr(grad, numel=CNN_PARAMS, name="grad"),
+                                        _ptr(self.loss_dev, torch.float64, 1, "loss")))
+        return grad, self.loss_dev
+
+    def train_step(self, g, m, s, lr: float = 1e-3):
+        """One Adam step; returns the device loss (before the step)."""
+        g, B = self._images(g, "g")
+        m, _ = self._images(m, "m")
+        s, _ = self._images(s, "s")
+        _check(_lib.aafwi_cnn_train_step(self._h, B, g.data_ptr(), m.data_ptr(), s.data_ptr(), float(lr),
+                                         _ptr(self.loss_dev, torch.float64, 1, "loss")))
+        return self.loss_dev
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(_lib.aafwi_cnn_destroy(self._h))
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

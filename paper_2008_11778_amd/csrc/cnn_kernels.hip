@@ -1,0 +1,620 @@
+// Learned preconditioner of the Anderson step: a 4-layer 3x3 CNN
+// (channels 2 -> 32 -> 32 -> 32 -> 1, ReLU after the first three, zero "same"
+// padding, no bias) on bf16 activations and weights with FP32 accumulation on
+// the matrix cores, its hand-written backward, the scale-free loss and Adam.
+//
+// The network maps [g / rms(g), (m - mean m) / std m] of one image to z; the
+// search direction is d = softplus(z) * g, so d = 0 exactly when g = 0 (the
+// fixed points of the descent map G of eq. GD are kept) and <d, g> > 0.
+// Training target for a step s taken by an optimiser: t = -s / rms(s); loss
+// per image mean((d / rms(d) - t)^2), averaged over the batch.
+//
+// Convolutions are implicit GEMMs on v_mfma_f32_16x16x16_bf16: one wave owns
+// 16 consecutive pixels (rows of the 16x16 tile) and all output channels
+// (16-column tiles); the reduction runs over (tap, 16-channel chunk).
+// Activations are NHWC with the channel count padded to a multiple of 16.
+// Weight copies: Wf[tap][co][ci] (forward), Wd[tap][ci][co] (input gradient).
+#include <cmath>
+#include <new>
+#include <vector>
+
+#include "common.hpp"
+
+namespace aafwi {
+namespace {
+
+typedef unsigned short bf16;
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+constexpr int kL = 4;
+constexpr int kCinP[kL] = {16, 32, 32, 32};   // padded input channels
+constexpr int kCoutP[kL] = {32, 32, 32, 16};  // padded output channels
+constexpr int kCin[kL] = {2, 32, 32, 32};
+constexpr int kCout[kL] = {32, 32, 32, 1};
+constexpr int kWgradChunk = 2048;  // pixels per split-K partial of the weight gradient
+constexpr int kRedBlocks = 64;     // per-image reduction partials
+
+__device__ __forceinline__ bf16 f2bf(float f) {
+    unsigned u = __builtin_bit_cast(unsigned, f);
+    u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
+    return (bf16)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(bf16 h) { return __builtin_bit_cast(float, (unsigned)h << 16); }
+
+__device__ __forceinline__ v4s ld4(const bf16* p) { return *reinterpret_cast<const v4s*>(p); }
+
+struct Pix {
+    int b, y, x;
+};
+__device__ __forceinline__ Pix pix(int p, int H, int W) {
+    Pix q;
+    q.x = p % W;
+    const int r = p / W;
+    q.y = r % H;
+    q.b = r / H;
+    return q;
+}
+
+// y = conv3x3(x) (+ ReLU, bf16 out) or, for the last layer, z = conv3x3(x) (FP32).
+template <int CIN, int COUT, bool LAST>
+__global__ __launch_bounds__(256) void k_conv_fwd(int P, int H, int W, const bf16* __restrict__ x,
+                                                  const bf16* __restrict__ wf, bf16* __restrict__ y,
+                                                  float* __restrict__ z) {
+    const int lane = threadIdx.x & 63;
+    const int p0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
+    if (p0 >= P) return;
+    const int i = lane & 15, grp = lane >> 4;
+    const int p = p0 + i;
+    const bool pin = p < P;
+    const Pix q = pix(pin ? p : 0, H, W);
+    v4f acc[COUT / 16];
+#pragma unroll
+    for (int nt = 0; nt < COUT / 16; ++nt) acc[nt] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+        const int yy = q.y + tap / 3 - 1, xx = q.x + tap % 3 - 1;
+        const bool ok = pin && yy >= 0 && yy < H && xx >= 0 && xx < W;
+        const long long src = ((long long)(q.b * H + yy) * W + xx) * CIN;
+#pragma unroll
+        for (int cc = 0; cc < CIN / 16; ++cc) {
+            const v4s a = ok ? ld4(x + src + cc * 16 + 4 * grp) : v4s{0, 0, 0, 0};
+#pragma unroll
+            for (int nt = 0; nt < COUT / 16; ++nt) {
+                const v4s bw = ld4(wf + ((tap * COUT + nt * 16 + i) * CIN + cc * 16 + 4 * grp));
+                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bw, acc[nt], 0, 0, 0);
+            }
+        }
+    }
+    // lane holds D[4*grp + r][i]: pixel p0 + 4*grp + r, channel nt*16 + i
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int pp = p0 + 4 * grp + r;
+        if (pp >= P) continue;
+        if (LAST) {
+            if (i == 0) z[pp] = acc[0][r];
+        } else {
+#pragma unroll
+            for (int nt = 0; nt < COUT / 16; ++nt) y[(long long)pp * COUT + nt * 16 + i] = f2bf(fmaxf(acc[nt][r], 0.f));
+        }
+    }
+}
+
+// dx[p][ci] = sum_tap sum_co dy[p - off(tap)][co] Wd[tap][ci][co], times the
+// ReLU mask (xin[p][ci] > 0) of the layer that produced this layer's input.
+template <int CIN, int COUT>
+__global__ __launch_bounds__(256) void k_conv_dgrad(int P, int H, int W, const bf16* __restrict__ dy,
+                                                    const bf16* __restrict__ wd, const bf16* __restrict__ xin,
+                                                    bf16* __restrict__ dx) {
+    const int lane = threadIdx.x & 63;
+    const int p0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
+    if (p0 >= P) return;
+    const int i = lane & 15, grp = lane >> 4;
+    const int p = p0 + i;
+    const bool pin = p < P;
+    const Pix q = pix(pin ? p : 0, H, W);
+    v4f acc[CIN / 16];
+#pragma unroll
+    for (int nt = 0; nt < CIN / 16; ++nt) acc[nt] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+        const int yy = q.y - (tap / 3 - 1), xx = q.x - (tap % 3 - 1);
+        const bool ok = pin && yy >= 0 && yy < H && xx >= 0 && xx < W;
+        const long long src = ((long long)(q.b * H + yy) * W + xx) * COUT;
+#pragma unroll
+        for (int cc = 0; cc < COUT / 16; ++cc) {
+            const v4s a = ok ? ld4(dy + src + cc * 16 + 4 * grp) : v4s{0, 0, 0, 0};
+#pragma unroll
+            for (int nt = 0; nt < CIN / 16; ++nt) {
+                const v4s bw = ld4(wd + ((tap * CIN + nt * 16 + i) * COUT + cc * 16 + 4 * grp));
+                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bw, acc[nt], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int pp = p0 + 4 * grp + r;
+        if (pp >= P) continue;
+#pragma unroll
+        for (int nt = 0; nt < CIN / 16; ++nt) {
+            const long long o = (long long)pp * CIN + nt * 16 + i;
+            dx[o] = bf2f(xin[o]) > 0.f ? f2bf(acc[nt][r]) : (bf16)0;
+        }
+    }
+}
+
+// Split-K weight gradient: part[chunk][tap][co][ci] = sum over the chunk's
+// pixels p of dy[p][co] x[p + off(tap)][ci].  One wave per (chunk, tap).
+template <int CIN, int COUT>
+__global__ __launch_bounds__(64) void k_conv_wgrad(int P, int H, int W, const bf16* __restrict__ dy,
+                                                   const bf16* __restrict__ x, float* __restrict__ part) {
+    const int lane = threadIdx.x;
+    const int chunk = blockIdx.x, tap = blockIdx.y;
+    const int i = lane & 15, grp = lane >> 4;
+    const int dyo = tap / 3 - 1, dxo = tap % 3 - 1;
+    v4f acc[COUT / 16][CIN / 16];
+#pragma unroll
+    for (int a = 0; a < COUT / 16; ++a)
+#pragma unroll
+        for (int b = 0; b < CIN / 16; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+    const int pbeg = chunk * kWgradChunk;
+    const int pend = min(pbeg + kWgradChunk, P);
+    for (int k0 = pbeg; k0 < pend; k0 += 16) {
+        // A[co][pix] = dy[k0 + 4*grp + r][co]; B[pix][ci] = x[(k0 + 4*grp + r) + off][ci]
+        short av[COUT / 16][4], bv[CIN / 16][4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int p = k0 + 4 * grp + r;
+            const bool pin = p < pend;
+            const Pix q = pix(pin ? p : 0, H, W);
+            const int yy = q.y + dyo, xx = q.x + dxo;
+            const bool ok = pin && yy >= 0 && yy < H && xx >= 0 && xx < W;
+            const long long xs = ((long long)(q.b * H + yy) * W + xx) * CIN;
+#pragma unroll
+            for (int a = 0; a < COUT / 16; ++a) av[a][r] = pin ? (short)dy[(long long)p * COUT + a * 16 + i] : (short)0;
+#pragma unroll
+            for (int b = 0; b < CIN / 16; ++b) bv[b][r] = ok ? (short)x[xs + b * 16 + i] : (short)0;
+        }
+#pragma unroll
+        for (int a = 0; a < COUT / 16; ++a) {
+            const v4s A = v4s{av[a][0], av[a][1], av[a][2], av[a][3]};
+#pragma unroll
+            for (int b = 0; b < CIN / 16; ++b) {
+                const v4s B = v4s{bv[b][0], bv[b][1], bv[b][2], bv[b][3]};
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, B, acc[a][b], 0, 0, 0);
+            }
+        }
+    }
+    // lane holds D[4*grp + r][i]: co = a*16 + 4*grp + r, ci = b*16 + i
+    float* out = part + ((long long)chunk * 9 + tap) * COUT * CIN;
+#pragma unroll
+    for (int a = 0; a < COUT / 16; ++a)
+#pragma unroll
+        for (int b = 0; b < CIN / 16; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) out[(a * 16 + 4 * grp + r) * CIN + b * 16 + i] = acc[a][b][r];
+}
+
+// grad[co][ci][tap] (real channels only) = sum over chunks, in chunk order.
+__global__ void k_wgrad_reduce(int nchunk, int coutp, int cinp, int cout, int cin, const float* __restrict__ part,
+                               float* __restrict__ grad) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= cout * cin * 9) return;
+    const int tap = idx % 9, ci = (idx / 9) % cin, co = idx / (9 * cin);
+    double acc = 0.0;
+    for (int c = 0; c < nchunk; ++c) acc += part[((long long)c * 9 + tap) * coutp * cinp + co * cinp + ci];
+    grad[idx] = (float)acc;
+}
+
+// ---------------------------------------------------------------------------
+// per-image FP64 reductions (fixed order)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <int NV>
+__device__ __forceinline__ void block_store(double (&v)[NV], double* dst) {
+    __shared__ double sh[4][NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        const double s = wave_sum(v[k]);
+        if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6][k] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < NV) dst[threadIdx.x] = sh[0][threadIdx.x] + sh[1][threadIdx.x] + sh[2][threadIdx.x] + sh[3][threadIdx.x];
+}
+
+// image b, block k: partial sums of g^2, m, m^2
+__global__ __launch_bounds__(256) void k_input_stats(int n, const float* __restrict__ g, const float* __restrict__ m,
+                                                     double* __restrict__ part) {
+    const int b = blockIdx.y;
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += kRedBlocks * 256) {
+        const double gv = g[(long long)b * n + i], mv = m[(long long)b * n + i];
+        v[0] += gv * gv;
+        v[1] += mv;
+        v[2] += mv * mv;
+    }
+    block_store<3>(v, part + ((long long)b * kRedBlocks + blockIdx.x) * 3);
+}
+
+template <int NV>
+__global__ void k_finish(int B, const double* __restrict__ part, double* __restrict__ out) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    for (int k = 0; k < NV; ++k) {
+        double acc = 0.0;
+        for (int j = 0; j < kRedBlocks; ++j) acc += part[((long long)b * kRedBlocks + j) * NV + k];
+        out[b * NV + k] = acc;
+    }
+}
+
+// a0[p][0] = g / rms(g), a0[p][1] = (m - mean) / std, channels 2..15 zero
+__global__ void k_pack_input(int B, int n, const float* __restrict__ g, const float* __restrict__ m,
+                             const double* __restrict__ st, bf16* __restrict__ a0) {
+    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= (long long)B * n) return;
+    const int b = (int)(p / n);
+    const double rg = sqrt(st[b * 3] / n);
+    const double mean = st[b * 3 + 1] / n;
+    const double var = fmax(st[b * 3 + 2] / n - mean * mean, 0.0);
+    const double sd = sqrt(var);
+    const float gh = rg > 0 ? (float)(g[p] / rg) : 0.f;
+    const float mh = sd > 0 ? (float)((m[p] - mean) / sd) : 0.f;
+    bf16* o = a0 + p * 16;
+    o[0] = f2bf(gh);
+    o[1] = f2bf(mh);
+#pragma unroll
+    for (int c = 2; c < 16; ++c) o[c] = 0;
+}
+
+__device__ __forceinline__ float softplusf(float z) { return fmaxf(z, 0.f) + log1pf(expf(-fabsf(z))); }
+__device__ __forceinline__ float sigmoidf(float z) { return 1.f / (1.f + expf(-z)); }
+
+// d = softplus(z) * g
+__global__ void k_direction(long long N, const float* __restrict__ z, const float* __restrict__ g, float* __restrict__ d) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) d[i] = softplusf(z[i]) * g[i];
+}
+
+// pass 1 of the loss: sum d^2 and sum s^2 per image
+__global__ __launch_bounds__(256) void k_loss_a(int n, const float* __restrict__ z, const float* __restrict__ g,
+                                                const float* __restrict__ s, double* __restrict__ part) {
+    const int b = blockIdx.y;
+    double v[2] = {0.0, 0.0};
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += kRedBlocks * 256) {
+        const long long o = (long long)b * n + i;
+        const double d = (double)softplusf(z[o]) * g[o];
+        v[0] += d * d;
+        v[1] += (double)s[o] * s[o];
+    }
+    block_store<2>(v, part + ((long long)b * kRedBlocks + blockIdx.x) * 2);
+}
+
+// pass 2: sum (u - t) u and sum (u - t)^2 with u = d / rms(d), t = -s / rms(s)
+__global__ __launch_bounds__(256) void k_loss_b(int n, const float* __restrict__ z, const float* __restrict__ g,
+                                                const float* __restrict__ s, const double* __restrict__ st1,
+                                                double* __restrict__ part) {
+    const int b = blockIdx.y;
+    const double rd = sqrt(st1[b * 2] / n), rs = sqrt(st1[b * 2 + 1] / n);
+    double v[2] = {0.0, 0.0};
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += kRedBlocks * 256) {
+        const long long o = (long long)b * n + i;
+        const double u = (double)softplusf(z[o]) * g[o] / rd;
+        const double e = u + (double)s[o] / rs;
+        v[0] += e * u;
+        v[1] += e * e;
+    }
+    block_store<2>(v, part + ((long long)b * kRedBlocks + blockIdx.x) * 2);
+}
+
+// pass 3: dL/dz = (2/(n rd)) [e - u mean(e u)] g sigmoid(z) / B, packed as
+// channel 0 of a 16-channel bf16 tensor
+__global__ void k_loss_c(int B, int n, const float* __restrict__ z, const float* __restrict__ g,
+                         const float* __restrict__ s, const double* __restrict__ st1, const double* __restrict__ st2,
+                         bf16* __restrict__ dz16) {
+    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= (long long)B * n) return;
+    const int b = (int)(p / n);
+    const double rd = sqrt(st1[b * 2] / n), rs = sqrt(st1[b * 2 + 1] / n);
+    const double u = (double)softplusf(z[p]) * g[p] / rd;
+    const double e = u + (double)s[p] / rs;
+    const double dd = 2.0 / (n * rd) * (e - u * st2[b * 2] / n);
+    const float dzv = (float)(dd * g[p] * sigmoidf(z[p]) / B);
+    bf16* o = dz16 + p * 16;
+    o[0] = f2bf(dzv);
+#pragma unroll
+    for (int c = 1; c < 16; ++c) o[c] = 0;
+}
+
+__global__ void k_loss_total(int B, int n, const double* __restrict__ st2, double* __restrict__ loss) {
+    if (threadIdx.x != 0) return;
+    double acc = 0.0;
+    for (int b = 0; b < B; ++b) acc += st2[b * 2 + 1] / n;
+    loss[0] = acc / B;
+}
+
+// Adam on FP32 master weights.
+__global__ void k_adam(int n, float lr, float b1, float b2, float eps, float c1, float c2, float* __restrict__ w,
+                       float* __restrict__ mo, float* __restrict__ vo, const float* __restrict__ gr) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float g = gr[i];
+    const float m = b1 * mo[i] + (1.f - b1) * g;
+    const float v = b2 * vo[i] + (1.f - b2) * g * g;
+    mo[i] = m;
+    vo[i] = v;
+    w[i] -= lr * (m / c1) / (sqrtf(v / c2) + eps);
+}
+
+// bf16 copies: Wf[tap][co][ci] and Wd[tap][ci][co] (padded with zeros)
+__global__ void k_pack_weights(int cout, int cin, int coutp, int cinp, const float* __restrict__ w,
+                               bf16* __restrict__ wf, bf16* __restrict__ wd) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= 9 * coutp * cinp) return;
+    const int ci = idx % cinp, co = (idx / cinp) % coutp, tap = idx / (cinp * coutp);
+    const float v = (co < cout && ci < cin) ? w[(co * cin + ci) * 9 + tap] : 0.f;
+    const bf16 h = f2bf(v);
+    wf[(tap * coutp + co) * cinp + ci] = h;
+    if (wd) wd[(tap * cinp + ci) * coutp + co] = h;
+}
+
+}  // namespace
+}  // namespace aafwi
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+using aafwi::Error;
+
+struct aafwi_cnn {
+    int H = 0, W = 0, Bmax = 0;
+    hipStream_t stream = nullptr;
+    int step = 0;
+    std::vector<void*> allocs;
+    float* w = nullptr;     // FP32 master weights (AAFWI_CNN_PARAMS)
+    float* mo = nullptr;    // Adam moments
+    float* vo = nullptr;
+    float* grad = nullptr;
+    aafwi::bf16* wf[aafwi::kL] = {};
+    aafwi::bf16* wd[aafwi::kL] = {};
+    aafwi::bf16* act[aafwi::kL] = {};  // inputs of layers 1..4 (a0..a3)
+    aafwi::bf16* dlt[aafwi::kL] = {};  // deltas at the outputs of layers 1..4
+    float* z = nullptr;
+    double* part = nullptr;
+    double* st_in = nullptr;
+    double* st1 = nullptr;
+    double* st2 = nullptr;
+    float* wpart = nullptr;
+};
+
+namespace {
+
+template <typename F>
+int guarded(F&& f) {
+    try {
+        return f();
+    } catch (const Error& e) {
+        aafwi::set_last_error(e.msg);
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        aafwi::set_last_error("host allocation failed");
+        return AAFWI_E_NOMEM;
+    } catch (...) {
+        aafwi::set_last_error("unknown error");
+        return AAFWI_E_INVALID;
+    }
+}
+
+template <typename T>
+T* calloc_dev(aafwi_cnn* c, size_t n) {
+    void* p = nullptr;
+    if (hipMalloc(&p, sizeof(T) * (n ? n : 1)) != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error{AAFWI_E_NOMEM, "cnn: device allocation failed"};
+    }
+    c->allocs.push_back(p);
+    AAFWI_HIP(hipMemset(p, 0, sizeof(T) * (n ? n : 1)));
+    return (T*)p;
+}
+
+int layer_offset(int l) {
+    int o = 0;
+    for (int i = 0; i < l; ++i) o += aafwi::kCout[i] * aafwi::kCin[i] * 9;
+    return o;
+}
+
+void pack_weights(aafwi_cnn* c) {
+    for (int l = 0; l < aafwi::kL; ++l) {
+        const int n = 9 * aafwi::kCoutP[l] * aafwi::kCinP[l];
+        hipLaunchKernelGGL(aafwi::k_pack_weights, dim3((n + 255) / 256), dim3(256), 0, c->stream, aafwi::kCout[l],
+                           aafwi::kCin[l], aafwi::kCoutP[l], aafwi::kCinP[l], c->w + layer_offset(l), c->wf[l], c->wd[l]);
+        AAFWI_HIP(hipGetLastError());
+    }
+}
+
+void forward(aafwi_cnn* c, int B, const float* g, const float* m) {
+    using namespace aafwi;
+    const int n = c->H * c->W, P = B * n;
+    hipLaunchKernelGGL(k_input_stats, dim3(kRedBlocks, B), dim3(256), 0, c->stream, n, g, m, c->part);
+    hipLaunchKernelGGL(k_finish<3>, dim3((B + 63) / 64), dim3(64), 0, c->stream, B, (const double*)c->part, c->st_in);
+    hipLaunchKernelGGL(k_pack_input, dim3((P + 255) / 256), dim3(256), 0, c->stream, B, n, g, m,
+                       (const double*)c->st_in, c->act[0]);
+    const dim3 grid((P + 63) / 64), block(256);
+    hipLaunchKernelGGL((k_conv_fwd<16, 32, false>), grid, block, 0, c->stream, P, c->H, c->W, c->act[0], c->wf[0],
+                       c->act[1], (float*)nullptr);
+    hipLaunchKernelGGL((k_conv_fwd<32, 32, false>), grid, block, 0, c->stream, P, c->H, c->W, c->act[1], c->wf[1],
+                       c->act[2], (float*)nullptr);
+    hipLaunchKernelGGL((k_conv_fwd<32, 32, false>), grid, block, 0, c->stream, P, c->H, c->W, c->act[2], c->wf[2],
+                       c->act[3], (float*)nullptr);
+    hipLaunchKernelGGL((k_conv_fwd<32, 16, true>), grid, block, 0, c->stream, P, c->H, c->W, c->act[3], c->wf[3],
+                       (bf16*)nullptr, c->z);
+    AAFWI_HIP(hipGetLastError());
+}
+
+// forward, loss and weight gradient (into c->grad); loss (device double) optional
+void gradients(aafwi_cnn* c, int B, const float* g, const float* m, const float* s, double* loss) {
+    using namespace aafwi;
+    forward(c, B, g, m);
+    const int n = c->H * c->W, P = B * n;
+    hipLaunchKernelGGL(k_loss_a, dim3(kRedBlocks, B), dim3(256), 0, c->stream, n, (const float*)c->z, g, s, c->part);
+    hipLaunchKernelGGL(k_finish<2>, dim3((B + 63) / 64), dim3(64), 0, c->stream, B, (const double*)c->part, c->st1);
+    hipLaunchKernelGGL(k_loss_b, dim3(kRedBlocks, B), dim3(256), 0, c->stream, n, (const float*)c->z, g, s,
+                       (const double*)c->st1, c->part);
+    hipLaunchKernelGGL(k_finish<2>, dim3((B + 63) / 64), dim3(64), 0, c->stream, B, (const double*)c->part, c->st2);
+    hipLaunchKernelGGL(k_loss_c, dim3((P + 255) / 256), dim3(256), 0, c->stream, B, n, (const float*)c->z, g, s,
+                       (const double*)c->st1, (const double*)c->st2, c->dlt[3]);
+    if (loss) hipLaunchKernelGGL(k_loss_total, dim3(1), dim3(64), 0, c->stream, B, n, (const double*)c->st2, loss);
+    AAFWI_HIP(hipGetLastError());
+    const dim3 grid((P + 63) / 64), block(256);
+    const int nchunk = (P + kWgradChunk - 1) / kWgradChunk;
+    // layer 4 (32 -> 1): weight gradient, then the delta at layer 3's output
+    hipLaunchKernelGGL((k_conv_wgrad<32, 16>), dim3(nchunk, 9), dim3(64), 0, c->stream, P, c->H, c->W, c->dlt[3],
+                       c->act[3], c->wpart);
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3((kCout[3] * kCin[3] * 9 + 255) / 256), dim3(256), 0, c->stream, nchunk,
+                       16, 32, kCout[3], kCin[3], (const float*)c->wpart, c->grad + layer_offset(3));
+    hipLaunchKernelGGL((k_conv_dgrad<32, 16>), grid, block, 0, c->stream, P, c->H, c->W, c->dlt[3], c->wd[3],
+                       c->act[3], c->dlt[2]);
+    for (int l = 2; l >= 1; --l) {
+        hipLaunchKernelGGL((k_conv_wgrad<32, 32>), dim3(nchunk, 9), dim3(64), 0, c->stream, P, c->H, c->W, c->dlt[l],
+                           c->act[l], c->wpart);
+        hipLaunchKernelGGL(k_wgrad_reduce, dim3((kCout[l] * kCin[l] * 9 + 255) / 256), dim3(256), 0, c->stream,
+                           nchunk, 32, 32, kCout[l], kCin[l], (const float*)c->wpart, c->grad + layer_offset(l));
+        hipLaunchKernelGGL((k_conv_dgrad<32, 32>), grid, block, 0, c->stream, P, c->H, c->W, c->dlt[l], c->wd[l],
+                           c->act[l], c->dlt[l - 1]);
+    }
+    hipLaunchKernelGGL((k_conv_wgrad<16, 32>), dim3(nchunk, 9), dim3(64), 0, c->stream, P, c->H, c->W, c->dlt[0],
+                       c->act[0], c->wpart);
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3((kCout[0] * kCin[0] * 9 + 255) / 256), dim3(256), 0, c->stream, nchunk,
+                       32, 16, kCout[0], kCin[0], (const float*)c->wpart, c->grad + layer_offset(0));
+    AAFWI_HIP(hipGetLastError());
+}
+
+void check_batch(const aafwi_cnn* c, int B) {
+    AAFWI_REQUIRE(B >= 1 && B <= c->Bmax, "cnn: batch size outside [1, max_batch]");
+}
+
+}  // namespace
+
+extern "C" int aafwi_cnn_create(int32_t nz, int32_t nx, int32_t max_batch, const float* weights, aafwi_stream stream,
+                                aafwi_cnn** out) {
+    return guarded([&]() -> int {
+        AAFWI_REQUIRE(out && weights, "cnn_create: NULL argument");
+        AAFWI_REQUIRE(nz >= 1 && nx >= 1 && max_batch >= 1, "cnn_create: bad size");
+        AAFWI_REQUIRE((long long)nz * nx * max_batch < (1LL << 31), "cnn_create: too many pixels");
+        *out = nullptr;
+        aafwi_cnn* c = new aafwi_cnn{};
+        try {
+            c->H = nz;
+            c->W = nx;
+            c->Bmax = max_batch;
+            c->stream = (hipStream_t)stream;
+            const size_t P = (size_t)nz * nx * max_batch;
+            c->w = calloc_dev<float>(c, AAFWI_CNN_PARAMS);
+            c->mo = calloc_dev<float>(c, AAFWI_CNN_PARAMS);
+            c->vo = calloc_dev<float>(c, AAFWI_CNN_PARAMS);
+            c->grad = calloc_dev<float>(c, AAFWI_CNN_PARAMS);
+            for (int l = 0; l < aafwi::kL; ++l) {
+                c->wf[l] = calloc_dev<aafwi::bf16>(c, 9 * aafwi::kCoutP[l] * aafwi::kCinP[l]);
+                c->wd[l] = calloc_dev<aafwi::bf16>(c, 9 * aafwi::kCoutP[l] * aafwi::kCinP[l]);
+                c->act[l] = calloc_dev<aafwi::bf16>(c, P * aafwi::kCinP[l]);
+                c->dlt[l] = calloc_dev<aafwi::bf16>(c, P * aafwi::kCoutP[l]);
+            }
+            c->z = calloc_dev<float>(c, P);
+            c->part = calloc_dev<double>(c, (size_t)max_batch * aafwi::kRedBlocks * 3);
+            c->st_in = calloc_dev<double>(c, (size_t)max_batch * 3);
+            c->st1 = calloc_dev<double>(c, (size_t)max_batch * 2);
+            c->st2 = calloc_dev<double>(c, (size_t)max_batch * 2);
+            const size_t nchunk = (P + aafwi::kWgradChunk - 1) / aafwi::kWgradChunk;
+            c->wpart = calloc_dev<float>(c, nchunk * 9 * 32 * 32);
+            AAFWI_HIP(hipMemcpy(c->w, weights, sizeof(float) * AAFWI_CNN_PARAMS, hipMemcpyHostToDevice));
+            pack_weights(c);
+            AAFWI_HIP(hipStreamSynchronize(c->stream));
+        } catch (...) {
+            for (void* p : c->allocs) (void)hipFree(p);
+            delete c;
+            throw;
+        }
+        *out = c;
+        return AAFWI_OK;
+    });
+}
+
+extern "C" int aafwi_cnn_destroy(aafwi_cnn* c) {
+    return guarded([&]() -> int {
+        if (!c) return AAFWI_OK;
+        (void)hipStreamSynchronize(c->stream);
+        for (void* p : c->allocs) (void)hipFree(p);
+        delete c;
+        return AAFWI_OK;
+    });
+}
+
+extern "C" int aafwi_cnn_set_weights(aafwi_cnn* c, const float* weights) {
+    return guarded([&]() -> int {
+        AAFWI_REQUIRE(c && weights, "cnn_set_weights: NULL argument");
+        AAFWI_HIP(hipStreamSynchronize(c->stream));
+        AAFWI_HIP(hipMemcpy(c->w, weights, sizeof(float) * AAFWI_CNN_PARAMS, hipMemcpyHostToDevice));
+        AAFWI_HIP(hipMemset(c->mo, 0, sizeof(float) * AAFWI_CNN_PARAMS));
+        AAFWI_HIP(hipMemset(c->vo, 0, sizeof(float) * AAFWI_CNN_PARAMS));
+        c->step = 0;
+        pack_weights(c);
+        return AAFWI_OK;
+    });
+}
+
+extern "C" int aafwi_cnn_get_weights(aafwi_cnn* c, float* weights) {
+    return guarded([&]() -> int {
+        AAFWI_REQUIRE(c && weights, "cnn_get_weights: NULL argument");
+        AAFWI_HIP(hipStreamSynchronize(c->stream));
+        AAFWI_HIP(hipMemcpy(weights, c->w, sizeof(float) * AAFWI_CNN_PARAMS, hipMemcpyDeviceToHost));
+        return AAFWI_OK;
+    });
+}
+
+extern "C" int aafwi_cnn_forward(aafwi_cnn* c, int32_t B, const float* g, const float* m, float* z, float* d) {
+    return guarded([&]() -> int {
+        AAFWI_REQUIRE(c && g && m, "cnn_forward: NULL argument");
+        check_batch(c, B);
+        forward(c, B, g, m);
+        const long long N = (long long)B * c->H * c->W;
+        if (z) AAFWI_HIP(hipMemcpyAsync(z, c->z, sizeof(float) * N, hipMemcpyDeviceToDevice, c->stream));
+        if (d) {
+            hipLaunchKernelGGL(aafwi::k_direction, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, c->stream, N,
+                               (const float*)c->z, g, d);
+            AAFWI_HIP(hipGetLastError());
+        }
+        return AAFWI_OK;
+    });
+}
+
+extern "C" int aafwi_cnn_gradients(aafwi_cnn* c, int32_t B, const float* g, const float* m, const float* s,
+                                   float* grad, double* loss) {
+    return guarded([&]() -> int {
+        AAFWI_REQUIRE(c && g && m && s && grad, "cnn_gradients: NULL argument");
+        check_batch(c, B);
+        gradients(c, B, g, m, s, loss);
+        AAFWI_HIP(hipMemcpyAsync(grad, c->grad, sizeof(float) * AAFWI_CNN_PARAMS, hipMemcpyDeviceToDevice, c->stream));
+        return AAFWI_OK;
+    });
+}
+
+extern "C" int aafwi_cnn_train_step(aafwi_cnn* c, int32_t B, const float* g, const float* m, const float* s, float lr,
+                                    double* loss) {
+    return guarded([&]() -> int {
+        AAFWI_REQUIRE(c && g && m && s, "cnn_train_step: NULL argument");
+        AAFWI_REQUIRE(std::isfinite(lr) && lr > 0, "cnn_train_step: lr must be positive");
+        check_batch(c, B);
+        gradients(c, B, g, m, s, loss);
+        c->step += 1;
+        const float b1 = 0.9f, b2 = 0.999f;
+        const float c1 = 1.f - std::pow(b1, (float)c->step), c2 = 1.f - std::pow(b2, (float)c->step);
+        hipLaunchKernelGGL(aafwi::k_adam, dim3((AAFWI_CNN_PARAMS + 255) / 256), dim3(256), 0, c->stream,
+                           AAFWI_CNN_PARAMS, lr, b1, b2, 1e-8f, c1, c2, c->w, c->mo, c->vo, (const float*)c->grad);
+        AAFWI_HIP(hipGetLastError());
+        pack_weights(c);
+        return AAFWI_OK;
+    });
+}
