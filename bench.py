@@ -125,6 +125,117 @@ def batched_workload(args):
     print(json.dumps(out), flush=True)
 
 
+def cnn_timing(net, B, H, W, reps=20):
+    """Mean ms of one forward and one training step of the network on B
+    images of H x W, timed with HIP events on the network's stream."""
+    import torch
+    r = torch.Generator(device="cuda").manual_seed(5005)
+    g = torch.randn(B, H, W, device="cuda", generator=r)
+    m = 1.0 + 0.1 * torch.randn(B, H, W, device="cuda", generator=r)
+    s = -g + 0.3 * torch.randn(B, H, W, device="cuda", generator=r)
+    d = torch.empty_like(g)
+    out = {}
+    for name, fn in (("forward", lambda: net.forward(g, m, z=False, d=d)),
+                     ("train_step", lambda: net.train_step(g, m, s, 1e-12))):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(net.stream)
+        for _ in range(reps):
+            fn()
+        e1.record(net.stream)
+        e1.synchronize()
+        out[name] = e0.elapsed_time(e1) / reps
+    return out
+
+
+def learned_workload(args):
+    """Learned direction: training data from plain AA and L-BFGS runs, Adam
+    training of the network, then plain AA versus AA on G_theta (with the
+    plain-AA fallback) on held-out instances, and the network's own speed on
+    a batch of 8 images of 384 x 1024."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2008_11778_amd import CNN, Context
+    from paper_2008_11778_amd.inversion import AADescent, FWIProblem
+    from paper_2008_11778_amd.learned import LearnedAADescent, aa_pairs, init_weights, lbfgs_pairs, merge, train
+
+    dev = torch.device("cuda", 0)
+    t_all = time.perf_counter()
+    train_cases = [synth.learned_instance(i) for i in range(args.train_instances)]
+    t0 = time.perf_counter()
+    pa = aa_pairs(train_cases, M=10, iters=args.train_iters)
+    log(f"AA pairs: {len(pa)} in {time.perf_counter() - t0:.1f}s")
+    t0 = time.perf_counter()
+    pl = lbfgs_pairs(train_cases[: args.lbfgs_instances], M=10, iters=6)
+    log(f"L-BFGS pairs: {len(pl)} in {time.perf_counter() - t0:.1f}s")
+    pairs = merge(pa, pl)
+    t_data = time.perf_counter() - t_all
+    nz, nx = train_cases[0][2].shape
+    net = CNN(nz, nx, 8, init_weights(5005))
+    t0 = time.perf_counter()
+    hist = train(net, pairs, epochs=args.epochs, batch=8, lr=1e-3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    log(f"training: {t_train:.1f}s, epoch losses {[round(x, 4) for x in hist]}")
+
+    rows = []
+    for j in range(args.test_instances):
+        g, mt, m0 = synth.learned_instance(500 + j)
+        res = {}
+        with Context(g) as ctx:
+            d_obs = ctx.forward_model(torch.from_numpy(mt).to(dev)).clone()
+            for kind in ("plain", "learned"):
+                prob = FWIProblem(ctx, d_obs)
+                p0 = torch.from_numpy(m0).to(dev)
+                run = (AADescent(prob, p0.reshape(-1), None, M=10) if kind == "plain"
+                       else LearnedAADescent(prob, p0, net, M=10))
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                logs = [run.first()]
+                curve, times = [], []
+                for _ in range(args.iters):
+                    logs.append(run.iterate())
+                    curve.append(logs[-1].J)
+                    times.append(time.perf_counter() - t0)
+                J_end = prob.misfit_keep(run.p)
+                torch.cuda.synchronize()
+                curve.append(J_end)
+                times.append(time.perf_counter() - t0)
+                res[kind] = dict(J0=logs[0].J, curve=curve, times=times,
+                                 fallbacks=sum(int(getattr(x, "fallback", False)) for x in logs),
+                                 n_fwd=prob.n_fwd, n_adj=prob.n_adj)
+                run.close()
+        target = res["plain"]["curve"][-1]
+        reach = next((t for J, t in zip(res["learned"]["curve"], res["learned"]["times"]) if J <= target), None)
+        rows.append(dict(instance=500 + j, J0=res["plain"]["J0"], plain_final=target,
+                         learned_final=res["learned"]["curve"][-1], plain_s=res["plain"]["times"][-1],
+                         learned_s_to_plain_final=reach, learned_fallbacks=res["learned"]["fallbacks"],
+                         plain_fwd_adj=(res["plain"]["n_fwd"], res["plain"]["n_adj"]),
+                         learned_fwd_adj=(res["learned"]["n_fwd"], res["learned"]["n_adj"])))
+        log(f"held-out {500 + j}: J0 {rows[-1]['J0']:.4e} plain {target:.4e} learned "
+            f"{rows[-1]['learned_final']:.4e} fallbacks {rows[-1]['learned_fallbacks']}")
+    ratio = [r["learned_final"] / r["plain_final"] for r in rows]
+    speed = cnn_timing(CNN(384, 1024, 8, init_weights(5005)), 8, 384, 1024)
+    flops = 2.0 * 8 * 384 * 1024 * 19296
+    out = {"metric": "final misfit after k AA iterations, learned G_theta vs plain G (held-out instances)",
+           "value": round(float(np.exp(np.mean(np.log(ratio)))), 4), "unit": "geomean J_learned / J_plain",
+           "higher_is_better": False, "n_gpus": 1, "iters": args.iters, "instances": rows,
+           "fallback_rate": round(sum(r["learned_fallbacks"] for r in rows) / (args.iters * len(rows)), 3),
+           "reached_plain_final": sum(r["learned_s_to_plain_final"] is not None for r in rows),
+           "training": {"pairs": len(pairs), "aa_pairs": len(pa), "lbfgs_pairs": len(pl), "epochs": args.epochs,
+                        "data_s": round(t_data, 1), "train_s": round(t_train, 1),
+                        "epoch_loss": [round(x, 4) for x in hist]},
+           "cnn_8x384x1024": {"forward_ms": round(speed["forward"], 3), "train_step_ms": round(speed["train_step"], 3),
+                              "forward_tflops": round(flops / speed["forward"] / 1e9, 1),
+                              "train_tflops": round(3 * flops / speed["train_step"] / 1e9, 1),
+                              "mfma_bf16_peak_tflops": 2500.0},
+           "dtype": "f32 waves, bf16 network", "data": "synthetic"}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -136,10 +247,15 @@ def main():
                     help="after the run, copy this many MiB device-to-device (counter calibration)")
     ap.add_argument("--tile", type=int, default=-1,
                     help="rows per wave for every stepping kernel (-1 = autotune, 0 = library default)")
-    ap.add_argument("--workload", default="fwi", choices=["fwi", "batched"])
+    ap.add_argument("--workload", default="fwi", choices=["fwi", "batched", "learned"])
     ap.add_argument("--instances", type=int, default=32, help="batched workload: number of instances")
     ap.add_argument("--iters", type=int, default=10, help="batched workload: AA iterations per instance")
     ap.add_argument("--ckpt", type=int, default=70, help="batched workload: checkpoint interval")
+    ap.add_argument("--train-instances", type=int, default=48, help="learned workload: training models")
+    ap.add_argument("--train-iters", type=int, default=8, help="learned workload: AA iterations per training model")
+    ap.add_argument("--lbfgs-instances", type=int, default=8, help="learned workload: L-BFGS training runs")
+    ap.add_argument("--test-instances", type=int, default=8, help="learned workload: held-out models")
+    ap.add_argument("--epochs", type=int, default=20, help="learned workload: training epochs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the shot-sharded multi-GPU "
@@ -147,6 +263,8 @@ def main():
         sys.exit(2)
     if args.workload == "batched":
         return batched_workload(args)
+    if args.workload == "learned":
+        return learned_workload(args)
 
     import numpy as np
     import torch

@@ -120,7 +120,8 @@ class BatchedAADescent:
             Jt = self._forward(pending)
             for i in idx:
                 self.red.dot_diff(self._g(i), self._m(i), self.p[i], out=self.slope[i:i + 1])
-            slope = self.slope.cpu().numpy()
+            with torch.cuda.stream(s):
+                slope = self.slope.cpu().numpy()
             for i in idx:
                 if Jt[i] <= J[i] + self.c1 * slope[i]:
                     with torch.cuda.stream(s):

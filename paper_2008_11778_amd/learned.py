@@ -1,0 +1,228 @@
+"""Anderson acceleration of a learned descent map, its training data and its
+training loop.
+
+The map keeps the structure of the Method section: G_theta(p) = p - eta_theta
+d_theta(p), with d_theta = softplus(z) * g and z the network's output on
+[g / rms(g), (m - mean m) / std m] (so G_theta has the fixed points of G in
+eq. GD).  Algorithm 2 runs unchanged on G_theta (its history holds d_theta
+instead of g).  Fallback: when the line search accepts no lambda in
+{1, 1/2, 1/4, 1/8} and J(pbar_theta) >= J(p_k) as well, the iteration is redone
+with plain Anderson acceleration on G, whose history is fed with (p_k, g_k) at
+every iteration so that it is ready when needed.
+
+Training pairs (g_k, p_k, s_k = p_{k+1} - p_k) come from plain Anderson runs
+(all instances of a batch advanced together by BatchedAADescent) and from
+L-BFGS runs; the network learns the direction of the step those optimisers
+took, up to scale.
+"""
+from __future__ import annotations
+
+import dataclasses
+import time
+
+import numpy as np
+import torch
+
+from ._lib import AA, CNN, Batch, Context, Reducer, blend
+from .inversion import ARMIJO_C1, LAMBDAS, FWIProblem, IterLog, step_size
+
+
+@dataclasses.dataclass
+class LearnedLog(IterLog):
+    fallback: bool = False
+
+
+class LearnedAADescent:
+    """Algorithm 2 on G_theta with the plain-AA fallback (one problem)."""
+
+    def __init__(self, problem, p0: torch.Tensor, net: CNN, M: int = 10, eta: float | None = None,
+                 eta_theta: float | None = None, cond_max: float = 1e5, lambdas=LAMBDAS, c1: float = ARMIJO_C1,
+                 eta_frac: float = 0.02):
+        self.problem, self.net, self.M = problem, net, M
+        self.eta, self.eta_theta, self.eta_frac = eta, eta_theta, eta_frac
+        self.lambdas, self.c1 = lambdas, c1
+        self.shape = tuple(p0.shape)
+        if len(self.shape) != 2 or (net.nz, net.nx) != self.shape:
+            raise ValueError("the model must be an [nz][nx] image of the network's size")
+        n = p0.numel()
+        self.aa_theta = AA(n, M, cond_max)
+        self.aa_plain = AA(n, M, cond_max)
+        self.red = Reducer()
+        self.p = p0.detach().clone().reshape(-1)
+        self.g = torch.empty_like(self.p)
+        self.d = torch.empty_like(self.p)
+        self.pbar, self.ptilde = torch.empty_like(self.p), torch.empty_like(self.p)
+        self.pbar_plain, self.ptilde_plain = torch.empty_like(self.p), torch.empty_like(self.p)
+        self.trials = [torch.empty_like(self.p) for _ in range(2)]
+        self.k = 0
+        self.n_fallback = 0
+        self.t0 = time.perf_counter()
+
+    def _img(self, x):
+        return x.view(1, *self.shape)
+
+    def _direction(self):
+        self.net.forward(self._img(self.g), self._img(self.p), z=False, d=self._img(self.d))
+
+    def _maps(self):
+        self.aa_theta.step(self.p, self.d, self.eta_theta, self.pbar, self.ptilde)
+        self.aa_plain.step(self.p, self.g, self.eta, self.pbar_plain, self.ptilde_plain)
+
+    def _search(self, ptilde, J):
+        """Backtracking search of Algorithm 2 (Step 4) between ptilde and the
+        matching pbar; returns (lambda, accepted buffer) or (0, None)."""
+        pbar = self.pbar if ptilde is self.ptilde else self.pbar_plain
+        for i, lam in enumerate(self.lambdas):
+            trial = self.trials[i % 2]
+            blend(lam, ptilde, pbar, trial)
+            Jt = self.problem.misfit_keep(trial)
+            slope = float(self.red.dot_diff(self.g, trial, self.p).item())
+            if Jt <= J + self.c1 * slope:
+                self.trials[i % 2] = torch.empty_like(self.p)
+                return lam, trial
+        return 0.0, None
+
+    def _log(self, J, lam, fallback):
+        return LearnedLog(self.k, J, lam, int(self.aa_theta.mk.item()), self.problem.n_adj, self.problem.n_fwd,
+                          time.perf_counter() - self.t0, fallback)
+
+    def first(self) -> LearnedLog:
+        J = self.problem.gradient(self.p, self.g)
+        self._direction()
+        if self.eta is None:
+            self.eta = step_size(self.p, self.g, self.eta_frac)
+        if self.eta_theta is None:
+            self.eta_theta = step_size(self.p, self.d, self.eta_frac)
+        self._maps()
+        self.p = self.pbar
+        self.pbar = torch.empty_like(self.p)
+        return self._log(J, 0.0, False)
+
+    def iterate(self) -> LearnedLog:
+        self.k += 1
+        J = self.problem.gradient(self.p, self.g)
+        self._direction()
+        self._maps()
+        lam, p_next = self._search(self.ptilde, J)
+        fallback = False
+        if p_next is None:
+            if self.problem.misfit_keep(self.pbar) < J:
+                p_next = self.pbar
+                self.pbar = torch.empty_like(self.p)
+            else:
+                fallback = True
+                self.n_fallback += 1
+                lam, p_next = self._search(self.ptilde_plain, J)
+                if p_next is None:
+                    p_next = self.pbar_plain
+                    self.pbar_plain = torch.empty_like(self.p)
+        self.p = p_next
+        return self._log(J, lam, fallback)
+
+    def close(self):
+        for a in (self.aa_theta, self.aa_plain):
+            a.close()
+
+
+def init_weights(seed: int):
+    """He-normal weights per layer ([C_out][C_in][3][3]); the last layer is
+    scaled by 0.1 so that softplus(z) starts near ln 2 (d close to g)."""
+    from ._lib import CNN_SHAPES
+    rng = np.random.default_rng(seed)
+    ws = []
+    for i, shp in enumerate(CNN_SHAPES):
+        w = rng.standard_normal(shp) * np.sqrt(2.0 / (shp[1] * 9))
+        ws.append(w * (0.1 if i == len(CNN_SHAPES) - 1 else 1.0))
+    return ws
+
+
+# ---------------------------------------------------------------------------
+# training data
+# ---------------------------------------------------------------------------
+@dataclasses.dataclass
+class Pairs:
+    g: torch.Tensor   # [N][nz][nx] gradients g_k
+    m: torch.Tensor   # [N][nz][nx] models p_k
+    s: torch.Tensor   # [N][nz][nx] steps p_{k+1} - p_k
+    source: list      # "aa" or "lbfgs" per pair
+
+    def __len__(self):
+        return self.g.shape[0]
+
+
+def _observed(geoms, m_trues):
+    """Observed data of each instance: the HIP forward model on the true model."""
+    out = []
+    for geom, mt in zip(geoms, m_trues):
+        with Context(geom) as ctx:
+            out.append(ctx.forward_model(torch.from_numpy(np.ascontiguousarray(mt)).cuda()).clone())
+    torch.cuda.synchronize()
+    return out
+
+
+def aa_pairs(cases, M: int = 10, iters: int = 8, ckpt_every: int = 50):
+    """Pairs from plain Anderson runs on a batch of instances of one size.
+    cases: list of (geometry, m_true, m0) on the same grid."""
+    geoms = [c[0] for c in cases]
+    d_obs = _observed(geoms, [c[1] for c in cases])
+    gs, ms, ss = [], [], []
+    with Batch(geoms, d_obs, ckpt_every=ckpt_every, use_graphs=True) as b:
+        from .batched import BatchedAADescent
+        run = BatchedAADescent(b, [torch.from_numpy(c[2]).cuda() for c in cases], M=M)
+        run.first()
+        for _ in range(iters):
+            with torch.cuda.stream(b.stream):
+                pk = [x.clone() for x in run.p]
+            run.iterate()
+            with torch.cuda.stream(b.stream):
+                for i in range(b.N):
+                    gs.append(b.grad[i].clone())
+                    ms.append(pk[i])
+                    ss.append(run.p[i] - pk[i])
+        run.close()
+        b.stream.synchronize()
+    shape = cases[0][2].shape
+    st = lambda xs: torch.stack([x.view(shape) for x in xs])
+    return Pairs(st(gs), st(ms), st(ss), ["aa"] * len(gs))
+
+
+def lbfgs_pairs(cases, M: int = 10, iters: int = 6, ckpt_every: int = 50):
+    """Pairs from L-BFGS(M) runs (one context per instance)."""
+    from .comparators import LBFGS
+    gs, ms, ss = [], [], []
+    shape = cases[0][2].shape
+    for geom, mt, m0 in cases:
+        with Context(geom, ckpt_every=ckpt_every) as ctx:
+            d_obs = ctx.forward_model(torch.from_numpy(np.ascontiguousarray(mt)).cuda()).clone()
+            prob = FWIProblem(ctx, d_obs)
+            run = LBFGS(prob, torch.from_numpy(m0).cuda(), M)
+            for _ in range(iters):
+                pk, gk = run.p.clone(), run.g.clone()
+                run.iterate()
+                gs.append(gk.view(shape))
+                ms.append(pk.view(shape))
+                ss.append((run.p - pk).view(shape))
+    return Pairs(torch.stack(gs), torch.stack(ms), torch.stack(ss), ["lbfgs"] * len(gs))
+
+
+def merge(*ps: Pairs) -> Pairs:
+    return Pairs(torch.cat([p.g for p in ps]), torch.cat([p.m for p in ps]), torch.cat([p.s for p in ps]),
+                 sum((p.source for p in ps), []))
+
+
+def train(net: CNN, pairs: Pairs, epochs: int = 20, batch: int = 8, lr: float = 1e-3, seed: int = 5006):
+    """Adam over shuffled mini-batches; returns the mean loss of each epoch."""
+    rng = np.random.default_rng(seed)
+    n = len(pairs)
+    hist = []
+    for _ in range(epochs):
+        order = rng.permutation(n)
+        losses = []
+        for i in range(0, n - batch + 1, batch):
+            idx = torch.from_numpy(order[i:i + batch]).to(pairs.g.device)
+            gb = pairs.g.index_select(0, idx).contiguous()
+            mb = pairs.m.index_select(0, idx).contiguous()
+            sb = pairs.s.index_select(0, idx).contiguous()
+            losses.append(net.train_step(gb, mb, sb, lr).clone())
+        hist.append(float(torch.cat(losses).mean().item()))
+    return hist

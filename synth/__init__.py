@@ -29,7 +29,7 @@ __all__ = [
     "Geometry", "ricker", "make_geometry", "seed", "linear_gaussian_model",
     "layered_model", "smooth", "lsrtm_background", "sparse_reflectors",
     "config1", "config2", "config3", "config4_instances", "config5",
-    "small_case",
+    "learned_instance", "small_case",
 ]
 
 PURPOSE_LAYERS, PURPOSE_ANOMALY, PURPOSE_TEXTURE, PURPOSE_FAULTS, \
@@ -255,6 +255,18 @@ def config5(nshots=96, nt=4000):
     nz, nx, h = 384, 1024, 12.5
     g = make_geometry(nz, nx, h, nt, 1e-3, nshots, rec_stride=2)
     v_true = layered_model(nz, nx, h, 5, 1000)
+    v0 = smooth(v_true, 8.0)
+    g = g.replace(vref=float(v0.max()))
+    return g, to_m(v_true), to_m(v0)
+
+
+def learned_instance(instance, nz=128, nx=320, h=12.5, nshots=16, nt=2000):
+    """One inversion problem for training or testing the learned direction:
+    a layered model with faults (the config-5 family at a reduced size),
+    its smoothed starting model, 16 shots and receivers every second cell.
+    Training uses instances 0, 1, ...; held-out tests use instances >= 500."""
+    g = make_geometry(nz, nx, h, nt, 1e-3, nshots, rec_stride=2)
+    v_true = layered_model(nz, nx, h, 5, instance)
     v0 = smooth(v_true, 8.0)
     g = g.replace(vref=float(v0.max()))
     return g, to_m(v_true), to_m(v0)
