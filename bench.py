@@ -36,23 +36,106 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(nt_sample: int = 300):
-    """The FP64 oracle on one shot of the same grid, nt_sample steps,
-    forward + adjoint gradient; returns G point-updates/s."""
+def _oracle_shot(args):
+    """One shot of the FP64 oracle gradient (forward + adjoint) for nt steps;
+    returns its wall time.  Runs in a child process."""
+    nt, shot = args
     import numpy as np
 
     import synth
     from oracle import fd
-    g, m_true, m0 = synth.config2(nshots=64, nt=nt_sample)
-    g1 = g.subset_shots([0])
-    d_obs = np.zeros((1, nt_sample, g1.nrec), np.float32)
+    g, _, m0 = synth.config2(nshots=64, nt=nt)
+    g1 = g.subset_shots([shot])
+    d_obs = np.zeros((1, nt, g1.nrec), np.float32)
     t0 = time.perf_counter()
     fd.adjoint_gradient(g1, m0, d_obs)
-    dt = time.perf_counter() - t0
-    updates = 2.0 * g1.nz_p * g1.nx_p * nt_sample
-    return dict(value=updates / dt / 1e9, unit="Gpt-updates/s", cores=1, kind="oracle",
-                sample=f"1 of 64 shots, {nt_sample} of 4000 steps, forward + adjoint gradient "
-                       f"(FP64 NumPy, single thread), {dt:.1f} s")
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(target_s: float = 15.0):
+    """The FP64 oracle (NumPy, one thread per process) on the same grid:
+    one shot per child process on every host core available to this job (at
+    most 16), each for a number of steps sized from a short calibration run
+    so that the sample takes about ``target_s`` seconds; returns aggregate
+    G point-updates/s."""
+    import subprocess
+
+    import synth
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    t_cal = _oracle_shot((40, 0))
+    nt = int(max(60, min(4000, 40 * target_s / t_cal)))
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    code = "import sys; sys.path.insert(0, {!r}); from bench import _oracle_shot; print(_oracle_shot(({}, {})))"
+    t0 = time.perf_counter()
+    procs = [subprocess.Popen([sys.executable, "-c", code.format(ROOT, nt, s)], env=env, stdout=subprocess.PIPE,
+                              text=True) for s in range(cores)]
+    times = []
+    try:
+        for p in procs:
+            out, _ = p.communicate(timeout=20 * target_s + 120)
+            if p.returncode != 0:
+                raise RuntimeError(f"oracle child exited with {p.returncode}")
+            times.append(float(out.strip().splitlines()[-1]))
+    finally:
+        for p in procs:
+            if p.poll() is None:
+                p.kill()
+    wall = time.perf_counter() - t0
+    g, _, _ = synth.config2(nshots=64, nt=nt)
+    updates = 2.0 * g.nz_p * g.nx_p * nt * cores
+    return dict(value=updates / wall / 1e9, unit="Gpt-updates/s", cores=cores, kind="oracle",
+                sample=f"{cores} of 64 shots (one per process), {nt} of 4000 steps each, forward + adjoint "
+                       f"gradient in FP64 NumPy; wall {wall:.1f} s, per-shot {min(times):.1f}-{max(times):.1f} s")
+
+
+def source_digest():
+    """sha256 of the stepping-kernel source: counter readings are valid only
+    for the kernels they were taken on."""
+    import hashlib
+    path = os.path.join(ROOT, "paper_2008_11778_amd", "csrc", "wave_kernels.hip")
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of ``kernel`` from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), or None
+    when it is missing or was taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            tr = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if tr.get("source_sha256") != source_digest() or kernel not in tr.get("kernels", {}):
+        return None
+    k = tr["kernels"][kernel]
+    return round((k["fetch_kib"] * tr["fetch_factor"] + k["write_kib"] * tr["write_factor"]) * 1024.0)
+
+
+def stencil_large(dev, nt=400):
+    """Forward stepping kernel on the 1024 x 384 grid with 96 shots (two
+    wavefield planes of 177 MB each: more than the 256 MB Infinity Cache),
+    every launch event-timed; 16 algorithmic bytes per point-update."""
+    import torch
+
+    import synth
+    from paper_2008_11778_amd import Context
+    g, _, m0 = synth.config5(nt=nt)
+    with Context(g, ckpt_every=50) as ctx:
+        m = torch.from_numpy(m0).to(dev)
+        ctx.forward_model(m)
+        ctx.kernel_timing(1)
+        ctx.forward_model(m)
+        mean_ms, cnt = ctx.kernel_timing_read(0)
+        rows = ctx.get_tile(0)
+    pts = g.nz_p * g.nx_p * g.nshots
+    gbs = 16.0 * pts / (mean_ms / 1e3) / 1e9
+    return {"workload": f"forward step, {g.nx}x{g.nz} grid, {g.nshots} shots, 20-cell sponge",
+            "mean_launch_us": round(mean_ms * 1e3, 2), "timed_launches": cnt, "rows_per_wave": rows,
+            "gpt_updates_per_s": round(pts / (mean_ms / 1e3) / 1e9, 1),
+            "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "working_set_mb": round(2 * pts * 4 / 1e6, 1)}
 
 
 def batched_workload(args):
@@ -218,6 +301,7 @@ def learned_workload(args):
         log(f"held-out {500 + j}: J0 {rows[-1]['J0']:.4e} plain {target:.4e} learned "
             f"{rows[-1]['learned_final']:.4e} fallbacks {rows[-1]['learned_fallbacks']}")
     ratio = [r["learned_final"] / r["plain_final"] for r in rows]
+    reached = [r for r in rows if r["learned_s_to_plain_final"] is not None]
     speed = cnn_timing(CNN(384, 1024, 8, init_weights(5005)), 8, 384, 1024)
     flops = 2.0 * 8 * 384 * 1024 * 19296
     out = {"metric": "final misfit after k AA iterations, learned G_theta vs plain G (held-out instances)",
@@ -225,6 +309,9 @@ def learned_workload(args):
            "higher_is_better": False, "n_gpus": 1, "iters": args.iters, "instances": rows,
            "fallback_rate": round(sum(r["learned_fallbacks"] for r in rows) / (args.iters * len(rows)), 3),
            "reached_plain_final": sum(r["learned_s_to_plain_final"] is not None for r in rows),
+           "time_to_plain_final_speedup": (round(sum(r["plain_s"] for r in reached)
+                                                 / sum(r["learned_s_to_plain_final"] for r in reached), 3)
+                                           if reached else None),
            "training": {"pairs": len(pairs), "aa_pairs": len(pa), "lbfgs_pairs": len(pl), "epochs": args.epochs,
                         "data_s": round(t_data, 1), "train_s": round(t_train, 1),
                         "epoch_loss": [round(x, 4) for x in hist]},
@@ -251,10 +338,10 @@ def main():
     ap.add_argument("--instances", type=int, default=32, help="batched workload: number of instances")
     ap.add_argument("--iters", type=int, default=10, help="batched workload: AA iterations per instance")
     ap.add_argument("--ckpt", type=int, default=70, help="batched workload: checkpoint interval")
-    ap.add_argument("--train-instances", type=int, default=48, help="learned workload: training models")
+    ap.add_argument("--train-instances", type=int, default=200, help="learned workload: training models")
     ap.add_argument("--train-iters", type=int, default=8, help="learned workload: AA iterations per training model")
     ap.add_argument("--lbfgs-instances", type=int, default=8, help="learned workload: L-BFGS training runs")
-    ap.add_argument("--test-instances", type=int, default=8, help="learned workload: held-out models")
+    ap.add_argument("--test-instances", type=int, default=16, help="learned workload: held-out models")
     ap.add_argument("--epochs", type=int, default=20, help="learned workload: training epochs")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -265,6 +352,13 @@ def main():
         return batched_workload(args)
     if args.workload == "learned":
         return learned_workload(args)
+    # the oracle runs first, in child processes started before this process
+    # touches the GPU
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the FP64 oracle on a bounded sample ...")
+        cpu = cpu_baseline()
+        log(f"oracle: {cpu}")
 
     import numpy as np
     import torch
@@ -330,7 +424,7 @@ def main():
     per_launch_bytes = BYTES[dom] * cells * g.nshots
     achieved = per_launch_bytes / mean_s / 1e9
     roofline = dict(kernel=NAMES[dom], bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
-                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(NAMES[dom]),
                     mean_launch_us=round(kt[dom][0] * 1e3, 2), timed_launches=kt[dom][1],
                     bytes_per_launch=per_launch_bytes)
     kernels = {NAMES[k]: dict(mean_us=round(kt[k][0] * 1e3, 2), timed=kt[k][1],
@@ -376,10 +470,11 @@ def main():
         out["copy_probe"] = {"mib": args.copy_probe, "gbs_read_plus_write": round(gbs, 1)}
         log(f"copy probe: {args.copy_probe} MiB x5, {gbs:.1f} GB/s (read + write)")
         del a, b
-    if not args.no_cpu_baseline:
-        log("timing the FP64 oracle on a bounded sample ...")
-        out["cpu_baseline"] = cpu_baseline()
     ctx.close()
+    out["stencil_large"] = stencil_large(dev)
+    log(f"forward step on the large grid: {out['stencil_large']}")
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 
