@@ -29,6 +29,11 @@ sys.path.insert(0, ROOT)
 METRIC = "FD Gpt-updates/s (fwd+adj) & %HBM roofline; time to misfit target, AA vs +learned"
 HBM_PEAK_GBS = 8000.0
 BYTES = {0: 16, 1: 20, 2: 28, 3: 32}  # algorithmic bytes per point-update, per kernel id
+# two-step launches, algorithmic bytes per padded cell and launch (two updates):
+# forward reads u^n, u^{n-1}, Kp and writes u^{n+1}, u^{n+2}; recompute also
+# writes two q-hat planes; adjoint reads lam^{n+1}, lam^{n+2}, Kp, two q-hat
+# planes and the image, writes lam^n, lam^{n-1} and the image
+BYTES2 = {0: 20, 1: 28, 2: 36}
 NAMES = {0: "fwd_step", 1: "rec_step", 2: "adj_step", 3: "born_step"}
 
 
@@ -116,24 +121,29 @@ def measured_traffic(kernel: str):
 def stencil_large(dev, nt=400):
     """Forward stepping kernel on the 1024 x 384 grid with 96 shots (two
     wavefield planes of 177 MB each: more than the 256 MB Infinity Cache),
-    every launch event-timed; 16 algorithmic bytes per point-update."""
+    in the autotuned launch mode, every launch event-timed; algorithmic bytes
+    per padded cell 16 per one-step launch, 20 per two-step launch."""
     import torch
 
     import synth
     from paper_2008_11778_amd import Context
     g, _, m0 = synth.config5(nt=nt)
+    from paper_2008_11778_amd import autotune
     with Context(g, ckpt_every=50) as ctx:
         m = torch.from_numpy(m0).to(dev)
+        autotune.apply(ctx, autotune.tune(g, m, verbose=True))
         ctx.forward_model(m)
         ctx.kernel_timing(1)
         ctx.forward_model(m)
         mean_ms, cnt = ctx.kernel_timing_read(0)
         rows = ctx.get_tile(0)
+        steps = 2 if ctx.time_blocking() else 1
     pts = g.nz_p * g.nx_p * g.nshots
-    gbs = 16.0 * pts / (mean_ms / 1e3) / 1e9
+    gbs = (BYTES2[0] if steps == 2 else BYTES[0]) * pts / (mean_ms / 1e3) / 1e9
     return {"workload": f"forward step, {g.nx}x{g.nz} grid, {g.nshots} shots, 20-cell sponge",
             "mean_launch_us": round(mean_ms * 1e3, 2), "timed_launches": cnt, "rows_per_wave": rows,
-            "gpt_updates_per_s": round(pts / (mean_ms / 1e3) / 1e9, 1),
+            "steps_per_launch": steps,
+            "gpt_updates_per_s": round(steps * pts / (mean_ms / 1e3) / 1e9, 1),
             "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
             "working_set_mb": round(2 * pts * 4 / 1e6, 1)}
 
@@ -334,6 +344,7 @@ def main():
                     help="after the run, copy this many MiB device-to-device (counter calibration)")
     ap.add_argument("--tile", type=int, default=-1,
                     help="rows per wave for every stepping kernel (-1 = autotune, 0 = library default)")
+    ap.add_argument("--no-time-blocking", action="store_true", help="one time step per stepping launch")
     ap.add_argument("--workload", default="fwi", choices=["fwi", "batched", "learned"])
     ap.add_argument("--instances", type=int, default=32, help="batched workload: number of instances")
     ap.add_argument("--iters", type=int, default=10, help="batched workload: AA iterations per instance")
@@ -380,6 +391,8 @@ def main():
         from paper_2008_11778_amd import autotune
         tiles = autotune.tune(g, m0t, verbose=True)
         autotune.apply(ctx, tiles)
+    if args.no_time_blocking:
+        ctx.set_time_blocking(False)
     log(f"rows per wave (fwd, rec, adj, born): {[tiles[k] for k in range(4)]}")
     log(f"device memory held by the context: {ctx.device_bytes() / 2**30:.1f} GiB")
     cells = g.nz_p * g.nx_p
@@ -417,20 +430,27 @@ def main():
     for kid in (0, 1, 2):
         mean_ms, cnt = ctx.kernel_timing_read(kid)
         kt[kid] = (mean_ms, cnt)
-    launches = {0: n_fwd * g.nt, 1: n_adj * g.nt, 2: n_adj * g.nt}
+    tb = ctx.time_blocking()
+    k_ck = 50
+    per_bwd = sum((min(k_ck, g.nt - j * k_ck) + 1) // 2 if tb else min(k_ck, g.nt - j * k_ck)
+                  for j in range((g.nt + k_ck - 1) // k_ck))
+    launches = {0: n_fwd * ((g.nt + 1) // 2 if tb else g.nt), 1: n_adj * per_bwd, 2: n_adj * per_bwd}
     totals = {k: kt[k][0] * launches[k] for k in kt}
     dom = max(totals, key=totals.get)
     mean_s = kt[dom][0] / 1e3
-    per_launch_bytes = BYTES[dom] * cells * g.nshots
+    launch_bytes = {k: (BYTES2[k] if tb else BYTES[k]) * cells * g.nshots for k in kt}
+    per_launch_bytes = launch_bytes[dom]
     achieved = per_launch_bytes / mean_s / 1e9
     roofline = dict(kernel=NAMES[dom], bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
                     unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(NAMES[dom]),
                     mean_launch_us=round(kt[dom][0] * 1e3, 2), timed_launches=kt[dom][1],
-                    bytes_per_launch=per_launch_bytes)
-    kernels = {NAMES[k]: dict(mean_us=round(kt[k][0] * 1e3, 2), timed=kt[k][1],
-                              gbs=round(BYTES[k] * cells * g.nshots / (kt[k][0] / 1e3) / 1e9, 1) if kt[k][0] else None)
+                    bytes_per_launch=per_launch_bytes, steps_per_launch=2 if tb else 1)
+    kernels = {NAMES[k]: dict(mean_us=round(kt[k][0] * 1e3, 2), timed=kt[k][1], steps_per_launch=2 if tb else 1,
+                              bytes_per_launch=launch_bytes[k],
+                              gbs=round(launch_bytes[k] / (kt[k][0] / 1e3) / 1e9, 1) if kt[k][0] else None)
                for k in kt}
-    it_bytes = upd_fwd * (16 * n_fwd + 20 * n_adj + 28 * n_adj)
+    per_upd = {k: launch_bytes[k] / (cells * g.nshots) / (2 if tb else 1) for k in kt}
+    it_bytes = upd_fwd * (per_upd[0] * n_fwd + per_upd[1] * n_adj + per_upd[2] * n_adj)
     out = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -451,6 +471,7 @@ def main():
             "global_batch": g.nshots, "seq_len": g.nt, "parallelism": "single GPU",
             "rows_per_wave": {NAMES[k]: tiles[k] for k in range(4)},
         },
+        "time_blocking": tb,
         "roofline": roofline,
         "kernels": kernels,
         "iteration": {"gradients": n_adj, "forward_runs": n_fwd,

@@ -302,6 +302,18 @@ int aafwi_set_tile(aafwi_ctx* ctx, int32_t kernel_id, int32_t rows_per_wave);
 /* Current strip height of stepping kernel kernel_id. */
 int aafwi_get_tile(const aafwi_ctx* ctx, int32_t kernel_id, int32_t* rows_per_wave);
 
+/* Time blocking of the forward, recompute and adjoint steps: each launch
+ * advances two time levels of a wave tile, evaluating the first level also on
+ * the 4-cell frame the second one needs, so every field plane is read and
+ * written once per two steps.  Traces, images and gradients are bitwise the
+ * same with it on or off (off: one step per launch).  Default at creation:
+ * on when two wavefield planes of all shots (of all instances) exceed
+ * 256 MB, off otherwise.  Synchronises the stream; drops captured batch
+ * graphs. */
+int aafwi_set_time_blocking(aafwi_ctx* ctx, int enable);
+int aafwi_get_time_blocking(const aafwi_ctx* ctx, int* enabled);
+int aafwi_batch_set_time_blocking(aafwi_batch* b, int enable);
+
 /* Thread-local message for the last non-zero return on this thread. */
 const char* aafwi_last_error(void);
 

@@ -81,6 +81,9 @@ _sig("aafwi_kernel_timing", _vp, ctypes.c_int)
 _sig("aafwi_kernel_timing_read", _vp, ctypes.c_int, ctypes.POINTER(_f64), ctypes.POINTER(_i64))
 _sig("aafwi_set_tile", _vp, _i32, _i32)
 _sig("aafwi_get_tile", _vp, _i32, ctypes.POINTER(_i32))
+_sig("aafwi_set_time_blocking", _vp, ctypes.c_int)
+_sig("aafwi_get_time_blocking", _vp, ctypes.POINTER(ctypes.c_int))
+_sig("aafwi_batch_set_time_blocking", _vp, ctypes.c_int)
 _sig("aafwi_batch_destroy", _vp)
 _sig("aafwi_batch_misfits", _vp, _vp)
 _sig("aafwi_batch_set_active", _vp, _vp)
@@ -250,6 +253,15 @@ class Context:
     def set_tile(self, rows_per_wave: int, kernel_id: int = -1):
         _check(_lib.aafwi_set_tile(self._h, int(kernel_id), int(rows_per_wave)))
 
+    def set_time_blocking(self, enable: bool):
+        """Two time steps per launch (default) or one; results are bitwise equal."""
+        _check(_lib.aafwi_set_time_blocking(self._h, int(bool(enable))))
+
+    def time_blocking(self) -> bool:
+        v = ctypes.c_int()
+        _check(_lib.aafwi_get_time_blocking(self._h, ctypes.byref(v)))
+        return bool(v.value)
+
     def get_tile(self, kernel_id: int) -> int:
         v = _i32()
         _check(_lib.aafwi_get_tile(self._h, int(kernel_id), ctypes.byref(v)))
@@ -312,6 +324,9 @@ class Batch:
         if use_graphs:
             _check(_lib.aafwi_batch_use_graphs(self._h, 1))
         self.active = np.ones(self.N, dtype=np.uint8)
+
+    def set_time_blocking(self, enable: bool):
+        _check(_lib.aafwi_batch_set_time_blocking(self._h, int(bool(enable))))
 
     def set_active(self, mask):
         self.active = np.ascontiguousarray(mask, dtype=np.uint8)

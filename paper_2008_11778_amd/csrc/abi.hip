@@ -47,7 +47,9 @@ struct InstHost {
     int nrr = 0;
     std::vector<float> wavelet;
     // device memory
-    float *K = nullptr, *E = nullptr, *F0 = nullptr, *F1 = nullptr, *L0 = nullptr, *L1 = nullptr;
+    float *K = nullptr, *E = nullptr;
+    float* F[4] = {nullptr, nullptr, nullptr, nullptr};
+    float* L[4] = {nullptr, nullptr, nullptr, nullptr};
     float *GI = nullptr, *ckpt = nullptr, *qseg = nullptr, *d = nullptr, *wav = nullptr, *mkeep = nullptr;
     float *m = nullptr, *grad = nullptr;  // caller buffers of batch instances
     const float* dobs = nullptr;
@@ -64,6 +66,10 @@ struct Engine {
     aafwi::Inst* dinst = nullptr;
     aafwi::TileRec* dtiles[4] = {nullptr, nullptr, nullptr, nullptr};
     int ntiles[4] = {0, 0, 0, 0};
+    // two-step tables (56 output columns per wave) of forward, recompute, adjoint
+    aafwi::TileRec* dtiles2[3] = {nullptr, nullptr, nullptr};
+    int ntiles2[3] = {0, 0, 0};
+    bool tb = false;  // forward, recompute and adjoint advance two steps per launch
     int tz[4] = {0, 0, 0, 0};
     int* active = nullptr;  // device [N], batches only
     std::vector<int> active_host;
@@ -206,10 +212,10 @@ void add_instance(Engine* e, const aafwi_geometry& G, const aafwi_batch_io* io) 
     const size_t ndata = (size_t)g.S * G.nt * G.nrec;
     I.K = dalloc<float>(e, g.plane);
     I.E = dalloc<float>(e, g.plane);
-    I.F0 = dalloc<float>(e, I.field);
-    I.F1 = dalloc<float>(e, I.field);
-    I.L0 = dalloc<float>(e, I.field);
-    I.L1 = dalloc<float>(e, I.field);
+    for (int i = 0; i < 4; ++i) {
+        I.F[i] = dalloc<float>(e, I.field);
+        I.L[i] = dalloc<float>(e, I.field);
+    }
     I.GI = dalloc<float>(e, I.field);
     I.ckpt = dalloc<float>(e, (size_t)I.field * 2 * I.nseg);
     I.qseg = dalloc<float>(e, (size_t)I.field * e->k);
@@ -231,10 +237,10 @@ void add_instance(Engine* e, const aafwi_geometry& G, const aafwi_batch_io* io) 
     AAFWI_HIP(hipMemcpy(I.rnext, rnext.data(), sizeof(int) * rnext.size(), hipMemcpyHostToDevice));
     AAFWI_HIP(hipMemcpy(I.wav, I.wavelet.data(), sizeof(float) * G.nt, hipMemcpyHostToDevice));
     // padding columns of every field read as zero forever (stores never reach them)
-    AAFWI_HIP(hipMemset(I.F0, 0, sizeof(float) * I.field));
-    AAFWI_HIP(hipMemset(I.F1, 0, sizeof(float) * I.field));
-    AAFWI_HIP(hipMemset(I.L0, 0, sizeof(float) * I.field));
-    AAFWI_HIP(hipMemset(I.L1, 0, sizeof(float) * I.field));
+    for (int i = 0; i < 4; ++i) {
+        AAFWI_HIP(hipMemset(I.F[i], 0, sizeof(float) * I.field));
+        AAFWI_HIP(hipMemset(I.L[i], 0, sizeof(float) * I.field));
+    }
     e->in.push_back(std::move(I));
 }
 
@@ -245,16 +251,17 @@ void add_instance(Engine* e, const aafwi_geometry& G, const aafwi_batch_io* io) 
 // region c, so every XCD holds the same share of every instance (instances
 // whose records end early leave every XCD equally); regions are padded to
 // equal length with no-op tiles (inst = -1).
-void build_tiles(Engine* e, int kid) {
+std::vector<aafwi::TileRec> tile_table(Engine* e, int kid, int width) {
     constexpr int kX = 8, kWaves = 4;
     std::vector<std::vector<aafwi::TileRec>> region(kX);
     for (int i = 0; i < (int)e->in.size(); ++i) {
         const aafwi::WaveGrid& g = e->in[i].g;
         const int tz = std::min(e->tz[kid] ? e->tz[kid] : default_tz(g.nzp), g.nzp);
+        const int ntx = (g.nxp + width - 1) / width;
         std::vector<aafwi::TileRec> t;
         for (int s = 0; s < g.S; ++s)
             for (int z0 = 0; z0 < g.nzp; z0 += tz)
-                for (int tx = 0; tx < g.ntx; ++tx) t.push_back({i, s, tx * 64, (z0 << 16) | std::min(z0 + tz, g.nzp)});
+                for (int tx = 0; tx < ntx; ++tx) t.push_back({i, s, tx * width, (z0 << 16) | std::min(z0 + tz, g.nzp)});
         const size_t n = t.size();
         for (int c = 0; c < kX; ++c)
             region[c].insert(region[c].end(), t.begin() + n * c / kX, t.begin() + n * (c + 1) / kX);
@@ -268,13 +275,22 @@ void build_tiles(Engine* e, int kid) {
         all.insert(all.end(), region[c].begin(), region[c].end());
         all.resize((size_t)(c + 1) * L, aafwi::TileRec{-1, 0, 0, 0});
     }
-    if (e->dtiles[kid]) {
-        (void)hipFree(e->dtiles[kid]);
-        e->allocs.erase(std::remove(e->allocs.begin(), e->allocs.end(), (void*)e->dtiles[kid]), e->allocs.end());
+    return all;
+}
+
+void upload_tiles(Engine* e, aafwi::TileRec*& dst, int& count, const std::vector<aafwi::TileRec>& all) {
+    if (dst) {
+        (void)hipFree(dst);
+        e->allocs.erase(std::remove(e->allocs.begin(), e->allocs.end(), (void*)dst), e->allocs.end());
     }
-    e->dtiles[kid] = dalloc<aafwi::TileRec>(e, all.size());
-    AAFWI_HIP(hipMemcpy(e->dtiles[kid], all.data(), sizeof(aafwi::TileRec) * all.size(), hipMemcpyHostToDevice));
-    e->ntiles[kid] = (int)all.size();
+    dst = dalloc<aafwi::TileRec>(e, all.size());
+    AAFWI_HIP(hipMemcpy(dst, all.data(), sizeof(aafwi::TileRec) * all.size(), hipMemcpyHostToDevice));
+    count = (int)all.size();
+}
+
+void build_tiles(Engine* e, int kid) {
+    upload_tiles(e, e->dtiles[kid], e->ntiles[kid], tile_table(e, kid, 64));
+    if (kid < 3) upload_tiles(e, e->dtiles2[kid], e->ntiles2[kid], tile_table(e, kid, aafwi::kTile2));
 }
 
 void finalize(Engine* e) {
@@ -285,7 +301,11 @@ void finalize(Engine* e) {
         aafwi::Inst& D = tab[i];
         D.g = I.g;
         D.K = I.K; D.E = I.E;
-        D.F0 = I.F0; D.F1 = I.F1; D.L0 = I.L0; D.L1 = I.L1; D.GI = I.GI;
+        for (int j = 0; j < 4; ++j) {
+            D.F[j] = I.F[j];
+            D.L[j] = I.L[j];
+        }
+        D.GI = I.GI;
         D.ckpt = I.ckpt; D.qseg = I.qseg; D.d = I.d; D.r = I.d; D.wav = I.wav;
         D.src = {I.src};
         D.rm = {I.rowmap, I.xmap, I.rnext, I.nrr, I.R};
@@ -296,6 +316,13 @@ void finalize(Engine* e) {
     e->dinst = dalloc<aafwi::Inst>(e, N);
     AAFWI_HIP(hipMemcpy(e->dinst, tab.data(), sizeof(aafwi::Inst) * N, hipMemcpyHostToDevice));
     for (int kid = 0; kid < 4; ++kid) build_tiles(e, kid);
+    // Default launch mode: two steps per launch once one time level pair of
+    // every instance (the one-step working set) outgrows the 256 MB
+    // Infinity Cache; below that, one-step kernels re-read their planes
+    // from the cache and are faster.  The autotuner measures both.
+    long long pair_bytes = 0;
+    for (const InstHost& I : e->in) pair_bytes += 2LL * I.field * (long long)sizeof(float);
+    e->tb = pair_bytes > (256LL << 20);
     e->J = dalloc<double>(e, N);
     e->part = dalloc<double>(e, aafwi::kReduceBlocks);
     e->flag = dalloc<int>(e, 1);
@@ -336,6 +363,11 @@ void step(Engine* e, int kid, const aafwi::StepArgs& a) {
     aafwi::launch_step(kid, e->stream, e->dtiles[kid], e->ntiles[kid], e->dinst, a);
 }
 
+void step2(Engine* e, int kid, const aafwi::StepArgs& a) {
+    Timed t(e, kid);
+    aafwi::launch_step2(kid, e->stream, e->dtiles2[kid], e->ntiles2[kid], e->dinst, a);
+}
+
 void model_prep(Engine* e, int i, const float* m) {
     const InstHost& I = e->in[i];
     const double c2 = ((double)I.dt / (double)I.h) * ((double)I.dt / (double)I.h);
@@ -354,14 +386,16 @@ void run_forward(Engine* e, const std::vector<const float*>& m, float* d_ovr, bo
     const int N = (int)e->in.size();
     for (int i = 0; i < N; ++i) {
         model_prep(e, i, m[i]);
-        aafwi::launch_zero(e->stream, e->in[i].F0, e->in[i].field);
-        aafwi::launch_zero(e->stream, e->in[i].F1, e->in[i].field);
+        for (int j = 0; j < 4; ++j) aafwi::launch_zero(e->stream, e->in[i].F[j], e->in[i].field);
     }
     aafwi::StepArgs a{0, 0, keep ? 1 : 0, d_ovr, nullptr, e->active};
     const int T = max_nt(e);
-    for (int n = 0; n < T; ++n) {
+    for (int n = 0; n < T; n += e->tb ? 2 : 1) {
         a.n = n;
-        step(e, AAFWI_K_FWD_STEP, a);
+        if (e->tb)
+            step2(e, AAFWI_K_FWD_STEP, a);
+        else
+            step(e, AAFWI_K_FWD_STEP, a);
     }
     if (keep)
         for (int i = 0; i < N; ++i)
@@ -384,8 +418,7 @@ void run_backward(Engine* e, const float* r_ovr, const std::vector<float*>& grad
     for (int i = 0; i < N; ++i) {
         InstHost& I = e->in[i];
         model_prep(e, i, I.mkeep);  // Kp of the kept run (a Born call may have replaced it)
-        aafwi::launch_zero(e->stream, I.L0, I.field);
-        aafwi::launch_zero(e->stream, I.L1, I.field);
+        for (int j = 0; j < 4; ++j) aafwi::launch_zero(e->stream, I.L[j], I.field);
         aafwi::launch_zero(e->stream, I.GI, I.field);
         maxseg = std::max(maxseg, I.nseg);
     }
@@ -394,13 +427,24 @@ void run_backward(Engine* e, const float* r_ovr, const std::vector<float*>& grad
         int len = 0;
         for (auto& I : e->in) len = std::max(len, seg_len(e, I, J));
         a.seg = J;
-        for (int tt = 0; tt < len; ++tt) {
-            a.n = tt;
-            step(e, AAFWI_K_REC_STEP, a);
-        }
-        for (int tt = len - 1; tt >= 0; --tt) {
-            a.n = tt;
-            step(e, AAFWI_K_ADJ_STEP, a);
+        if (e->tb) {
+            for (int tt = 0; tt < len; tt += 2) {
+                a.n = tt;
+                step2(e, AAFWI_K_REC_STEP, a);
+            }
+            for (int tt = len - 1; tt >= 0; tt -= 2) {
+                a.n = tt;
+                step2(e, AAFWI_K_ADJ_STEP, a);
+            }
+        } else {
+            for (int tt = 0; tt < len; ++tt) {
+                a.n = tt;
+                step(e, AAFWI_K_REC_STEP, a);
+            }
+            for (int tt = len - 1; tt >= 0; --tt) {
+                a.n = tt;
+                step(e, AAFWI_K_ADJ_STEP, a);
+            }
         }
     }
     for (int i = 0; i < N; ++i) {
@@ -472,6 +516,14 @@ int set_tile(Engine* e, int kernel_id, int rows) {
             e->tz[k] = rows;
             build_tiles(e, k);
         }
+    for (auto& kv : e->graphs) (void)hipGraphExecDestroy(kv.second);
+    e->graphs.clear();
+    return AAFWI_OK;
+}
+
+int set_time_blocking(Engine* e, int enable) {
+    AAFWI_HIP(hipStreamSynchronize(e->stream));
+    e->tb = enable != 0;
     for (auto& kv : e->graphs) (void)hipGraphExecDestroy(kv.second);
     e->graphs.clear();
     return AAFWI_OK;
@@ -621,10 +673,10 @@ extern "C" int aafwi_born(aafwi_ctx* c, const float* m0, const float* dm, float*
         // the kept checkpoints are untouched; Kp is rebuilt before any backward pass
         model_prep(e, 0, m0);
         aafwi::launch_born_prep(e->stream, I.g, m0, dm, I.E);
-        aafwi::launch_zero(e->stream, I.F0, I.field);
-        aafwi::launch_zero(e->stream, I.F1, I.field);
-        aafwi::launch_zero(e->stream, I.L0, I.field);
-        aafwi::launch_zero(e->stream, I.L1, I.field);
+        for (int j = 0; j < 2; ++j) {
+            aafwi::launch_zero(e->stream, I.F[j], I.field);
+            aafwi::launch_zero(e->stream, I.L[j], I.field);
+        }
         aafwi::StepArgs a{0, 0, 0, d_scat, nullptr, nullptr};
         for (int n = 0; n < I.nt; ++n) {
             a.n = n;
@@ -662,6 +714,21 @@ extern "C" int aafwi_set_tile(aafwi_ctx* c, int32_t kernel_id, int32_t rows) {
     return guarded([&]() -> int {
         AAFWI_REQUIRE(c, "set_tile: NULL context");
         return set_tile(c->e, kernel_id, rows);
+    });
+}
+
+extern "C" int aafwi_set_time_blocking(aafwi_ctx* c, int enable) {
+    return guarded([&]() -> int {
+        AAFWI_REQUIRE(c, "set_time_blocking: NULL context");
+        return set_time_blocking(c->e, enable);
+    });
+}
+
+extern "C" int aafwi_get_time_blocking(const aafwi_ctx* c, int* enabled) {
+    return guarded([&]() -> int {
+        AAFWI_REQUIRE(c && enabled, "get_time_blocking: NULL argument");
+        *enabled = c->e->tb ? 1 : 0;
+        return AAFWI_OK;
     });
 }
 
@@ -807,6 +874,13 @@ extern "C" int aafwi_batch_set_tile(aafwi_batch* b, int32_t kernel_id, int32_t r
     return guarded([&]() -> int {
         AAFWI_REQUIRE(b, "batch_set_tile: NULL batch");
         return set_tile(b->e, kernel_id, rows);
+    });
+}
+
+extern "C" int aafwi_batch_set_time_blocking(aafwi_batch* b, int enable) {
+    return guarded([&]() -> int {
+        AAFWI_REQUIRE(b, "batch_set_time_blocking: NULL batch");
+        return set_time_blocking(b->e, enable);
     });
 }
 

@@ -68,10 +68,14 @@ struct Inst {
     WaveGrid g;
     const float* K;        // Kp on the padded grid [plane]
     const float* E;        // Born perturbation dm/m0 [plane]
-    float* F0;             // forward (or background) pair [S][plane]
-    float* F1;
-    float* L0;             // adjoint (or scattered) pair [S][plane]
-    float* L1;
+    // Wavefields [S][plane].  One-step kernels ping-pong between F[0..1]
+    // (forward), L[0..1] (adjoint) and, for Born, F[0..1] (background) and
+    // L[0..1] (scattered): level n+1 overwrites level n-1 in place, which
+    // only the owning point reads.  Two-step kernels keep level n in
+    // F[n % 4] / L[n % 4], so a launch that advances two levels never
+    // overwrites a level that a neighbouring tile may still read.
+    float* F[4];
+    float* L[4];
     float* GI;             // image accumulators [S][plane]
     float* ckpt;           // [nseg][2][S][plane]
     float* qseg;           // [k][S][plane]
@@ -85,7 +89,8 @@ struct Inst {
     long long field;       // S * plane floats
 };
 
-// One wave's work: 64 columns from x0, rows [z0, z1) of shot s of instance
+// One wave's work: 64 columns from x0 (one-step kernels) or 56 output
+// columns from x0 (two-step kernels), rows [z0, z1) of shot s of instance
 // inst.  z01 packs z0 << 16 | z1.
 struct TileRec {
     int inst, s, x0, z01;
@@ -93,7 +98,9 @@ struct TileRec {
 
 // Per-launch step selection.  Forward and Born: n is the time step.
 // Recompute and adjoint: seg counts segments from the end of each instance's
-// record and n is the step inside the segment.  Instances derive their own
+// record and n is the step inside the segment.  Two-step launches cover
+// steps {n, n+1} (forward, recompute) or {n, n-1} (adjoint), clipped to each
+// instance's range.  Instances derive their own
 // step index, buffer parity and checkpoint slot from these, so instances with
 // different record lengths share one launch.
 struct StepArgs {
@@ -115,6 +122,9 @@ void launch_compare(hipStream_t st, long long n, const float* a, const float* b,
 // Stepping kernels over a tile table (kernel ids as AAFWI_K_*).
 void launch_step(int kernel_id, hipStream_t st, const TileRec* tiles, int ntiles, const Inst* insts,
                  const StepArgs& a);
+void launch_step2(int kernel_id, hipStream_t st, const TileRec* tiles, int ntiles, const Inst* insts,
+                  const StepArgs& a);
+constexpr int kTile2 = 56;  // output columns of a two-step wave tile
 // Per-instance kernels; `active`/`inst` make them no-ops for masked instances.
 void launch_fold(hipStream_t st, const WaveGrid& g, float inv_dt2, const float* gimg, float* grad,
                  const int* active, int inst);

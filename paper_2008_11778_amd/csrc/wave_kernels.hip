@@ -206,7 +206,8 @@ __device__ __forceinline__ void stage(float* rows, const Queue<U>& c, const floa
 
 // Sponge factors (A, B) of row z for this lane; exactly (1, 1) when the whole
 // tile row is in the undamped interior (a wave-uniform branch).
-__device__ __forceinline__ void sponge_ab(const WaveGrid& g, const Lanes& L, int z, float& A, float& B) {
+template <typename LanesT>
+__device__ __forceinline__ void sponge_ab(const WaveGrid& g, const LanesT& L, int z, float& A, float& B) {
     const bool interior = L.interior_x && z >= g.nb && z < g.nb + g.nz;
     if (interior) {
         A = 1.0f;
@@ -249,8 +250,8 @@ __global__ __launch_bounds__(256) void k_fwd_step(const TileRec* __restrict__ ti
     if (!kRecompute) {
         n = a.n;
         if (n >= I.nt) return;
-        u = (n & 1) ? I.F1 : I.F0;  // u^n
-        out = (n & 1) ? I.F0 : I.F1;  // u^{n-1}, overwritten by u^{n+1}
+        u = I.F[n & 1];  // u^n
+        out = I.F[(n + 1) & 1];  // u^{n-1}, overwritten by u^{n+1}
         uprev = out;
         if (a.keep && n % I.k == 0) ck_u = I.ckpt + (long long)(n / I.k) * 2 * I.field;
     } else {
@@ -258,18 +259,18 @@ __global__ __launch_bounds__(256) void k_fwd_step(const TileRec* __restrict__ ti
         const int tt = a.n;
         n = j * I.k + tt;
         if (j < 0 || n >= I.nt) return;
-        const float* c0 = I.ckpt + (long long)j * 2 * I.field;  // u^{jk}
+        const float* c0 = I.ckpt + (long long)j * 2 * I.field;  // u^{jk}, u^{jk-1}
         if (tt == 0) {
             u = c0;
             uprev = c0 + I.field;
-            out = I.F0;
+            out = I.F[0];
         } else if (tt == 1) {
-            u = I.F0;
+            u = I.F[0];
             uprev = c0;
-            out = I.F1;
+            out = I.F[1];
         } else {
-            u = (tt & 1) ? I.F0 : I.F1;
-            out = (tt & 1) ? I.F1 : I.F0;
+            u = I.F[(tt + 1) & 1];
+            out = I.F[tt & 1];
             uprev = out;
         }
         q = I.qseg + (long long)tt * I.field;
@@ -360,9 +361,9 @@ __global__ __launch_bounds__(256) void k_adj_step(const TileRec* __restrict__ ti
     const int n = j * I.k + tt;
     if (j < 0 || n >= I.nt) return;
     // lam^{n+1} sits in L[(nt-1-n) & 1]; lam^n overwrites lam^{n+2} in the other
-    const bool par = ((I.nt - 1 - n) & 1) != 0;
-    const float* l = par ? I.L1 : I.L0;
-    float* out = par ? I.L0 : I.L1;
+    const int par = (I.nt - 1 - n) & 1;
+    const float* l = I.L[par];
+    float* out = I.L[par ^ 1];
     const float* lprev = out;
     const float* r = a.r_ovr ? a.r_ovr : I.r;
     const float* q = I.qseg + (long long)tt * I.field;
@@ -432,6 +433,374 @@ __global__ __launch_bounds__(256) void k_adj_step(const TileRec* __restrict__ ti
 }
 
 // ---------------------------------------------------------------------------
+// Two steps per launch (forward, recompute, adjoint).
+//
+// A wave owns 56 output columns [x0, x0+56) and rows [z0, z1).  Its 64 lanes
+// cover columns x0-4 .. x0+59.  Step one (level n -> n+1) is evaluated on all
+// 64 lanes for rows z0-4 .. z1+3, which is exactly the 4-cell neighbourhood
+// that step two (n+1 -> n+2) needs for the owned columns and rows; step two
+// trails step one by one register block (4 rows) and reads the step-one
+// values from registers (z) and from an LDS row (x).  Out-of-grid rows and
+// columns of step one come out zero by themselves: their loads, Kp
+// included, read zero through the buffer range check.  Each time level is
+// read and written once per launch instead of once per step; the price is
+// the recomputed 4-cell frame (64 of 56 columns, tz+8 of tz rows).  The
+// arithmetic of every point is that of the one-step kernels, in the same
+// order, so both paths give bitwise identical fields, traces and images.
+// ---------------------------------------------------------------------------
+struct Lanes2 {
+    int xc;           // column of this lane: x0 - 4 + lane
+    bool xin;         // inside the padded grid
+    bool own;         // an output column of this tile (lanes 4..59)
+    unsigned base;    // byte offset of (row 0, xc), or out of the buffer
+    unsigned hbase;   // lanes 0-7: (row 0, x-halo column of step one)
+    int hslot;
+    bool interior_x;  // all 64 lane columns undamped
+    float sx;
+};
+
+__device__ __forceinline__ Lanes2 lanes2(const WaveGrid& g, const Tile& t) {
+    Lanes2 L;
+    L.xc = t.x0 - 4 + t.lane;
+    L.xin = L.xc >= 0 && L.xc < g.nxp;
+    L.own = t.lane >= 4 && t.lane < 60 && L.xin;
+    L.base = L.xin ? (unsigned)L.xc * 4u : kOut;
+    const int hx = (t.lane < 4) ? (t.x0 - 8 + t.lane) : (t.x0 + 56 + t.lane);
+    const bool hok = t.lane < 8 && hx >= 0 && hx < g.nxp;
+    L.hbase = hok ? (unsigned)hx * 4u : kOut;
+    L.hslot = (t.lane < 4) ? t.lane : (64 + t.lane);
+    L.interior_x = (t.x0 - 4 >= g.nb) && (t.x0 + 60 <= g.nb + g.nx);
+    L.sx = sponge_st(L.xc, g.nx, g.nb, g.inv_nb, g.scoef);
+    return L;
+}
+
+// Byte offset of row z (may be negative: the unsigned sum then lies beyond
+// the plane and reads as zero).
+__device__ __forceinline__ unsigned row_off(int z, int pitch) { return (unsigned)(z * pitch * 4); }
+
+// Stage the step-two centre rows (no halo: lanes 0-3 and 60-63 of step two
+// are not output columns, whatever they read).
+template <int U>
+__device__ __forceinline__ void stage2(float* rows, const Queue<U>& b, int lane) {
+    wave_sync();
+#pragma unroll
+    for (int j = 0; j < U; ++j) rows[j * 72 + 4 + lane] = b.q[j + 4];
+    wave_sync();
+}
+
+// Receiver-row slots of the rows z0-4 .. z0+123 a two-step tile touches,
+// held one per lane in two registers (loaded once per tile) and read back per
+// row with a wave-uniform lane index: no memory access inside the row loop,
+// whose prefetched loads would otherwise all be waited for.
+struct FrameRows {
+    int lo, hi;
+};
+
+__device__ __forceinline__ FrameRows frame_rowmap(const RecMaps& rm, const WaveGrid& g, const Tile& t) {
+    FrameRows f;
+    const int za = t.z0 - 4 + t.lane, zb = t.z0 + 60 + t.lane, zmax = min(t.z1 + 4, g.nzp);
+    f.lo = (za >= 0 && za < zmax) ? rm.rowmap[t.s * g.nzp + za] : -1;
+    f.hi = (zb < zmax) ? rm.rowmap[t.s * g.nzp + zb] : -1;
+    return f;
+}
+
+__device__ __forceinline__ int frame_slot(const FrameRows& f, int z, int z0) {
+    const int i = z - (z0 - 4);
+    return i < 64 ? __builtin_amdgcn_readlane(f.lo, i) : __builtin_amdgcn_readlane(f.hi, i - 64);
+}
+
+// Sum of the residuals injected at this lane's node of row slot `slot`.
+__device__ __forceinline__ float injected(const RecMaps& rm, const WaveGrid& g, int s, int slot, int x,
+                                          const float* r, int nt, int n) {
+    float rs = 0.0f;
+    int ri = rm.xmap[((long long)s * rm.nrr + slot) * g.pitch + x];
+    while (ri >= 0) {
+        rs += r[((long long)s * nt + n) * rm.R + ri];
+        ri = rm.next[s * rm.R + ri];
+    }
+    return rs;
+}
+
+__device__ __forceinline__ void sample(const RecMaps& rm, const WaveGrid& g, int s, int slot, int x, float* d,
+                                       int nt, int n, float v) {
+    int ri = rm.xmap[((long long)s * rm.nrr + slot) * g.pitch + x];
+    while (ri >= 0) {
+        d[((long long)s * nt + n) * rm.R + ri] = v;
+        ri = rm.next[s * rm.R + ri];
+    }
+}
+
+template <int U, bool kRecompute>
+__global__ __launch_bounds__(256) void k_fwd_step2(const TileRec* __restrict__ tiles, int ntiles,
+                                                   const Inst* __restrict__ insts, StepArgs a) {
+    __shared__ float lds[kWaves][2 * U * 72];
+    const Tile t = decode_tile(tiles, ntiles);
+    if (!t.live) return;
+    if (a.active && !a.active[t.inst]) return;
+    const Inst& I = insts[t.inst];
+    const WaveGrid g = I.g;
+    int n, tt = 0, cnt;
+    const float* u;
+    const float* uprev;
+    if (!kRecompute) {
+        n = a.n;
+        if (n >= I.nt) return;
+        cnt = min(2, I.nt - n);
+        u = I.F[n & 3];
+        uprev = I.F[(n + 3) & 3];
+    } else {
+        const int j = I.nseg - 1 - a.seg;
+        tt = a.n;
+        if (j < 0) return;
+        const int len = min(I.k, I.nt - j * I.k);
+        if (tt >= len) return;
+        cnt = min(2, len - tt);
+        n = j * I.k + tt;
+        const float* c0 = I.ckpt + (long long)j * 2 * I.field;  // u^{jk}, u^{jk-1}
+        u = tt == 0 ? c0 : I.F[n & 3];
+        uprev = tt == 0 ? c0 + I.field : I.F[(n + 3) & 3];
+    }
+    const bool two = cnt == 2;
+    float* out1 = I.F[(n + 1) & 3];
+    float* out2 = I.F[(n + 2) & 3];
+    // checkpoint slots reached by this launch: (u^n, u^{n-1}) and (u^{n+1}, u^n)
+    float* ck0 = nullptr;
+    float* ck1 = nullptr;
+    if (!kRecompute && a.keep) {
+        if (n % I.k == 0) ck0 = I.ckpt + (long long)(n / I.k) * 2 * I.field;
+        if (two && (n + 1) % I.k == 0) ck1 = I.ckpt + (long long)((n + 1) / I.k) * 2 * I.field;
+    }
+    const float w0 = I.wav[n];
+    const float w1 = two ? I.wav[n + 1] : 0.0f;
+    const int nt = I.nt;
+    const RecMaps rm = I.rm;
+    float* d = a.d_ovr ? a.d_ovr : I.d;
+    const int lane = t.lane;
+    float* rowsA = &lds[threadIdx.x >> 6][0];
+    float* rowsB = rowsA + U * 72;
+    const long long off0 = (long long)t.s * g.plane;
+    const Rsrc UR = view(u + off0, g.plane);
+    const Rsrc UP = view(uprev + off0, g.plane);
+    const Rsrc O1 = view(out1 + off0, g.plane);
+    const Rsrc O2 = view(out2 + off0, g.plane);
+    const Rsrc KR = view(I.K, g.plane);
+    const Rsrc C0U = view(ck0 ? ck0 + off0 : u, g.plane);
+    const Rsrc C0P = view(ck0 ? ck0 + I.field + off0 : u, g.plane);
+    const Rsrc C1U = view(ck1 ? ck1 + off0 : u, g.plane);
+    const Rsrc C1P = view(ck1 ? ck1 + I.field + off0 : u, g.plane);
+    float* q0 = kRecompute ? I.qseg + (long long)tt * I.field + off0 : out1;
+    const Rsrc Q0 = view(q0, g.plane);
+    const Rsrc Q1 = view(kRecompute && two ? q0 + I.field : out1, g.plane);
+    const Lanes2 L = lanes2(g, t);
+    const int2 sn = I.src.node[t.s];
+    const unsigned rb = (unsigned)g.pitch * 4u;
+    const unsigned own_mask = L.own ? 0u : kOut;  // OR-ed into store offsets
+    const int my_rm = kRecompute ? -1 : strip_rowmap(rm, g, t);
+
+    const int za0 = t.z0 - 4;
+    const int zend = two ? t.z1 + 4 : t.z1;
+    unsigned o = L.base + row_off(za0, g.pitch), oh = L.hbase + row_off(za0, g.pitch);
+    Queue<U> c;   // u^n at rows za-4 .. za+U+3
+    Queue<U> b;   // u^{n+1} at rows za-8 .. za+U-1
+#pragma unroll
+    for (int i = 0; i < U + 8; ++i) b.q[i] = 0.0f;
+    queue_prime(c, UR, o, rb);
+    float pv[U], kv[U], hv[U], kb[U];
+    rows_fetch(pv, UP, o, rb);
+    rows_fetch(kv, KR, o, rb);
+    rows_fetch(hv, UR, oh, rb);
+#pragma unroll
+    for (int j = 0; j < U; ++j) kb[j] = 0.0f;
+    for (int za = za0; za < zend; za += U, o += U * rb, oh += U * rb) {
+        float nq[U], npv[U], nkv[U], nhv[U];
+        queue_fetch(nq, UR, o, rb);
+        rows_fetch(npv, UP, o + U * rb, rb);
+        rows_fetch(nkv, KR, o + U * rb, rb);
+        rows_fetch(nhv, UR, oh + U * rb, rb);
+        stage(rowsA, c, hv, lane, L.hslot);
+        // step one at rows za .. za+U-1, all lanes
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const int z = za + j;
+            float acc = lap8(c, j, rowsA + j * 72, lane);
+            if (z == sn.x && L.xc == sn.y) acc += w0;
+            float A, B;
+            sponge_ab(g, L, z, A, B);
+            const float qh = kv[j] * acc;
+            const float un = fmaf(2.0f * A, c.q[j + 4], fmaf(-B, pv[j], qh));
+            b.q[8 + j] = un;
+            if (z >= t.z0 && z < t.z1) {
+                const unsigned oz = (o + (unsigned)j * rb) | own_mask;
+                if (ck0) {
+                    bst(C0U, oz, c.q[j + 4]);
+                    bst(C0P, oz, pv[j]);
+                }
+                if (ck1) {
+                    bst(C1U, oz, un);
+                    bst(C1P, oz, c.q[j + 4]);
+                }
+                bst(O1, oz, un);
+                if (kRecompute) bst(Q0, oz, qh);
+                if (!kRecompute) {
+                    const int slot = __builtin_amdgcn_readlane(my_rm, z - t.z0);
+                    if (slot >= 0 && L.own) sample(rm, g, t.s, slot, L.xc, d, nt, n, un);
+                }
+            }
+        }
+        // step two at rows za-4 .. za-1
+        if (two && za - 4 >= t.z0) {
+            stage2(rowsB, b, lane);
+#pragma unroll
+            for (int j = 0; j < U; ++j) {
+                const int z = za - 4 + j;
+                if (z >= t.z1) break;
+                float acc = lap8(b, j, rowsB + j * 72, lane);
+                if (z == sn.x && L.xc == sn.y) acc += w1;
+                float A, B;
+                sponge_ab(g, L, z, A, B);
+                const float qh = kb[j] * acc;
+                const float un = fmaf(2.0f * A, b.q[j + 4], fmaf(-B, c.q[j], qh));
+                const unsigned oz = (o + (unsigned)j * rb - 4u * rb) | own_mask;
+                bst(O2, oz, un);
+                if (kRecompute) bst(Q1, oz, qh);
+                if (!kRecompute) {
+                    const int slot = __builtin_amdgcn_readlane(my_rm, z - t.z0);
+                    if (slot >= 0 && L.own) sample(rm, g, t.s, slot, L.xc, d, nt, n + 1, un);
+                }
+            }
+        }
+        queue_advance(c, nq);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) b.q[i] = b.q[i + U];
+        rows_copy(kb, kv);
+        rows_copy(pv, npv);
+        rows_copy(kv, nkv);
+        rows_copy(hv, nhv);
+    }
+}
+
+// Adjoint + imaging, steps n (lam^{n+1}, lam^{n+2} -> lam^n) and n-1; the
+// image takes lam^n q^n then lam^{n-1} q^{n-1} at every owned point, in that
+// order, in one read-modify-write.
+template <int U>
+__global__ __launch_bounds__(256) void k_adj_step2(const TileRec* __restrict__ tiles, int ntiles,
+                                                   const Inst* __restrict__ insts, StepArgs a) {
+    __shared__ float lds[kWaves][2 * U * 72];
+    const Tile t = decode_tile(tiles, ntiles);
+    if (!t.live) return;
+    if (a.active && !a.active[t.inst]) return;
+    const Inst& I = insts[t.inst];
+    const WaveGrid g = I.g;
+    const int j0 = I.nseg - 1 - a.seg;
+    if (j0 < 0) return;
+    const int len = min(I.k, I.nt - j0 * I.k);
+    if (a.n - 1 >= len) return;
+    const int tt = min(a.n, len - 1);  // upper step of the pair inside the segment
+    const bool two = tt == a.n && tt >= 1;
+    const int n = j0 * I.k + tt;
+    const float* l = I.L[(n + 1) & 3];
+    const float* lprev = I.L[(n + 2) & 3];
+    float* out1 = I.L[n & 3];
+    float* out2 = I.L[(n + 3) & 3];
+    const float* r = a.r_ovr ? a.r_ovr : I.r;
+    const float* qa = I.qseg + (long long)tt * I.field;
+    const float* qb = two ? qa - I.field : qa;
+    const int nt = I.nt;
+    const RecMaps rm = I.rm;
+    const float h2 = I.h2;
+    const int lane = t.lane;
+    float* rowsA = &lds[threadIdx.x >> 6][0];
+    float* rowsB = rowsA + U * 72;
+    const long long off0 = (long long)t.s * g.plane;
+    const Rsrc UR = view(l + off0, g.plane);
+    const Rsrc UP = view(lprev + off0, g.plane);
+    const Rsrc O1 = view(out1 + off0, g.plane);
+    const Rsrc O2 = view(out2 + off0, g.plane);
+    const Rsrc KR = view(I.K, g.plane);
+    const Rsrc QA = view(qa + off0, g.plane);
+    const Rsrc QB = view(qb + off0, g.plane);
+    const Rsrc GI = view(I.GI + off0, g.plane);
+    const Lanes2 L = lanes2(g, t);
+    const unsigned rb = (unsigned)g.pitch * 4u;
+    const unsigned own_mask = L.own ? 0u : kOut;
+    const FrameRows fr = frame_rowmap(rm, g, t);
+
+    const int za0 = t.z0 - 4;
+    const int zend = two ? t.z1 + 4 : t.z1;
+    unsigned o = L.base + row_off(za0, g.pitch), oh = L.hbase + row_off(za0, g.pitch);
+    Queue<U> c;   // lam^{n+1} at rows za-4 .. za+U+3
+    Queue<U> b;   // lam^n at rows za-8 .. za+U-1
+#pragma unroll
+    for (int i = 0; i < U + 8; ++i) b.q[i] = 0.0f;
+    queue_prime(c, UR, o, rb);
+    float pv[U], kv[U], hv[U], kb[U], qav[U], qbv[U], gv[U];
+    rows_fetch(pv, UP, o, rb);
+    rows_fetch(kv, KR, o, rb);
+    rows_fetch(hv, UR, oh, rb);
+#pragma unroll
+    for (int j = 0; j < U; ++j) kb[j] = qav[j] = qbv[j] = gv[j] = 0.0f;
+    for (int za = za0; za < zend; za += U, o += U * rb, oh += U * rb) {
+        float nq[U], npv[U], nkv[U], nhv[U], nqa[U], nqb[U], ngv[U];
+        queue_fetch(nq, UR, o, rb);
+        rows_fetch(npv, UP, o + U * rb, rb);
+        rows_fetch(nkv, KR, o + U * rb, rb);
+        rows_fetch(nhv, UR, oh + U * rb, rb);
+        // image operands of rows za .. za+U-1 (step two's rows of the next block)
+        if (two) {
+            rows_fetch(nqa, QA, o, rb);
+            rows_fetch(nqb, QB, o, rb);
+            rows_fetch(ngv, GI, o, rb);
+        }
+        stage(rowsA, c, hv, lane, L.hslot);
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const int z = za + j;
+            float acc = lap8(c, j, rowsA + j * 72, lane);
+            const int slot = frame_slot(fr, z, t.z0);
+            if (slot >= 0 && L.xin) acc = fmaf(-h2, injected(rm, g, t.s, slot, L.xc, r, nt, n), acc);
+            float A, B;
+            sponge_ab(g, L, z, A, B);
+            const float ln = fmaf(2.0f * A, c.q[j + 4], fmaf(-B, pv[j], kv[j] * acc));
+            b.q[8 + j] = ln;
+            if (z >= t.z0 && z < t.z1) {
+                const unsigned oz = (o + (unsigned)j * rb) | own_mask;
+                bst(O1, oz, ln);
+                if (!two) bst(GI, oz, fmaf(ln, bld(QA, oz), bld(GI, oz)));
+            }
+        }
+        if (two && za - 4 >= t.z0) {
+            stage2(rowsB, b, lane);
+#pragma unroll
+            for (int j = 0; j < U; ++j) {
+                const int z = za - 4 + j;
+                if (z >= t.z1) break;
+                float acc = lap8(b, j, rowsB + j * 72, lane);
+                const int slot = frame_slot(fr, z, t.z0);
+                if (slot >= 0 && L.xin) acc = fmaf(-h2, injected(rm, g, t.s, slot, L.xc, r, nt, n - 1), acc);
+                float A, B;
+                sponge_ab(g, L, z, A, B);
+                const float lm = fmaf(2.0f * A, b.q[j + 4], fmaf(-B, c.q[j], kb[j] * acc));
+                const unsigned oz = (o + (unsigned)j * rb - 4u * rb) | own_mask;
+                bst(O2, oz, lm);
+                bst(GI, oz, fmaf(lm, qbv[j], fmaf(b.q[j + 4], qav[j], gv[j])));
+            }
+        }
+        queue_advance(c, nq);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) b.q[i] = b.q[i + U];
+        rows_copy(kb, kv);
+        rows_copy(pv, npv);
+        rows_copy(kv, nkv);
+        rows_copy(hv, nhv);
+        if (two) {
+            rows_copy(qav, nqa);
+            rows_copy(qbv, nqb);
+            rows_copy(gv, ngv);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Born pair step: background u0 and scattered du with source -E * qhat0,
 // E = dm_pad / m0_pad (eq. Born: -m_r d^2u0/dt^2), sampling du.
 // ---------------------------------------------------------------------------
@@ -446,11 +815,11 @@ __global__ __launch_bounds__(256) void k_born_step(const TileRec* __restrict__ t
     const WaveGrid g = I.g;
     const int n = a.n;
     if (n >= I.nt) return;
-    const float* u = (n & 1) ? I.F1 : I.F0;
-    float* uout = (n & 1) ? I.F0 : I.F1;
+    const float* u = I.F[n & 1];
+    float* uout = I.F[(n + 1) & 1];
     const float* uprev = uout;
-    const float* du = (n & 1) ? I.L1 : I.L0;
-    float* duout = (n & 1) ? I.L0 : I.L1;
+    const float* du = I.L[n & 1];
+    float* duout = I.L[(n + 1) & 1];
     const float* duprev = duout;
     const float w = I.wav[n];
     const int nt = I.nt;
@@ -711,6 +1080,25 @@ void launch_step(int kernel_id, hipStream_t st, const TileRec* tiles, int ntiles
         default:
             hipLaunchKernelGGL(k_born_step<kUBorn>, grid, block, 0, st, tiles, ntiles, insts, a);
             break;
+    }
+    AAFWI_HIP(hipGetLastError());
+}
+
+void launch_step2(int kernel_id, hipStream_t st, const TileRec* tiles, int ntiles, const Inst* insts,
+                  const StepArgs& a) {
+    const dim3 grid((ntiles + kWaves - 1) / kWaves), block(64 * kWaves);
+    switch (kernel_id) {
+        case AAFWI_K_FWD_STEP:
+            hipLaunchKernelGGL((k_fwd_step2<kUFwd, false>), grid, block, 0, st, tiles, ntiles, insts, a);
+            break;
+        case AAFWI_K_REC_STEP:
+            hipLaunchKernelGGL((k_fwd_step2<kUFwd, true>), grid, block, 0, st, tiles, ntiles, insts, a);
+            break;
+        case AAFWI_K_ADJ_STEP:
+            hipLaunchKernelGGL(k_adj_step2<kUAdj>, grid, block, 0, st, tiles, ntiles, insts, a);
+            break;
+        default:
+            throw Error{AAFWI_E_INVALID, "launch_step2: no two-step Born kernel"};
     }
     AAFWI_HIP(hipGetLastError());
 }
