@@ -102,7 +102,7 @@ def source_digest():
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def measured_traffic(kernel: str):
+def measured_traffic(kernel: str, steps_per_launch: int):
     """HBM bytes per launch of ``kernel`` from the committed counter summary
     (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), or None
     when it is missing or was taken on other kernel sources."""
@@ -112,7 +112,8 @@ def measured_traffic(kernel: str):
             tr = json.load(f)
     except (OSError, ValueError):
         return None
-    if tr.get("source_sha256") != source_digest() or kernel not in tr.get("kernels", {}):
+    if (tr.get("source_sha256") != source_digest() or kernel not in tr.get("kernels", {})
+            or tr.get("steps_per_launch") != steps_per_launch):
         return None
     k = tr["kernels"][kernel]
     return round((k["fetch_kib"] * tr["fetch_factor"] + k["write_kib"] * tr["write_factor"]) * 1024.0)
@@ -242,6 +243,26 @@ def cnn_timing(net, B, H, W, reps=20):
     return out
 
 
+def cnn_workload(args):
+    """Speed of the learned-direction network alone: forward and Adam training
+    step on 8 images of 384 x 1024 (random inputs), HIP-event timed; reports
+    algorithmic TFLOP/s against the bf16 matrix-core peak."""
+    from paper_2008_11778_amd import CNN
+    from paper_2008_11778_amd.learned import init_weights
+    B, H, W = 8, 384, 1024
+    speed = cnn_timing(CNN(H, W, B, init_weights(5005)), B, H, W, reps=args.steps * 10)
+    flops = 2.0 * B * H * W * 19296
+    out = {"metric": "learned-direction network speed (bf16 matrix cores)", "value": round(
+        flops / speed["forward"] / 1e9, 1), "unit": "TFLOP/s (forward, algorithmic)", "n_gpus": 1,
+           "higher_is_better": True, "forward_ms": round(speed["forward"], 3),
+           "train_step_ms": round(speed["train_step"], 3),
+           "train_tflops": round(3 * flops / speed["train_step"] / 1e9, 1),
+           "peak_tflops": 2500.0, "frac": round(flops / speed["forward"] / 1e9 / 2500.0, 4),
+           "config": {"workload": f"{B} images of {H} x {W}, 4-layer 3x3 CNN 2-32-32-32-1"},
+           "dtype": "bf16 (fp32 accumulate)", "data": "synthetic"}
+    print(json.dumps(out), flush=True)
+
+
 def learned_workload(args):
     """Learned direction: training data from plain AA and L-BFGS runs, Adam
     training of the network, then plain AA versus AA on G_theta (with the
@@ -340,12 +361,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--time-every", type=int, default=16, help="event-time every n-th stepping launch")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-large", action="store_true", help="skip the large-grid forward-step measurement")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="after the run, copy this many MiB device-to-device (counter calibration)")
     ap.add_argument("--tile", type=int, default=-1,
                     help="rows per wave for every stepping kernel (-1 = autotune, 0 = library default)")
     ap.add_argument("--no-time-blocking", action="store_true", help="one time step per stepping launch")
-    ap.add_argument("--workload", default="fwi", choices=["fwi", "batched", "learned"])
+    ap.add_argument("--shape", default="",
+                    help="launch shape instead of autotuning: 'one' or 'two' (steps per launch) followed by the "
+                         "rows per wave of the forward, recompute, adjoint and Born steps, e.g. one:8,64,28,64")
+    ap.add_argument("--workload", default="fwi", choices=["fwi", "batched", "learned", "cnn"])
     ap.add_argument("--instances", type=int, default=32, help="batched workload: number of instances")
     ap.add_argument("--iters", type=int, default=10, help="batched workload: AA iterations per instance")
     ap.add_argument("--ckpt", type=int, default=70, help="batched workload: checkpoint interval")
@@ -363,6 +388,8 @@ def main():
         return batched_workload(args)
     if args.workload == "learned":
         return learned_workload(args)
+    if args.workload == "cnn":
+        return cnn_workload(args)
     # the oracle runs first, in child processes started before this process
     # touches the GPU
     cpu = None
@@ -384,7 +411,13 @@ def main():
     log(f"workload: {g.nx}x{g.nz} grid, {g.nshots} shots, {g.nt} steps, {g.nrec} receivers")
     ctx = Context(g, ckpt_every=50)
     m0t = torch.from_numpy(m0).to(dev)
-    if args.tile >= 0:
+    if args.shape:
+        mode, rows = args.shape.split(":")
+        tiles = {"tb": mode == "two"}
+        tiles.update({k: int(v) for k, v in enumerate(rows.split(","))})
+        from paper_2008_11778_amd import autotune
+        autotune.apply(ctx, tiles)
+    elif args.tile >= 0:
         ctx.set_tile(args.tile)
         tiles = {k: ctx.get_tile(k) for k in range(4)}
     else:
@@ -442,7 +475,7 @@ def main():
     per_launch_bytes = launch_bytes[dom]
     achieved = per_launch_bytes / mean_s / 1e9
     roofline = dict(kernel=NAMES[dom], bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
-                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(NAMES[dom]),
+                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(NAMES[dom], 2 if tb else 1),
                     mean_launch_us=round(kt[dom][0] * 1e3, 2), timed_launches=kt[dom][1],
                     bytes_per_launch=per_launch_bytes, steps_per_launch=2 if tb else 1)
     kernels = {NAMES[k]: dict(mean_us=round(kt[k][0] * 1e3, 2), timed=kt[k][1], steps_per_launch=2 if tb else 1,
@@ -492,8 +525,9 @@ def main():
         log(f"copy probe: {args.copy_probe} MiB x5, {gbs:.1f} GB/s (read + write)")
         del a, b
     ctx.close()
-    out["stencil_large"] = stencil_large(dev)
-    log(f"forward step on the large grid: {out['stencil_large']}")
+    if not args.no_large:
+        out["stencil_large"] = stencil_large(dev)
+        log(f"forward step on the large grid: {out['stencil_large']}")
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
