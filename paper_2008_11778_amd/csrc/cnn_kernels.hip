@@ -14,6 +14,7 @@
 // (16-column tiles); the reduction runs over (tap, 16-channel chunk).
 // Activations are NHWC with the channel count padded to a multiple of 16.
 // Weight copies: Wf[tap][co][ci] (forward), Wd[tap][ci][co] (input gradient).
+#include <algorithm>
 #include <cmath>
 #include <new>
 #include <vector>
@@ -56,89 +57,82 @@ __device__ __forceinline__ Pix pix(int p, int H, int W) {
     return q;
 }
 
-// y = conv3x3(x) (+ ReLU, bf16 out) or, for the last layer, z = conv3x3(x) (FP32).
-template <int CIN, int COUT, bool LAST>
-__global__ __launch_bounds__(256) void k_conv_fwd(int P, int H, int W, const bf16* __restrict__ x,
-                                                  const bf16* __restrict__ wf, bf16* __restrict__ y,
-                                                  float* __restrict__ z) {
-    const int lane = threadIdx.x & 63;
-    const int p0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
-    if (p0 >= P) return;
-    const int i = lane & 15, grp = lane >> 4;
-    const int p = p0 + i;
-    const bool pin = p < P;
-    const Pix q = pix(pin ? p : 0, H, W);
-    v4f acc[COUT / 16];
-#pragma unroll
-    for (int nt = 0; nt < COUT / 16; ++nt) acc[nt] = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int tap = 0; tap < 9; ++tap) {
-        const int yy = q.y + tap / 3 - 1, xx = q.x + tap % 3 - 1;
-        const bool ok = pin && yy >= 0 && yy < H && xx >= 0 && xx < W;
-        const long long src = ((long long)(q.b * H + yy) * W + xx) * CIN;
-#pragma unroll
-        for (int cc = 0; cc < CIN / 16; ++cc) {
-            const v4s a = ok ? ld4(x + src + cc * 16 + 4 * grp) : v4s{0, 0, 0, 0};
-#pragma unroll
-            for (int nt = 0; nt < COUT / 16; ++nt) {
-                const v4s bw = ld4(wf + ((tap * COUT + nt * 16 + i) * CIN + cc * 16 + 4 * grp));
-                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bw, acc[nt], 0, 0, 0);
-            }
-        }
-    }
-    // lane holds D[4*grp + r][i]: pixel p0 + 4*grp + r, channel nt*16 + i
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int pp = p0 + 4 * grp + r;
-        if (pp >= P) continue;
-        if (LAST) {
-            if (i == 0) z[pp] = acc[0][r];
-        } else {
-#pragma unroll
-            for (int nt = 0; nt < COUT / 16; ++nt) y[(long long)pp * COUT + nt * 16 + i] = f2bf(fmaxf(acc[nt][r], 0.f));
-        }
-    }
-}
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef unsigned v4u __attribute__((ext_vector_type(4)));
 
-// dx[p][ci] = sum_tap sum_co dy[p - off(tap)][co] Wd[tap][ci][co], times the
-// ReLU mask (xin[p][ci] > 0) of the layer that produced this layer's input.
-template <int CIN, int COUT>
-__global__ __launch_bounds__(256) void k_conv_dgrad(int P, int H, int W, const bf16* __restrict__ dy,
-                                                    const bf16* __restrict__ wd, const bf16* __restrict__ xin,
-                                                    bf16* __restrict__ dx) {
+__device__ __forceinline__ bf8 ld8(const bf16* p) { return __builtin_bit_cast(bf8, *reinterpret_cast<const v4u*>(p)); }
+__device__ __forceinline__ bf8 zero8() { return __builtin_bit_cast(bf8, v4u{0u, 0u, 0u, 0u}); }
+
+enum ConvMode { kHidden = 0, kLast = 1, kInputGrad = 2 };
+
+// 3x3 convolution as an implicit GEMM on v_mfma_f32_16x16x32_bf16, for the
+// forward pass (x: [P][C] -> y: [P][NOUT] with ReLU, or z: [P] FP32 for the
+// last layer) and the input gradient (x = dy: [P][C], taps mirrored, output
+// masked by the ReLU of the layer input `mask`).  The reduction index is
+// k = tap * C + c, cut into chunks of 32: lane group g of a fragment holds
+// k = 32 ch + 8 g .. 8 g + 7, i.e. 8 consecutive channels of one tap (one
+// 16-byte load).  w is [tap][NOUT][C] bf16.  Each wave keeps all its weight
+// fragments in registers and walks 16-pixel tiles with a grid stride.
+template <int C, int NOUT, int MODE>
+__global__ __launch_bounds__(256) void k_conv_mm(int P, int H, int W, const bf16* __restrict__ x,
+                                                 const bf16* __restrict__ w, const bf16* __restrict__ mask,
+                                                 bf16* __restrict__ y, float* __restrict__ z) {
+    constexpr int NCH = (9 * C + 31) / 32;
+    constexpr int NT = NOUT / 16;
+    constexpr int sgn = MODE == kInputGrad ? -1 : 1;
     const int lane = threadIdx.x & 63;
-    const int p0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
-    if (p0 >= P) return;
     const int i = lane & 15, grp = lane >> 4;
-    const int p = p0 + i;
-    const bool pin = p < P;
-    const Pix q = pix(pin ? p : 0, H, W);
-    v4f acc[CIN / 16];
+    bf8 bw[NCH][NT];
+    int tap_of[NCH], c_of[NCH];
 #pragma unroll
-    for (int nt = 0; nt < CIN / 16; ++nt) acc[nt] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int ch = 0; ch < NCH; ++ch) {
+        const int k0 = 32 * ch + 8 * grp;
+        tap_of[ch] = k0 / C;
+        c_of[ch] = k0 % C;
 #pragma unroll
-    for (int tap = 0; tap < 9; ++tap) {
-        const int yy = q.y - (tap / 3 - 1), xx = q.x - (tap % 3 - 1);
-        const bool ok = pin && yy >= 0 && yy < H && xx >= 0 && xx < W;
-        const long long src = ((long long)(q.b * H + yy) * W + xx) * COUT;
-#pragma unroll
-        for (int cc = 0; cc < COUT / 16; ++cc) {
-            const v4s a = ok ? ld4(dy + src + cc * 16 + 4 * grp) : v4s{0, 0, 0, 0};
-#pragma unroll
-            for (int nt = 0; nt < CIN / 16; ++nt) {
-                const v4s bw = ld4(wd + ((tap * CIN + nt * 16 + i) * COUT + cc * 16 + 4 * grp));
-                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bw, acc[nt], 0, 0, 0);
-            }
-        }
+        for (int nt = 0; nt < NT; ++nt)
+            bw[ch][nt] = tap_of[ch] < 9 ? ld8(w + ((tap_of[ch] * NOUT + nt * 16 + i) * C + c_of[ch])) : zero8();
     }
+    const int ntile = (P + 15) / 16;
+    const int nwave = gridDim.x * 4;
+    for (int tile = blockIdx.x * 4 + (threadIdx.x >> 6); tile < ntile; tile += nwave) {
+        const int p0 = tile * 16;
+        const int p = p0 + i;
+        const bool pin = p < P;
+        const Pix q = pix(pin ? p : 0, H, W);
+        bf8 a[NCH];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int pp = p0 + 4 * grp + r;
-        if (pp >= P) continue;
+        for (int ch = 0; ch < NCH; ++ch) {
+            const int tap = tap_of[ch];
+            const int yy = q.y + sgn * (tap / 3 - 1), xx = q.x + sgn * (tap % 3 - 1);
+            const bool ok = pin && tap < 9 && yy >= 0 && yy < H && xx >= 0 && xx < W;
+            a[ch] = ok ? ld8(x + ((long long)(q.b * H + yy) * W + xx) * C + c_of[ch]) : zero8();
+        }
+        v4f acc[NT];
 #pragma unroll
-        for (int nt = 0; nt < CIN / 16; ++nt) {
-            const long long o = (long long)pp * CIN + nt * 16 + i;
-            dx[o] = bf2f(xin[o]) > 0.f ? f2bf(acc[nt][r]) : (bf16)0;
+        for (int nt = 0; nt < NT; ++nt) acc[nt] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ch], bw[ch][nt], acc[nt], 0, 0, 0);
+        // lane holds D[4 grp + r][i]: pixel p0 + 4 grp + r, output channel nt*16 + i
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int pp = p0 + 4 * grp + r;
+            if (pp >= P) continue;
+            if (MODE == kLast) {
+                if (i == 0) z[pp] = acc[0][r];
+            } else {
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) {
+                    const long long o = (long long)pp * NOUT + nt * 16 + i;
+                    if (MODE == kHidden)
+                        y[o] = f2bf(fmaxf(acc[nt][r], 0.f));
+                    else
+                        y[o] = bf2f(mask[o]) > 0.f ? f2bf(acc[nt][r]) : (bf16)0;
+                }
+            }
         }
     }
 }
@@ -195,14 +189,30 @@ __global__ __launch_bounds__(64) void k_conv_wgrad(int P, int H, int W, const bf
             for (int r = 0; r < 4; ++r) out[(a * 16 + 4 * grp + r) * CIN + b * 16 + i] = acc[a][b][r];
 }
 
-// grad[co][ci][tap] (real channels only) = sum over chunks, in chunk order.
-__global__ void k_wgrad_reduce(int nchunk, int coutp, int cinp, int cout, int cin, const float* __restrict__ part,
-                               float* __restrict__ grad) {
+// Chunk partials -> weight gradient in two fixed-order FP64 stages: group g
+// of kRedGroups sums its contiguous run of chunks (coalesced over the
+// partial layout [chunk][tap][co][ci]), then the groups are summed in order
+// into grad[co][ci][tap] (real channels only).
+constexpr int kRedGroups = 32;
+
+__global__ void k_wgrad_reduce1(int nchunk, int m, const float* __restrict__ part, double* __restrict__ gsum) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int gidx = blockIdx.y;
+    if (e >= m) return;
+    const int c0 = (int)((long long)nchunk * gidx / kRedGroups), c1 = (int)((long long)nchunk * (gidx + 1) / kRedGroups);
+    double acc = 0.0;
+    for (int c = c0; c < c1; ++c) acc += part[(long long)c * m + e];
+    gsum[(long long)gidx * m + e] = acc;
+}
+
+__global__ void k_wgrad_reduce2(int m, int coutp, int cinp, int cout, int cin, const double* __restrict__ gsum,
+                                float* __restrict__ grad) {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= cout * cin * 9) return;
     const int tap = idx % 9, ci = (idx / 9) % cin, co = idx / (9 * cin);
+    const int e = (tap * coutp + co) * cinp + ci;
     double acc = 0.0;
-    for (int c = 0; c < nchunk; ++c) acc += part[((long long)c * 9 + tap) * coutp * cinp + co * cinp + ci];
+    for (int gidx = 0; gidx < kRedGroups; ++gidx) acc += gsum[(long long)gidx * m + e];
     grad[idx] = (float)acc;
 }
 
@@ -388,6 +398,7 @@ struct aafwi_cnn {
     double* st1 = nullptr;
     double* st2 = nullptr;
     float* wpart = nullptr;
+    double* gsum = nullptr;
 };
 
 namespace {
@@ -435,6 +446,24 @@ void pack_weights(aafwi_cnn* c) {
     }
 }
 
+template <int C, int NOUT, int MODE>
+void conv(aafwi_cnn* c, int P, const aafwi::bf16* x, const aafwi::bf16* w, const aafwi::bf16* mask, aafwi::bf16* y,
+          float* z) {
+    const int ntile = (P + 15) / 16;
+    const int blocks = std::min((ntile + 3) / 4, 2048);
+    hipLaunchKernelGGL((aafwi::k_conv_mm<C, NOUT, MODE>), dim3(blocks), dim3(256), 0, c->stream, P, c->H, c->W, x, w,
+                       mask, y, z);
+}
+
+void weight_reduce(aafwi_cnn* c, int nchunk, int coutp, int cinp, int layer) {
+    using namespace aafwi;
+    const int m = 9 * coutp * cinp;
+    hipLaunchKernelGGL(k_wgrad_reduce1, dim3((m + 255) / 256, kRedGroups), dim3(256), 0, c->stream, nchunk, m,
+                       (const float*)c->wpart, c->gsum);
+    hipLaunchKernelGGL(k_wgrad_reduce2, dim3((kCout[layer] * kCin[layer] * 9 + 255) / 256), dim3(256), 0, c->stream,
+                       m, coutp, cinp, kCout[layer], kCin[layer], (const double*)c->gsum, c->grad + layer_offset(layer));
+}
+
 void forward(aafwi_cnn* c, int B, const float* g, const float* m) {
     using namespace aafwi;
     const int n = c->H * c->W, P = B * n;
@@ -442,15 +471,10 @@ void forward(aafwi_cnn* c, int B, const float* g, const float* m) {
     hipLaunchKernelGGL(k_finish<3>, dim3((B + 63) / 64), dim3(64), 0, c->stream, B, (const double*)c->part, c->st_in);
     hipLaunchKernelGGL(k_pack_input, dim3((P + 255) / 256), dim3(256), 0, c->stream, B, n, g, m,
                        (const double*)c->st_in, c->act[0]);
-    const dim3 grid((P + 63) / 64), block(256);
-    hipLaunchKernelGGL((k_conv_fwd<16, 32, false>), grid, block, 0, c->stream, P, c->H, c->W, c->act[0], c->wf[0],
-                       c->act[1], (float*)nullptr);
-    hipLaunchKernelGGL((k_conv_fwd<32, 32, false>), grid, block, 0, c->stream, P, c->H, c->W, c->act[1], c->wf[1],
-                       c->act[2], (float*)nullptr);
-    hipLaunchKernelGGL((k_conv_fwd<32, 32, false>), grid, block, 0, c->stream, P, c->H, c->W, c->act[2], c->wf[2],
-                       c->act[3], (float*)nullptr);
-    hipLaunchKernelGGL((k_conv_fwd<32, 16, true>), grid, block, 0, c->stream, P, c->H, c->W, c->act[3], c->wf[3],
-                       (bf16*)nullptr, c->z);
+    conv<16, 32, kHidden>(c, P, c->act[0], c->wf[0], nullptr, c->act[1], nullptr);
+    conv<32, 32, kHidden>(c, P, c->act[1], c->wf[1], nullptr, c->act[2], nullptr);
+    conv<32, 32, kHidden>(c, P, c->act[2], c->wf[2], nullptr, c->act[3], nullptr);
+    conv<32, 16, kLast>(c, P, c->act[3], c->wf[3], nullptr, nullptr, c->z);
     AAFWI_HIP(hipGetLastError());
 }
 
@@ -468,27 +492,21 @@ void gradients(aafwi_cnn* c, int B, const float* g, const float* m, const float*
                        (const double*)c->st1, (const double*)c->st2, c->dlt[3]);
     if (loss) hipLaunchKernelGGL(k_loss_total, dim3(1), dim3(64), 0, c->stream, B, n, (const double*)c->st2, loss);
     AAFWI_HIP(hipGetLastError());
-    const dim3 grid((P + 63) / 64), block(256);
     const int nchunk = (P + kWgradChunk - 1) / kWgradChunk;
     // layer 4 (32 -> 1): weight gradient, then the delta at layer 3's output
     hipLaunchKernelGGL((k_conv_wgrad<32, 16>), dim3(nchunk, 9), dim3(64), 0, c->stream, P, c->H, c->W, c->dlt[3],
                        c->act[3], c->wpart);
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3((kCout[3] * kCin[3] * 9 + 255) / 256), dim3(256), 0, c->stream, nchunk,
-                       16, 32, kCout[3], kCin[3], (const float*)c->wpart, c->grad + layer_offset(3));
-    hipLaunchKernelGGL((k_conv_dgrad<32, 16>), grid, block, 0, c->stream, P, c->H, c->W, c->dlt[3], c->wd[3],
-                       c->act[3], c->dlt[2]);
+    weight_reduce(c, nchunk, 16, 32, 3);
+    conv<16, 32, kInputGrad>(c, P, c->dlt[3], c->wd[3], c->act[3], c->dlt[2], nullptr);
     for (int l = 2; l >= 1; --l) {
         hipLaunchKernelGGL((k_conv_wgrad<32, 32>), dim3(nchunk, 9), dim3(64), 0, c->stream, P, c->H, c->W, c->dlt[l],
                            c->act[l], c->wpart);
-        hipLaunchKernelGGL(k_wgrad_reduce, dim3((kCout[l] * kCin[l] * 9 + 255) / 256), dim3(256), 0, c->stream,
-                           nchunk, 32, 32, kCout[l], kCin[l], (const float*)c->wpart, c->grad + layer_offset(l));
-        hipLaunchKernelGGL((k_conv_dgrad<32, 32>), grid, block, 0, c->stream, P, c->H, c->W, c->dlt[l], c->wd[l],
-                           c->act[l], c->dlt[l - 1]);
+        weight_reduce(c, nchunk, 32, 32, l);
+        conv<32, 32, kInputGrad>(c, P, c->dlt[l], c->wd[l], c->act[l], c->dlt[l - 1], nullptr);
     }
     hipLaunchKernelGGL((k_conv_wgrad<16, 32>), dim3(nchunk, 9), dim3(64), 0, c->stream, P, c->H, c->W, c->dlt[0],
                        c->act[0], c->wpart);
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3((kCout[0] * kCin[0] * 9 + 255) / 256), dim3(256), 0, c->stream, nchunk,
-                       32, 16, kCout[0], kCin[0], (const float*)c->wpart, c->grad + layer_offset(0));
+    weight_reduce(c, nchunk, 32, 16, 0);
     AAFWI_HIP(hipGetLastError());
 }
 
@@ -529,6 +547,7 @@ extern "C" int aafwi_cnn_create(int32_t nz, int32_t nx, int32_t max_batch, const
             c->st2 = calloc_dev<double>(c, (size_t)max_batch * 2);
             const size_t nchunk = (P + aafwi::kWgradChunk - 1) / aafwi::kWgradChunk;
             c->wpart = calloc_dev<float>(c, nchunk * 9 * 32 * 32);
+            c->gsum = calloc_dev<double>(c, (size_t)aafwi::kRedGroups * 9 * 32 * 32);
             AAFWI_HIP(hipMemcpy(c->w, weights, sizeof(float) * AAFWI_CNN_PARAMS, hipMemcpyHostToDevice));
             pack_weights(c);
             AAFWI_HIP(hipStreamSynchronize(c->stream));
