@@ -102,20 +102,24 @@ def source_digest():
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def measured_traffic(kernel: str, steps_per_launch: int):
+def measured_traffic(kernel: str, steps_per_launch: int, tiles: dict):
     """HBM bytes per launch of ``kernel`` from the committed counter summary
     (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), or None
-    when it is missing or was taken on other kernel sources."""
+    when it is missing or was taken on other kernel sources or another launch
+    shape (steps per launch, rows per wave, tile order)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as f:
             tr = json.load(f)
     except (OSError, ValueError):
         return None
-    if (tr.get("source_sha256") != source_digest() or kernel not in tr.get("kernels", {})
-            or tr.get("steps_per_launch") != steps_per_launch):
+    if tr.get("source_sha256") != source_digest() or kernel not in tr.get("kernels", {}):
         return None
     k = tr["kernels"][kernel]
+    kid = {v: i for i, v in NAMES.items()}[kernel]
+    if (k.get("steps_per_launch") != steps_per_launch or k.get("rows") != tiles.get(kid)
+            or k.get("order") != tiles.get(f"order{kid}", 0)):
+        return None
     return round((k["fetch_kib"] * tr["fetch_factor"] + k["write_kib"] * tr["write_factor"]) * 1024.0)
 
 
@@ -138,7 +142,7 @@ def stencil_large(dev, nt=400):
         ctx.forward_model(m)
         mean_ms, cnt = ctx.kernel_timing_read(0)
         rows = ctx.get_tile(0)
-        steps = 2 if ctx.time_blocking() else 1
+        steps = 2 if ctx.time_blocking() & 1 else 1
     pts = g.nz_p * g.nx_p * g.nshots
     gbs = (BYTES2[0] if steps == 2 else BYTES[0]) * pts / (mean_ms / 1e3) / 1e9
     return {"workload": f"forward step, {g.nx}x{g.nz} grid, {g.nshots} shots, 20-cell sponge",
@@ -368,8 +372,9 @@ def main():
                     help="rows per wave for every stepping kernel (-1 = autotune, 0 = library default)")
     ap.add_argument("--no-time-blocking", action="store_true", help="one time step per stepping launch")
     ap.add_argument("--shape", default="",
-                    help="launch shape instead of autotuning: 'one' or 'two' (steps per launch) followed by the "
-                         "rows per wave of the forward, recompute, adjoint and Born steps, e.g. one:8,64,28,64")
+                    help="launch shape instead of autotuning: steps per launch of the forward, recompute and "
+                         "adjoint kernels, rows per wave of the forward, recompute, adjoint and Born steps, and "
+                         "optionally their tile orders, e.g. 1,1,2:8,64,20,64:1,0,0,0")
     ap.add_argument("--workload", default="fwi", choices=["fwi", "batched", "learned", "cnn"])
     ap.add_argument("--instances", type=int, default=32, help="batched workload: number of instances")
     ap.add_argument("--iters", type=int, default=10, help="batched workload: AA iterations per instance")
@@ -412,9 +417,13 @@ def main():
     ctx = Context(g, ckpt_every=50)
     m0t = torch.from_numpy(m0).to(dev)
     if args.shape:
-        mode, rows = args.shape.split(":")
-        tiles = {"tb": mode == "two"}
-        tiles.update({k: int(v) for k, v in enumerate(rows.split(","))})
+        # e.g. 1,1,2:8,64,28,64:0,0,1,0 -> steps per launch of forward, recompute, adjoint;
+        # rows per wave of forward, recompute, adjoint, Born; tile orders
+        parts = args.shape.split(":")
+        tiles = {f"two{k}": int(v) == 2 for k, v in enumerate(parts[0].split(","))}
+        tiles.update({k: int(v) for k, v in enumerate(parts[1].split(","))})
+        if len(parts) > 2:
+            tiles.update({f"order{k}": int(v) for k, v in enumerate(parts[2].split(","))})
         from paper_2008_11778_amd import autotune
         autotune.apply(ctx, tiles)
     elif args.tile >= 0:
@@ -426,7 +435,7 @@ def main():
         autotune.apply(ctx, tiles)
     if args.no_time_blocking:
         ctx.set_time_blocking(False)
-    log(f"rows per wave (fwd, rec, adj, born): {[tiles[k] for k in range(4)]}")
+    log(f"launch shape: {tiles}")
     log(f"device memory held by the context: {ctx.device_bytes() / 2**30:.1f} GiB")
     cells = g.nz_p * g.nx_p
     upd_fwd = float(cells) * g.nt * g.nshots
@@ -463,26 +472,27 @@ def main():
     for kid in (0, 1, 2):
         mean_ms, cnt = ctx.kernel_timing_read(kid)
         kt[kid] = (mean_ms, cnt)
-    tb = ctx.time_blocking()
+    mask = ctx.time_blocking()
+    sp = {k: 2 if mask >> k & 1 else 1 for k in range(3)}  # steps per launch
     k_ck = 50
-    per_bwd = sum((min(k_ck, g.nt - j * k_ck) + 1) // 2 if tb else min(k_ck, g.nt - j * k_ck)
-                  for j in range((g.nt + k_ck - 1) // k_ck))
-    launches = {0: n_fwd * ((g.nt + 1) // 2 if tb else g.nt), 1: n_adj * per_bwd, 2: n_adj * per_bwd}
+    seg = [min(k_ck, g.nt - j * k_ck) for j in range((g.nt + k_ck - 1) // k_ck)]
+    launches = {0: n_fwd * -(-g.nt // sp[0]), 1: n_adj * sum(-(-L // sp[1]) for L in seg),
+                2: n_adj * sum(-(-L // sp[2]) for L in seg)}
     totals = {k: kt[k][0] * launches[k] for k in kt}
     dom = max(totals, key=totals.get)
     mean_s = kt[dom][0] / 1e3
-    launch_bytes = {k: (BYTES2[k] if tb else BYTES[k]) * cells * g.nshots for k in kt}
+    launch_bytes = {k: (BYTES2[k] if sp[k] == 2 else BYTES[k]) * cells * g.nshots for k in kt}
     per_launch_bytes = launch_bytes[dom]
     achieved = per_launch_bytes / mean_s / 1e9
     roofline = dict(kernel=NAMES[dom], bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
-                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(NAMES[dom], 2 if tb else 1),
+                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(NAMES[dom], sp[dom], tiles),
                     mean_launch_us=round(kt[dom][0] * 1e3, 2), timed_launches=kt[dom][1],
-                    bytes_per_launch=per_launch_bytes, steps_per_launch=2 if tb else 1)
-    kernels = {NAMES[k]: dict(mean_us=round(kt[k][0] * 1e3, 2), timed=kt[k][1], steps_per_launch=2 if tb else 1,
+                    bytes_per_launch=per_launch_bytes, steps_per_launch=sp[dom])
+    kernels = {NAMES[k]: dict(mean_us=round(kt[k][0] * 1e3, 2), timed=kt[k][1], steps_per_launch=sp[k],
                               bytes_per_launch=launch_bytes[k],
                               gbs=round(launch_bytes[k] / (kt[k][0] / 1e3) / 1e9, 1) if kt[k][0] else None)
                for k in kt}
-    per_upd = {k: launch_bytes[k] / (cells * g.nshots) / (2 if tb else 1) for k in kt}
+    per_upd = {k: launch_bytes[k] / (cells * g.nshots) / sp[k] for k in kt}
     it_bytes = upd_fwd * (per_upd[0] * n_fwd + per_upd[1] * n_adj + per_upd[2] * n_adj)
     out = {
         "metric": METRIC,
@@ -503,8 +513,9 @@ def main():
                         "checkpoints every 50 steps, AA M=10",
             "global_batch": g.nshots, "seq_len": g.nt, "parallelism": "single GPU",
             "rows_per_wave": {NAMES[k]: tiles[k] for k in range(4)},
+            "tile_order": {NAMES[k]: tiles.get(f"order{k}", 0) for k in range(4)},
         },
-        "time_blocking": tb,
+        "steps_per_launch": {NAMES[k]: sp[k] for k in range(3)},
         "roofline": roofline,
         "kernels": kernels,
         "iteration": {"gradients": n_adj, "forward_runs": n_fwd,

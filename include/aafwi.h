@@ -299,6 +299,13 @@ int aafwi_kernel_timing_read(aafwi_ctx* ctx, int kernel_id, double* mean_ms, int
  * by the tile autotuner; results do not depend on it (bitwise). */
 int aafwi_set_tile(aafwi_ctx* ctx, int32_t kernel_id, int32_t rows_per_wave);
 
+/* Order of the wave tiles of stepping kernel kernel_id (or -1 for all) in
+ * its launch: 0 = the x-tiles of one strip are adjacent (default), 1 = the
+ * strips of one tile column are adjacent.  Adjacent tiles run at about the
+ * same time on one XCD, so the order decides whether the x-halo or the
+ * strip-overlap re-reads hit in L2.  Results do not depend on it (bitwise). */
+int aafwi_set_tile_order(aafwi_ctx* ctx, int32_t kernel_id, int32_t order);
+
 /* Current strip height of stepping kernel kernel_id. */
 int aafwi_get_tile(const aafwi_ctx* ctx, int32_t kernel_id, int32_t* rows_per_wave);
 
@@ -311,7 +318,11 @@ int aafwi_get_tile(const aafwi_ctx* ctx, int32_t kernel_id, int32_t* rows_per_wa
  * 256 MB, off otherwise.  Synchronises the stream; drops captured batch
  * graphs. */
 int aafwi_set_time_blocking(aafwi_ctx* ctx, int enable);
-int aafwi_get_time_blocking(const aafwi_ctx* ctx, int* enabled);
+/* The same for one kernel (AAFWI_K_FWD_STEP, _REC_STEP or _ADJ_STEP): the
+ * three choices are independent. */
+int aafwi_set_time_blocking_kernel(aafwi_ctx* ctx, int32_t kernel_id, int enable);
+/* mask: bit k set when kernel k advances two steps per launch. */
+int aafwi_get_time_blocking(const aafwi_ctx* ctx, int* mask);
 int aafwi_batch_set_time_blocking(aafwi_batch* b, int enable);
 
 /* Thread-local message for the last non-zero return on this thread. */

@@ -82,6 +82,8 @@ _sig("aafwi_kernel_timing_read", _vp, ctypes.c_int, ctypes.POINTER(_f64), ctypes
 _sig("aafwi_set_tile", _vp, _i32, _i32)
 _sig("aafwi_get_tile", _vp, _i32, ctypes.POINTER(_i32))
 _sig("aafwi_set_time_blocking", _vp, ctypes.c_int)
+_sig("aafwi_set_time_blocking_kernel", _vp, _i32, ctypes.c_int)
+_sig("aafwi_set_tile_order", _vp, _i32, _i32)
 _sig("aafwi_get_time_blocking", _vp, ctypes.POINTER(ctypes.c_int))
 _sig("aafwi_batch_set_time_blocking", _vp, ctypes.c_int)
 _sig("aafwi_batch_destroy", _vp)
@@ -253,14 +255,23 @@ class Context:
     def set_tile(self, rows_per_wave: int, kernel_id: int = -1):
         _check(_lib.aafwi_set_tile(self._h, int(kernel_id), int(rows_per_wave)))
 
-    def set_time_blocking(self, enable: bool):
-        """Two time steps per launch (default) or one; results are bitwise equal."""
-        _check(_lib.aafwi_set_time_blocking(self._h, int(bool(enable))))
+    def set_tile_order(self, order: int, kernel_id: int = -1):
+        """0: x-tiles of a strip adjacent in the launch; 1: strips of a column adjacent."""
+        _check(_lib.aafwi_set_tile_order(self._h, int(kernel_id), int(order)))
 
-    def time_blocking(self) -> bool:
+    def set_time_blocking(self, enable: bool, kernel_id: int = -1):
+        """Two time steps per launch or one (for one of the forward,
+        recompute, adjoint kernels, or all three); results are bitwise equal."""
+        if kernel_id < 0:
+            _check(_lib.aafwi_set_time_blocking(self._h, int(bool(enable))))
+        else:
+            _check(_lib.aafwi_set_time_blocking_kernel(self._h, int(kernel_id), int(bool(enable))))
+
+    def time_blocking(self) -> int:
+        """Bit mask: bit k set when kernel k advances two steps per launch."""
         v = ctypes.c_int()
         _check(_lib.aafwi_get_time_blocking(self._h, ctypes.byref(v)))
-        return bool(v.value)
+        return int(v.value)
 
     def get_tile(self, kernel_id: int) -> int:
         v = _i32()

@@ -4,10 +4,11 @@ For a grid class (padded rows, padded columns, shot count) every candidate
 rows-per-wave value is timed with the library's event timer on a short
 record (same grid and shots, few time steps), separately for the forward,
 recompute, adjoint and Born steps, with one and with two time steps per
-launch.  The fastest height per kernel is kept for each mode, and the mode
-with the smaller time per gradient step (two forwards, as in an Anderson
-iteration with one line-search trial, plus recompute and adjoint) wins.
-The choice is cached in a JSON file.  Results are bitwise independent of it.
+launch and with both tile orders (x-tiles of a strip adjacent, or strips of
+a column adjacent).  Per kernel the fastest (mode, height, order) per time
+step is kept; the forward, recompute and adjoint choose their modes
+independently.  The choice is cached in a JSON file.  Results are bitwise
+independent of it.
 """
 from __future__ import annotations
 
@@ -31,7 +32,7 @@ def _short(geom, nt):
 
 def grid_key(geom) -> str:
     S = int(np.asarray(geom.src_iz).size)
-    return f"{geom.nz + 2 * geom.nb}x{geom.nx + 2 * geom.nb}x{S}/tb"
+    return f"{geom.nz + 2 * geom.nb}x{geom.nx + 2 * geom.nb}x{S}/mode-order"
 
 
 def cache_path() -> str:
@@ -40,8 +41,8 @@ def cache_path() -> str:
 
 
 def tune(geom, m, candidates=CANDIDATES, nt=48, use_cache=True, verbose=False) -> dict:
-    """Return {"tb": two steps per launch, kernel_id: rows_per_wave} for this
-    grid class (m: device model)."""
+    """Return {kernel_id: rows per wave, "order<k>": tile order, "two<k>":
+    two steps per launch (k < 3)} for this grid class (m: device model)."""
     import torch
 
     from ._lib import Context
@@ -51,49 +52,53 @@ def tune(geom, m, candidates=CANDIDATES, nt=48, use_cache=True, verbose=False) -
         with open(path) as f:
             cached = json.load(f)
         if key in cached:
-            return {(k if k == "tb" else int(k)): v for k, v in cached[key].items()}
+            return {(k if not k.isdigit() else int(k)): v for k, v in cached[key].items()}
     g = _short(geom, nt)
-    best = {(tb, k): (float("inf"), 0) for tb in (False, True) for k in KERNELS}
+    best = {(tb, k): (float("inf"), 0, 0) for tb in (False, True) for k in KERNELS}
     table = {}
     with Context(g, ckpt_every=nt) as ctx:
         r = torch.zeros(ctx.data_shape, device=m.device)
         dm = torch.zeros_like(m)
-        for tb in (False, True):
+        shapes = [(tb, order, rows) for tb in (False, True) for order in (0, 1) for rows in candidates
+                  if rows <= g.nz + 2 * g.nb]
+        for tb, order, rows in shapes:
             ctx.set_time_blocking(tb)
-            for rows in candidates:
-                if rows > g.nz + 2 * g.nb:
+            ctx.set_tile_order(order)
+            ctx.set_tile(rows)
+            ctx.forward_model(m, keep_ckpt=True)  # warm
+            ctx.kernel_timing(1)
+            ctx.forward_model(m, keep_ckpt=True)
+            ctx.adjoint_from_residual(r)
+            if not tb:
+                ctx.born(m, dm)
+            for k in KERNELS:
+                ms, cnt = ctx.kernel_timing_read(k)
+                if not cnt:
                     continue
-                ctx.set_tile(rows)
-                ctx.forward_model(m, keep_ckpt=True)  # warm
-                ctx.kernel_timing(1)
-                ctx.forward_model(m, keep_ckpt=True)
-                ctx.adjoint_from_residual(r)
-                if not tb:
-                    ctx.born(m, dm)
-                for k in KERNELS:
-                    ms, cnt = ctx.kernel_timing_read(k)
-                    if not cnt:
-                        continue
-                    per_step = ms / (2 if tb and k < 3 else 1)
-                    table[(tb, rows, k)] = per_step
-                    if per_step < best[(tb, k)][0]:
-                        best[(tb, k)] = (per_step, rows)
-                ctx.kernel_timing(0)
-    cost = {tb: 2 * best[(tb, 0)][0] + best[(tb, 1)][0] + best[(tb, 2)][0] for tb in (False, True)}
-    tb = cost[True] < cost[False]
+                per_step = ms / (2 if tb and k < 3 else 1)
+                table[(tb, order, rows, k)] = per_step
+                if per_step < best[(tb, k)][0]:
+                    best[(tb, k)] = (per_step, rows, order)
+            ctx.kernel_timing(0)
     if verbose:
         for mode in (False, True):
             for k in KERNELS:
-                row = " ".join(f"{rows}:{table[(mode, rows, k)] * 1e3:.1f}us" for rows in candidates
-                               if (mode, rows, k) in table)
-                if row:
-                    print(f"autotune {key} {'two' if mode else 'one'}-step kernel {k} (per step): {row} "
-                          f"-> {best[(mode, k)][1]}", flush=True)
-        print(f"autotune {key}: per-step cost one-step {cost[False] * 1e3:.1f}us, two-step "
-              f"{cost[True] * 1e3:.1f}us -> {'two' if tb else 'one'}-step", flush=True)
-    out = {"tb": bool(tb)}
+                for order in (0, 1):
+                    row = " ".join(f"{rows}:{table[(mode, order, rows, k)] * 1e3:.1f}us" for rows in candidates
+                                   if (mode, order, rows, k) in table)
+                    if row:
+                        print(f"autotune {key} {'two' if mode else 'one'}-step kernel {k} order {order} (per step): "
+                              f"{row}", flush=True)
+    out = {}
     for k in KERNELS:
-        out[k] = best[(tb if k < 3 else False, k)][1]
+        two = k < 3 and best[(True, k)][0] < best[(False, k)][0]
+        t, rows, order = best[(two, k)]
+        out[k], out[f"order{k}"] = rows, order
+        if k < 3:
+            out[f"two{k}"] = bool(two)
+        if verbose:
+            print(f"autotune {key} kernel {k}: {'two' if two else 'one'}-step, rows {rows}, order {order}, "
+                  f"{t * 1e3:.1f} us per step", flush=True)
     if use_cache:
         os.makedirs(os.path.dirname(path), exist_ok=True)
         cached = {}
@@ -107,8 +112,11 @@ def tune(geom, m, candidates=CANDIDATES, nt=48, use_cache=True, verbose=False) -
 
 
 def apply(ctx, tiles: dict):
-    if "tb" in tiles:
-        ctx.set_time_blocking(bool(tiles["tb"]))
-    for k, rows in tiles.items():
-        if k != "tb":
-            ctx.set_tile(int(rows), int(k))
+    """Set the launch modes, strip heights and tile orders of a tune() result."""
+    for k in KERNELS:
+        if f"two{k}" in tiles:
+            ctx.set_time_blocking(bool(tiles[f"two{k}"]), k)
+        if k in tiles:
+            ctx.set_tile(int(tiles[k]), k)
+        if f"order{k}" in tiles:
+            ctx.set_tile_order(int(tiles[f"order{k}"]), k)

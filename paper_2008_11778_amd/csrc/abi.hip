@@ -69,8 +69,9 @@ struct Engine {
     // two-step tables (56 output columns per wave) of forward, recompute, adjoint
     aafwi::TileRec* dtiles2[3] = {nullptr, nullptr, nullptr};
     int ntiles2[3] = {0, 0, 0};
-    bool tb = false;  // forward, recompute and adjoint advance two steps per launch
+    bool tb[3] = {false, false, false};  // forward / recompute / adjoint: two steps per launch
     int tz[4] = {0, 0, 0, 0};
+    int order[4] = {0, 0, 0, 0};  // tile order: 0 = x-tiles of a strip adjacent, 1 = strips of a column adjacent
     int* active = nullptr;  // device [N], batches only
     std::vector<int> active_host;
     double* J = nullptr;    // device [N]
@@ -259,9 +260,17 @@ std::vector<aafwi::TileRec> tile_table(Engine* e, int kid, int width) {
         const int tz = std::min(e->tz[kid] ? e->tz[kid] : default_tz(g.nzp), g.nzp);
         const int ntx = (g.nxp + width - 1) / width;
         std::vector<aafwi::TileRec> t;
-        for (int s = 0; s < g.S; ++s)
-            for (int z0 = 0; z0 < g.nzp; z0 += tz)
-                for (int tx = 0; tx < ntx; ++tx) t.push_back({i, s, tx * width, (z0 << 16) | std::min(z0 + tz, g.nzp)});
+        for (int s = 0; s < g.S; ++s) {
+            if (e->order[kid] == 0) {
+                for (int z0 = 0; z0 < g.nzp; z0 += tz)
+                    for (int tx = 0; tx < ntx; ++tx)
+                        t.push_back({i, s, tx * width, (z0 << 16) | std::min(z0 + tz, g.nzp)});
+            } else {
+                for (int tx = 0; tx < ntx; ++tx)
+                    for (int z0 = 0; z0 < g.nzp; z0 += tz)
+                        t.push_back({i, s, tx * width, (z0 << 16) | std::min(z0 + tz, g.nzp)});
+            }
+        }
         const size_t n = t.size();
         for (int c = 0; c < kX; ++c)
             region[c].insert(region[c].end(), t.begin() + n * c / kX, t.begin() + n * (c + 1) / kX);
@@ -322,7 +331,7 @@ void finalize(Engine* e) {
     // from the cache and are faster.  The autotuner measures both.
     long long pair_bytes = 0;
     for (const InstHost& I : e->in) pair_bytes += 2LL * I.field * (long long)sizeof(float);
-    e->tb = pair_bytes > (256LL << 20);
+    for (bool& t : e->tb) t = pair_bytes > (256LL << 20);
     e->J = dalloc<double>(e, N);
     e->part = dalloc<double>(e, aafwi::kReduceBlocks);
     e->flag = dalloc<int>(e, 1);
@@ -390,9 +399,10 @@ void run_forward(Engine* e, const std::vector<const float*>& m, float* d_ovr, bo
     }
     aafwi::StepArgs a{0, 0, keep ? 1 : 0, d_ovr, nullptr, e->active};
     const int T = max_nt(e);
-    for (int n = 0; n < T; n += e->tb ? 2 : 1) {
+    const bool two = e->tb[AAFWI_K_FWD_STEP];
+    for (int n = 0; n < T; n += two ? 2 : 1) {
         a.n = n;
-        if (e->tb)
+        if (two)
             step2(e, AAFWI_K_FWD_STEP, a);
         else
             step(e, AAFWI_K_FWD_STEP, a);
@@ -427,20 +437,26 @@ void run_backward(Engine* e, const float* r_ovr, const std::vector<float*>& grad
         int len = 0;
         for (auto& I : e->in) len = std::max(len, seg_len(e, I, J));
         a.seg = J;
-        if (e->tb) {
+        // recompute and adjoint choose their launch mode independently: the
+        // segment's q planes do not depend on it, and the adjoint keeps one
+        // mode (one buffer convention) for the whole pass
+        if (e->tb[AAFWI_K_REC_STEP]) {
             for (int tt = 0; tt < len; tt += 2) {
                 a.n = tt;
                 step2(e, AAFWI_K_REC_STEP, a);
-            }
-            for (int tt = len - 1; tt >= 0; tt -= 2) {
-                a.n = tt;
-                step2(e, AAFWI_K_ADJ_STEP, a);
             }
         } else {
             for (int tt = 0; tt < len; ++tt) {
                 a.n = tt;
                 step(e, AAFWI_K_REC_STEP, a);
             }
+        }
+        if (e->tb[AAFWI_K_ADJ_STEP]) {
+            for (int tt = len - 1; tt >= 0; tt -= 2) {
+                a.n = tt;
+                step2(e, AAFWI_K_ADJ_STEP, a);
+            }
+        } else {
             for (int tt = len - 1; tt >= 0; --tt) {
                 a.n = tt;
                 step(e, AAFWI_K_ADJ_STEP, a);
@@ -521,9 +537,25 @@ int set_tile(Engine* e, int kernel_id, int rows) {
     return AAFWI_OK;
 }
 
-int set_time_blocking(Engine* e, int enable) {
+int set_tile_order(Engine* e, int kernel_id, int order) {
+    AAFWI_REQUIRE(order == 0 || order == 1, "set_tile_order: order must be 0 or 1");
+    AAFWI_REQUIRE(kernel_id >= -1 && kernel_id < 4, "set_tile_order: kernel_id must be -1 or a kernel id");
     AAFWI_HIP(hipStreamSynchronize(e->stream));
-    e->tb = enable != 0;
+    for (int k = 0; k < 4; ++k)
+        if (kernel_id == -1 || kernel_id == k) {
+            e->order[k] = order;
+            build_tiles(e, k);
+        }
+    for (auto& kv : e->graphs) (void)hipGraphExecDestroy(kv.second);
+    e->graphs.clear();
+    return AAFWI_OK;
+}
+
+int set_time_blocking(Engine* e, int kernel_id, int enable) {
+    AAFWI_REQUIRE(kernel_id >= -1 && kernel_id < 3, "set_time_blocking: kernel_id must be -1, 0, 1 or 2");
+    AAFWI_HIP(hipStreamSynchronize(e->stream));
+    for (int k = 0; k < 3; ++k)
+        if (kernel_id == -1 || kernel_id == k) e->tb[k] = enable != 0;
     for (auto& kv : e->graphs) (void)hipGraphExecDestroy(kv.second);
     e->graphs.clear();
     return AAFWI_OK;
@@ -717,17 +749,31 @@ extern "C" int aafwi_set_tile(aafwi_ctx* c, int32_t kernel_id, int32_t rows) {
     });
 }
 
-extern "C" int aafwi_set_time_blocking(aafwi_ctx* c, int enable) {
+extern "C" int aafwi_set_tile_order(aafwi_ctx* c, int32_t kernel_id, int32_t order) {
     return guarded([&]() -> int {
-        AAFWI_REQUIRE(c, "set_time_blocking: NULL context");
-        return set_time_blocking(c->e, enable);
+        AAFWI_REQUIRE(c, "set_tile_order: NULL context");
+        return set_tile_order(c->e, kernel_id, order);
     });
 }
 
-extern "C" int aafwi_get_time_blocking(const aafwi_ctx* c, int* enabled) {
+extern "C" int aafwi_set_time_blocking(aafwi_ctx* c, int enable) {
     return guarded([&]() -> int {
-        AAFWI_REQUIRE(c && enabled, "get_time_blocking: NULL argument");
-        *enabled = c->e->tb ? 1 : 0;
+        AAFWI_REQUIRE(c, "set_time_blocking: NULL context");
+        return set_time_blocking(c->e, -1, enable);
+    });
+}
+
+extern "C" int aafwi_set_time_blocking_kernel(aafwi_ctx* c, int32_t kernel_id, int enable) {
+    return guarded([&]() -> int {
+        AAFWI_REQUIRE(c, "set_time_blocking_kernel: NULL context");
+        return set_time_blocking(c->e, kernel_id, enable);
+    });
+}
+
+extern "C" int aafwi_get_time_blocking(const aafwi_ctx* c, int* mask) {
+    return guarded([&]() -> int {
+        AAFWI_REQUIRE(c && mask, "get_time_blocking: NULL argument");
+        *mask = (c->e->tb[0] ? 1 : 0) | (c->e->tb[1] ? 2 : 0) | (c->e->tb[2] ? 4 : 0);
         return AAFWI_OK;
     });
 }
@@ -880,7 +926,7 @@ extern "C" int aafwi_batch_set_tile(aafwi_batch* b, int32_t kernel_id, int32_t r
 extern "C" int aafwi_batch_set_time_blocking(aafwi_batch* b, int enable) {
     return guarded([&]() -> int {
         AAFWI_REQUIRE(b, "batch_set_time_blocking: NULL batch");
-        return set_time_blocking(b->e, enable);
+        return set_time_blocking(b->e, -1, enable);
     });
 }
 
