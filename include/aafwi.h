@@ -155,6 +155,17 @@ int aafwi_aa_step(aafwi_aa* aa, const float* p_k, const float* g_k, float eta, f
                   float* p_tilde, double* gamma, int32_t* mk);
 
 /* Condition number of A_k found by the last step (device double), for logs. */
+/* Least-squares solver of Step 2.  AAFWI_AA_GRAM (default): FP64 normal
+ * equations of the exact gradient differences, cyclic Jacobi.  AAFWI_AA_QR:
+ * the rank-updated QR factorisation of the paper's Step 2 (columns appended
+ * by Gram-Schmidt with reorthogonalisation, the oldest removed by Givens
+ * rotations; Q is n x M doubles on the device, allocated on first use);
+ * its accuracy degrades with cond(A_k), not cond(A_k)^2.  Both apply the
+ * same drop rule.  Switching clears the history.  Synchronises the stream. */
+#define AAFWI_AA_GRAM 0
+#define AAFWI_AA_QR   1
+int aafwi_aa_set_solver(aafwi_aa* aa, int solver);
+
 int aafwi_aa_last_cond(aafwi_aa* aa, double* cond_dev);
 
 /* out = lambda*p_tilde + (1-lambda)*p_bar (Algorithm 2, Step 5), formed in

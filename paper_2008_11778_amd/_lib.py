@@ -72,6 +72,8 @@ _sig("aafwi_aa_reset", _vp)
 _sig("aafwi_aa_destroy", _vp)
 _sig("aafwi_aa_step", _vp, _vp, _vp, _f32, _vp, _vp, _vp, _vp)
 _sig("aafwi_aa_last_cond", _vp, _vp)
+_sig("aafwi_aa_set_solver", _vp, ctypes.c_int)
+AA_GRAM, AA_QR = 0, 1
 _sig("aafwi_blend", _vp, _i64, _f32, _vp, _vp, _vp)
 _sig("aafwi_dot", _vp, _i64, _vp, _vp, _vp, _vp)
 _sig("aafwi_dot_diff", _vp, _i64, _vp, _vp, _vp, _vp, _vp)
@@ -394,7 +396,7 @@ class Batch:
 class AA:
     """Device state of Algorithm 2 (Steps 1-3) for vectors of n values."""
 
-    def __init__(self, n: int, M: int, cond_max: float = 1e5, stream=None):
+    def __init__(self, n: int, M: int, cond_max: float = 1e5, stream=None, solver: str = "gram"):
         self.n, self.M = int(n), int(M)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self.device = torch.device("cuda", torch.cuda.current_device())
@@ -404,6 +406,13 @@ class AA:
         self.gamma = torch.zeros(self.M, dtype=torch.float64, device=self.device)
         self.mk = torch.zeros(1, dtype=torch.int32, device=self.device)
         self.cond = torch.zeros(1, dtype=torch.float64, device=self.device)
+        if solver != "gram":
+            self.set_solver(solver)
+
+    def set_solver(self, solver: str):
+        """'gram' (FP64 normal equations) or 'qr' (rank-updated QR); clears the history."""
+        code = {"gram": AA_GRAM, "qr": AA_QR}[solver]
+        _check(_lib.aafwi_aa_set_solver(self._h, code))
 
     def reset(self):
         _check(_lib.aafwi_aa_reset(self._h))

@@ -14,6 +14,17 @@
 // gamma = V diag(1/l) V^T rhs.  The mixing pass forms, per element in FP64,
 //   p_bar   = p_k - eta g_k
 //   p_tilde = p_bar - sum_i gamma_i [(p_{i+1} - p_i) - eta (g_{i+1} - g_i)].
+//
+// Second solver (the update the paper's Algorithm 2, Step 2 names): a QR
+// factorisation dG = Q R kept up to date as columns enter and leave the
+// window, with Q (n x m, FP64) on the device and R (m x m) in the state.  A
+// new difference column is orthogonalised against Q by classical
+// Gram-Schmidt with one reorthogonalisation; dropping the oldest column
+// leaves R upper Hessenberg, which Givens rotations G restore, and Q becomes
+// the leading columns of Q G^T (applied as one small matrix product per
+// element).  gamma = R^{-1} Q^T g_k by back substitution.  The conditioning
+// of R is that of dG, so the solve is not squared as in the Gram form; the
+// drop rule is the same (cond_2(R) = sqrt(lmax/lmin) of R^T R).
 #include <cmath>
 #include <new>
 
@@ -29,6 +40,12 @@ struct AAState {
     double gram[kAACap * kAACap];
     double rhs[kAACap];
     double gamma[kAACap];
+    // QR solver
+    int rot_in, rot_out;          // pending Q <- Q W, W: rot_in x rot_out (0: none)
+    double R[kAACap * kAACap];    // upper triangular, row-major, stride kAACap
+    double W[kAACap * kAACap];
+    double c1[kAACap], c2[kAACap];
+    double nrm2;
 };
 
 namespace {
@@ -254,6 +271,283 @@ __global__ __launch_bounds__(256) void k_aa_mix(long long n, const float* __rest
     p_tilde[e] = (float)pt;
 }
 
+// ---------------------------------------------------------------------------
+// QR solver kernels
+// ---------------------------------------------------------------------------
+// Delete column 0 of the m-column factor (R, rhs): R[:, 1:] is upper
+// Hessenberg; rotations on rows (i, i+1) zero its subdiagonal.  W (m_in x m)
+// accumulates Q's pending transform: W <- (W G^T)[:, :m-1].
+__device__ void qr_drop_first(AAState* s, int m, double* rhs) {
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j + 1 < m; ++j) s->R[i * kAACap + j] = s->R[i * kAACap + j + 1];
+    const int m_in = s->rot_in;
+    for (int i = 0; i + 1 < m; ++i) {
+        const double a = s->R[i * kAACap + i], b = s->R[(i + 1) * kAACap + i];
+        const double r = hypot(a, b);
+        const double c = r > 0.0 ? a / r : 1.0, sn = r > 0.0 ? b / r : 0.0;
+        for (int j = i; j + 1 < m; ++j) {
+            const double x = s->R[i * kAACap + j], y = s->R[(i + 1) * kAACap + j];
+            s->R[i * kAACap + j] = c * x + sn * y;
+            s->R[(i + 1) * kAACap + j] = -sn * x + c * y;
+        }
+        s->R[(i + 1) * kAACap + i] = 0.0;
+        if (rhs) {
+            const double x = rhs[i], y = rhs[i + 1];
+            rhs[i] = c * x + sn * y;
+            rhs[i + 1] = -sn * x + c * y;
+        }
+        for (int k = 0; k < m_in; ++k) {  // columns i, i+1 of W times G_i^T
+            const double x = s->W[k * kAACap + i], y = s->W[k * kAACap + i + 1];
+            s->W[k * kAACap + i] = c * x + sn * y;
+            s->W[k * kAACap + i + 1] = -sn * x + c * y;
+        }
+    }
+    for (int i = 0; i + 1 < m; ++i) s->R[i * kAACap + (m - 1)] = 0.0;
+    for (int j = 0; j < m; ++j) s->R[(m - 1) * kAACap + j] = 0.0;
+    s->rot_out = m - 1;
+}
+
+__device__ void qr_begin_transform(AAState* s, int m) {
+    s->rot_in = m;
+    s->rot_out = m;
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) s->W[i * kAACap + j] = (i == j) ? 1.0 : 0.0;
+}
+
+// Before the push: a full ring drops its oldest iterate and difference column.
+__global__ void k_qr_prepare(AAState* s, int cap) {
+    if (threadIdx.x != 0) return;
+    s->rot_in = s->rot_out = 0;
+    if (s->count == cap) {
+        const int m = s->count - 1;
+        qr_begin_transform(s, m);
+        qr_drop_first(s, m, nullptr);
+        s->head = (s->head + 1) % cap;
+        s->count -= 1;
+    }
+    s->slot_new = (s->head + s->count) % cap;
+}
+
+// Q[:, j] <- sum_i Q[:, i] W[i][j], j < rot_out (no-op without a pending transform).
+template <int CAP>
+__global__ __launch_bounds__(256) void k_qr_rotate(long long n, double* __restrict__ Q, const AAState* __restrict__ s) {
+    const int m_in = s->rot_in, m_out = s->rot_out;
+    if (m_in == 0) return;
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    double row[CAP];
+#pragma unroll
+    for (int i = 0; i < CAP; ++i) row[i] = i < m_in ? Q[(long long)i * n + e] : 0.0;
+    for (int j = 0; j < m_out; ++j) {
+        double acc = 0.0;
+#pragma unroll
+        for (int i = 0; i < CAP; ++i)
+            if (i < m_in) acc += row[i] * s->W[i * kAACap + j];
+        Q[(long long)j * n + e] = acc;
+    }
+}
+
+// Block partials of up to CAP dot products (written to part[block][i]).
+template <int CAP>
+__device__ __forceinline__ void store_partials(double (&v)[CAP], int ncol, double* part) {
+    __shared__ double sh[kReduceThreads / 64][CAP];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < CAP; ++i) {
+        const double a = wave_reduce(v[i]);
+        if (lane == 0) sh[wv][i] = a;
+    }
+    __syncthreads();
+    if (threadIdx.x < ncol) {
+        double t = 0.0;
+        for (int w = 0; w < kReduceThreads / 64; ++w) t += sh[w][threadIdx.x];
+        part[(long long)blockIdx.x * 2 * kAACap + threadIdx.x] = t;
+    }
+}
+
+// Push (p_new, g_new) into the ring; a = g_new - g_last (FP64) into Q[:, m];
+// partials of Q[:, i] . a, i < m.
+template <int CAP>
+__global__ __launch_bounds__(kReduceThreads) void k_qr_append(long long n, const float* __restrict__ p_new,
+                                                              const float* __restrict__ g_new,
+                                                              float* __restrict__ ring_p, float* __restrict__ ring_g,
+                                                              int cap, double* __restrict__ Q,
+                                                              const AAState* __restrict__ s,
+                                                              double* __restrict__ part) {
+    const int cnt = s->count, slot_new = s->slot_new;
+    const int m = cnt - 1;  // existing difference columns (if cnt >= 1)
+    const int last = (s->head + cnt - 1 + cap) % cap;
+    double v[CAP];
+#pragma unroll
+    for (int i = 0; i < CAP; ++i) v[i] = 0.0;
+    for (long long e = (long long)blockIdx.x * kReduceThreads + threadIdx.x; e < n;
+         e += (long long)kReduceBlocks * kReduceThreads) {
+        const float gn = g_new[e];
+        ring_p[(long long)slot_new * n + e] = p_new[e];
+        if (cnt >= 1) {
+            const double a = (double)gn - (double)ring_g[(long long)last * n + e];
+            Q[(long long)m * n + e] = a;
+#pragma unroll
+            for (int i = 0; i < CAP; ++i)
+                if (i < m) v[i] += Q[(long long)i * n + e] * a;
+        }
+        ring_g[(long long)slot_new * n + e] = gn;
+    }
+    store_partials<CAP>(v, CAP, part);
+}
+
+// a <- a - Q[:, :m] c (c = c1 or c2); partials of Q[:, i] . a (i < m), or of
+// a . a when `norm` is set.
+template <int CAP>
+__global__ __launch_bounds__(kReduceThreads) void k_qr_subtract(long long n, double* __restrict__ Q,
+                                                                const AAState* __restrict__ s, int second,
+                                                                double* __restrict__ part) {
+    const int m = s->count - 1;
+    double v[CAP];
+#pragma unroll
+    for (int i = 0; i < CAP; ++i) v[i] = 0.0;
+    if (m >= 0) {
+        const double* c = second ? s->c2 : s->c1;
+        double cc[CAP];
+#pragma unroll
+        for (int i = 0; i < CAP; ++i) cc[i] = i < m ? c[i] : 0.0;
+        for (long long e = (long long)blockIdx.x * kReduceThreads + threadIdx.x; e < n;
+             e += (long long)kReduceBlocks * kReduceThreads) {
+            double a = Q[(long long)m * n + e];
+            double q[CAP];
+#pragma unroll
+            for (int i = 0; i < CAP; ++i) q[i] = i < m ? Q[(long long)i * n + e] : 0.0;
+#pragma unroll
+            for (int i = 0; i < CAP; ++i)
+                if (i < m) a -= cc[i] * q[i];
+            Q[(long long)m * n + e] = a;
+            if (!second) {
+#pragma unroll
+                for (int i = 0; i < CAP; ++i)
+                    if (i < m) v[i] += q[i] * a;
+            } else {
+                v[0] += a * a;
+            }
+        }
+    }
+    store_partials<CAP>(v, CAP, part);
+}
+
+// Q[:, m] <- a / rho; partials of Q[:, i] . g_k for i <= m.
+template <int CAP>
+__global__ __launch_bounds__(kReduceThreads) void k_qr_scale_rhs(long long n, double* __restrict__ Q,
+                                                                 const float* __restrict__ g_k,
+                                                                 const AAState* __restrict__ s,
+                                                                 double* __restrict__ part) {
+    const int m = s->count - 1;
+    const double rho = sqrt(s->nrm2);
+    const double inv = rho > 0.0 ? 1.0 / rho : 0.0;
+    double v[CAP];
+#pragma unroll
+    for (int i = 0; i < CAP; ++i) v[i] = 0.0;
+    for (long long e = (long long)blockIdx.x * kReduceThreads + threadIdx.x; e < n;
+         e += (long long)kReduceBlocks * kReduceThreads) {
+        const double g = (double)g_k[e];
+        if (m >= 0) {
+            const double q = Q[(long long)m * n + e] * inv;
+            Q[(long long)m * n + e] = q;
+        }
+#pragma unroll
+        for (int i = 0; i < CAP; ++i)
+            if (i <= m) v[i] += Q[(long long)i * n + e] * g;
+    }
+    store_partials<CAP>(v, CAP, part);
+}
+
+// Fixed-order sum of the block partials into dst[0..ncol).
+__global__ void k_qr_reduce(const double* __restrict__ part, int which, AAState* s) {
+    const int t = threadIdx.x;
+    double acc = 0.0;
+    if (t < kAACap)
+        for (int b = 0; b < kReduceBlocks; ++b) acc += part[(long long)b * 2 * kAACap + t];
+    if (t >= kAACap) return;
+    if (which == 0) s->c1[t] = acc;
+    if (which == 1) s->c2[t] = acc;
+    if (which == 2 && t == 0) s->nrm2 = acc;
+    if (which == 3) s->rhs[t] = acc;
+}
+
+// Finish the push (new column of R), apply the drop rule, solve R gamma = Q^T g_k.
+__global__ __launch_bounds__(64) void k_qr_solve(AAState* s, int cap, double cond_max) {
+    __shared__ double S[kAACap * kAACap];
+    __shared__ double V[kAACap * kAACap];
+    if (threadIdx.x != 0) return;
+    const int cnt = s->count;
+    int m = 0;
+    if (cnt >= 1) {
+        const int k = cnt - 1;  // the new column
+        for (int i = 0; i < k; ++i) {
+            s->R[i * kAACap + k] = s->c1[i] + s->c2[i];
+            s->R[k * kAACap + i] = 0.0;
+        }
+        s->R[k * kAACap + k] = sqrt(s->nrm2);
+        m = k + 1;
+    }
+    s->count = cnt + 1;
+    qr_begin_transform(s, m);
+    s->rot_in = 0;  // no transform unless a column is dropped below
+    double cond = 1.0;
+    while (m > 0) {
+        // singular values of R from the eigenvalues of R^T R
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < m; ++j) {
+                double acc = 0.0;
+                for (int k = 0; k <= (i < j ? i : j); ++k) acc += s->R[k * kAACap + i] * s->R[k * kAACap + j];
+                S[i * kAACap + j] = acc;
+            }
+        jacobi_eig(S, V, m);
+        double lmax = 0.0, lmin = INFINITY;
+        for (int i = 0; i < m; ++i) {
+            lmax = fmax(lmax, S[i * kAACap + i]);
+            lmin = fmin(lmin, S[i * kAACap + i]);
+        }
+        cond = (lmin > 0.0) ? sqrt(lmax / lmin) : INFINITY;
+        if (cond <= cond_max) {
+            for (int i = m - 1; i >= 0; --i) {
+                double acc = s->rhs[i];
+                for (int j = i + 1; j < m; ++j) acc -= s->R[i * kAACap + j] * s->gamma[j];
+                s->gamma[i] = acc / s->R[i * kAACap + i];
+            }
+            break;
+        }
+        if (s->rot_in == 0) qr_begin_transform(s, m);
+        qr_drop_first(s, m, s->rhs);  // rhs becomes (G Q^T g_k) of the remaining columns
+        s->head = (s->head + 1) % cap;
+        s->count -= 1;
+        m -= 1;
+        cond = 1.0;
+    }
+    s->mk = m;
+    s->cond = (m > 0) ? cond : 0.0;
+}
+
+template <int CAP>
+void aa_launch_qr(hipStream_t st, long long n, const float* p, const float* g, float eta, float* ring_p,
+                  float* ring_g, int cap, AAState* s, double* part, double cond_max, double* Q, float* pbar,
+                  float* ptilde) {
+    const dim3 red(kReduceBlocks), rt(kReduceThreads), el((unsigned)((n + 255) / 256));
+    hipLaunchKernelGGL(k_qr_prepare, dim3(1), dim3(64), 0, st, s, cap);
+    hipLaunchKernelGGL(k_qr_rotate<CAP>, el, dim3(256), 0, st, n, Q, (const AAState*)s);
+    hipLaunchKernelGGL(k_qr_append<CAP>, red, rt, 0, st, n, p, g, ring_p, ring_g, cap, Q, (const AAState*)s, part);
+    hipLaunchKernelGGL(k_qr_reduce, dim3(1), dim3(64), 0, st, (const double*)part, 0, s);
+    hipLaunchKernelGGL(k_qr_subtract<CAP>, red, rt, 0, st, n, Q, (const AAState*)s, 0, part);
+    hipLaunchKernelGGL(k_qr_reduce, dim3(1), dim3(64), 0, st, (const double*)part, 1, s);
+    hipLaunchKernelGGL(k_qr_subtract<CAP>, red, rt, 0, st, n, Q, (const AAState*)s, 1, part);
+    hipLaunchKernelGGL(k_qr_reduce, dim3(1), dim3(64), 0, st, (const double*)part, 2, s);
+    hipLaunchKernelGGL(k_qr_scale_rhs<CAP>, red, rt, 0, st, n, Q, g, (const AAState*)s, part);
+    hipLaunchKernelGGL(k_qr_reduce, dim3(1), dim3(64), 0, st, (const double*)part, 3, s);
+    hipLaunchKernelGGL(k_qr_solve, dim3(1), dim3(64), 0, st, s, cap, cond_max);
+    hipLaunchKernelGGL(k_qr_rotate<CAP>, el, dim3(256), 0, st, n, Q, (const AAState*)s);
+    hipLaunchKernelGGL(k_aa_mix<CAP>, el, dim3(256), 0, st, n, p, g, eta, (const float*)ring_p,
+                       (const float*)ring_g, cap, (const AAState*)s, pbar, ptilde);
+    AAFWI_HIP(hipGetLastError());
+}
+
 __global__ __launch_bounds__(kReduceThreads) void k_dot(long long n, const float* __restrict__ x,
                                                         const float* __restrict__ y,
                                                         const float* __restrict__ z,
@@ -365,6 +659,8 @@ struct aafwi_aa {
     float* ring_g;
     aafwi::AAState* state;
     double* part;
+    int solver;        // AAFWI_AA_GRAM or AAFWI_AA_QR
+    double* Q;         // QR solver: n x M, FP64 (allocated on first use)
 };
 
 namespace {
@@ -391,6 +687,7 @@ void aa_free(aafwi_aa* a) {
     if (a->ring_g) (void)hipFree(a->ring_g);
     if (a->state) (void)hipFree(a->state);
     if (a->part) (void)hipFree(a->part);
+    if (a->Q) (void)hipFree(a->Q);
     delete a;
 }
 
@@ -452,17 +749,44 @@ extern "C" int aafwi_aa_step(aafwi_aa* a, const float* p_k, const float* g_k, fl
         AAFWI_REQUIRE(a != nullptr, "aa_step: NULL state");
         AAFWI_REQUIRE(p_k && g_k && p_bar && p_tilde, "aa_step: NULL vector");
         AAFWI_REQUIRE(std::isfinite(eta) && eta >= 0.0f, "aa_step: eta must be finite and >= 0");
-        switch (a->capT) {
-            case 4: aafwi::aa_launch<4>(a->stream, a->n, p_k, g_k, eta, a->ring_p, a->ring_g, a->cap, a->state, a->part, a->cond_max, p_bar, p_tilde); break;
-            case 8: aafwi::aa_launch<8>(a->stream, a->n, p_k, g_k, eta, a->ring_p, a->ring_g, a->cap, a->state, a->part, a->cond_max, p_bar, p_tilde); break;
-            case 16: aafwi::aa_launch<16>(a->stream, a->n, p_k, g_k, eta, a->ring_p, a->ring_g, a->cap, a->state, a->part, a->cond_max, p_bar, p_tilde); break;
-            default: aafwi::aa_launch<32>(a->stream, a->n, p_k, g_k, eta, a->ring_p, a->ring_g, a->cap, a->state, a->part, a->cond_max, p_bar, p_tilde); break;
+        if (a->solver == AAFWI_AA_QR) {
+            switch (a->capT) {
+                case 4: aafwi::aa_launch_qr<4>(a->stream, a->n, p_k, g_k, eta, a->ring_p, a->ring_g, a->cap, a->state, a->part, a->cond_max, a->Q, p_bar, p_tilde); break;
+                case 8: aafwi::aa_launch_qr<8>(a->stream, a->n, p_k, g_k, eta, a->ring_p, a->ring_g, a->cap, a->state, a->part, a->cond_max, a->Q, p_bar, p_tilde); break;
+                case 16: aafwi::aa_launch_qr<16>(a->stream, a->n, p_k, g_k, eta, a->ring_p, a->ring_g, a->cap, a->state, a->part, a->cond_max, a->Q, p_bar, p_tilde); break;
+                default: aafwi::aa_launch_qr<32>(a->stream, a->n, p_k, g_k, eta, a->ring_p, a->ring_g, a->cap, a->state, a->part, a->cond_max, a->Q, p_bar, p_tilde); break;
+            }
+        } else {
+            switch (a->capT) {
+                case 4: aafwi::aa_launch<4>(a->stream, a->n, p_k, g_k, eta, a->ring_p, a->ring_g, a->cap, a->state, a->part, a->cond_max, p_bar, p_tilde); break;
+                case 8: aafwi::aa_launch<8>(a->stream, a->n, p_k, g_k, eta, a->ring_p, a->ring_g, a->cap, a->state, a->part, a->cond_max, p_bar, p_tilde); break;
+                case 16: aafwi::aa_launch<16>(a->stream, a->n, p_k, g_k, eta, a->ring_p, a->ring_g, a->cap, a->state, a->part, a->cond_max, p_bar, p_tilde); break;
+                default: aafwi::aa_launch<32>(a->stream, a->n, p_k, g_k, eta, a->ring_p, a->ring_g, a->cap, a->state, a->part, a->cond_max, p_bar, p_tilde); break;
+            }
         }
         if (gamma)
             AAFWI_HIP(hipMemcpyAsync(gamma, a->state->gamma, sizeof(double) * a->M, hipMemcpyDeviceToDevice,
                                      a->stream));
         if (mk)
             AAFWI_HIP(hipMemcpyAsync(mk, &a->state->mk, sizeof(int32_t), hipMemcpyDeviceToDevice, a->stream));
+        return AAFWI_OK;
+    });
+}
+
+extern "C" int aafwi_aa_set_solver(aafwi_aa* a, int solver) {
+    return guarded([&]() -> int {
+        AAFWI_REQUIRE(a != nullptr, "aa_set_solver: NULL state");
+        AAFWI_REQUIRE(solver == AAFWI_AA_GRAM || solver == AAFWI_AA_QR, "aa_set_solver: unknown solver");
+        AAFWI_HIP(hipStreamSynchronize(a->stream));
+        if (solver == AAFWI_AA_QR && !a->Q) {
+            if (hipMalloc((void**)&a->Q, sizeof(double) * (size_t)a->n * a->M) != hipSuccess) {
+                (void)hipGetLastError();
+                a->Q = nullptr;
+                throw aafwi::Error{AAFWI_E_NOMEM, "aa_set_solver: device allocation failed"};
+            }
+        }
+        a->solver = solver;
+        AAFWI_HIP(hipMemsetAsync(a->state, 0, sizeof(aafwi::AAState), a->stream));
         return AAFWI_OK;
     });
 }

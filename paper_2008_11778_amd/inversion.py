@@ -123,11 +123,11 @@ class AADescent:
 
     def __init__(self, problem, p0: torch.Tensor, eta: float | None, M: int, cond_max: float = 1e5,
                  lambdas=LAMBDAS, c1: float = ARMIJO_C1, linesearch: bool = True,
-                 eta_frac: float = 0.02):
+                 eta_frac: float = 0.02, aa_solver: str = "gram"):
         self.problem, self.M, self.eta = problem, M, eta
         self.lambdas, self.c1, self.linesearch, self.eta_frac = lambdas, c1, linesearch, eta_frac
         self.shape = p0.shape
-        self.aa = AA(p0.numel(), max(M, 1), cond_max) if M > 0 else None
+        self.aa = AA(p0.numel(), max(M, 1), cond_max, solver=aa_solver) if M > 0 else None
         self.red = Reducer()
         self.p = p0.detach().clone().reshape(-1)
         self.g = torch.empty_like(self.p)
@@ -187,10 +187,11 @@ class AADescent:
 
 def aa_descent(problem, p0: torch.Tensor, eta: float | None, M: int, iters: int, cond_max: float = 1e5,
                lambdas=LAMBDAS, c1: float = ARMIJO_C1, linesearch: bool = True,
-               keep_iterates: bool = True, log_path: str | None = None, callback=None):
+               keep_iterates: bool = True, log_path: str | None = None, callback=None, aa_solver: str = "gram"):
     """Run Algorithm 2 for ``iters`` iterations after p_1 = G(p_0).
-    Returns (iterates p_0..p_{iters+1}, history of IterLog, final p)."""
-    run = AADescent(problem, p0, eta, M, cond_max, lambdas, c1, linesearch)
+    Returns (iterates p_0..p_{iters+1}, history of IterLog, final p).
+    aa_solver: "gram" (FP64 normal equations) or "qr" (rank-updated QR)."""
+    run = AADescent(problem, p0, eta, M, cond_max, lambdas, c1, linesearch, aa_solver=aa_solver)
     iterates = [run.p.clone()] if keep_iterates else []
     hist = []
     out = open(log_path, "a") if log_path else None

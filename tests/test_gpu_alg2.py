@@ -35,16 +35,23 @@ def _oracle_run(g, m0, d_obs, eta, M, iters):
     return res["iterates"], res
 
 
-def test_alg2_config1_matches_oracle(problem):
+@pytest.fixture(scope="module")
+def oracle_alg2(problem):
+    g, m0, d_obs, eta = problem
+    return _oracle_run(g, m0, d_obs, eta, 5, 5)
+
+
+@pytest.mark.parametrize("solver", ["gram", "qr"])
+def test_alg2_config1_matches_oracle(problem, oracle_alg2, solver):
     import torch
     from paper_2008_11778_amd import Context
     from paper_2008_11778_amd.inversion import FWIProblem, aa_descent
     g, m0, d_obs, eta = problem
     dev = torch.device("cuda", 0)
-    ref_it, ref = _oracle_run(g, m0, d_obs, eta, 5, 5)
+    ref_it, ref = oracle_alg2
     with Context(g) as ctx:
         prob = FWIProblem(ctx, torch.from_numpy(d_obs).to(dev))
-        its, hist, _ = aa_descent(prob, torch.from_numpy(m0).to(dev), eta, M=5, iters=5)
+        its, hist, _ = aa_descent(prob, torch.from_numpy(m0).to(dev), eta, M=5, iters=5, aa_solver=solver)
         its = [t.cpu().numpy() for t in its]
     lams = [h.lam for h in hist[1:]]
     print("lambdas gpu", lams, "oracle", ref["lambdas"])
