@@ -176,3 +176,45 @@ def lbfgs(fun_grad, p0, M, iters, a1=1.0):
         p, J, g = p + s, Jn, gn
         out.append(p.copy())
     return out
+
+
+def ncg(fun_grad, p0, iters, a1=1.0, c2=0.1, line_search=None):
+    """Nonlinear conjugate gradients, Polak-Ribiere+ (Nocedal & Wright,
+    eq. 5.44-5.45): d_0 = -g_0, beta = max(0, g_{k+1}.(g_{k+1} - g_k) / g_k.g_k),
+    d_{k+1} = -g_{k+1} + beta d_k, restarted with -g_{k+1} when that is not
+    a descent direction.  Step lengths from a strong-Wolfe search
+    (c1 = 1e-4, c2 = 0.1) started at a1 / |g_0| on the first iteration and at
+    alpha_{k-1} g_{k-1}.d_{k-1} / g_k.d_k afterwards (N&W eq. 3.60).
+    ``line_search(phi, dphi, f0, d0, a_init)`` replaces the search (tests)."""
+    p = np.asarray(p0, np.float64).ravel().copy()
+    J, g = fun_grad(p)
+    g = np.asarray(g, np.float64).ravel()
+    d = -g
+    a_init = a1 / max(np.linalg.norm(g), 1e-300)
+    out = [p.copy()]
+    for _ in range(iters):
+        cache = {}
+
+        def eval_at(a):
+            if a not in cache:
+                Ja, ga = fun_grad(p + a * d)
+                cache[a] = (Ja, np.asarray(ga, np.float64).ravel())
+            return cache[a]
+
+        phi = lambda a: eval_at(a)[0]
+        dphi = lambda a: float(np.dot(eval_at(a)[1], d))
+        d0 = float(np.dot(g, d))
+        if line_search is None:
+            a = strong_wolfe(phi, dphi, J, d0, a1=a_init, c2=c2)
+        else:
+            a = line_search(phi, dphi, J, d0, a_init)
+        Jn, gn = eval_at(a)
+        p = p + a * d
+        beta = max(0.0, float(np.dot(gn, gn - g)) / float(np.dot(g, g)))
+        dn = -gn + beta * d
+        if float(np.dot(gn, dn)) >= 0.0:
+            dn = -gn
+        a_init = a * d0 / float(np.dot(gn, dn))
+        J, g, d = Jn, gn, dn
+        out.append(p.copy())
+    return out

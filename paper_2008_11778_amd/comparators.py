@@ -224,3 +224,58 @@ class LBFGS:
         self.p, self.g, self.J = pn, gn, Jn
         self.k += 1
         return Jn
+
+
+# ----------------------------------------------------------------------------
+# nonlinear conjugate gradients
+# ----------------------------------------------------------------------------
+
+class NCG:
+    """Polak-Ribiere+ nonlinear CG on a problem with ``gradient(p, g) -> J``.
+
+    beta = max(0, g_{k+1}.(g_{k+1} - g_k) / g_k.g_k), d_{k+1} = -g_{k+1} + beta d_k,
+    restarted with -g_{k+1} when not a descent direction; strong-Wolfe steps
+    (c1 = 1e-4, c2 = 0.1) started at alpha_{k-1} g_{k-1}.d_{k-1} / g_k.d_k.
+    The first step is scaled so that its largest entry is ``first_step``
+    times the largest entry of p (the analogue of the fixed-step rule)."""
+
+    def __init__(self, problem, p0, first_step=0.02, c2=0.1):
+        self.problem, self.first_step, self.c2 = problem, first_step, c2
+        self.red = Reducer()
+        self.p = p0.detach().clone().reshape(-1)
+        self.g = torch.empty_like(self.p)
+        self.J = problem.gradient(self.p, self.g)
+        self.d = _scale_into(-1.0, self.g, torch.empty_like(self.g))
+        self.a_init = self.first_step * float(self.p.abs().max().item()) / float(self.d.abs().max().item())
+        self.k = 0
+        self.n_evals = 1
+
+    def iterate(self):
+        red, d = self.red, self.d
+        d0 = float(red.dot(self.g, d).item())
+        cache = {}
+
+        def ev(a):
+            if a not in cache:
+                trial = _copy(self.p, torch.empty_like(self.p))
+                axpy(a, d, trial)
+                gt = torch.empty_like(self.p)
+                Ja = self.problem.gradient(trial, gt)
+                self.n_evals += 1
+                cache[a] = (Ja, float(red.dot(gt, d).item()), trial, gt)
+            return cache[a]
+
+        a = strong_wolfe(lambda a: ev(a)[0], lambda a: ev(a)[1], self.J, d0, a1=self.a_init, c2=self.c2)
+        Jn, _, pn, gn = ev(a)
+        gg = float(red.dot(self.g, self.g).item())
+        beta = max(0.0, float(red.dot_diff(gn, gn, self.g).item()) / gg)
+        dn = _scale_into(beta, d, torch.empty_like(d))
+        axpy(-1.0, gn, dn)
+        gd = float(red.dot(gn, dn).item())
+        if gd >= 0.0:
+            _scale_into(-1.0, gn, dn)
+            gd = float(red.dot(gn, dn).item())
+        self.a_init = a * d0 / gd
+        self.p, self.g, self.d, self.J = pn, gn, dn, Jn
+        self.k += 1
+        return Jn

@@ -29,7 +29,7 @@ __all__ = [
     "Geometry", "ricker", "make_geometry", "seed", "linear_gaussian_model",
     "layered_model", "smooth", "lsrtm_background", "sparse_reflectors",
     "config1", "config2", "config3", "config4_instances", "config5",
-    "learned_instance", "small_case",
+    "learned_instance", "small_case", "uniform_noise",
 ]
 
 PURPOSE_LAYERS, PURPOSE_ANOMALY, PURPOSE_TEXTURE, PURPOSE_FAULTS, \
@@ -270,6 +270,16 @@ def learned_instance(instance, nz=128, nx=320, h=12.5, nshots=16, nt=2000):
     v0 = smooth(v_true, 8.0)
     g = g.replace(vref=float(v0.max()))
     return g, to_m(v_true), to_m(v0)
+
+
+def uniform_noise(d, snr_db, config, instance=0):
+    """Mean-zero uniform noise for the data cube d at the given signal-to-noise
+    ratio in dB (10 log10 of mean(d^2) / noise variance), FP32."""
+    d = np.asarray(d, np.float64)
+    p_sig = float(np.mean(d * d))
+    a = np.sqrt(3.0 * p_sig / 10.0 ** (snr_db / 10.0))
+    r = seed(config, instance, PURPOSE_NOISE)
+    return r.uniform(-a, a, size=d.shape).astype(np.float32)
 
 
 def small_case(nz=24, nx=28, nb=8, nt=150, nshots=2, nrec=8, h=10.0, dt=1e-3, f0=25.0,

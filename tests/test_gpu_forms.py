@@ -185,3 +185,27 @@ def test_lbfgs_fwi_decreases_and_satisfies_armijo(fwi_small):
         for _ in range(3):
             Js.append(opt.iterate())
     assert all(b < a for a, b in zip(Js, Js[1:])), Js
+
+
+def test_ncg_matches_oracle_iterates(fwi_small):
+    """Polak-Ribiere+ CG on the HIP path against the oracle's, from the same
+    start and the same first step: same line-search outcome, iterates within
+    the gradient tolerance."""
+    from paper_2008_11778_amd import Context
+    from paper_2008_11778_amd.comparators import NCG
+    from paper_2008_11778_amd.inversion import FWIProblem
+    g, m, d_obs = fwi_small
+    shape = m.shape
+    with Context(g) as ctx:
+        prob = FWIProblem(ctx, T(d_obs))
+        opt = NCG(prob, T(m))
+        a1 = opt.a_init * float(np.linalg.norm(fd.adjoint_gradient(g, m, d_obs)[1]))
+        its = [opt.p.cpu().numpy()]
+        Js = [opt.J]
+        for _ in range(2):
+            Js.append(opt.iterate())
+            its.append(opt.p.cpu().numpy())
+    ref = krylov.ncg(lambda p: fd.adjoint_gradient(g, p.reshape(shape), d_obs), m.ravel(), 2, a1=a1)
+    assert all(b < a for a, b in zip(Js, Js[1:])), Js
+    for k, (a, b) in enumerate(zip(its, ref)):
+        assert rel(a, b) <= 1e-3, (k, rel(a, b))

@@ -170,3 +170,38 @@ def test_lbfgs_converges_on_quadratic_and_wolfe_holds():
     assert np.linalg.norm(xs[-1] - xstar) < 1e-5 * np.linalg.norm(xstar)
     Js = [fg(x)[0] for x in xs]
     assert all(b_ <= a_ + 1e-12 for a_, b_ in zip(Js, Js[1:]))
+
+
+def test_ncg_with_exact_steps_is_linear_cg():
+    """On an SPD quadratic with exact line searches, Polak-Ribiere nonlinear CG
+    produces the iterates of linear CG (scipy.sparse.linalg.cg)."""
+    from scipy.sparse.linalg import cg
+    r = np.random.default_rng(31)
+    n = 30
+    Q, _ = np.linalg.qr(r.standard_normal((n, n)))
+    A = Q @ np.diag(np.linspace(1.0, 50.0, n)) @ Q.T
+    b = r.standard_normal(n)
+    fg = lambda x: (0.5 * x @ A @ x - b @ x, A @ x - b)
+
+    def exact(phi, dphi, f0, d0, a_init):
+        # phi is quadratic in a: phi'(0) = d0, phi'(1) = dphi(1); exact minimiser
+        return -d0 / (dphi(1.0) - d0)
+
+    xs = krylov.ncg(fg, np.zeros(n), 8, line_search=exact)
+    ref = []
+    cg(A, b, x0=np.zeros(n), rtol=1e-30, maxiter=8, callback=lambda xk: ref.append(xk.copy()))
+    for k in range(8):
+        np.testing.assert_allclose(xs[k + 1], ref[k], rtol=1e-8, atol=1e-10)
+
+
+def test_ncg_wolfe_converges_and_descends():
+    r = np.random.default_rng(32)
+    n = 25
+    Q, _ = np.linalg.qr(r.standard_normal((n, n)))
+    A = Q @ np.diag(np.linspace(1.0, 20.0, n)) @ Q.T
+    b = r.standard_normal(n)
+    fg = lambda x: (0.5 * x @ A @ x - b @ x + 0.05 * np.sum(x ** 4), A @ x - b + 0.2 * x ** 3)
+    xs = krylov.ncg(fg, np.zeros(n), 60)
+    J = [fg(x)[0] for x in xs]
+    assert all(b2 <= a2 + 1e-12 for a2, b2 in zip(J, J[1:]))
+    assert np.linalg.norm(fg(xs[-1])[1]) < 1e-6
