@@ -166,6 +166,18 @@ int aafwi_aa_step(aafwi_aa* aa, const float* p_k, const float* g_k, float eta, f
 #define AAFWI_AA_QR   1
 int aafwi_aa_set_solver(aafwi_aa* aa, int solver);
 
+/* Damping beta > 0 of the mixed step (eq. AAupdate0; default 1):
+ * p_tilde = xbar + beta fbar with xbar = p_k - sum gamma_i (p_{i+1} - p_i) and
+ * fbar = f_k - sum gamma_i (f_{i+1} - f_i); p_bar stays G(p_k).  Takes effect
+ * at the next step. */
+int aafwi_aa_set_damping(aafwi_aa* aa, float beta);
+
+/* Weighted l2 norm for the least-squares problem of Step 2:
+ * min || W^(1/2) (A_k gamma - f_k) || with w (device, n positive floats, kept
+ * by reference until replaced; NULL = unweighted).  The drop rule then uses
+ * cond_2(W^(1/2) A_k).  Clears the history.  Synchronises the stream. */
+int aafwi_aa_set_weights(aafwi_aa* aa, const float* w);
+
 int aafwi_aa_last_cond(aafwi_aa* aa, double* cond_dev);
 
 /* out = lambda*p_tilde + (1-lambda)*p_bar (Algorithm 2, Step 5), formed in

@@ -9,6 +9,12 @@ Section "Method").  TEST INFRASTRUCTURE ONLY.
   (eq. AA2_update).
 * For steepest descent G(p) = p - eta grad J(p) (eq. GD) the residual is
   f_k = -eta grad J(p_k).
+* Damping beta (eq. AAupdate0) in the gamma form: with xbar = p_k - sum_i
+  gamma_i (p_{i+1} - p_i) and fbar = f_k - sum_i gamma_i (f_{i+1} - f_i)
+  (that is, sum alpha_i p_i and sum alpha_i f_i), p_{k+1} = xbar + beta fbar.
+* A weighted l2 norm in the least-squares problem (the norm is left open
+  where eq. AAopt is stated): min ||W^(1/2) (A_k gamma - f_k)|| for positive
+  per-entry weights w; the drop rule then uses cond_2(W^(1/2) A_k).
 * Algorithm 2: pbar = G(p_k), ptilde from the gamma form, and the new
   iterate lambda ptilde + (1 - lambda) pbar with lambda from a backtracking
   test on J.
@@ -96,9 +102,11 @@ class AAHistory:
     while cond_2(A_k) > cond_max the oldest entry is dropped for good.
     """
 
-    def __init__(self, M: int, cond_max: float = COND_MAX):
+    def __init__(self, M: int, cond_max: float = COND_MAX, beta: float = 1.0, weights=None):
         self.M = M
         self.cond_max = cond_max
+        self.beta = float(beta)
+        self.sw = None if weights is None else np.sqrt(np.asarray(weights, np.float64).ravel())
         self.p = []
         self.g = []
 
@@ -126,15 +134,26 @@ class AAHistory:
             f, Gp, A, dG = self._matrices(eta)
             if A.shape[1] == 0:
                 break
-            sv = np.linalg.svd(A, compute_uv=False)
+            Aw = A if self.sw is None else self.sw[:, None] * A
+            sv = np.linalg.svd(Aw, compute_uv=False)
             cond = np.inf if sv[-1] <= 0.0 else sv[0] / sv[-1]
             if cond <= self.cond_max:
                 break
             self.p.pop(0)
             self.g.pop(0)
-        gamma = gamma_weights(A, f[-1])
+        if self.sw is None:
+            gamma = gamma_weights(A, f[-1])
+        else:
+            gamma = gamma_weights(self.sw[:, None] * A, self.sw * f[-1])
         pbar = Gp[-1]
-        ptilde = pbar - dG @ gamma if gamma.size else pbar.copy()
+        if self.beta == 1.0:
+            ptilde = pbar - dG @ gamma if gamma.size else pbar.copy()
+        else:
+            dP = np.stack([self.p[i + 1] - self.p[i] for i in range(len(self.p) - 1)], axis=1) \
+                if len(self.p) > 1 else np.zeros((pbar.size, 0))
+            xbar = self.p[-1] - dP @ gamma if gamma.size else self.p[-1].copy()
+            fbar = f[-1] - A @ gamma if gamma.size else f[-1].copy()
+            ptilde = xbar + self.beta * fbar
         return pbar, ptilde, gamma, A.shape[1]
 
 
@@ -150,13 +169,13 @@ def multisecant_matrix(P: np.ndarray, D: np.ndarray) -> np.ndarray:
 # ----------------------------------------------------------------------------
 
 def alg2(grad_fn, misfit_fn, p0, eta, M, iters, cond_max=COND_MAX, lambdas=LAMBDAS,
-         c1=ARMIJO_C1, linesearch=True):
+         c1=ARMIJO_C1, linesearch=True, beta=1.0, weights=None):
     """Run Algorithm 2 for ``iters`` AA iterations after p_1 = G(p_0).
 
     grad_fn(p) -> (J, g); misfit_fn(p) -> J.  Returns a dict with the
     accepted iterates, misfits, chosen lambdas and evaluation counts.
     """
-    hist = AAHistory(M, cond_max)
+    hist = AAHistory(M, cond_max, beta, weights)
     p = np.asarray(p0, np.float64).ravel().copy()
     J0, g0 = grad_fn(p)
     g0 = np.asarray(g0, np.float64).ravel()

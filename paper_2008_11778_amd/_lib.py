@@ -73,6 +73,8 @@ _sig("aafwi_aa_destroy", _vp)
 _sig("aafwi_aa_step", _vp, _vp, _vp, _f32, _vp, _vp, _vp, _vp)
 _sig("aafwi_aa_last_cond", _vp, _vp)
 _sig("aafwi_aa_set_solver", _vp, ctypes.c_int)
+_sig("aafwi_aa_set_damping", _vp, _f32)
+_sig("aafwi_aa_set_weights", _vp, _vp)
 AA_GRAM, AA_QR = 0, 1
 _sig("aafwi_blend", _vp, _i64, _f32, _vp, _vp, _vp)
 _sig("aafwi_dot", _vp, _i64, _vp, _vp, _vp, _vp)
@@ -413,6 +415,16 @@ class AA:
         """'gram' (FP64 normal equations) or 'qr' (rank-updated QR); clears the history."""
         code = {"gram": AA_GRAM, "qr": AA_QR}[solver]
         _check(_lib.aafwi_aa_set_solver(self._h, code))
+
+    def set_damping(self, beta: float):
+        """Damping of the mixed step (eq. AAupdate0); 1 = none."""
+        _check(_lib.aafwi_aa_set_damping(self._h, float(beta)))
+
+    def set_weights(self, w):
+        """Per-entry least-squares weights (device tensor of n floats, kept
+        referenced here) or None; clears the history."""
+        self._w = None if w is None else w
+        _check(_lib.aafwi_aa_set_weights(self._h, None if w is None else _ptr(w, numel=self.n, name="w")))
 
     def reset(self):
         _check(_lib.aafwi_aa_reset(self._h))

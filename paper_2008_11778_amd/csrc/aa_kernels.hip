@@ -78,6 +78,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_aa_dots(long long n, const f
                                                             float* __restrict__ ring_p,
                                                             float* __restrict__ ring_g, int cap,
                                                             const AAState* __restrict__ s,
+                                                            const float* __restrict__ w,
                                                             double* __restrict__ part) {
     const int cnt = s->count, head = s->head, slot_new = s->slot_new;
     double cross[CAP], rhs[CAP];
@@ -97,20 +98,22 @@ __global__ __launch_bounds__(kReduceThreads) void k_aa_dots(long long n, const f
 #pragma unroll
         for (int i = 0; i < CAP; ++i)
             if (i == cnt - 1) glast = (double)gv[i];
+        const double wv = w ? (double)w[e] : 1.0;
         const double dnew = (double)gn - glast;
+        const double wd = wv * dnew, wg = wv * (double)gn;
 #pragma unroll
         for (int i = 0; i + 1 < CAP; ++i) {
             if (i + 1 < cnt) {
                 const double dg = (double)gv[i + 1] - (double)gv[i];
-                cross[i] += dnew * dg;
-                rhs[i] += dg * (double)gn;
+                cross[i] += wd * dg;
+                rhs[i] += dg * wg;
             }
         }
 #pragma unroll
         for (int i = 0; i < CAP; ++i) {
             if (i == cnt - 1) {
-                cross[i] += dnew * dnew;
-                rhs[i] += dnew * (double)gn;
+                cross[i] += wd * dnew;
+                rhs[i] += dnew * wg;
             }
         }
     }
@@ -237,9 +240,11 @@ __global__ __launch_bounds__(64) void k_aa_solve(AAState* s, const double* __res
     s->cond = (ndg > 0) ? cond : 0.0;
 }
 
+// p_bar = p_k - eta g_k; with damping beta (beta = 1: eq. AA2_update)
+// p_tilde = xbar + beta fbar = (p_k - beta eta g_k) - sum_i gamma_i [dp_i - beta eta dg_i].
 template <int CAP>
 __global__ __launch_bounds__(256) void k_aa_mix(long long n, const float* __restrict__ p_k,
-                                                const float* __restrict__ g_k, float eta,
+                                                const float* __restrict__ g_k, float eta, float beta,
                                                 const float* __restrict__ ring_p,
                                                 const float* __restrict__ ring_g, int cap,
                                                 const AAState* __restrict__ s, float* __restrict__ p_bar,
@@ -248,8 +253,9 @@ __global__ __launch_bounds__(256) void k_aa_mix(long long n, const float* __rest
     if (e >= n) return;
     const int mk = s->mk, head = s->head;
     const double et = (double)eta;
+    const double eb = (double)eta * (double)beta;
     const double pb = (double)p_k[e] - et * (double)g_k[e];
-    double pt = pb;
+    double pt = (double)p_k[e] - eb * (double)g_k[e];
     if (mk > 0) {
         float pv[CAP], gv[CAP];
 #pragma unroll
@@ -262,7 +268,7 @@ __global__ __launch_bounds__(256) void k_aa_mix(long long n, const float* __rest
 #pragma unroll
         for (int i = 0; i + 1 < CAP; ++i) {
             if (i < mk) {
-                const double dGi = ((double)pv[i + 1] - (double)pv[i]) - et * ((double)gv[i + 1] - (double)gv[i]);
+                const double dGi = ((double)pv[i + 1] - (double)pv[i]) - eb * ((double)gv[i + 1] - (double)gv[i]);
                 pt -= s->gamma[i] * dGi;
             }
         }
@@ -373,6 +379,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_qr_append(long long n, const
                                                               float* __restrict__ ring_p, float* __restrict__ ring_g,
                                                               int cap, double* __restrict__ Q,
                                                               const AAState* __restrict__ s,
+                                                              const float* __restrict__ w,
                                                               double* __restrict__ part) {
     const int cnt = s->count, slot_new = s->slot_new;
     const int m = cnt - 1;  // existing difference columns (if cnt >= 1)
@@ -385,7 +392,8 @@ __global__ __launch_bounds__(kReduceThreads) void k_qr_append(long long n, const
         const float gn = g_new[e];
         ring_p[(long long)slot_new * n + e] = p_new[e];
         if (cnt >= 1) {
-            const double a = (double)gn - (double)ring_g[(long long)last * n + e];
+            const double sw = w ? sqrt((double)w[e]) : 1.0;
+            const double a = sw * ((double)gn - (double)ring_g[(long long)last * n + e]);
             Q[(long long)m * n + e] = a;
 #pragma unroll
             for (int i = 0; i < CAP; ++i)
@@ -433,11 +441,12 @@ __global__ __launch_bounds__(kReduceThreads) void k_qr_subtract(long long n, dou
     store_partials<CAP>(v, CAP, part);
 }
 
-// Q[:, m] <- a / rho; partials of Q[:, i] . g_k for i <= m.
+// Q[:, m] <- a / rho; partials of Q[:, i] . (W^(1/2) g_k) for i <= m.
 template <int CAP>
 __global__ __launch_bounds__(kReduceThreads) void k_qr_scale_rhs(long long n, double* __restrict__ Q,
                                                                  const float* __restrict__ g_k,
                                                                  const AAState* __restrict__ s,
+                                                                 const float* __restrict__ w,
                                                                  double* __restrict__ part) {
     const int m = s->count - 1;
     const double rho = sqrt(s->nrm2);
@@ -447,7 +456,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_qr_scale_rhs(long long n, do
     for (int i = 0; i < CAP; ++i) v[i] = 0.0;
     for (long long e = (long long)blockIdx.x * kReduceThreads + threadIdx.x; e < n;
          e += (long long)kReduceBlocks * kReduceThreads) {
-        const double g = (double)g_k[e];
+        const double g = (w ? sqrt((double)w[e]) : 1.0) * (double)g_k[e];
         if (m >= 0) {
             const double q = Q[(long long)m * n + e] * inv;
             Q[(long long)m * n + e] = q;
@@ -527,23 +536,23 @@ __global__ __launch_bounds__(64) void k_qr_solve(AAState* s, int cap, double con
 }
 
 template <int CAP>
-void aa_launch_qr(hipStream_t st, long long n, const float* p, const float* g, float eta, float* ring_p,
-                  float* ring_g, int cap, AAState* s, double* part, double cond_max, double* Q, float* pbar,
-                  float* ptilde) {
+void aa_launch_qr(hipStream_t st, long long n, const float* p, const float* g, float eta, float beta,
+                  const float* w, float* ring_p, float* ring_g, int cap, AAState* s, double* part,
+                  double cond_max, double* Q, float* pbar, float* ptilde) {
     const dim3 red(kReduceBlocks), rt(kReduceThreads), el((unsigned)((n + 255) / 256));
     hipLaunchKernelGGL(k_qr_prepare, dim3(1), dim3(64), 0, st, s, cap);
     hipLaunchKernelGGL(k_qr_rotate<CAP>, el, dim3(256), 0, st, n, Q, (const AAState*)s);
-    hipLaunchKernelGGL(k_qr_append<CAP>, red, rt, 0, st, n, p, g, ring_p, ring_g, cap, Q, (const AAState*)s, part);
+    hipLaunchKernelGGL(k_qr_append<CAP>, red, rt, 0, st, n, p, g, ring_p, ring_g, cap, Q, (const AAState*)s, w, part);
     hipLaunchKernelGGL(k_qr_reduce, dim3(1), dim3(64), 0, st, (const double*)part, 0, s);
     hipLaunchKernelGGL(k_qr_subtract<CAP>, red, rt, 0, st, n, Q, (const AAState*)s, 0, part);
     hipLaunchKernelGGL(k_qr_reduce, dim3(1), dim3(64), 0, st, (const double*)part, 1, s);
     hipLaunchKernelGGL(k_qr_subtract<CAP>, red, rt, 0, st, n, Q, (const AAState*)s, 1, part);
     hipLaunchKernelGGL(k_qr_reduce, dim3(1), dim3(64), 0, st, (const double*)part, 2, s);
-    hipLaunchKernelGGL(k_qr_scale_rhs<CAP>, red, rt, 0, st, n, Q, g, (const AAState*)s, part);
+    hipLaunchKernelGGL(k_qr_scale_rhs<CAP>, red, rt, 0, st, n, Q, g, (const AAState*)s, w, part);
     hipLaunchKernelGGL(k_qr_reduce, dim3(1), dim3(64), 0, st, (const double*)part, 3, s);
     hipLaunchKernelGGL(k_qr_solve, dim3(1), dim3(64), 0, st, s, cap, cond_max);
     hipLaunchKernelGGL(k_qr_rotate<CAP>, el, dim3(256), 0, st, n, Q, (const AAState*)s);
-    hipLaunchKernelGGL(k_aa_mix<CAP>, el, dim3(256), 0, st, n, p, g, eta, (const float*)ring_p,
+    hipLaunchKernelGGL(k_aa_mix<CAP>, el, dim3(256), 0, st, n, p, g, eta, beta, (const float*)ring_p,
                        (const float*)ring_g, cap, (const AAState*)s, pbar, ptilde);
     AAFWI_HIP(hipGetLastError());
 }
@@ -605,17 +614,17 @@ __global__ void k_axpy(long long n, float a, const float* x, float* y) {
 }
 
 template <int CAP>
-void aa_launch(hipStream_t st, long long n, const float* p, const float* g, float eta, float* ring_p,
-               float* ring_g, int cap, AAState* s, double* part, double cond_max, float* pbar,
+void aa_launch(hipStream_t st, long long n, const float* p, const float* g, float eta, float beta, const float* w,
+               float* ring_p, float* ring_g, int cap, AAState* s, double* part, double cond_max, float* pbar,
                float* ptilde) {
     hipLaunchKernelGGL(k_aa_prepare, dim3(1), dim3(64), 0, st, s, cap);
     AAFWI_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_aa_dots<CAP>, dim3(kReduceBlocks), dim3(kReduceThreads), 0, st, n, p, g, ring_p,
-                       ring_g, cap, (const AAState*)s, part);
+                       ring_g, cap, (const AAState*)s, w, part);
     AAFWI_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_aa_solve<CAP>, dim3(1), dim3(64), 0, st, s, (const double*)part, cap, cond_max);
     AAFWI_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_aa_mix<CAP>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, p, g, eta,
+    hipLaunchKernelGGL(k_aa_mix<CAP>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, p, g, eta, beta,
                        (const float*)ring_p, (const float*)ring_g, cap, (const AAState*)s, pbar, ptilde);
     AAFWI_HIP(hipGetLastError());
 }
@@ -661,6 +670,8 @@ struct aafwi_aa {
     double* part;
     int solver;        // AAFWI_AA_GRAM or AAFWI_AA_QR
     double* Q;         // QR solver: n x M, FP64 (allocated on first use)
+    float beta;        // damping of the mixed step (1 = none)
+    const float* w;    // least-squares weights (device, n), or NULL
 };
 
 namespace {
@@ -707,6 +718,7 @@ extern "C" int aafwi_aa_create(int64_t n, int32_t M, double cond_max, aafwi_stre
         a->capT = a->cap <= 4 ? 4 : a->cap <= 8 ? 8 : a->cap <= 16 ? 16 : 32;
         a->cond_max = cond_max;
         a->stream = (hipStream_t)stream;
+        a->beta = 1.0f;
         try {
             auto alloc = [&](void** p, size_t bytes) {
                 if (hipMalloc(p, bytes) != hipSuccess)
@@ -751,17 +763,17 @@ extern "C" int aafwi_aa_step(aafwi_aa* a, const float* p_k, const float* g_k, fl
         AAFWI_REQUIRE(std::isfinite(eta) && eta >= 0.0f, "aa_step: eta must be finite and >= 0");
         if (a->solver == AAFWI_AA_QR) {
             switch (a->capT) {
-                case 4: aafwi::aa_launch_qr<4>(a->stream, a->n, p_k, g_k, eta, a->ring_p, a->ring_g, a->cap, a->state, a->part, a->cond_max, a->Q, p_bar, p_tilde); break;
-                case 8: aafwi::aa_launch_qr<8>(a->stream, a->n, p_k, g_k, eta, a->ring_p, a->ring_g, a->cap, a->state, a->part, a->cond_max, a->Q, p_bar, p_tilde); break;
-                case 16: aafwi::aa_launch_qr<16>(a->stream, a->n, p_k, g_k, eta, a->ring_p, a->ring_g, a->cap, a->state, a->part, a->cond_max, a->Q, p_bar, p_tilde); break;
-                default: aafwi::aa_launch_qr<32>(a->stream, a->n, p_k, g_k, eta, a->ring_p, a->ring_g, a->cap, a->state, a->part, a->cond_max, a->Q, p_bar, p_tilde); break;
+                case 4: aafwi::aa_launch_qr<4>(a->stream, a->n, p_k, g_k, eta, a->beta, a->w, a->ring_p, a->ring_g, a->cap, a->state, a->part, a->cond_max, a->Q, p_bar, p_tilde); break;
+                case 8: aafwi::aa_launch_qr<8>(a->stream, a->n, p_k, g_k, eta, a->beta, a->w, a->ring_p, a->ring_g, a->cap, a->state, a->part, a->cond_max, a->Q, p_bar, p_tilde); break;
+                case 16: aafwi::aa_launch_qr<16>(a->stream, a->n, p_k, g_k, eta, a->beta, a->w, a->ring_p, a->ring_g, a->cap, a->state, a->part, a->cond_max, a->Q, p_bar, p_tilde); break;
+                default: aafwi::aa_launch_qr<32>(a->stream, a->n, p_k, g_k, eta, a->beta, a->w, a->ring_p, a->ring_g, a->cap, a->state, a->part, a->cond_max, a->Q, p_bar, p_tilde); break;
             }
         } else {
             switch (a->capT) {
-                case 4: aafwi::aa_launch<4>(a->stream, a->n, p_k, g_k, eta, a->ring_p, a->ring_g, a->cap, a->state, a->part, a->cond_max, p_bar, p_tilde); break;
-                case 8: aafwi::aa_launch<8>(a->stream, a->n, p_k, g_k, eta, a->ring_p, a->ring_g, a->cap, a->state, a->part, a->cond_max, p_bar, p_tilde); break;
-                case 16: aafwi::aa_launch<16>(a->stream, a->n, p_k, g_k, eta, a->ring_p, a->ring_g, a->cap, a->state, a->part, a->cond_max, p_bar, p_tilde); break;
-                default: aafwi::aa_launch<32>(a->stream, a->n, p_k, g_k, eta, a->ring_p, a->ring_g, a->cap, a->state, a->part, a->cond_max, p_bar, p_tilde); break;
+                case 4: aafwi::aa_launch<4>(a->stream, a->n, p_k, g_k, eta, a->beta, a->w, a->ring_p, a->ring_g, a->cap, a->state, a->part, a->cond_max, p_bar, p_tilde); break;
+                case 8: aafwi::aa_launch<8>(a->stream, a->n, p_k, g_k, eta, a->beta, a->w, a->ring_p, a->ring_g, a->cap, a->state, a->part, a->cond_max, p_bar, p_tilde); break;
+                case 16: aafwi::aa_launch<16>(a->stream, a->n, p_k, g_k, eta, a->beta, a->w, a->ring_p, a->ring_g, a->cap, a->state, a->part, a->cond_max, p_bar, p_tilde); break;
+                default: aafwi::aa_launch<32>(a->stream, a->n, p_k, g_k, eta, a->beta, a->w, a->ring_p, a->ring_g, a->cap, a->state, a->part, a->cond_max, p_bar, p_tilde); break;
             }
         }
         if (gamma)
@@ -786,6 +798,25 @@ extern "C" int aafwi_aa_set_solver(aafwi_aa* a, int solver) {
             }
         }
         a->solver = solver;
+        AAFWI_HIP(hipMemsetAsync(a->state, 0, sizeof(aafwi::AAState), a->stream));
+        return AAFWI_OK;
+    });
+}
+
+extern "C" int aafwi_aa_set_damping(aafwi_aa* a, float beta) {
+    return guarded([&]() -> int {
+        AAFWI_REQUIRE(a != nullptr, "aa_set_damping: NULL state");
+        AAFWI_REQUIRE(std::isfinite(beta) && beta > 0.0f, "aa_set_damping: beta must be finite and positive");
+        a->beta = beta;
+        return AAFWI_OK;
+    });
+}
+
+extern "C" int aafwi_aa_set_weights(aafwi_aa* a, const float* w) {
+    return guarded([&]() -> int {
+        AAFWI_REQUIRE(a != nullptr, "aa_set_weights: NULL state");
+        AAFWI_HIP(hipStreamSynchronize(a->stream));
+        a->w = w;
         AAFWI_HIP(hipMemsetAsync(a->state, 0, sizeof(aafwi::AAState), a->stream));
         return AAFWI_OK;
     });

@@ -116,6 +116,8 @@ class AADescent:
     each ``iterate()`` performs one iteration k >= 1.
 
     M = 0 is steepest descent with the fixed step (the Picard iteration of G).
+    aa_solver selects the least-squares solver ("gram" or "qr"), aa_beta the
+    damping of the mixed step and aa_weights a weighted l2 norm for Step 2.
     The problem sees flat tensors; the accepted trial buffer becomes the new
     iterate itself, so the problem recognises (by object identity) that its
     kept forward run is at that iterate.
@@ -123,11 +125,16 @@ class AADescent:
 
     def __init__(self, problem, p0: torch.Tensor, eta: float | None, M: int, cond_max: float = 1e5,
                  lambdas=LAMBDAS, c1: float = ARMIJO_C1, linesearch: bool = True,
-                 eta_frac: float = 0.02, aa_solver: str = "gram"):
+                 eta_frac: float = 0.02, aa_solver: str = "gram", aa_beta: float = 1.0, aa_weights=None):
         self.problem, self.M, self.eta = problem, M, eta
         self.lambdas, self.c1, self.linesearch, self.eta_frac = lambdas, c1, linesearch, eta_frac
         self.shape = p0.shape
         self.aa = AA(p0.numel(), max(M, 1), cond_max, solver=aa_solver) if M > 0 else None
+        if self.aa is not None:
+            if aa_beta != 1.0:
+                self.aa.set_damping(aa_beta)
+            if aa_weights is not None:
+                self.aa.set_weights(aa_weights.reshape(-1))
         self.red = Reducer()
         self.p = p0.detach().clone().reshape(-1)
         self.g = torch.empty_like(self.p)

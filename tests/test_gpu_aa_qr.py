@@ -1,8 +1,11 @@
-"""The rank-updated QR solver of the Anderson least squares (Algorithm 2,
-Step 2) against the oracle's definition of gamma (SVD least squares in FP64
-of the same FP32 gradients): the step, the window drops (full ring and
-condition guard), and its accuracy on an ill-conditioned window, where the
-FP64 normal equations lose about cond^2 * eps and the QR update cond * eps."""
+"""Options of the Anderson step against the oracle.
+
+* The rank-updated QR solver of the least squares (Algorithm 2, Step 2)
+  against the oracle's definition of gamma (SVD least squares in FP64 of the
+  same FP32 gradients): the step, the window drops (full ring and condition
+  guard), and its accuracy on an ill-conditioned window, where the FP64
+  normal equations lose about cond^2 * eps and the QR update cond * eps.
+* Damping beta and a weighted l2 norm, on both solvers."""
 import numpy as np
 import pytest
 
@@ -89,3 +92,32 @@ def test_qr_is_accurate_on_an_ill_conditioned_window():
     print("gamma error vs FP64 SVD least squares:", errs)
     assert errs["qr"] <= 1e-9
     assert errs["qr"] < errs["gram"]
+
+
+@pytest.mark.parametrize("solver", ["gram", "qr"])
+def test_damped_and_weighted_steps_match_oracle(solver):
+    """Damping beta (eq. AAupdate0 in the gamma form) and a weighted l2
+    least-squares norm, on both solvers, against the oracle step."""
+    import torch
+    from paper_2008_11778_amd import AA
+    r = np.random.default_rng(12)
+    n, M, eta, beta = 4000, 3, 0.21, 0.6
+    w = r.uniform(0.2, 3.0, n).astype(np.float32)
+    ref = oaa.AAHistory(M, cond_max=1e5, beta=beta, weights=w.astype(np.float64))
+    aa = AA(n, M, cond_max=1e5, solver=solver)
+    aa.set_damping(beta)
+    wt = T(w)
+    aa.set_weights(wt)
+    p = r.standard_normal(n).astype(np.float32)
+    for k in range(7):
+        g = (r.standard_normal(n) + 0.2 * k).astype(np.float32)
+        pb, pt = aa.step(T(p), T(g), eta)
+        pbr, ptr_, gam, mk = ref.step(p, g, eta)
+        assert int(aa.mk.item()) == mk
+        assert rel(pb.cpu().numpy(), pbr) <= 1e-6
+        assert rel(pt.cpu().numpy(), ptr_) <= 1e-5, (k, rel(pt.cpu().numpy(), ptr_))
+        if mk:
+            np.testing.assert_allclose(aa.gamma.cpu().numpy()[:mk], gam, rtol=1e-6, atol=1e-9)
+        p = ptr_.astype(np.float32)
+    torch.cuda.synchronize()
+    aa.close()

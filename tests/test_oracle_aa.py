@@ -205,3 +205,42 @@ def test_ncg_wolfe_converges_and_descends():
     J = [fg(x)[0] for x in xs]
     assert all(b2 <= a2 + 1e-12 for a2, b2 in zip(J, J[1:]))
     assert np.linalg.norm(fg(xs[-1])[1]) < 1e-6
+
+
+def test_damped_gamma_form_equals_alpha_form():
+    """With damping beta the gamma-form step xbar + beta fbar equals
+    Algorithm 1's (1 - beta) sum alpha p + beta sum alpha G(p) (eq. AAupdate0)
+    for the alpha that gamma maps to."""
+    r = np.random.default_rng(41)
+    n, M, eta, beta = 12, 3, 0.3, 0.45
+    hist = aa.AAHistory(M, cond_max=1e12, beta=beta)
+    ps = [r.standard_normal(n) for _ in range(M + 1)]
+    gs = [r.standard_normal(n) for _ in range(M + 1)]
+    for p, g in zip(ps, gs):
+        _, pt, gamma, mk = hist.step(p, g, eta)
+    alpha = aa.gamma_to_alpha(gamma)
+    P = np.stack(ps, axis=1)
+    GP = np.stack([p - eta * g for p, g in zip(ps, gs)], axis=1)
+    np.testing.assert_allclose(alpha, aa.alpha_weights(GP - P), rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(pt, aa.alpha_update(P, GP, alpha, beta), rtol=1e-12, atol=1e-12)
+
+
+def test_weighted_gamma_solves_weighted_normal_equations():
+    r = np.random.default_rng(42)
+    n, M, eta = 40, 3, 0.2
+    w = r.uniform(0.2, 3.0, n)
+    ps = [r.standard_normal(n) for _ in range(M + 1)]
+    gs = [r.standard_normal(n) for _ in range(M + 1)]
+    hw = aa.AAHistory(M, cond_max=1e12, weights=w)
+    hc = aa.AAHistory(M, cond_max=1e12, weights=np.full(n, 7.0))
+    h1 = aa.AAHistory(M, cond_max=1e12)
+    for p, g in zip(ps, gs):
+        _, _, gw, _ = hw.step(p, g, eta)
+        _, _, gc, _ = hc.step(p, g, eta)
+        _, _, g1, _ = h1.step(p, g, eta)
+    A = np.stack([(-eta) * (gs[i + 1] - gs[i]) for i in range(M)], axis=1)
+    f = -eta * gs[-1]
+    ref = np.linalg.solve(A.T @ (w[:, None] * A), A.T @ (w * f))
+    np.testing.assert_allclose(gw, ref, rtol=1e-10)
+    np.testing.assert_allclose(gc, g1, rtol=1e-10)   # a constant weight changes nothing
+    assert np.abs(gw - g1).max() > 1e-3               # a varying one does
