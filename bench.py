@@ -340,6 +340,85 @@ def noisy_workload(args):
     print(json.dumps(out), flush=True)
 
 
+def lsrtm_workload(args):
+    """LSRTM on the 768 x 256, 64-shot case (smooth v(z) background, 40 sparse
+    reflectors): steepest descent with the fixed step 1/lambda_max(L^T L),
+    restarted GMRES(10) on L^T L x = L^T d_r, Algorithm 2 (M = 10) on the same
+    fixed-step map from zero and from the scaled Laplacian-filtered RTM
+    image, which is also reported on its own.  Relative model error
+    |x - dm| / |dm| and data misfit |L x - d_r| / |d_r| after each iteration
+    (one Born and one Born-adjoint run each), with wall times."""
+    import torch
+
+    import synth
+    from paper_2008_11778_amd import Context
+    from paper_2008_11778_amd.comparators import gmres_restarted, power_iteration
+    from paper_2008_11778_amd.inversion import AADescent, LSRTMProblem
+
+    dev = torch.device("cuda", 0)
+    g, m0_np, dm_np = synth.config3()
+    iters = args.iters
+    res = {}
+    with Context(g, ckpt_every=50) as ctx:
+        m0 = torch.from_numpy(m0_np).to(dev)
+        dm = torch.from_numpy(dm_np).to(dev).reshape(-1)
+        d_r = ctx.born(m0, dm.reshape(m0.shape)).clone()
+        prob = LSRTMProblem(ctx, m0, d_r)
+        nd = float(torch.linalg.norm(d_r.double()))
+        ndm = float(torch.linalg.norm(dm.double()))
+        tmp = ctx._new(ctx.data_shape)
+
+        def errs(x):
+            ctx.born(m0, x.reshape(m0.shape), tmp)
+            return (float(torch.linalg.norm(x.reshape(-1).double() - dm.double())) / ndm,
+                    float(torch.linalg.norm(tmp.double() - d_r.double())) / nd)
+
+        t0 = time.perf_counter()
+        lam = power_iteration(prob.normal_op, m0.numel(), dev, iters=8)
+        eta = 1.0 / lam
+        log(f"lambda_max(L^T L) ~ {lam:.4e} ({time.perf_counter() - t0:.1f} s)")
+        t0 = time.perf_counter()
+        x0, alpha = prob.scaled_start(g.h)
+        torch.cuda.synchronize()
+        res["filtered_rtm"] = [(0, *errs(x0), time.perf_counter() - t0)]
+        for name in ("sd", "gmres", "aa", "aa_rtm_start"):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            curve = []
+            if name == "gmres":
+                rhs = ctx._new((ctx.nz, ctx.nx))
+                ctx.born_adjoint(m0, d_r, rhs)
+                xs = gmres_restarted(prob.normal_op, rhs, torch.zeros_like(rhs), 10, iters)
+                torch.cuda.synchronize()
+                elapsed = time.perf_counter() - t0
+                for k, x in enumerate(xs):
+                    curve.append((k + 1, *errs(x), elapsed * (k + 1) / len(xs)))
+            else:
+                start = x0 if name == "aa_rtm_start" else torch.zeros_like(m0)
+                run = AADescent(prob, start, eta, M=0 if name == "sd" else 10, linesearch=name != "sd")
+                run.first()
+                torch.cuda.synchronize()
+                t = time.perf_counter() - t0
+                for k in range(iters):
+                    t1 = time.perf_counter()
+                    run.iterate()
+                    torch.cuda.synchronize()
+                    t += time.perf_counter() - t1  # the error evaluation below is not timed
+                    curve.append((k + 1, *errs(run.p), t))
+                run.close()
+            res[name] = curve
+            log(f"{name}: model error {curve[-1][1]:.4f}, data misfit {curve[-1][2]:.4f}, {curve[-1][3]:.1f} s")
+    out = {"metric": "LSRTM relative model error after k iterations (768x256, 64 shots)",
+           "value": {k: round(v[-1][1], 5) for k, v in res.items()}, "unit": "|x - dm| / |dm|",
+           "higher_is_better": False, "n_gpus": 1, "iters": iters,
+           "data_misfit": {k: round(v[-1][2], 5) for k, v in res.items()},
+           "rtm_scale": alpha, "step": eta,
+           "curves": {k: [[c[0], round(c[1], 5), round(c[2], 5), round(c[3], 2)] for c in v] for k, v in res.items()},
+           "config": {"workload": "768x256 grid, 64 shots, 4000 steps, v(z) 1500-4500 m/s, 40 reflectors"},
+           "dtype": "f32", "data": "synthetic"}
+    print(json.dumps(out), flush=True)
+
+
 def cnn_workload(args):
     """Speed of the learned-direction network alone: forward and Adam training
     step on 8 images of 384 x 1024 (random inputs), HIP-event timed; reports
@@ -468,7 +547,7 @@ def main():
                     help="launch shape instead of autotuning: steps per launch of the forward, recompute and "
                          "adjoint kernels, rows per wave of the forward, recompute, adjoint and Born steps, and "
                          "optionally their tile orders, e.g. 1,1,2:8,64,20,64:1,0,0,0")
-    ap.add_argument("--workload", default="fwi", choices=["fwi", "batched", "learned", "cnn", "noisy"])
+    ap.add_argument("--workload", default="fwi", choices=["fwi", "batched", "learned", "cnn", "noisy", "lsrtm"])
     ap.add_argument("--budget", type=float, default=20, help="noisy workload: gradient evaluations per optimiser")
     ap.add_argument("--instances", type=int, default=32, help="batched workload: number of instances")
     ap.add_argument("--iters", type=int, default=10, help="batched workload: AA iterations per instance")
@@ -491,6 +570,8 @@ def main():
         return cnn_workload(args)
     if args.workload == "noisy":
         return noisy_workload(args)
+    if args.workload == "lsrtm":
+        return lsrtm_workload(args)
     # the oracle runs first, in child processes started before this process
     # touches the GPU
     cpu = None

@@ -201,6 +201,12 @@ int aafwi_dot_diff(aafwi_stream stream, int64_t n, const float* g, const float* 
                    const float* b, double* out, double* workspace);
 
 /* y = a*x + y in FP32 (device [n]); x may alias y. */
+/* Laplacian-filtered RTM image (Section "Numerical Example", the LSRTM
+ * comparison): out = -Lap_h image on an nz x nx interior image (device,
+ * row-major), 8th-order second differences with zero outside the image,
+ * spacing h.  out must not alias image. */
+int aafwi_laplacian_filter(aafwi_stream stream, int32_t nz, int32_t nx, float h, const float* image, float* out);
+
 int aafwi_axpy(aafwi_stream stream, int64_t n, float a, const float* x, float* y);
 
 /* out = a*x in FP32 (device [n]); out may alias x. */

@@ -252,6 +252,22 @@ def born_adjoint(geom, m0, y):
 # general linear source -> data map and its adjoint (for the dot-product test)
 # ----------------------------------------------------------------------------
 
+def rtm_filter(image, h):
+    """Laplacian-filtered RTM image (Section "Numerical Example", the LSRTM
+    comparison): -Lap_h of the image with the 8th-order second differences,
+    zero outside the interior grid."""
+    return -laplacian(np.asarray(image, np.float64), h)
+
+
+def scaled_rtm_start(geom, m0, d_r):
+    """The filtered RTM image f = rtm_filter(L^T d_r) scaled by the alpha that
+    minimises ||alpha L f - d_r||: a starting model for LSRTM."""
+    f = rtm_filter(born_adjoint(geom, m0, d_r), geom.h)
+    lf = born(geom, m0, f)
+    alpha = float(np.sum(lf * d_r) / np.sum(lf * lf))
+    return alpha * f, alpha
+
+
 def source_to_data(geom, m, src_field, s=0):
     """d = R u for an arbitrary space-time source field src_field [nt, nz_p, nx_p]
     entering as K * src^n (no point source)."""

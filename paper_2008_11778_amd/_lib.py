@@ -80,6 +80,7 @@ _sig("aafwi_blend", _vp, _i64, _f32, _vp, _vp, _vp)
 _sig("aafwi_dot", _vp, _i64, _vp, _vp, _vp, _vp)
 _sig("aafwi_dot_diff", _vp, _i64, _vp, _vp, _vp, _vp, _vp)
 _sig("aafwi_axpy", _vp, _i64, _f32, _vp, _vp)
+_sig("aafwi_laplacian_filter", _vp, _i32, _i32, _f32, _vp, _vp)
 _sig("aafwi_scale", _vp, _i64, _f32, _vp, _vp)
 _sig("aafwi_kernel_timing", _vp, ctypes.c_int)
 _sig("aafwi_kernel_timing_read", _vp, ctypes.c_int, ctypes.POINTER(_f64), ctypes.POINTER(_i64))
@@ -495,6 +496,17 @@ def scale(a, x, out=None, stream=None):
     n = x.numel()
     _check(_lib.aafwi_scale(_stream_handle(stream), n, float(a), _ptr(x, numel=n, name="x"),
                             _ptr(out, numel=n, name="out")))
+    return out
+
+
+def laplacian_filter(image, h, out=None, stream=None):
+    """-Lap_h of an [nz][nx] image (the Laplacian-filtered RTM image)."""
+    if image.dim() != 2:
+        raise ValueError("image must be [nz][nx]")
+    out = torch.empty_like(image) if out is None else out
+    nz, nx = image.shape
+    _check(_lib.aafwi_laplacian_filter(_stream_handle(stream), nz, nx, float(h), _ptr(image, name="image"),
+                                       _ptr(out, numel=nz * nx, name="out")))
     return out
 
 

@@ -607,6 +607,26 @@ __global__ void k_scale(long long n, float a, const float* x, float* out) {
     out[i] = a * x[i];
 }
 
+// out = -Lap_h img on an nz x nx image (8th-order second differences, zero
+// outside the image): the Laplacian-filtered RTM image.
+__global__ void k_laplacian_filter(int nz, int nx, float inv_h2, const float* __restrict__ img,
+                                   float* __restrict__ out) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x, z = blockIdx.y;
+    if (x >= nx) return;
+    const float c[5] = {-205.0f / 72.0f, 8.0f / 5.0f, -1.0f / 5.0f, 8.0f / 315.0f, -1.0f / 560.0f};
+    const long long o = (long long)z * nx + x;
+    float acc = 2.0f * c[0] * img[o];
+#pragma unroll
+    for (int j = 1; j <= 4; ++j) {
+        const float zl = z - j >= 0 ? img[o - (long long)j * nx] : 0.0f;
+        const float zr = z + j < nz ? img[o + (long long)j * nx] : 0.0f;
+        const float xl = x - j >= 0 ? img[o - j] : 0.0f;
+        const float xr = x + j < nx ? img[o + j] : 0.0f;
+        acc = fmaf(c[j], (zl + zr) + (xl + xr), acc);
+    }
+    out[o] = -acc * inv_h2;
+}
+
 __global__ void k_axpy(long long n, float a, const float* x, float* y) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -862,6 +882,20 @@ extern "C" int aafwi_scale(aafwi_stream stream, int64_t n, float a, const float*
     return guarded([&]() -> int {
         AAFWI_REQUIRE(n > 0 && x && out, "scale: bad argument");
         aafwi::launch_scale((hipStream_t)stream, n, a, x, out);
+        return AAFWI_OK;
+    });
+}
+
+extern "C" int aafwi_laplacian_filter(aafwi_stream stream, int32_t nz, int32_t nx, float h, const float* image,
+                                      float* out) {
+    return guarded([&]() -> int {
+        AAFWI_REQUIRE(nz >= 1 && nx >= 1 && image && out && image != out, "laplacian_filter: bad argument");
+        AAFWI_REQUIRE(std::isfinite(h) && h > 0.0f, "laplacian_filter: h must be positive");
+        AAFWI_REQUIRE(nz < 65536, "laplacian_filter: too many rows");
+        const float inv_h2 = (float)(1.0 / ((double)h * (double)h));
+        hipLaunchKernelGGL(aafwi::k_laplacian_filter, dim3((nx + 255) / 256, nz), dim3(256), 0, (hipStream_t)stream,
+                           nz, nx, inv_h2, image, out);
+        AAFWI_HIP(hipGetLastError());
         return AAFWI_OK;
     });
 }

@@ -24,7 +24,7 @@ import time
 
 import torch
 
-from ._lib import AA, Context, Reducer, axpy, blend
+from ._lib import AA, Context, Reducer, axpy, blend, laplacian_filter, scale
 
 LAMBDAS = (1.0, 0.5, 0.25, 0.125)
 ARMIJO_C1 = 1e-4
@@ -90,6 +90,32 @@ class LSRTMProblem:
         self.ctx.born_adjoint(self.m0, self.r, grad)
         self.n_adj += 1
         return J
+
+    def rtm_image(self):
+        """m_RTM = L^T d_r (Section "FWI and LSRTM")."""
+        img = self.ctx._new((self.ctx.nz, self.ctx.nx))
+        self.ctx.born_adjoint(self.m0, self.d_r, img)
+        self.kept = None
+        self.n_fwd += 1
+        self.n_adj += 1
+        return img
+
+    def filtered_rtm(self, h: float):
+        """-Lap_h m_RTM, the Laplacian-filtered RTM image."""
+        return laplacian_filter(self.rtm_image(), h)
+
+    def scaled_start(self, h: float):
+        """alpha f with f the filtered RTM image and alpha = <L f, d_r> / |L f|^2
+        (the scale that minimises |alpha L f - d_r|); returns (x0, alpha)."""
+        f = self.filtered_rtm(h)
+        self.ctx.born(self.m0, f, self.d)
+        self.kept = None  # self.d no longer holds the data of a kept iterate
+        self.n_fwd += 1
+        red = Reducer()
+        num = float(red.dot(self.d, self.d_r).item())
+        den = float(red.dot(self.d, self.d).item())
+        alpha = num / den
+        return scale(alpha, f), alpha
 
     def normal_op(self, x: torch.Tensor, out: torch.Tensor):
         """out = L^T L x (one Born and one Born adjoint)."""

@@ -209,3 +209,27 @@ def test_ncg_matches_oracle_iterates(fwi_small):
     assert all(b < a for a, b in zip(Js, Js[1:])), Js
     for k, (a, b) in enumerate(zip(its, ref)):
         assert rel(a, b) <= 1e-3, (k, rel(a, b))
+
+
+def test_laplacian_filter_matches_oracle():
+    from paper_2008_11778_amd._lib import laplacian_filter
+    r = np.random.default_rng(44)
+    img = r.standard_normal((37, 53)).astype(np.float32)
+    out = laplacian_filter(T(img), 12.5).cpu().numpy()
+    assert rel(out, fd.rtm_filter(img, 12.5)) <= 1e-6
+
+
+def test_filtered_rtm_and_scaled_start_match_oracle(lsrtm_small):
+    from paper_2008_11778_amd import Context
+    from paper_2008_11778_amd.inversion import LSRTMProblem
+    g, m0, dm, d_r = lsrtm_small
+    x_ref, a_ref = fd.scaled_rtm_start(g, m0, d_r)
+    f_ref = fd.rtm_filter(fd.born_adjoint(g, m0, d_r), g.h)
+    with Context(g) as ctx:
+        prob = LSRTMProblem(ctx, T(m0), T(d_r))
+        f = prob.filtered_rtm(g.h).cpu().numpy()
+        x0, alpha = prob.scaled_start(g.h)
+        x0 = x0.cpu().numpy()
+    assert rel(f, f_ref) <= 1e-3
+    assert abs(alpha - a_ref) / abs(a_ref) <= 1e-3
+    assert rel(x0, x_ref) <= 1e-3

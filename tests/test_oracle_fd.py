@@ -200,3 +200,26 @@ def test_energy_decays_with_sponge_after_source():
         _, _, (u, up) = fd.forward_shot(g.replace(nt=k), m, 0)
         es.append(fd.energy(u, up, m_pad, g.h, g.dt))
     assert all(b <= a * (1 + 1e-12) for a, b in zip(es, es[1:])), es
+
+
+def test_rtm_filter_is_exact_on_quadratics():
+    """-Lap of x^2 + 3 z^2 is -8 away from the image edge (the 8th-order
+    second differences are exact on polynomials of low degree)."""
+    h = 12.5
+    z = np.arange(30)[:, None] * h
+    x = np.arange(40)[None, :] * h
+    f = fd.rtm_filter(x * x + 3.0 * z * z, h)
+    np.testing.assert_allclose(f[4:-4, 4:-4], -8.0, rtol=1e-9)
+    # at the edge the zero extension shows: the first row differs
+    assert abs(f[0, 20] + 8.0) > 1.0
+
+
+def test_scaled_rtm_start_minimises_the_data_misfit():
+    g, m = synth.small_case(nz=20, nx=26, nb=6, nt=120, nshots=2, nrec=8, instance=7)
+    dm = np.zeros(m.shape)
+    dm[10, 5:20] = 0.05 * m[10, 5:20]
+    d_r = fd.born(g, m, dm)
+    x0, alpha = fd.scaled_rtm_start(g, m, d_r)
+    J = lambda a: float(np.sum((fd.born(g, m, x0 * (a / alpha)) - d_r) ** 2))
+    assert alpha > 0 and J(alpha) < J(alpha * 1.01) and J(alpha) < J(alpha * 0.99)
+    assert J(alpha) < float(np.sum(d_r ** 2))
