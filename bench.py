@@ -442,8 +442,10 @@ def cnn_workload(args):
 def learned_workload(args):
     """Learned direction: training data from plain AA and L-BFGS runs, Adam
     training of the network, then plain AA versus AA on G_theta (with the
-    plain-AA fallback) on held-out instances, and the network's own speed on
-    a batch of 8 images of 384 x 1024."""
+    plain-AA fallback) on held-out instances of the training size and on
+    held-out full-size (1024 x 384, 96 shots, 4000 steps) models of the same
+    family (the network is fully convolutional on scale-free inputs), and the
+    network's own speed on a batch of 8 images of 384 x 1024."""
     import numpy as np
     import torch
 
@@ -471,17 +473,19 @@ def learned_workload(args):
     t_train = time.perf_counter() - t0
     log(f"training: {t_train:.1f}s, epoch losses {[round(x, 4) for x in hist]}")
 
-    rows = []
-    for j in range(args.test_instances):
-        g, mt, m0 = synth.learned_instance(500 + j)
+    def compare(instance, geom, mt, m0, net_j, tune=False):
+        """Plain AA and learned AA (M = 10) from m0 for args.iters iterations."""
         res = {}
-        with Context(g) as ctx:
+        with Context(geom) as ctx:
+            if tune:
+                from paper_2008_11778_amd import autotune
+                autotune.apply(ctx, autotune.tune(geom, torch.from_numpy(m0).to(dev)))
             d_obs = ctx.forward_model(torch.from_numpy(mt).to(dev)).clone()
             for kind in ("plain", "learned"):
                 prob = FWIProblem(ctx, d_obs)
                 p0 = torch.from_numpy(m0).to(dev)
                 run = (AADescent(prob, p0.reshape(-1), None, M=10) if kind == "plain"
-                       else LearnedAADescent(prob, p0, net, M=10))
+                       else LearnedAADescent(prob, p0, net_j, M=10))
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
                 logs = [run.first()]
@@ -500,13 +504,27 @@ def learned_workload(args):
                 run.close()
         target = res["plain"]["curve"][-1]
         reach = next((t for J, t in zip(res["learned"]["curve"], res["learned"]["times"]) if J <= target), None)
-        rows.append(dict(instance=500 + j, J0=res["plain"]["J0"], plain_final=target,
-                         learned_final=res["learned"]["curve"][-1], plain_s=res["plain"]["times"][-1],
-                         learned_s_to_plain_final=reach, learned_fallbacks=res["learned"]["fallbacks"],
-                         plain_fwd_adj=(res["plain"]["n_fwd"], res["plain"]["n_adj"]),
-                         learned_fwd_adj=(res["learned"]["n_fwd"], res["learned"]["n_adj"])))
-        log(f"held-out {500 + j}: J0 {rows[-1]['J0']:.4e} plain {target:.4e} learned "
-            f"{rows[-1]['learned_final']:.4e} fallbacks {rows[-1]['learned_fallbacks']}")
+        row = dict(instance=instance, J0=res["plain"]["J0"], plain_final=target,
+                   learned_final=res["learned"]["curve"][-1], plain_s=res["plain"]["times"][-1],
+                   learned_s_to_plain_final=reach, learned_fallbacks=res["learned"]["fallbacks"],
+                   plain_fwd_adj=(res["plain"]["n_fwd"], res["plain"]["n_adj"]),
+                   learned_fwd_adj=(res["learned"]["n_fwd"], res["learned"]["n_adj"]))
+        log(f"held-out {instance} ({geom.nx}x{geom.nz}, {geom.nshots} shots): J0 {row['J0']:.4e} plain {target:.4e} "
+            f"learned {row['learned_final']:.4e} fallbacks {row['learned_fallbacks']} "
+            f"(plain {row['plain_s']:.1f} s, learned reached it at {reach})")
+        return row
+
+    rows = []
+    for j in range(args.test_instances):
+        g, mt, m0 = synth.learned_instance(500 + j)
+        rows.append(compare(500 + j, g, mt, m0, net))
+    large = []
+    if args.large_test:
+        net_l = CNN(384, 1024, 1, net.get_weights())
+        for j in range(args.large_test):
+            g, mt, m0 = synth.learned_instance(700 + j, nz=384, nx=1024, nshots=96, nt=4000)
+            large.append(compare(700 + j, g, mt, m0, net_l, tune=True))
+        net_l.close()
     ratio = [r["learned_final"] / r["plain_final"] for r in rows]
     reached = [r for r in rows if r["learned_s_to_plain_final"] is not None]
     speed = cnn_timing(CNN(384, 1024, 8, init_weights(5005)), 8, 384, 1024)
@@ -516,6 +534,10 @@ def learned_workload(args):
            "higher_is_better": False, "n_gpus": 1, "iters": args.iters, "instances": rows,
            "fallback_rate": round(sum(r["learned_fallbacks"] for r in rows) / (args.iters * len(rows)), 3),
            "reached_plain_final": sum(r["learned_s_to_plain_final"] is not None for r in rows),
+           "full_size": {"workload": "1024x384 grid, 96 shots, 4000 steps, receivers every 2nd column",
+                         "instances": large,
+                         "geomean_ratio": (round(float(np.exp(np.mean(np.log(
+                             [r["learned_final"] / r["plain_final"] for r in large])))), 4) if large else None)},
            "time_to_plain_final_speedup": (round(sum(r["plain_s"] for r in reached)
                                                  / sum(r["learned_s_to_plain_final"] for r in reached), 3)
                                            if reached else None),
@@ -557,6 +579,8 @@ def main():
     ap.add_argument("--lbfgs-instances", type=int, default=8, help="learned workload: L-BFGS training runs")
     ap.add_argument("--test-instances", type=int, default=16, help="learned workload: held-out models")
     ap.add_argument("--epochs", type=int, default=20, help="learned workload: training epochs")
+    ap.add_argument("--large-test", type=int, default=2,
+                    help="learned workload: held-out 1024x384, 96-shot, 4000-step models")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the shot-sharded multi-GPU "
