@@ -323,7 +323,8 @@ int aafwi_kernel_timing(aafwi_ctx* ctx, int every);
  * launches of kernel `kernel_id`. */
 int aafwi_kernel_timing_read(aafwi_ctx* ctx, int kernel_id, double* mean_ms, int64_t* count);
 
-/* Set the z-strip height (rows per wave, 0..64; 0 picks the default) of
+/* Set the z-strip height (rows per wave, 0..120; 0 picks the default; the
+ * one-step kernels use at most 64) of
  * stepping kernel kernel_id (an AAFWI_K_* id, or -1 for all of them).  Used
  * by the tile autotuner; results do not depend on it (bitwise). */
 int aafwi_set_tile(aafwi_ctx* ctx, int32_t kernel_id, int32_t rows_per_wave);

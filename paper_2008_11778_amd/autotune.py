@@ -19,6 +19,7 @@ import types
 import numpy as np
 
 CANDIDATES = (8, 12, 16, 20, 24, 28, 32, 40, 48, 64)
+CANDIDATES_TWO = (16, 20, 24, 32, 40, 48, 64, 80, 96, 120)  # two-step launches (strips up to 120 rows)
 KERNELS = (0, 1, 2, 3)  # forward, recompute, adjoint, Born
 
 
@@ -32,7 +33,7 @@ def _short(geom, nt):
 
 def grid_key(geom) -> str:
     S = int(np.asarray(geom.src_iz).size)
-    return f"{geom.nz + 2 * geom.nb}x{geom.nx + 2 * geom.nb}x{S}/mode-order"
+    return f"{geom.nz + 2 * geom.nb}x{geom.nx + 2 * geom.nb}x{S}/mode-order-120"
 
 
 def cache_path() -> str:
@@ -59,7 +60,8 @@ def tune(geom, m, candidates=CANDIDATES, nt=48, use_cache=True, verbose=False) -
     with Context(g, ckpt_every=nt) as ctx:
         r = torch.zeros(ctx.data_shape, device=m.device)
         dm = torch.zeros_like(m)
-        shapes = [(tb, order, rows) for tb in (False, True) for order in (0, 1) for rows in candidates
+        shapes = [(tb, order, rows) for tb in (False, True) for order in (0, 1)
+                  for rows in (CANDIDATES_TWO if tb and candidates is CANDIDATES else candidates)
                   if rows <= g.nz + 2 * g.nb]
         for tb, order, rows in shapes:
             ctx.set_time_blocking(tb)
@@ -84,7 +86,8 @@ def tune(geom, m, candidates=CANDIDATES, nt=48, use_cache=True, verbose=False) -
         for mode in (False, True):
             for k in KERNELS:
                 for order in (0, 1):
-                    row = " ".join(f"{rows}:{table[(mode, order, rows, k)] * 1e3:.1f}us" for rows in candidates
+                    row = " ".join(f"{rows}:{table[(mode, order, rows, k)] * 1e3:.1f}us"
+                                   for rows in sorted(set(candidates) | set(CANDIDATES_TWO))
                                    if (mode, order, rows, k) in table)
                     if row:
                         print(f"autotune {key} {'two' if mode else 'one'}-step kernel {k} order {order} (per step): "

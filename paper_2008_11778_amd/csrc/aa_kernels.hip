@@ -136,11 +136,23 @@ __global__ __launch_bounds__(kReduceThreads) void k_aa_dots(long long n, const f
     }
 }
 
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Cyclic Jacobi eigen-decomposition of the symmetric n x n matrix S (row
-// stride kAACap), overwritten by its diagonalisation; V receives the vectors.
-__device__ void jacobi_eig(double* S, double* V, int n) {
-    for (int i = 0; i < n; ++i)
-        for (int j = 0; j < n; ++j) V[i * kAACap + j] = (i == j) ? 1.0 : 0.0;
+// stride kAACap, n <= 31), overwritten by its diagonalisation; V receives the
+// vectors.  The row and column updates of each rotation are spread over one
+// wavefront (lane k owns row and column k of S and row k of V); the
+// rotation parameters are computed by every lane from the same values.
+// Called by all 64 lanes of a single-wave block, S and V in LDS.
+__device__ void jacobi_eig_wave(double* S, double* V, int n) {
+    const int k = threadIdx.x;
+    if (k < n)
+        for (int i = 0; i < n; ++i) V[k * kAACap + i] = (i == k) ? 1.0 : 0.0;
+    wave_sync_lds();
     for (int sweep = 0; sweep < 60; ++sweep) {
         double off = 0.0, diag = 0.0;
         for (int i = 0; i < n; ++i) {
@@ -156,22 +168,26 @@ __device__ void jacobi_eig(double* S, double* V, int n) {
                 const double theta = (aqq - app) / (2.0 * apq);
                 const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
                 const double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
-                for (int k = 0; k < n; ++k) {  // columns p, q
+                wave_sync_lds();
+                if (k < n) {  // columns p, q
                     const double skp = S[k * kAACap + p], skq = S[k * kAACap + q];
                     S[k * kAACap + p] = c * skp - sn * skq;
                     S[k * kAACap + q] = sn * skp + c * skq;
                 }
-                for (int k = 0; k < n; ++k) {  // rows p, q
+                wave_sync_lds();
+                if (k < n) {  // rows p, q
                     const double spk = S[p * kAACap + k], sqk = S[q * kAACap + k];
                     S[p * kAACap + k] = c * spk - sn * sqk;
                     S[q * kAACap + k] = sn * spk + c * sqk;
                 }
-                S[p * kAACap + q] = S[q * kAACap + p] = 0.0;
-                for (int k = 0; k < n; ++k) {
+                wave_sync_lds();
+                if (k == 0) S[p * kAACap + q] = S[q * kAACap + p] = 0.0;
+                if (k < n) {
                     const double vkp = V[k * kAACap + p], vkq = V[k * kAACap + q];
                     V[k * kAACap + p] = c * vkp - sn * vkq;
                     V[k * kAACap + q] = sn * vkp + c * vkq;
                 }
+                wave_sync_lds();
             }
         }
     }
@@ -189,59 +205,75 @@ __global__ __launch_bounds__(64) void k_aa_solve(AAState* s, const double* __res
         for (int b = 0; b < kReduceBlocks; ++b) acc += part[(long long)b * 2 * CAP + t];
         sums[t] = acc;
     }
+    __shared__ int ctl[2];  // lane 0 -> wave: columns left (ndg), done flag
     __syncthreads();
-    if (t != 0) return;
-    const int cnt = s->count;  // before the push
-    if (cnt >= 1) {
-        const int k = cnt - 1;  // index of the new difference column
-        for (int i = 0; i < k; ++i) {
-            s->gram[k * kAACap + i] = sums[i];
-            s->gram[i * kAACap + k] = sums[i];
-        }
-        s->gram[k * kAACap + k] = sums[k];
-        for (int i = 0; i <= k; ++i) s->rhs[i] = sums[CAP + i];
-    }
-    s->count = cnt + 1;
-    int ndg = s->count - 1;
+    // lane 0 keeps the window bookkeeping; the eigen-decompositions use the wave
+    int ndg = 0;
     double cond = 1.0;
-    while (ndg > 0) {
-        for (int i = 0; i < ndg; ++i)
-            for (int j = 0; j < ndg; ++j) S[i * kAACap + j] = s->gram[i * kAACap + j];
-        jacobi_eig(S, V, ndg);
-        double lmax = 0.0, lmin = INFINITY;
-        for (int i = 0; i < ndg; ++i) {
-            lmax = fmax(lmax, S[i * kAACap + i]);
-            lmin = fmin(lmin, S[i * kAACap + i]);
-        }
-        cond = (lmin > 0.0) ? sqrt(lmax / lmin) : INFINITY;
-        if (cond <= cond_max) {
-            for (int i = 0; i < ndg; ++i) {
-                double acc = 0.0;
-                for (int j = 0; j < ndg; ++j) {
-                    double vr = 0.0;
-                    for (int k = 0; k < ndg; ++k) vr += V[k * kAACap + j] * s->rhs[k];
-                    acc += V[i * kAACap + j] * vr / S[j * kAACap + j];
-                }
-                s->gamma[i] = acc;
+    if (t == 0) {
+        const int cnt = s->count;  // before the push
+        if (cnt >= 1) {
+            const int k = cnt - 1;  // index of the new difference column
+            for (int i = 0; i < k; ++i) {
+                s->gram[k * kAACap + i] = sums[i];
+                s->gram[i * kAACap + k] = sums[i];
             }
-            break;
+            s->gram[k * kAACap + k] = sums[k];
+            for (int i = 0; i <= k; ++i) s->rhs[i] = sums[CAP + i];
         }
-        // drop the oldest column for good
-        for (int i = 0; i + 1 < ndg; ++i) {
-            for (int j = 0; j + 1 < ndg; ++j) s->gram[i * kAACap + j] = s->gram[(i + 1) * kAACap + j + 1];
-            s->rhs[i] = s->rhs[i + 1];
-        }
-        s->head = (s->head + 1) % cap;
-        s->count -= 1;
-        ndg -= 1;
-        cond = 1.0;
+        s->count = cnt + 1;
+        ndg = s->count - 1;
+        ctl[0] = ndg;
     }
-    s->mk = ndg;
-    s->cond = (ndg > 0) ? cond : 0.0;
+    wave_sync_lds();
+    while (ctl[0] > 0) {
+        const int nd = ctl[0];
+        if (t == 0)
+            for (int i = 0; i < nd; ++i)
+                for (int j = 0; j < nd; ++j) S[i * kAACap + j] = s->gram[i * kAACap + j];
+        wave_sync_lds();
+        jacobi_eig_wave(S, V, nd);
+        wave_sync_lds();
+        if (t == 0) {
+            double lmax = 0.0, lmin = INFINITY;
+            for (int i = 0; i < nd; ++i) {
+                lmax = fmax(lmax, S[i * kAACap + i]);
+                lmin = fmin(lmin, S[i * kAACap + i]);
+            }
+            cond = (lmin > 0.0) ? sqrt(lmax / lmin) : INFINITY;
+            ctl[1] = cond <= cond_max;
+            if (ctl[1]) {
+                for (int i = 0; i < nd; ++i) {
+                    double acc = 0.0;
+                    for (int j = 0; j < nd; ++j) {
+                        double vr = 0.0;
+                        for (int k = 0; k < nd; ++k) vr += V[k * kAACap + j] * s->rhs[k];
+                        acc += V[i * kAACap + j] * vr / S[j * kAACap + j];
+                    }
+                    s->gamma[i] = acc;
+                }
+            } else {
+                // drop the oldest column for good
+                for (int i = 0; i + 1 < nd; ++i) {
+                    for (int j = 0; j + 1 < nd; ++j) s->gram[i * kAACap + j] = s->gram[(i + 1) * kAACap + j + 1];
+                    s->rhs[i] = s->rhs[i + 1];
+                }
+                s->head = (s->head + 1) % cap;
+                s->count -= 1;
+                ctl[0] = nd - 1;
+                cond = 1.0;
+            }
+        }
+        wave_sync_lds();
+        if (ctl[1]) break;
+    }
+    if (t == 0) {
+        ndg = ctl[0];
+        s->mk = ndg;
+        s->cond = (ndg > 0) ? cond : 0.0;
+    }
 }
 
-// p_bar = p_k - eta g_k; with damping beta (beta = 1: eq. AA2_update)
-// p_tilde = xbar + beta fbar = (p_k - beta eta g_k) - sum_i gamma_i [dp_i - beta eta dg_i].
 template <int CAP>
 __global__ __launch_bounds__(256) void k_aa_mix(long long n, const float* __restrict__ p_k,
                                                 const float* __restrict__ g_k, float eta, float beta,
@@ -485,54 +517,70 @@ __global__ void k_qr_reduce(const double* __restrict__ part, int which, AAState*
 __global__ __launch_bounds__(64) void k_qr_solve(AAState* s, int cap, double cond_max) {
     __shared__ double S[kAACap * kAACap];
     __shared__ double V[kAACap * kAACap];
-    if (threadIdx.x != 0) return;
-    const int cnt = s->count;
-    int m = 0;
-    if (cnt >= 1) {
-        const int k = cnt - 1;  // the new column
-        for (int i = 0; i < k; ++i) {
-            s->R[i * kAACap + k] = s->c1[i] + s->c2[i];
-            s->R[k * kAACap + i] = 0.0;
-        }
-        s->R[k * kAACap + k] = sqrt(s->nrm2);
-        m = k + 1;
-    }
-    s->count = cnt + 1;
-    qr_begin_transform(s, m);
-    s->rot_in = 0;  // no transform unless a column is dropped below
+    __shared__ int ctl[2];  // lane 0 -> wave: columns left (m), done flag
+    const int t = threadIdx.x;
     double cond = 1.0;
-    while (m > 0) {
-        // singular values of R from the eigenvalues of R^T R
-        for (int i = 0; i < m; ++i)
-            for (int j = 0; j < m; ++j) {
-                double acc = 0.0;
-                for (int k = 0; k <= (i < j ? i : j); ++k) acc += s->R[k * kAACap + i] * s->R[k * kAACap + j];
-                S[i * kAACap + j] = acc;
+    if (t == 0) {
+        const int cnt = s->count;
+        int m = 0;
+        if (cnt >= 1) {
+            const int k = cnt - 1;  // the new column
+            for (int i = 0; i < k; ++i) {
+                s->R[i * kAACap + k] = s->c1[i] + s->c2[i];
+                s->R[k * kAACap + i] = 0.0;
             }
-        jacobi_eig(S, V, m);
-        double lmax = 0.0, lmin = INFINITY;
-        for (int i = 0; i < m; ++i) {
-            lmax = fmax(lmax, S[i * kAACap + i]);
-            lmin = fmin(lmin, S[i * kAACap + i]);
+            s->R[k * kAACap + k] = sqrt(s->nrm2);
+            m = k + 1;
         }
-        cond = (lmin > 0.0) ? sqrt(lmax / lmin) : INFINITY;
-        if (cond <= cond_max) {
-            for (int i = m - 1; i >= 0; --i) {
-                double acc = s->rhs[i];
-                for (int j = i + 1; j < m; ++j) acc -= s->R[i * kAACap + j] * s->gamma[j];
-                s->gamma[i] = acc / s->R[i * kAACap + i];
-            }
-            break;
-        }
-        if (s->rot_in == 0) qr_begin_transform(s, m);
-        qr_drop_first(s, m, s->rhs);  // rhs becomes (G Q^T g_k) of the remaining columns
-        s->head = (s->head + 1) % cap;
-        s->count -= 1;
-        m -= 1;
-        cond = 1.0;
+        s->count = cnt + 1;
+        qr_begin_transform(s, m);
+        s->rot_in = 0;  // no transform unless a column is dropped below
+        ctl[0] = m;
+        ctl[1] = 0;
     }
-    s->mk = m;
-    s->cond = (m > 0) ? cond : 0.0;
+    wave_sync_lds();
+    while (ctl[0] > 0) {
+        const int m = ctl[0];
+        if (t == 0)  // singular values of R from the eigenvalues of R^T R
+            for (int i = 0; i < m; ++i)
+                for (int j = 0; j < m; ++j) {
+                    double acc = 0.0;
+                    for (int k = 0; k <= (i < j ? i : j); ++k) acc += s->R[k * kAACap + i] * s->R[k * kAACap + j];
+                    S[i * kAACap + j] = acc;
+                }
+        wave_sync_lds();
+        jacobi_eig_wave(S, V, m);
+        wave_sync_lds();
+        if (t == 0) {
+            double lmax = 0.0, lmin = INFINITY;
+            for (int i = 0; i < m; ++i) {
+                lmax = fmax(lmax, S[i * kAACap + i]);
+                lmin = fmin(lmin, S[i * kAACap + i]);
+            }
+            cond = (lmin > 0.0) ? sqrt(lmax / lmin) : INFINITY;
+            ctl[1] = cond <= cond_max;
+            if (ctl[1]) {
+                for (int i = m - 1; i >= 0; --i) {
+                    double acc = s->rhs[i];
+                    for (int j = i + 1; j < m; ++j) acc -= s->R[i * kAACap + j] * s->gamma[j];
+                    s->gamma[i] = acc / s->R[i * kAACap + i];
+                }
+            } else {
+                if (s->rot_in == 0) qr_begin_transform(s, m);
+                qr_drop_first(s, m, s->rhs);  // rhs becomes (G Q^T g_k) of the remaining columns
+                s->head = (s->head + 1) % cap;
+                s->count -= 1;
+                ctl[0] = m - 1;
+                cond = 1.0;
+            }
+        }
+        wave_sync_lds();
+        if (ctl[1]) break;
+    }
+    if (t == 0) {
+        s->mk = ctl[0];
+        s->cond = (ctl[0] > 0) ? cond : 0.0;
+    }
 }
 
 template <int CAP>

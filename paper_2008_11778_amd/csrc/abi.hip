@@ -257,7 +257,9 @@ std::vector<aafwi::TileRec> tile_table(Engine* e, int kid, int width) {
     std::vector<std::vector<aafwi::TileRec>> region(kX);
     for (int i = 0; i < (int)e->in.size(); ++i) {
         const aafwi::WaveGrid& g = e->in[i].g;
-        const int tz = std::min(e->tz[kid] ? e->tz[kid] : default_tz(g.nzp), g.nzp);
+        // one-step kernels keep a strip's receiver rows one per lane: at most 64 rows
+        const int tz_set = e->tz[kid] ? e->tz[kid] : default_tz(g.nzp);
+        const int tz = std::min(width == 64 ? std::min(tz_set, 64) : tz_set, g.nzp);
         const int ntx = (g.nxp + width - 1) / width;
         std::vector<aafwi::TileRec> t;
         for (int s = 0; s < g.S; ++s) {
@@ -524,7 +526,7 @@ int timing_read(Engine* e, int id, double* mean_ms, int64_t* count) {
 }
 
 int set_tile(Engine* e, int kernel_id, int rows) {
-    AAFWI_REQUIRE(rows >= 0 && rows <= 64, "set_tile: rows per wave must be in [0, 64]");
+    AAFWI_REQUIRE(rows >= 0 && rows <= 120, "set_tile: rows per wave must be in [0, 120]");
     AAFWI_REQUIRE(kernel_id >= -1 && kernel_id < 4, "set_tile: kernel_id must be -1 or a kernel id");
     AAFWI_HIP(hipStreamSynchronize(e->stream));
     for (int k = 0; k < 4; ++k)

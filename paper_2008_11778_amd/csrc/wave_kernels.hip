@@ -488,7 +488,8 @@ __device__ __forceinline__ void stage2(float* rows, const Queue<U>& b, int lane)
     wave_sync();
 }
 
-// Receiver-row slots of the rows z0-4 .. z0+123 a two-step tile touches,
+// Receiver-row slots of the rows z0-4 .. z0+123 a two-step tile touches
+// (strips of up to 120 rows),
 // held one per lane in two registers (loaded once per tile) and read back per
 // row with a wave-uniform lane index: no memory access inside the row loop,
 // whose prefetched loads would otherwise all be waited for.
@@ -595,7 +596,8 @@ __global__ __launch_bounds__(256) void k_fwd_step2(const TileRec* __restrict__ t
     const int2 sn = I.src.node[t.s];
     const unsigned rb = (unsigned)g.pitch * 4u;
     const unsigned own_mask = L.own ? 0u : kOut;  // OR-ed into store offsets
-    const int my_rm = kRecompute ? -1 : strip_rowmap(rm, g, t);
+    FrameRows fr{-1, -1};
+    if (!kRecompute) fr = frame_rowmap(rm, g, t);
 
     const int za0 = t.z0 - 4;
     const int zend = two ? t.z1 + 4 : t.z1;
@@ -642,7 +644,7 @@ __global__ __launch_bounds__(256) void k_fwd_step2(const TileRec* __restrict__ t
                 bst(O1, oz, un);
                 if (kRecompute) bst(Q0, oz, qh);
                 if (!kRecompute) {
-                    const int slot = __builtin_amdgcn_readlane(my_rm, z - t.z0);
+                    const int slot = frame_slot(fr, z, t.z0);
                     if (slot >= 0 && L.own) sample(rm, g, t.s, slot, L.xc, d, nt, n, un);
                 }
             }
@@ -664,7 +666,7 @@ __global__ __launch_bounds__(256) void k_fwd_step2(const TileRec* __restrict__ t
                 bst(O2, oz, un);
                 if (kRecompute) bst(Q1, oz, qh);
                 if (!kRecompute) {
-                    const int slot = __builtin_amdgcn_readlane(my_rm, z - t.z0);
+                    const int slot = frame_slot(fr, z, t.z0);
                     if (slot >= 0 && L.own) sample(rm, g, t.s, slot, L.xc, d, nt, n + 1, un);
                 }
             }

@@ -19,7 +19,8 @@ def T(a):
 
 def ragged_case(nshots=3, nt=301):
     """70 x 150 interior (90 x 170 padded: three full 56-column tiles and a
-    2-column tail), sources in a corner, mid-grid and the far edge,
+    2-column tail; strips of more than 64 rows apply to the two-step kernels
+    only), sources in a corner, mid-grid and the far edge,
     receivers in two rows including the edge columns and a shared node."""
     g, m = synth.small_case(nz=70, nx=150, nb=10, nt=nt, nshots=nshots, nrec=12, f0=20.0, instance=3)
     rec_iz = np.tile(np.array([2] * 6 + [40] * 6, np.int32), (nshots, 1))
@@ -41,7 +42,7 @@ def run(g, m, d_obs, k, rows, tb):
         return d, grad.cpu().numpy(), float(J.item()), img.cpu().numpy()
 
 
-@pytest.mark.parametrize("k,rows", [(7, 0), (50, 13), (301, 37), (1, 64), (20, 4)])
+@pytest.mark.parametrize("k,rows", [(7, 0), (50, 13), (301, 37), (1, 64), (20, 4), (16, 120), (9, 77)])
 def test_two_step_equals_one_step_bitwise(k, rows):
     g, m = ragged_case()
     r = np.random.default_rng(5)
