@@ -25,7 +25,6 @@ namespace aafwi {
 namespace {
 
 typedef unsigned short bf16;
-typedef short v4s __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 constexpr int kL = 4;
@@ -33,7 +32,6 @@ constexpr int kCinP[kL] = {16, 32, 32, 32};   // padded input channels
 constexpr int kCoutP[kL] = {32, 32, 32, 16};  // padded output channels
 constexpr int kCin[kL] = {2, 32, 32, 32};
 constexpr int kCout[kL] = {32, 32, 32, 1};
-constexpr int kWgradChunk = 2048;  // pixels per split-K partial of the weight gradient
 constexpr int kRedBlocks = 64;     // per-image reduction partials
 
 __device__ __forceinline__ bf16 f2bf(float f) {
@@ -42,20 +40,6 @@ __device__ __forceinline__ bf16 f2bf(float f) {
     return (bf16)(u >> 16);
 }
 __device__ __forceinline__ float bf2f(bf16 h) { return __builtin_bit_cast(float, (unsigned)h << 16); }
-
-__device__ __forceinline__ v4s ld4(const bf16* p) { return *reinterpret_cast<const v4s*>(p); }
-
-struct Pix {
-    int b, y, x;
-};
-__device__ __forceinline__ Pix pix(int p, int H, int W) {
-    Pix q;
-    q.x = p % W;
-    const int r = p / W;
-    q.y = r % H;
-    q.b = r / H;
-    return q;
-}
 
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef unsigned v4u __attribute__((ext_vector_type(4)));
@@ -70,63 +54,80 @@ enum ConvMode { kHidden = 0, kLast = 1, kInputGrad = 2 };
 // last layer) and the input gradient (x = dy: [P][C], taps mirrored, output
 // masked by the ReLU of the layer input `mask`).  The reduction index is
 // k = tap * C + c, cut into chunks of 32: lane group g of a fragment holds
-// k = 32 ch + 8 g .. 8 g + 7, i.e. 8 consecutive channels of one tap (one
-// 16-byte load).  w is [tap][NOUT][C] bf16.  Each wave keeps all its weight
-// fragments in registers and walks 16-pixel tiles with a grid stride.
+// k = 32 ch + 8 g .. 8 g + 7, i.e. 8 consecutive channels of one tap.  w is
+// [tap][NOUT][C] bf16; every wave keeps all its weight fragments in
+// registers.  A block of four waves walks 64-pixel row segments with a grid
+// stride: it stages input rows y-1 .. y+1 over columns x0-1 .. x0+64 (zeros
+// outside the image) in LDS once, and wave w takes pixels x0+16w .. x0+16w+15,
+// reading each A fragment as one 16-byte LDS load.
+constexpr int kCSeg = 64;
+
 template <int C, int NOUT, int MODE>
-__global__ __launch_bounds__(256) void k_conv_mm(int P, int H, int W, const bf16* __restrict__ x,
+__global__ __launch_bounds__(256) void k_conv_mm(int B, int H, int W, const bf16* __restrict__ x,
                                                  const bf16* __restrict__ w, const bf16* __restrict__ mask,
                                                  bf16* __restrict__ y, float* __restrict__ z) {
     constexpr int NCH = (9 * C + 31) / 32;
     constexpr int NT = NOUT / 16;
     constexpr int sgn = MODE == kInputGrad ? -1 : 1;
-    const int lane = threadIdx.x & 63;
+    constexpr int CS = C + 8;  // LDS pixel stride: 16-byte aligned rows of channels
+    __shared__ __align__(16) bf16 xL[3 * (kCSeg + 2) * CS];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int i = lane & 15, grp = lane >> 4;
     bf8 bw[NCH][NT];
-    int tap_of[NCH], c_of[NCH];
+    int lofs[NCH];  // LDS element offset of this lane's A fragment, relative to the pixel's centre tap
+    bool tap_ok[NCH];
 #pragma unroll
     for (int ch = 0; ch < NCH; ++ch) {
         const int k0 = 32 * ch + 8 * grp;
-        tap_of[ch] = k0 / C;
-        c_of[ch] = k0 % C;
+        const int tap = k0 / C, c0 = k0 % C;
+        tap_ok[ch] = tap < 9;
+        const int dyo = sgn * (tap / 3 - 1), dxo = sgn * (tap % 3 - 1);
+        lofs[ch] = ((dyo + 1) * (kCSeg + 2) + 1 + dxo) * CS + c0;
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt)
-            bw[ch][nt] = tap_of[ch] < 9 ? ld8(w + ((tap_of[ch] * NOUT + nt * 16 + i) * C + c_of[ch])) : zero8();
+            bw[ch][nt] = tap_ok[ch] ? ld8(w + ((tap * NOUT + nt * 16 + i) * C + c0)) : zero8();
     }
-    const int ntile = (P + 15) / 16;
-    const int nwave = gridDim.x * 4;
-    for (int tile = blockIdx.x * 4 + (threadIdx.x >> 6); tile < ntile; tile += nwave) {
-        const int p0 = tile * 16;
-        const int p = p0 + i;
-        const bool pin = p < P;
-        const Pix q = pix(pin ? p : 0, H, W);
-        bf8 a[NCH];
-#pragma unroll
-        for (int ch = 0; ch < NCH; ++ch) {
-            const int tap = tap_of[ch];
-            const int yy = q.y + sgn * (tap / 3 - 1), xx = q.x + sgn * (tap % 3 - 1);
-            const bool ok = pin && tap < 9 && yy >= 0 && yy < H && xx >= 0 && xx < W;
-            a[ch] = ok ? ld8(x + ((long long)(q.b * H + yy) * W + xx) * C + c_of[ch]) : zero8();
+    const int segs_x = (W + kCSeg - 1) / kCSeg;
+    const int nseg = B * H * segs_x;
+    for (int seg = blockIdx.x; seg < nseg; seg += gridDim.x) {
+        const int sx = seg % segs_x, rowi = seg / segs_x;
+        const int yy0 = rowi % H, bimg = rowi / H;
+        const int x0 = sx * kCSeg;
+        __syncthreads();
+        for (int e = threadIdx.x; e < 3 * (kCSeg + 2) * (C / 8); e += 256) {
+            const int cg = e % (C / 8), q = e / (C / 8);
+            const int j = q % (kCSeg + 2), rr = q / (kCSeg + 2);
+            const int yy = yy0 + rr - 1, xx = x0 - 1 + j;
+            v4u v = v4u{0u, 0u, 0u, 0u};
+            if (yy >= 0 && yy < H && xx >= 0 && xx < W)
+                v = *reinterpret_cast<const v4u*>(x + ((long long)(bimg * H + yy) * W + xx) * C + cg * 8);
+            *reinterpret_cast<v4u*>(xL + (rr * (kCSeg + 2) + j) * CS + cg * 8) = v;
         }
+        __syncthreads();
+        const int px = 16 * wv + i;  // this lane's pixel in the segment (A rows)
         v4f acc[NT];
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) acc[nt] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int ch = 0; ch < NCH; ++ch)
+        for (int ch = 0; ch < NCH; ++ch) {
+            const bf8 a = tap_ok[ch] ? __builtin_bit_cast(bf8, *reinterpret_cast<const v4u*>(xL + lofs[ch] + px * CS))
+                                     : zero8();
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt)
-                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ch], bw[ch][nt], acc[nt], 0, 0, 0);
-        // lane holds D[4 grp + r][i]: pixel p0 + 4 grp + r, output channel nt*16 + i
+                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[ch][nt], acc[nt], 0, 0, 0);
+        }
+        // lane holds D[4 grp + r][i]: pixel 16 wv + 4 grp + r of the segment, output channel nt*16 + i
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int pp = p0 + 4 * grp + r;
-            if (pp >= P) continue;
+            const int xx = x0 + 16 * wv + 4 * grp + r;
+            if (xx >= W) continue;
+            const long long pp = (long long)rowi * W + xx;
             if (MODE == kLast) {
                 if (i == 0) z[pp] = acc[0][r];
             } else {
 #pragma unroll
                 for (int nt = 0; nt < NT; ++nt) {
-                    const long long o = (long long)pp * NOUT + nt * 16 + i;
+                    const long long o = pp * NOUT + nt * 16 + i;
                     if (MODE == kHidden)
                         y[o] = f2bf(fmaxf(acc[nt][r], 0.f));
                     else
@@ -137,56 +138,99 @@ __global__ __launch_bounds__(256) void k_conv_mm(int P, int H, int W, const bf16
     }
 }
 
-// Split-K weight gradient: part[chunk][tap][co][ci] = sum over the chunk's
-// pixels p of dy[p][co] x[p + off(tap)][ci].  One wave per (chunk, tap).
+// Weight gradient: part[block][tap][co][ci] = sum over the block's pixels p of
+// dy[p][co] x[p + off(tap)][ci] (FP32 partials, summed over blocks in a fixed
+// order by the reduction below).  A block of three waves takes 32-pixel row
+// segments (b, y, x0..x0+31) with a grid stride: it stages dy of the segment
+// and the input rows y-1, y, y+1 over columns x0-1 .. x0+32 (zeros outside
+// the image) in LDS, and wave r accumulates the three taps of tap row r as
+// GEMMs over the segment's pixels on v_mfma_f32_16x16x32_bf16: A = dy^T
+// (co x pixels), B = x shifted by the tap (pixels x ci).  A fragment takes 8
+// consecutive pixels of one channel: the LDS pixel stride is padded by two
+// channels so that those gathers do not collide in the LDS banks.
+constexpr int kSeg = 32;
+constexpr int kWgradMaxBlocks = 1024;
+
+template <int C>
+__device__ __forceinline__ bf8 gather8(const bf16* base) {  // base[s * (C + 2)], s = 0..7
+    v4u v;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        v[k] = (unsigned)base[(2 * k) * (C + 2)] | ((unsigned)base[(2 * k + 1) * (C + 2)] << 16);
+    return __builtin_bit_cast(bf8, v);
+}
+
 template <int CIN, int COUT>
-__global__ __launch_bounds__(64) void k_conv_wgrad(int P, int H, int W, const bf16* __restrict__ dy,
+__global__ __launch_bounds__(192) void k_conv_wgrad(int B, int H, int W, const bf16* __restrict__ dy,
                                                    const bf16* __restrict__ x, float* __restrict__ part) {
-    const int lane = threadIdx.x;
-    const int chunk = blockIdx.x, tap = blockIdx.y;
+    __shared__ bf16 dyL[kSeg * (COUT + 2)];
+    __shared__ bf16 xL[3 * (kSeg + 2) * (CIN + 2)];
+    constexpr int MT = COUT / 16, NT = CIN / 16;
+    const int lane = threadIdx.x & 63, r = threadIdx.x >> 6;  // r: tap row (dy offset r - 1)
     const int i = lane & 15, grp = lane >> 4;
-    const int dyo = tap / 3 - 1, dxo = tap % 3 - 1;
-    v4f acc[COUT / 16][CIN / 16];
+    const int segs_x = (W + kSeg - 1) / kSeg;
+    const int nseg = B * H * segs_x;
+    v4f acc[3][MT][NT];
 #pragma unroll
-    for (int a = 0; a < COUT / 16; ++a)
+    for (int d = 0; d < 3; ++d)
 #pragma unroll
-        for (int b = 0; b < CIN / 16; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
-    const int pbeg = chunk * kWgradChunk;
-    const int pend = min(pbeg + kWgradChunk, P);
-    for (int k0 = pbeg; k0 < pend; k0 += 16) {
-        // A[co][pix] = dy[k0 + 4*grp + r][co]; B[pix][ci] = x[(k0 + 4*grp + r) + off][ci]
-        short av[COUT / 16][4], bv[CIN / 16][4];
+        for (int a = 0; a < MT; ++a)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int p = k0 + 4 * grp + r;
-            const bool pin = p < pend;
-            const Pix q = pix(pin ? p : 0, H, W);
-            const int yy = q.y + dyo, xx = q.x + dxo;
-            const bool ok = pin && yy >= 0 && yy < H && xx >= 0 && xx < W;
-            const long long xs = ((long long)(q.b * H + yy) * W + xx) * CIN;
+            for (int b = 0; b < NT; ++b) acc[d][a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int seg = blockIdx.x; seg < nseg; seg += gridDim.x) {
+        const int sx = seg % segs_x, rowi = seg / segs_x;  // rowi = b * H + y
+        const int y = rowi % H, bimg = rowi / H;
+        const int x0 = sx * kSeg;
+        __syncthreads();  // the previous segment's LDS reads are done
+        // dy of the segment: 32 pixels x COUT/8 groups of 8 channels
+        for (int e = threadIdx.x; e < kSeg * (COUT / 8); e += 192) {
+            const int px = e / (COUT / 8), cg = e % (COUT / 8);
+            const int xx = x0 + px;
+            v4u v = v4u{0u, 0u, 0u, 0u};
+            if (xx < W) v = *reinterpret_cast<const v4u*>(dy + ((long long)rowi * W + xx) * COUT + cg * 8);
+            unsigned* dst = reinterpret_cast<unsigned*>(dyL + px * (COUT + 2) + cg * 8);
 #pragma unroll
-            for (int a = 0; a < COUT / 16; ++a) av[a][r] = pin ? (short)dy[(long long)p * COUT + a * 16 + i] : (short)0;
-#pragma unroll
-            for (int b = 0; b < CIN / 16; ++b) bv[b][r] = ok ? (short)x[xs + b * 16 + i] : (short)0;
+            for (int k = 0; k < 4; ++k) dst[k] = v[k];
         }
+        // x rows y-1 .. y+1, columns x0-1 .. x0+32
+        for (int e = threadIdx.x; e < 3 * (kSeg + 2) * (CIN / 8); e += 192) {
+            const int cg = e % (CIN / 8), q = e / (CIN / 8);
+            const int j = q % (kSeg + 2), rr = q / (kSeg + 2);
+            const int yy = y + rr - 1, xx = x0 - 1 + j;
+            v4u v = v4u{0u, 0u, 0u, 0u};
+            if (yy >= 0 && yy < H && xx >= 0 && xx < W)
+                v = *reinterpret_cast<const v4u*>(x + ((long long)(bimg * H + yy) * W + xx) * CIN + cg * 8);
+            unsigned* dst = reinterpret_cast<unsigned*>(xL + (rr * (kSeg + 2) + j) * (CIN + 2) + cg * 8);
 #pragma unroll
-        for (int a = 0; a < COUT / 16; ++a) {
-            const v4s A = v4s{av[a][0], av[a][1], av[a][2], av[a][3]};
+            for (int k = 0; k < 4; ++k) dst[k] = v[k];
+        }
+        __syncthreads();
+        // K = the segment's 32 pixels, one 32-deep MFMA step per tile
+        bf8 A[MT];
 #pragma unroll
-            for (int b = 0; b < CIN / 16; ++b) {
-                const v4s B = v4s{bv[b][0], bv[b][1], bv[b][2], bv[b][3]};
-                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, B, acc[a][b], 0, 0, 0);
+        for (int a = 0; a < MT; ++a) A[a] = gather8<COUT>(dyL + (8 * grp) * (COUT + 2) + a * 16 + i);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+#pragma unroll
+            for (int b = 0; b < NT; ++b) {
+                const bf8 Bf = gather8<CIN>(xL + (r * (kSeg + 2) + 8 * grp + d) * (CIN + 2) + b * 16 + i);
+#pragma unroll
+                for (int a = 0; a < MT; ++a)
+                    acc[d][a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[a], Bf, acc[d][a][b], 0, 0, 0);
             }
         }
     }
-    // lane holds D[4*grp + r][i]: co = a*16 + 4*grp + r, ci = b*16 + i
-    float* out = part + ((long long)chunk * 9 + tap) * COUT * CIN;
+    // lane holds D[4 grp + q][i]: co = a*16 + 4 grp + q, ci = b*16 + i; tap = 3 r + d
+    float* out = part + (long long)blockIdx.x * 9 * COUT * CIN;
 #pragma unroll
-    for (int a = 0; a < COUT / 16; ++a)
+    for (int d = 0; d < 3; ++d)
 #pragma unroll
-        for (int b = 0; b < CIN / 16; ++b)
+        for (int a = 0; a < MT; ++a)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) out[(a * 16 + 4 * grp + r) * CIN + b * 16 + i] = acc[a][b][r];
+            for (int b = 0; b < NT; ++b)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    out[((3 * r + d) * COUT + a * 16 + 4 * grp + q) * CIN + b * 16 + i] = acc[d][a][b][q];
 }
 
 // Chunk partials -> weight gradient in two fixed-order FP64 stages: group g
@@ -447,11 +491,11 @@ void pack_weights(aafwi_cnn* c) {
 }
 
 template <int C, int NOUT, int MODE>
-void conv(aafwi_cnn* c, int P, const aafwi::bf16* x, const aafwi::bf16* w, const aafwi::bf16* mask, aafwi::bf16* y,
+void conv(aafwi_cnn* c, int B, const aafwi::bf16* x, const aafwi::bf16* w, const aafwi::bf16* mask, aafwi::bf16* y,
           float* z) {
-    const int ntile = (P + 15) / 16;
-    const int blocks = std::min((ntile + 3) / 4, 2048);
-    hipLaunchKernelGGL((aafwi::k_conv_mm<C, NOUT, MODE>), dim3(blocks), dim3(256), 0, c->stream, P, c->H, c->W, x, w,
+    const int nseg = B * c->H * ((c->W + aafwi::kCSeg - 1) / aafwi::kCSeg);
+    const int blocks = std::min(nseg, 2048);
+    hipLaunchKernelGGL((aafwi::k_conv_mm<C, NOUT, MODE>), dim3(blocks), dim3(256), 0, c->stream, B, c->H, c->W, x, w,
                        mask, y, z);
 }
 
@@ -471,10 +515,10 @@ void forward(aafwi_cnn* c, int B, const float* g, const float* m) {
     hipLaunchKernelGGL(k_finish<3>, dim3((B + 63) / 64), dim3(64), 0, c->stream, B, (const double*)c->part, c->st_in);
     hipLaunchKernelGGL(k_pack_input, dim3((P + 255) / 256), dim3(256), 0, c->stream, B, n, g, m,
                        (const double*)c->st_in, c->act[0]);
-    conv<16, 32, kHidden>(c, P, c->act[0], c->wf[0], nullptr, c->act[1], nullptr);
-    conv<32, 32, kHidden>(c, P, c->act[1], c->wf[1], nullptr, c->act[2], nullptr);
-    conv<32, 32, kHidden>(c, P, c->act[2], c->wf[2], nullptr, c->act[3], nullptr);
-    conv<32, 16, kLast>(c, P, c->act[3], c->wf[3], nullptr, nullptr, c->z);
+    conv<16, 32, kHidden>(c, B, c->act[0], c->wf[0], nullptr, c->act[1], nullptr);
+    conv<32, 32, kHidden>(c, B, c->act[1], c->wf[1], nullptr, c->act[2], nullptr);
+    conv<32, 32, kHidden>(c, B, c->act[2], c->wf[2], nullptr, c->act[3], nullptr);
+    conv<32, 16, kLast>(c, B, c->act[3], c->wf[3], nullptr, nullptr, c->z);
     AAFWI_HIP(hipGetLastError());
 }
 
@@ -492,19 +536,20 @@ void gradients(aafwi_cnn* c, int B, const float* g, const float* m, const float*
                        (const double*)c->st1, (const double*)c->st2, c->dlt[3]);
     if (loss) hipLaunchKernelGGL(k_loss_total, dim3(1), dim3(64), 0, c->stream, B, n, (const double*)c->st2, loss);
     AAFWI_HIP(hipGetLastError());
-    const int nchunk = (P + kWgradChunk - 1) / kWgradChunk;
+    const int nseg = B * c->H * ((c->W + kSeg - 1) / kSeg);
+    const int nchunk = std::min(nseg, kWgradMaxBlocks);
     // layer 4 (32 -> 1): weight gradient, then the delta at layer 3's output
-    hipLaunchKernelGGL((k_conv_wgrad<32, 16>), dim3(nchunk, 9), dim3(64), 0, c->stream, P, c->H, c->W, c->dlt[3],
+    hipLaunchKernelGGL((k_conv_wgrad<32, 16>), dim3(nchunk), dim3(192), 0, c->stream, B, c->H, c->W, c->dlt[3],
                        c->act[3], c->wpart);
     weight_reduce(c, nchunk, 16, 32, 3);
-    conv<16, 32, kInputGrad>(c, P, c->dlt[3], c->wd[3], c->act[3], c->dlt[2], nullptr);
+    conv<16, 32, kInputGrad>(c, B, c->dlt[3], c->wd[3], c->act[3], c->dlt[2], nullptr);
     for (int l = 2; l >= 1; --l) {
-        hipLaunchKernelGGL((k_conv_wgrad<32, 32>), dim3(nchunk, 9), dim3(64), 0, c->stream, P, c->H, c->W, c->dlt[l],
+        hipLaunchKernelGGL((k_conv_wgrad<32, 32>), dim3(nchunk), dim3(192), 0, c->stream, B, c->H, c->W, c->dlt[l],
                            c->act[l], c->wpart);
         weight_reduce(c, nchunk, 32, 32, l);
-        conv<32, 32, kInputGrad>(c, P, c->dlt[l], c->wd[l], c->act[l], c->dlt[l - 1], nullptr);
+        conv<32, 32, kInputGrad>(c, B, c->dlt[l], c->wd[l], c->act[l], c->dlt[l - 1], nullptr);
     }
-    hipLaunchKernelGGL((k_conv_wgrad<16, 32>), dim3(nchunk, 9), dim3(64), 0, c->stream, P, c->H, c->W, c->dlt[0],
+    hipLaunchKernelGGL((k_conv_wgrad<16, 32>), dim3(nchunk), dim3(192), 0, c->stream, B, c->H, c->W, c->dlt[0],
                        c->act[0], c->wpart);
     weight_reduce(c, nchunk, 32, 16, 0);
     AAFWI_HIP(hipGetLastError());
@@ -545,7 +590,8 @@ extern "C" int aafwi_cnn_create(int32_t nz, int32_t nx, int32_t max_batch, const
             c->st_in = calloc_dev<double>(c, (size_t)max_batch * 3);
             c->st1 = calloc_dev<double>(c, (size_t)max_batch * 2);
             c->st2 = calloc_dev<double>(c, (size_t)max_batch * 2);
-            const size_t nchunk = (P + aafwi::kWgradChunk - 1) / aafwi::kWgradChunk;
+            const size_t nseg = (size_t)max_batch * nz * ((nx + aafwi::kSeg - 1) / aafwi::kSeg);
+            const size_t nchunk = std::min(nseg, (size_t)aafwi::kWgradMaxBlocks);
             c->wpart = calloc_dev<float>(c, nchunk * 9 * 32 * 32);
             c->gsum = calloc_dev<double>(c, (size_t)aafwi::kRedGroups * 9 * 32 * 32);
             AAFWI_HIP(hipMemcpy(c->w, weights, sizeof(float) * AAFWI_CNN_PARAMS, hipMemcpyHostToDevice));
