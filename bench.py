@@ -102,20 +102,22 @@ def source_digest():
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def measured_traffic(kernel: str, steps_per_launch: int, tiles: dict):
+def measured_traffic(kernel: str, steps_per_launch: int, tiles: dict, section: str = "kernels"):
     """HBM bytes per launch of ``kernel`` from the committed counter summary
     (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), or None
     when it is missing or was taken on other kernel sources or another launch
-    shape (steps per launch, rows per wave, tile order)."""
+    shape (steps per launch, rows per wave, tile order).  ``section`` selects
+    the workload: "kernels" for the FWI-gradient grid, "large_kernels" for
+    the 1024 x 384, 96-shot grid."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as f:
             tr = json.load(f)
     except (OSError, ValueError):
         return None
-    if tr.get("source_sha256") != source_digest() or kernel not in tr.get("kernels", {}):
+    if tr.get("source_sha256") != source_digest() or kernel not in tr.get(section, {}):
         return None
-    k = tr["kernels"][kernel]
+    k = tr[section][kernel]
     kid = {v: i for i, v in NAMES.items()}[kernel]
     if (k.get("steps_per_launch") != steps_per_launch or k.get("rows") != tiles.get(kid)
             or k.get("order") != tiles.get(f"order{kid}", 0)):
@@ -154,7 +156,7 @@ def aa_step_timing(n, M=10, steps=30):
     return out
 
 
-def stencil_large(dev, nt=400):
+def stencil_large(dev, nt=400, retune=False):
     """Forward stepping kernel on the 1024 x 384 grid with 96 shots (two
     wavefield planes of 177 MB each: more than the 256 MB Infinity Cache),
     in the autotuned launch mode, every launch event-timed; algorithmic bytes
@@ -167,20 +169,22 @@ def stencil_large(dev, nt=400):
     from paper_2008_11778_amd import autotune
     with Context(g, ckpt_every=50) as ctx:
         m = torch.from_numpy(m0).to(dev)
-        autotune.apply(ctx, autotune.tune(g, m, verbose=True))
+        tiles = autotune.tune(g, m, use_cache=not retune, verbose=True)
+        autotune.apply(ctx, tiles)
         ctx.forward_model(m)
         ctx.kernel_timing(1)
         ctx.forward_model(m)
         mean_ms, cnt = ctx.kernel_timing_read(0)
         rows = ctx.get_tile(0)
         steps = 2 if ctx.time_blocking() & 1 else 1
+        traffic = measured_traffic("fwd_step", steps, {0: rows, "order0": tiles.get("order0", 0)}, "large_kernels")
     pts = g.nz_p * g.nx_p * g.nshots
     gbs = (BYTES2[0] if steps == 2 else BYTES[0]) * pts / (mean_ms / 1e3) / 1e9
     return {"workload": f"forward step, {g.nx}x{g.nz} grid, {g.nshots} shots, 20-cell sponge",
             "mean_launch_us": round(mean_ms * 1e3, 2), "timed_launches": cnt, "rows_per_wave": rows,
             "steps_per_launch": steps,
             "gpt_updates_per_s": round(steps * pts / (mean_ms / 1e3) / 1e9, 1),
-            "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
             "working_set_mb": round(2 * pts * 4 / 1e6, 1)}
 
 
@@ -565,6 +569,8 @@ def main():
     ap.add_argument("--tile", type=int, default=-1,
                     help="rows per wave for every stepping kernel (-1 = autotune, 0 = library default)")
     ap.add_argument("--no-time-blocking", action="store_true", help="one time step per stepping launch")
+    ap.add_argument("--retune", action="store_true",
+                    help="time every launch shape now instead of taking the cached or shipped choice")
     ap.add_argument("--shape", default="",
                     help="launch shape instead of autotuning: steps per launch of the forward, recompute and "
                          "adjoint kernels, rows per wave of the forward, recompute, adjoint and Born steps, and "
@@ -632,7 +638,7 @@ def main():
         tiles = {k: ctx.get_tile(k) for k in range(4)}
     else:
         from paper_2008_11778_amd import autotune
-        tiles = autotune.tune(g, m0t, verbose=True)
+        tiles = autotune.tune(g, m0t, use_cache=not args.retune, verbose=True)
         autotune.apply(ctx, tiles)
     if args.no_time_blocking:
         ctx.set_time_blocking(False)
@@ -740,7 +746,7 @@ def main():
     out["aa_step"] = aa_step_timing(g.nz * g.nx)
     log(f"Anderson step: {out['aa_step']}")
     if not args.no_large:
-        out["stencil_large"] = stencil_large(dev)
+        out["stencil_large"] = stencil_large(dev, retune=args.retune)
         log(f"forward step on the large grid: {out['stencil_large']}")
     if cpu is not None:
         out["cpu_baseline"] = cpu

@@ -146,12 +146,10 @@ __device__ __forceinline__ void rows_copy(float (&dst)[U], const float (&src)[U]
     for (int i = 0; i < U; ++i) dst[i] = src[i];
 }
 
-// Unscaled 8th-order Laplacian of row j of the block: z-pairs from the
-// queue, x-pairs from LDS row j (centre of lane l at row[4 + l]).
-template <int U>
-__device__ __forceinline__ float lap8(const Queue<U>& c, int j, const float* row, int lane) {
-    const float* r = row + 4 + lane;
-    const float* q = c.q + j + 4;
+// Unscaled 8th-order Laplacian at one point: z-pairs from the register
+// column q (centred on the point), x-pairs from the LDS row r (centred on
+// the point's lane).
+__device__ __forceinline__ float lap8p(const float* q, const float* r) {
     const float s1 = (q[-1] + q[1]) + (r[-1] + r[1]);
     const float s2 = (q[-2] + q[2]) + (r[-2] + r[2]);
     const float s3 = (q[-3] + q[3]) + (r[-3] + r[3]);
@@ -162,6 +160,11 @@ __device__ __forceinline__ float lap8(const Queue<U>& c, int j, const float* row
     acc = fmaf(kC3, s3, acc);
     acc = fmaf(kC4, s4, acc);
     return acc;
+}
+
+template <int U>
+__device__ __forceinline__ float lap8(const Queue<U>& c, int j, const float* row, int lane) {
+    return lap8p(c.q + j + 4, row + 4 + lane);
 }
 
 // Per-lane addressing of a wave tile: node offset (bytes, row z0) and halo
@@ -219,12 +222,48 @@ __device__ __forceinline__ void sponge_ab(const WaveGrid& g, const LanesT& L, in
     }
 }
 
+// Global-address-space views of pointers read from the instance table.  The
+// compiler cannot infer where such pointers point, and generic (FLAT)
+// accesses would make every later wait in a stepping loop drain all
+// outstanding loads and stores instead of only the ones it needs.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* gc(const T* p) {
+    return (const __attribute__((address_space(1))) T*)p;
+}
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gm(T* p) {
+    return (__attribute__((address_space(1))) T*)p;
+}
+
+// Sum of the residuals injected at this lane's node of row slot `slot`.
+__device__ __forceinline__ float injected(const RecMaps& rm, const WaveGrid& g, int s, int slot, int x,
+                                          const float* r, int nt, int n) {
+    float rs = 0.0f;
+    int ri = gc(rm.xmap)[((long long)s * rm.nrr + slot) * g.pitch + x];
+    while (ri >= 0) {
+        rs += gc(r)[((long long)s * nt + n) * rm.R + ri];
+        ri = gc(rm.next)[s * rm.R + ri];
+    }
+    return rs;
+}
+
+// Store v as the trace sample of every receiver at this lane's node of row
+// slot `slot`.
+__device__ __forceinline__ void sample(const RecMaps& rm, const WaveGrid& g, int s, int slot, int x, float* d,
+                                       int nt, int n, float v) {
+    int ri = gc(rm.xmap)[((long long)s * rm.nrr + slot) * g.pitch + x];
+    while (ri >= 0) {
+        gm(d)[((long long)s * nt + n) * rm.R + ri] = v;
+        ri = gc(rm.next)[s * rm.R + ri];
+    }
+}
+
 // Receiver-row slots of the strip's rows, one per lane (strips are at most
 // 64 rows); read back per row with a wave-uniform lane index.
 __device__ __forceinline__ int strip_rowmap(const RecMaps& rm, const WaveGrid& g, const Tile& t) {
     const bool ok = t.lane < t.z1 - t.z0;
     const int i = t.s * g.nzp + t.z0 + t.lane;
-    const int v = rm.rowmap[ok ? i : t.s * g.nzp];
+    const int v = gc(rm.rowmap)[ok ? i : t.s * g.nzp];
     return ok ? v : -1;
 }
 
@@ -328,13 +367,7 @@ __global__ __launch_bounds__(256) void k_fwd_step(const TileRec* __restrict__ ti
             if (kRecompute) bst(QR, oz, qh);
             if (!kRecompute) {
                 const int slot = __builtin_amdgcn_readlane(my_rm, z - t.z0);
-                if (slot >= 0 && L.xin) {
-                    int ri = rm.xmap[((long long)t.s * rm.nrr + slot) * g.pitch + L.x];
-                    while (ri >= 0) {
-                        d[((long long)t.s * nt + n) * rm.R + ri] = un;
-                        ri = rm.next[t.s * rm.R + ri];
-                    }
-                }
+                if (slot >= 0 && L.xin) sample(rm, g, t.s, slot, L.x, d, nt, n, un);
             }
         }
         queue_advance(c, nq);
@@ -408,15 +441,7 @@ __global__ __launch_bounds__(256) void k_adj_step(const TileRec* __restrict__ ti
             const unsigned oz = o + (unsigned)j * rb;
             float acc = lap8(c, j, rows + j * 72, lane);
             const int slot = __builtin_amdgcn_readlane(my_rm, z - t.z0);
-            if (slot >= 0 && L.xin) {
-                int ri = rm.xmap[((long long)t.s * rm.nrr + slot) * g.pitch + L.x];
-                float rs = 0.0f;
-                while (ri >= 0) {
-                    rs += r[((long long)t.s * nt + n) * rm.R + ri];
-                    ri = rm.next[t.s * rm.R + ri];
-                }
-                acc = fmaf(-h2, rs, acc);
-            }
+            if (slot >= 0 && L.xin) acc = fmaf(-h2, injected(rm, g, t.s, slot, L.x, r, nt, n), acc);
             float A, B;
             sponge_ab(g, L, z, A, B);
             const float ln = fmaf(2.0f * A, c.q[j + 4], fmaf(-B, pv[j], kv[j] * acc));
@@ -478,16 +503,6 @@ __device__ __forceinline__ Lanes2 lanes2(const WaveGrid& g, const Tile& t) {
 // the plane and reads as zero).
 __device__ __forceinline__ unsigned row_off(int z, int pitch) { return (unsigned)(z * pitch * 4); }
 
-// Stage the step-two centre rows (no halo: lanes 0-3 and 60-63 of step two
-// are not output columns, whatever they read).
-template <int U>
-__device__ __forceinline__ void stage2(float* rows, const Queue<U>& b, int lane) {
-    wave_sync();
-#pragma unroll
-    for (int j = 0; j < U; ++j) rows[j * 72 + 4 + lane] = b.q[j + 4];
-    wave_sync();
-}
-
 // Receiver-row slots of the rows z0-4 .. z0+123 a two-step tile touches
 // (strips of up to 120 rows),
 // held one per lane in two registers (loaded once per tile) and read back per
@@ -500,8 +515,8 @@ struct FrameRows {
 __device__ __forceinline__ FrameRows frame_rowmap(const RecMaps& rm, const WaveGrid& g, const Tile& t) {
     FrameRows f;
     const int za = t.z0 - 4 + t.lane, zb = t.z0 + 60 + t.lane, zmax = min(t.z1 + 4, g.nzp);
-    f.lo = (za >= 0 && za < zmax) ? rm.rowmap[t.s * g.nzp + za] : -1;
-    f.hi = (zb < zmax) ? rm.rowmap[t.s * g.nzp + zb] : -1;
+    f.lo = (za >= 0 && za < zmax) ? gc(rm.rowmap)[t.s * g.nzp + za] : -1;
+    f.hi = (zb < zmax) ? gc(rm.rowmap)[t.s * g.nzp + zb] : -1;
     return f;
 }
 
@@ -510,30 +525,108 @@ __device__ __forceinline__ int frame_slot(const FrameRows& f, int z, int z0) {
     return i < 64 ? __builtin_amdgcn_readlane(f.lo, i) : __builtin_amdgcn_readlane(f.hi, i - 64);
 }
 
-// Sum of the residuals injected at this lane's node of row slot `slot`.
-__device__ __forceinline__ float injected(const RecMaps& rm, const WaveGrid& g, int s, int slot, int x,
-                                          const float* r, int nt, int n) {
-    float rs = 0.0f;
-    int ri = rm.xmap[((long long)s * rm.nrr + slot) * g.pitch + x];
-    while (ri >= 0) {
-        rs += r[((long long)s * nt + n) * rm.R + ri];
-        ri = rm.next[s * rm.R + ri];
+// Register rings of the two-step kernels.  The loop over 4-row blocks is
+// unrolled four times and every row block of every stream has a fixed ring
+// slot: block k sits in slot k & 3 of a 4-deep ring and k & 1 of a 2-deep
+// one.  The loads of block k+1 go to slots that block k does not touch and
+// nothing moves between slots, so each block waits for its own rows right
+// before using them, with the next block's loads still in flight.  (A queue
+// shifted at the end of every block copies the rows just loaded, which waits
+// for all of them there and leaves the wave with nothing in flight.)
+template <int K>
+struct Blk {
+    static constexpr int prev = (K + 3) & 3, cur = K & 3, next = (K + 1) & 3, ahead = (K + 2) & 3;
+    static constexpr int even = K & 1, odd = (K + 1) & 1;
+};
+
+// The 12-row z-window (rows za-4 .. za+7) from three ring slots.
+__device__ __forceinline__ void window(float (&w)[12], const float (&a)[4], const float (&b)[4],
+                                       const float (&c)[4]) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        w[i] = a[i];
+        w[4 + i] = b[i];
+        w[8 + i] = c[i];
     }
-    return rs;
 }
 
-__device__ __forceinline__ void sample(const RecMaps& rm, const WaveGrid& g, int s, int slot, int x, float* d,
-                                       int nt, int n, float v) {
-    int ri = rm.xmap[((long long)s * rm.nrr + slot) * g.pitch + x];
-    while (ri >= 0) {
-        d[((long long)s * nt + n) * rm.R + ri] = v;
-        ri = rm.next[s * rm.R + ri];
+// Stage rows 4..7 of a window (the block's rows) into LDS, with the x-halo
+// of lanes 0-7 when given.
+__device__ __forceinline__ void stage_w(float* rows, const float (&w)[12], const float (&hv)[4], int lane,
+                                        int hslot) {
+    wave_sync();
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        rows[j * 72 + 4 + lane] = w[j + 4];
+        if (lane < 8) rows[j * 72 + hslot] = hv[j];
     }
+    wave_sync();
+}
+
+// Step two's rows: centre values only (lanes 0-3 and 60-63 of step two are
+// not output columns, whatever they read).
+__device__ __forceinline__ void stage_c(float* rows, const float (&w)[12], int lane) {
+    wave_sync();
+#pragma unroll
+    for (int j = 0; j < 4; ++j) rows[j * 72 + 4 + lane] = w[j + 4];
+    wave_sync();
+}
+
+template <int V>
+struct IC {
+    static constexpr int value = V;
+};
+
+// Store with the row offset in the scalar offset operand; only for rows
+// known to lie inside the plane (lanes pushed out of it keep their bit-31
+// offset in voffset and still drop the store).
+__device__ __forceinline__ void bst_row(Rsrc r, unsigned voff, unsigned soff, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+}
+
+// Frame rows z0-4+i (i < 128) flagged in a two-word lane mask: whether rows
+// i0 .. i0+7 are all unflagged.
+__device__ __forceinline__ bool rows_clear(unsigned long long lo, unsigned long long hi, int i0) {
+    unsigned long long w;
+    if (i0 >= 64)
+        w = hi >> (i0 - 64);
+    else if (i0 == 0)
+        w = lo;
+    else
+        w = (lo >> i0) | (hi << (64 - i0));
+    return (w & 0xffull) == 0;
+}
+
+// Blocks whose eight rows (step one at za .. za+3, step two at za-4 .. za-1)
+// lie inside the strip and the undamped interior, with no receiver or
+// source row among them, take a branch-free path: A = B = 1 exactly, no
+// per-row tests, the same arithmetic in the same order.
+struct FastRows {
+    int zlo, zhi;                // za-4 >= zlo and za+3 < zhi
+    unsigned long long lo, hi;   // flagged frame rows
+    bool on;                     // the tile qualifies at all
+};
+
+__device__ __forceinline__ FastRows fast_rows(const WaveGrid& g, const Tile& t, const Lanes2& L, const FrameRows& fr,
+                                              int src_row, bool on) {
+    FastRows f;
+    f.zlo = max(t.z0, g.nb);
+    f.zhi = min(t.z1, g.nb + g.nz);
+    const int za = t.z0 - 4 + t.lane, zb = t.z0 + 60 + t.lane;
+    f.lo = __builtin_amdgcn_ballot_w64(fr.lo >= 0 || za == src_row);
+    f.hi = __builtin_amdgcn_ballot_w64(fr.hi >= 0 || zb == src_row);
+    f.on = on && L.interior_x;
+    return f;
+}
+
+__device__ __forceinline__ bool is_fast(const FastRows& f, int za, int z0) {
+    return f.on && za - 4 >= f.zlo && za + 3 < f.zhi && rows_clear(f.lo, f.hi, za - z0);
 }
 
 template <int U, bool kRecompute>
 __global__ __launch_bounds__(256) void k_fwd_step2(const TileRec* __restrict__ tiles, int ntiles,
                                                    const Inst* __restrict__ insts, StepArgs a) {
+    static_assert(U == 4, "the two-step register rings hold 4-row blocks");
     __shared__ float lds[kWaves][2 * U * 72];
     const Tile t = decode_tile(tiles, ntiles);
     if (!t.live) return;
@@ -598,48 +691,92 @@ __global__ __launch_bounds__(256) void k_fwd_step2(const TileRec* __restrict__ t
     const unsigned own_mask = L.own ? 0u : kOut;  // OR-ed into store offsets
     FrameRows fr{-1, -1};
     if (!kRecompute) fr = frame_rowmap(rm, g, t);
+    const FastRows fast = fast_rows(g, t, L, fr, sn.x, two && !ck0 && !ck1);
 
     const int za0 = t.z0 - 4;
     const int zend = two ? t.z1 + 4 : t.z1;
+    int za = za0;
     unsigned o = L.base + row_off(za0, g.pitch), oh = L.hbase + row_off(za0, g.pitch);
-    Queue<U> c;   // u^n at rows za-4 .. za+U+3
-    Queue<U> b;   // u^{n+1} at rows za-8 .. za+U-1
+    float c[4][4];   // u^n: blocks k-1, k, k+1 in use, k+2 arriving
+    float b[4][4];   // u^{n+1} of step one: blocks k-2, k-1, k
+    float kp[4][4];  // Kp: block k-1 (step two), k (step one), k+1 arriving
+    float p[2][4];   // u^{n-1}: block k, k+1 arriving
+    float h[2][4];   // x-halo of u^n (lanes 0-7): block k, k+1 arriving
 #pragma unroll
-    for (int i = 0; i < U + 8; ++i) b.q[i] = 0.0f;
-    queue_prime(c, UR, o, rb);
-    float pv[U], kv[U], hv[U], kb[U];
-    rows_fetch(pv, UP, o, rb);
-    rows_fetch(kv, KR, o, rb);
-    rows_fetch(hv, UR, oh, rb);
+    for (int i = 0; i < 4; ++i) {
+        c[3][i] = bld(UR, o + (unsigned)(i - 4) * rb);
+        c[0][i] = bld(UR, o + (unsigned)i * rb);
+        c[1][i] = bld(UR, o + (unsigned)(4 + i) * rb);
+        kp[3][i] = 0.0f;
 #pragma unroll
-    for (int j = 0; j < U; ++j) kb[j] = 0.0f;
-    for (int za = za0; za < zend; za += U, o += U * rb, oh += U * rb) {
-        float nq[U], npv[U], nkv[U], nhv[U];
-        queue_fetch(nq, UR, o, rb);
-        rows_fetch(npv, UP, o + U * rb, rb);
-        rows_fetch(nkv, KR, o + U * rb, rb);
-        rows_fetch(nhv, UR, oh + U * rb, rb);
-        stage(rowsA, c, hv, lane, L.hslot);
-        // step one at rows za .. za+U-1, all lanes
+        for (int r = 0; r < 4; ++r) b[r][i] = 0.0f;
+    }
+    rows_fetch(p[0], UP, o, rb);
+    rows_fetch(kp[0], KR, o, rb);
+    rows_fetch(h[0], UR, oh, rb);
+
+    auto block = [&](auto KC) __attribute__((always_inline)) {
+        using S = Blk<decltype(KC)::value>;
+        // the next block's rows
 #pragma unroll
-        for (int j = 0; j < U; ++j) {
+        for (int i = 0; i < 4; ++i) c[S::ahead][i] = bld(UR, o + (unsigned)(8 + i) * rb);
+        rows_fetch(p[S::odd], UP, o + 4 * rb, rb);
+        rows_fetch(kp[S::next], KR, o + 4 * rb, rb);
+        rows_fetch(h[S::odd], UR, oh + 4 * rb, rb);
+        float q[12];
+        window(q, c[S::prev], c[S::cur], c[S::next]);
+        stage_w(rowsA, q, h[S::even], lane, L.hslot);
+        if (is_fast(fast, za, t.z0)) {
+            // with A = B = 1 the leapfrog update would otherwise fuse Kp*acc
+            // into the subtraction and skip the rounding of q-hat
+#pragma clang fp contract(off)
+            const unsigned os = o | own_mask;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float acc = lap8p(q + j + 4, rowsA + j * 72 + 4 + lane);
+                const float qh = kp[S::cur][j] * acc;
+                const float un = fmaf(2.0f, q[j + 4], fmaf(-1.0f, p[S::even][j], qh));
+                b[S::cur][j] = un;
+                bst_row(O1, os, (unsigned)j * rb, un);
+                if (kRecompute) bst_row(Q0, os, (unsigned)j * rb, qh);
+            }
+            float v[12];
+            window(v, b[S::ahead], b[S::prev], b[S::cur]);
+            stage_c(rowsB, v, lane);
+            const unsigned os2 = os - 4u * rb;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float acc = lap8p(v + j + 4, rowsB + j * 72 + 4 + lane);
+                const float qh = kp[S::prev][j] * acc;
+                const float un = fmaf(2.0f, v[j + 4], fmaf(-1.0f, q[j], qh));
+                bst_row(O2, os2, (unsigned)j * rb, un);
+                if (kRecompute) bst_row(Q1, os2, (unsigned)j * rb, qh);
+            }
+            za += 4;
+            o += 4 * rb;
+            oh += 4 * rb;
+            return;
+        }
+        // step one at rows za .. za+3, all lanes
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
             const int z = za + j;
-            float acc = lap8(c, j, rowsA + j * 72, lane);
+            float acc = lap8p(q + j + 4, rowsA + j * 72 + 4 + lane);
             if (z == sn.x && L.xc == sn.y) acc += w0;
             float A, B;
             sponge_ab(g, L, z, A, B);
-            const float qh = kv[j] * acc;
-            const float un = fmaf(2.0f * A, c.q[j + 4], fmaf(-B, pv[j], qh));
-            b.q[8 + j] = un;
+            const float qh = kp[S::cur][j] * acc;
+            const float un = fmaf(2.0f * A, q[j + 4], fmaf(-B, p[S::even][j], qh));
+            b[S::cur][j] = un;
             if (z >= t.z0 && z < t.z1) {
                 const unsigned oz = (o + (unsigned)j * rb) | own_mask;
                 if (ck0) {
-                    bst(C0U, oz, c.q[j + 4]);
-                    bst(C0P, oz, pv[j]);
+                    bst(C0U, oz, q[j + 4]);
+                    bst(C0P, oz, p[S::even][j]);
                 }
                 if (ck1) {
                     bst(C1U, oz, un);
-                    bst(C1P, oz, c.q[j + 4]);
+                    bst(C1P, oz, q[j + 4]);
                 }
                 bst(O1, oz, un);
                 if (kRecompute) bst(Q0, oz, qh);
@@ -651,17 +788,19 @@ __global__ __launch_bounds__(256) void k_fwd_step2(const TileRec* __restrict__ t
         }
         // step two at rows za-4 .. za-1
         if (two && za - 4 >= t.z0) {
-            stage2(rowsB, b, lane);
+            float v[12];
+            window(v, b[S::ahead], b[S::prev], b[S::cur]);
+            stage_c(rowsB, v, lane);
 #pragma unroll
-            for (int j = 0; j < U; ++j) {
+            for (int j = 0; j < 4; ++j) {
                 const int z = za - 4 + j;
                 if (z >= t.z1) break;
-                float acc = lap8(b, j, rowsB + j * 72, lane);
+                float acc = lap8p(v + j + 4, rowsB + j * 72 + 4 + lane);
                 if (z == sn.x && L.xc == sn.y) acc += w1;
                 float A, B;
                 sponge_ab(g, L, z, A, B);
-                const float qh = kb[j] * acc;
-                const float un = fmaf(2.0f * A, b.q[j + 4], fmaf(-B, c.q[j], qh));
+                const float qh = kp[S::prev][j] * acc;
+                const float un = fmaf(2.0f * A, v[j + 4], fmaf(-B, q[j], qh));
                 const unsigned oz = (o + (unsigned)j * rb - 4u * rb) | own_mask;
                 bst(O2, oz, un);
                 if (kRecompute) bst(Q1, oz, qh);
@@ -671,13 +810,18 @@ __global__ __launch_bounds__(256) void k_fwd_step2(const TileRec* __restrict__ t
                 }
             }
         }
-        queue_advance(c, nq);
-#pragma unroll
-        for (int i = 0; i < 8; ++i) b.q[i] = b.q[i + U];
-        rows_copy(kb, kv);
-        rows_copy(pv, npv);
-        rows_copy(kv, nkv);
-        rows_copy(hv, nhv);
+        za += 4;
+        o += 4 * rb;
+        oh += 4 * rb;
+    };
+    while (za < zend) {
+        block(IC<0>{});
+        if (za >= zend) break;
+        block(IC<1>{});
+        if (za >= zend) break;
+        block(IC<2>{});
+        if (za >= zend) break;
+        block(IC<3>{});
     }
 }
 
@@ -687,6 +831,7 @@ __global__ __launch_bounds__(256) void k_fwd_step2(const TileRec* __restrict__ t
 template <int U>
 __global__ __launch_bounds__(256) void k_adj_step2(const TileRec* __restrict__ tiles, int ntiles,
                                                    const Inst* __restrict__ insts, StepArgs a) {
+    static_assert(U == 4, "the two-step register rings hold 4-row blocks");
     __shared__ float lds[kWaves][2 * U * 72];
     const Tile t = decode_tile(tiles, ntiles);
     if (!t.live) return;
@@ -726,44 +871,87 @@ __global__ __launch_bounds__(256) void k_adj_step2(const TileRec* __restrict__ t
     const unsigned rb = (unsigned)g.pitch * 4u;
     const unsigned own_mask = L.own ? 0u : kOut;
     const FrameRows fr = frame_rowmap(rm, g, t);
+    const FastRows fast = fast_rows(g, t, L, fr, -1, two);
 
     const int za0 = t.z0 - 4;
     const int zend = two ? t.z1 + 4 : t.z1;
+    int za = za0;
     unsigned o = L.base + row_off(za0, g.pitch), oh = L.hbase + row_off(za0, g.pitch);
-    Queue<U> c;   // lam^{n+1} at rows za-4 .. za+U+3
-    Queue<U> b;   // lam^n at rows za-8 .. za+U-1
+    float c[4][4];   // lam^{n+1}: blocks k-1, k, k+1 in use, k+2 arriving
+    float b[4][4];   // lam^n of step one: blocks k-2, k-1, k
+    float kp[4][4];  // Kp: block k-1 (step two), k (step one), k+1 arriving
+    float p[2][4];   // lam^{n+2}: block k, k+1 arriving
+    float h[2][4];   // x-halo of lam^{n+1} (lanes 0-7)
+    float ia[2][4], ib[2][4], ig[2][4];  // q^n, q^{n-1}, image at step two's rows of this block / the next
 #pragma unroll
-    for (int i = 0; i < U + 8; ++i) b.q[i] = 0.0f;
-    queue_prime(c, UR, o, rb);
-    float pv[U], kv[U], hv[U], kb[U], qav[U], qbv[U], gv[U];
-    rows_fetch(pv, UP, o, rb);
-    rows_fetch(kv, KR, o, rb);
-    rows_fetch(hv, UR, oh, rb);
+    for (int i = 0; i < 4; ++i) {
+        c[3][i] = bld(UR, o + (unsigned)(i - 4) * rb);
+        c[0][i] = bld(UR, o + (unsigned)i * rb);
+        c[1][i] = bld(UR, o + (unsigned)(4 + i) * rb);
+        kp[3][i] = 0.0f;
+        ia[0][i] = ib[0][i] = ig[0][i] = 0.0f;
 #pragma unroll
-    for (int j = 0; j < U; ++j) kb[j] = qav[j] = qbv[j] = gv[j] = 0.0f;
-    for (int za = za0; za < zend; za += U, o += U * rb, oh += U * rb) {
-        float nq[U], npv[U], nkv[U], nhv[U], nqa[U], nqb[U], ngv[U];
-        queue_fetch(nq, UR, o, rb);
-        rows_fetch(npv, UP, o + U * rb, rb);
-        rows_fetch(nkv, KR, o + U * rb, rb);
-        rows_fetch(nhv, UR, oh + U * rb, rb);
-        // image operands of rows za .. za+U-1 (step two's rows of the next block)
+        for (int rr = 0; rr < 4; ++rr) b[rr][i] = 0.0f;
+    }
+    rows_fetch(p[0], UP, o, rb);
+    rows_fetch(kp[0], KR, o, rb);
+    rows_fetch(h[0], UR, oh, rb);
+
+    auto block = [&](auto KC) __attribute__((always_inline)) {
+        using S = Blk<decltype(KC)::value>;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) c[S::ahead][i] = bld(UR, o + (unsigned)(8 + i) * rb);
+        rows_fetch(p[S::odd], UP, o + 4 * rb, rb);
+        rows_fetch(kp[S::next], KR, o + 4 * rb, rb);
+        rows_fetch(h[S::odd], UR, oh + 4 * rb, rb);
+        // image operands of rows za .. za+3 (step two's rows of the next block)
         if (two) {
-            rows_fetch(nqa, QA, o, rb);
-            rows_fetch(nqb, QB, o, rb);
-            rows_fetch(ngv, GI, o, rb);
+            rows_fetch(ia[S::odd], QA, o, rb);
+            rows_fetch(ib[S::odd], QB, o, rb);
+            rows_fetch(ig[S::odd], GI, o, rb);
         }
-        stage(rowsA, c, hv, lane, L.hslot);
+        float q[12];
+        window(q, c[S::prev], c[S::cur], c[S::next]);
+        stage_w(rowsA, q, h[S::even], lane, L.hslot);
+        if (is_fast(fast, za, t.z0)) {
+            // with A = B = 1 the leapfrog update would otherwise fuse Kp*acc
+            // into the subtraction and skip the rounding of q-hat
+#pragma clang fp contract(off)
+            const unsigned os = o | own_mask;
 #pragma unroll
-        for (int j = 0; j < U; ++j) {
+            for (int j = 0; j < 4; ++j) {
+                const float acc = lap8p(q + j + 4, rowsA + j * 72 + 4 + lane);
+                const float ln = fmaf(2.0f, q[j + 4], fmaf(-1.0f, p[S::even][j], kp[S::cur][j] * acc));
+                b[S::cur][j] = ln;
+                bst_row(O1, os, (unsigned)j * rb, ln);
+            }
+            float v[12];
+            window(v, b[S::ahead], b[S::prev], b[S::cur]);
+            stage_c(rowsB, v, lane);
+            const unsigned os2 = os - 4u * rb;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float acc = lap8p(v + j + 4, rowsB + j * 72 + 4 + lane);
+                const float lm = fmaf(2.0f, v[j + 4], fmaf(-1.0f, q[j], kp[S::prev][j] * acc));
+                bst_row(O2, os2, (unsigned)j * rb, lm);
+                bst_row(GI, os2, (unsigned)j * rb,
+                        fmaf(lm, ib[S::even][j], fmaf(v[j + 4], ia[S::even][j], ig[S::even][j])));
+            }
+            za += 4;
+            o += 4 * rb;
+            oh += 4 * rb;
+            return;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
             const int z = za + j;
-            float acc = lap8(c, j, rowsA + j * 72, lane);
+            float acc = lap8p(q + j + 4, rowsA + j * 72 + 4 + lane);
             const int slot = frame_slot(fr, z, t.z0);
             if (slot >= 0 && L.xin) acc = fmaf(-h2, injected(rm, g, t.s, slot, L.xc, r, nt, n), acc);
             float A, B;
             sponge_ab(g, L, z, A, B);
-            const float ln = fmaf(2.0f * A, c.q[j + 4], fmaf(-B, pv[j], kv[j] * acc));
-            b.q[8 + j] = ln;
+            const float ln = fmaf(2.0f * A, q[j + 4], fmaf(-B, p[S::even][j], kp[S::cur][j] * acc));
+            b[S::cur][j] = ln;
             if (z >= t.z0 && z < t.z1) {
                 const unsigned oz = (o + (unsigned)j * rb) | own_mask;
                 bst(O1, oz, ln);
@@ -771,34 +959,36 @@ __global__ __launch_bounds__(256) void k_adj_step2(const TileRec* __restrict__ t
             }
         }
         if (two && za - 4 >= t.z0) {
-            stage2(rowsB, b, lane);
+            float v[12];
+            window(v, b[S::ahead], b[S::prev], b[S::cur]);
+            stage_c(rowsB, v, lane);
 #pragma unroll
-            for (int j = 0; j < U; ++j) {
+            for (int j = 0; j < 4; ++j) {
                 const int z = za - 4 + j;
                 if (z >= t.z1) break;
-                float acc = lap8(b, j, rowsB + j * 72, lane);
+                float acc = lap8p(v + j + 4, rowsB + j * 72 + 4 + lane);
                 const int slot = frame_slot(fr, z, t.z0);
                 if (slot >= 0 && L.xin) acc = fmaf(-h2, injected(rm, g, t.s, slot, L.xc, r, nt, n - 1), acc);
                 float A, B;
                 sponge_ab(g, L, z, A, B);
-                const float lm = fmaf(2.0f * A, b.q[j + 4], fmaf(-B, c.q[j], kb[j] * acc));
+                const float lm = fmaf(2.0f * A, v[j + 4], fmaf(-B, q[j], kp[S::prev][j] * acc));
                 const unsigned oz = (o + (unsigned)j * rb - 4u * rb) | own_mask;
                 bst(O2, oz, lm);
-                bst(GI, oz, fmaf(lm, qbv[j], fmaf(b.q[j + 4], qav[j], gv[j])));
+                bst(GI, oz, fmaf(lm, ib[S::even][j], fmaf(v[j + 4], ia[S::even][j], ig[S::even][j])));
             }
         }
-        queue_advance(c, nq);
-#pragma unroll
-        for (int i = 0; i < 8; ++i) b.q[i] = b.q[i + U];
-        rows_copy(kb, kv);
-        rows_copy(pv, npv);
-        rows_copy(kv, nkv);
-        rows_copy(hv, nhv);
-        if (two) {
-            rows_copy(qav, nqa);
-            rows_copy(qbv, nqb);
-            rows_copy(gv, ngv);
-        }
+        za += 4;
+        o += 4 * rb;
+        oh += 4 * rb;
+    };
+    while (za < zend) {
+        block(IC<0>{});
+        if (za >= zend) break;
+        block(IC<1>{});
+        if (za >= zend) break;
+        block(IC<2>{});
+        if (za >= zend) break;
+        block(IC<3>{});
     }
 }
 
@@ -882,13 +1072,7 @@ __global__ __launch_bounds__(256) void k_born_step(const TileRec* __restrict__ t
             bst(UO, oz, un);
             bst(DO, oz, dn);
             const int slot = __builtin_amdgcn_readlane(my_rm, z - t.z0);
-            if (slot >= 0 && L.xin) {
-                int ri = rm.xmap[((long long)t.s * rm.nrr + slot) * g.pitch + L.x];
-                while (ri >= 0) {
-                    d[((long long)t.s * nt + n) * rm.R + ri] = dn;
-                    ri = rm.next[t.s * rm.R + ri];
-                }
-            }
+            if (slot >= 0 && L.xin) sample(rm, g, t.s, slot, L.x, d, nt, n, dn);
         }
         queue_advance(c, nq);
         queue_advance(e, ne);
