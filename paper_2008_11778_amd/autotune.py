@@ -6,7 +6,7 @@ record (same grid and shots, few time steps), separately for the forward,
 recompute, adjoint and Born steps, with one and with two time steps per
 launch and with both tile orders (x-tiles of a strip adjacent, or strips of
 a column adjacent).  Per kernel the fastest (mode, height, order) per time
-step is kept; the forward, recompute and adjoint choose their modes
+step is kept, ties within 2 % going to the tallest strips; the forward, recompute and adjoint choose their modes
 independently.  The choice is cached in a JSON file; shapes measured on
 MI355X for the common grid classes ship with the package (a tuning table
 like a library's performance database) and are used when the user cache has
@@ -24,6 +24,7 @@ import numpy as np
 CANDIDATES = (8, 12, 16, 20, 24, 28, 32, 40, 48, 64)
 CANDIDATES_TWO = (16, 20, 24, 32, 40, 48, 64, 80, 96, 120)  # two-step launches (strips up to 120 rows)
 KERNELS = (0, 1, 2, 3)  # forward, recompute, adjoint, Born
+TIE = 0.02
 
 
 def _short(geom, nt):
@@ -112,6 +113,14 @@ def tune(geom, m, candidates=CANDIDATES, nt=48, use_cache=True, verbose=False) -
                     if row:
                         print(f"autotune {key} {'two' if mode else 'one'}-step kernel {k} order {order} (per step): "
                               f"{row}", flush=True)
+    # within TIE of the fastest shape of a mode, take the tallest strips:
+    # the same speed within timing noise, less halo re-reading
+    for (tb, k), (t_best, _, _) in list(best.items()):
+        near = [(rows, -order, order) for (tb2, order, rows, k2), per in table.items()
+                if tb2 == tb and k2 == k and per <= t_best * (1 + TIE)]
+        if near:
+            rows, _, order = max(near)
+            best[(tb, k)] = (table[(tb, order, rows, k)], rows, order)
     out = {}
     for k in KERNELS:
         two = k < 3 and best[(True, k)][0] < best[(False, k)][0]
