@@ -56,25 +56,67 @@ enum ConvMode { kHidden = 0, kLast = 1, kInputGrad = 2 };
 // k = tap * C + c, cut into chunks of 32: lane group g of a fragment holds
 // k = 32 ch + 8 g .. 8 g + 7, i.e. 8 consecutive channels of one tap.  w is
 // [tap][NOUT][C] bf16; every wave keeps all its weight fragments in
-// registers.  A block of four waves walks 64-pixel row segments with a grid
-// stride: it stages input rows y-1 .. y+1 over columns x0-1 .. x0+64 (zeros
-// outside the image) in LDS once, and wave w takes pixels x0+16w .. x0+16w+15,
-// reading each A fragment as one 16-byte LDS load.
+// registers.  A block of four waves owns a 64-pixel-wide column segment of
+// one image over a run of rows and walks down it: a 3-row LDS ring holds
+// input rows y-1 .. y+1 (columns x0-1 .. x0+64, zeros outside the image),
+// each output row adds one new input row, and the row after that is fetched
+// into registers while the current row runs on the matrix cores.  Wave w
+// takes pixels x0+16w .. x0+16w+15 and reads each A fragment as one 16-byte
+// LDS load.
 constexpr int kCSeg = 64;
 
+template <int C>
+struct RowFetch {
+    static constexpr int kChunks = (kCSeg + 2) * (C / 8);  // 16-byte pieces of one staged row
+    static constexpr int kPer = (kChunks + 255) / 256;
+    v4u v[kPer];
+};
+
+// Global -> registers: input row yy over columns x0-1 .. x0+64 (zeros outside).
+template <int C>
+__device__ __forceinline__ void row_fetch(RowFetch<C>& f, const bf16* __restrict__ x, int bimg, int H, int W,
+                                          int yy, int x0) {
+#pragma unroll
+    for (int k = 0; k < RowFetch<C>::kPer; ++k) {
+        const int e = threadIdx.x + 256 * k;
+        const int cg = e % (C / 8), j = e / (C / 8);
+        const int xx = x0 - 1 + j;
+        v4u v = v4u{0u, 0u, 0u, 0u};
+        if (e < RowFetch<C>::kChunks && yy >= 0 && yy < H && xx >= 0 && xx < W)
+            v = *reinterpret_cast<const v4u*>(x + ((long long)(bimg * H + yy) * W + xx) * C + cg * 8);
+        f.v[k] = v;
+    }
+}
+
+// Registers -> LDS row (pixel stride CS).
+template <int C, int CS>
+__device__ __forceinline__ void row_store(const RowFetch<C>& f, bf16* row) {
+#pragma unroll
+    for (int k = 0; k < RowFetch<C>::kPer; ++k) {
+        const int e = threadIdx.x + 256 * k;
+        const int cg = e % (C / 8), j = e / (C / 8);
+        if (e < RowFetch<C>::kChunks) *reinterpret_cast<v4u*>(row + j * CS + cg * 8) = f.v[k];
+    }
+}
+
 template <int C, int NOUT, int MODE>
-__global__ __launch_bounds__(256) void k_conv_mm(int B, int H, int W, const bf16* __restrict__ x,
+__global__ __launch_bounds__(256) void k_conv_mm(int B, int H, int W, int rows, const bf16* __restrict__ x,
                                                  const bf16* __restrict__ w, const bf16* __restrict__ mask,
                                                  bf16* __restrict__ y, float* __restrict__ z) {
     constexpr int NCH = (9 * C + 31) / 32;
     constexpr int NT = NOUT / 16;
     constexpr int sgn = MODE == kInputGrad ? -1 : 1;
-    constexpr int CS = C + 8;  // LDS pixel stride: 16-byte aligned rows of channels
-    __shared__ __align__(16) bf16 xL[3 * (kCSeg + 2) * CS];
+    constexpr int CS = C + 8;                // LDS pixel stride: 16-byte aligned rows of channels
+    constexpr int RW = (kCSeg + 2) * CS;     // one staged row
+    static_assert(MODE == kLast || NOUT == 32, "hidden and input-gradient layers have 32 outputs");
+    constexpr int TS = NOUT + 8;             // transpose tile pixel stride
+    __shared__ __align__(16) bf16 xL[3 * RW];
+    __shared__ __align__(16) bf16 tL[4][16 * TS];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int i = lane & 15, grp = lane >> 4;
     bf8 bw[NCH][NT];
-    int lofs[NCH];  // LDS element offset of this lane's A fragment, relative to the pixel's centre tap
+    int rsel[NCH];  // input row of this lane's A fragment relative to the output row, + 1
+    int cofs[NCH];  // element offset inside a staged row, relative to the pixel
     bool tap_ok[NCH];
 #pragma unroll
     for (int ch = 0; ch < NCH; ++ch) {
@@ -82,58 +124,83 @@ __global__ __launch_bounds__(256) void k_conv_mm(int B, int H, int W, const bf16
         const int tap = k0 / C, c0 = k0 % C;
         tap_ok[ch] = tap < 9;
         const int dyo = sgn * (tap / 3 - 1), dxo = sgn * (tap % 3 - 1);
-        lofs[ch] = ((dyo + 1) * (kCSeg + 2) + 1 + dxo) * CS + c0;
+        rsel[ch] = dyo + 1;
+        cofs[ch] = (1 + dxo) * CS + c0;
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt)
             bw[ch][nt] = tap_ok[ch] ? ld8(w + ((tap * NOUT + nt * 16 + i) * C + c0)) : zero8();
     }
     const int segs_x = (W + kCSeg - 1) / kCSeg;
-    const int nseg = B * H * segs_x;
-    for (int seg = blockIdx.x; seg < nseg; seg += gridDim.x) {
-        const int sx = seg % segs_x, rowi = seg / segs_x;
-        const int yy0 = rowi % H, bimg = rowi / H;
-        const int x0 = sx * kCSeg;
-        __syncthreads();
-        for (int e = threadIdx.x; e < 3 * (kCSeg + 2) * (C / 8); e += 256) {
-            const int cg = e % (C / 8), q = e / (C / 8);
-            const int j = q % (kCSeg + 2), rr = q / (kCSeg + 2);
-            const int yy = yy0 + rr - 1, xx = x0 - 1 + j;
-            v4u v = v4u{0u, 0u, 0u, 0u};
-            if (yy >= 0 && yy < H && xx >= 0 && xx < W)
-                v = *reinterpret_cast<const v4u*>(x + ((long long)(bimg * H + yy) * W + xx) * C + cg * 8);
-            *reinterpret_cast<v4u*>(xL + (rr * (kCSeg + 2) + j) * CS + cg * 8) = v;
-        }
-        __syncthreads();
-        const int px = 16 * wv + i;  // this lane's pixel in the segment (A rows)
-        v4f acc[NT];
+    const int runs = (H + rows - 1) / rows;
+    const int nwork = B * runs * segs_x;
+    const int px = 16 * wv + i;  // this lane's pixel in the segment (A rows)
+    for (int wk = blockIdx.x; wk < nwork; wk += gridDim.x) {
+        const int sx = wk % segs_x, t = wk / segs_x;
+        const int run = t % runs, bimg = t / runs;
+        const int x0 = sx * kCSeg, ya = run * rows, yb = min(H, ya + rows);
+        RowFetch<C> f;
+        __syncthreads();  // the ring's previous contents are no longer read
+        row_fetch<C>(f, x, bimg, H, W, ya - 1, x0);
+        row_store<C, CS>(f, xL + ((ya + 2) % 3) * RW);
+        row_fetch<C>(f, x, bimg, H, W, ya, x0);
+        row_store<C, CS>(f, xL + (ya % 3) * RW);
+        row_fetch<C>(f, x, bimg, H, W, ya + 1, x0);
+        for (int yy = ya; yy < yb; ++yy) {
+            row_store<C, CS>(f, xL + ((yy + 1) % 3) * RW);  // input row yy+1 into the slot of row yy-2
+            __syncthreads();
+            if (yy + 1 < yb) row_fetch<C>(f, x, bimg, H, W, yy + 2, x0);  // in flight during the products
+            const int base[3] = {((yy + 2) % 3) * RW, (yy % 3) * RW, ((yy + 1) % 3) * RW};
+            v4f acc[NT];
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) acc[nt] = v4f{0.f, 0.f, 0.f, 0.f};
+            for (int nt = 0; nt < NT; ++nt) acc[nt] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int ch = 0; ch < NCH; ++ch) {
-            const bf8 a = tap_ok[ch] ? __builtin_bit_cast(bf8, *reinterpret_cast<const v4u*>(xL + lofs[ch] + px * CS))
-                                     : zero8();
+            for (int ch = 0; ch < NCH; ++ch) {
+                const int off = (rsel[ch] == 0 ? base[0] : rsel[ch] == 1 ? base[1] : base[2]) + cofs[ch] + px * CS;
+                const bf8 a = tap_ok[ch] ? __builtin_bit_cast(bf8, *reinterpret_cast<const v4u*>(xL + off)) : zero8();
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt)
-                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[ch][nt], acc[nt], 0, 0, 0);
-        }
-        // lane holds D[4 grp + r][i]: pixel 16 wv + 4 grp + r of the segment, output channel nt*16 + i
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int xx = x0 + 16 * wv + 4 * grp + r;
-            if (xx >= W) continue;
-            const long long pp = (long long)rowi * W + xx;
+                for (int nt = 0; nt < NT; ++nt)
+                    acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[ch][nt], acc[nt], 0, 0, 0);
+            }
+            // lane holds D[4 grp + r][i]: pixel 16 wv + 4 grp + r of the segment, output channel nt*16 + i
+            const long long rowp = (long long)(bimg * H + yy) * W;
             if (MODE == kLast) {
-                if (i == 0) z[pp] = acc[0][r];
-            } else {
 #pragma unroll
-                for (int nt = 0; nt < NT; ++nt) {
-                    const long long o = pp * NOUT + nt * 16 + i;
-                    if (MODE == kHidden)
-                        y[o] = f2bf(fmaxf(acc[nt][r], 0.f));
-                    else
-                        y[o] = bf2f(mask[o]) > 0.f ? f2bf(acc[nt][r]) : (bf16)0;
+                for (int r = 0; r < 4; ++r) {
+                    const int xx = x0 + 16 * wv + 4 * grp + r;
+                    if (xx < W && i == 0) z[rowp + xx] = acc[0][r];
+                }
+            } else {
+                // through the wave's LDS tile to one 16-byte store (8 channels of one pixel) per lane
+                bf16* tw = tL[wv];
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt)
+                        tw[(4 * grp + r) * TS + nt * 16 + i] =
+                            f2bf(MODE == kHidden ? fmaxf(acc[nt][r], 0.f) : acc[nt][r]);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                const int p = lane >> 2, cg = lane & 3;
+                const int xx = x0 + 16 * wv + p;
+                if (xx < W) {
+                    v4u v = *reinterpret_cast<const v4u*>(tw + p * TS + cg * 8);
+                    const long long o = (rowp + xx) * NOUT + cg * 8;
+                    if (MODE == kInputGrad) {
+                        // keep the gradient where the layer input (post-ReLU) is positive
+                        const v4u mk = *reinterpret_cast<const v4u*>(mask + o);
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const unsigned lo = mk[q] & 0xffffu, hi = mk[q] >> 16;
+                            const unsigned keep = (bf2f((bf16)lo) > 0.f ? 0xffffu : 0u) |
+                                                  (bf2f((bf16)hi) > 0.f ? 0xffff0000u : 0u);
+                            v[q] &= keep;
+                        }
+                    }
+                    *reinterpret_cast<v4u*>(y + o) = v;
                 }
             }
+            __syncthreads();  // every wave is done with row yy-1's slot and its transpose tile
         }
     }
 }
@@ -493,10 +560,14 @@ void pack_weights(aafwi_cnn* c) {
 template <int C, int NOUT, int MODE>
 void conv(aafwi_cnn* c, int B, const aafwi::bf16* x, const aafwi::bf16* w, const aafwi::bf16* mask, aafwi::bf16* y,
           float* z) {
-    const int nseg = B * c->H * ((c->W + aafwi::kCSeg - 1) / aafwi::kCSeg);
-    const int blocks = std::min(nseg, 2048);
-    hipLaunchKernelGGL((aafwi::k_conv_mm<C, NOUT, MODE>), dim3(blocks), dim3(256), 0, c->stream, B, c->H, c->W, x, w,
-                       mask, y, z);
+    // runs of 16 rows, shorter when that leaves fewer than ~2 blocks per CU
+    const int segs = B * ((c->W + aafwi::kCSeg - 1) / aafwi::kCSeg);
+    int rows = 16;
+    while (rows > 4 && segs * ((c->H + rows - 1) / rows) < 512) rows /= 2;
+    const int nwork = segs * ((c->H + rows - 1) / rows);
+    const int blocks = std::min(nwork, 2048);
+    hipLaunchKernelGGL((aafwi::k_conv_mm<C, NOUT, MODE>), dim3(blocks), dim3(256), 0, c->stream, B, c->H, c->W, rows,
+                       x, w, mask, y, z);
 }
 
 void weight_reduce(aafwi_cnn* c, int nchunk, int coutp, int cinp, int layer) {
