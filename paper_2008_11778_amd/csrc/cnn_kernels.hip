@@ -207,16 +207,20 @@ __global__ __launch_bounds__(256) void k_conv_mm(int B, int H, int W, int rows, 
 
 // Weight gradient: part[block][tap][co][ci] = sum over the block's pixels p of
 // dy[p][co] x[p + off(tap)][ci] (FP32 partials, summed over blocks in a fixed
-// order by the reduction below).  A block of three waves takes 32-pixel row
-// segments (b, y, x0..x0+31) with a grid stride: it stages dy of the segment
-// and the input rows y-1, y, y+1 over columns x0-1 .. x0+32 (zeros outside
-// the image) in LDS, and wave r accumulates the three taps of tap row r as
-// GEMMs over the segment's pixels on v_mfma_f32_16x16x32_bf16: A = dy^T
-// (co x pixels), B = x shifted by the tap (pixels x ci).  A fragment takes 8
-// consecutive pixels of one channel: the LDS pixel stride is padded by two
-// channels so that those gathers do not collide in the LDS banks.
+// order by the reduction below).  A block of three waves owns a 32-pixel
+// column segment of one image over a run of rows and walks down it: a 3-row
+// LDS ring holds input rows y-1 .. y+1 (columns x0-1 .. x0+32, zeros outside
+// the image), dy of row y sits beside it, and the next rows of x and dy are
+// fetched into registers while the current row runs on the matrix cores.
+// Wave r accumulates the three taps of tap row r as GEMMs over the row's
+// pixels on v_mfma_f32_16x16x32_bf16: A = dy^T (co x pixels), B = x shifted
+// by the tap (pixels x ci).  A fragment takes 8 consecutive pixels of one
+// channel: the LDS pixel stride is padded by two channels so that those
+// gathers do not collide in the LDS banks.  Blocks take (image, row run,
+// segment) items with a grid stride and keep accumulating across them.
 constexpr int kSeg = 32;
 constexpr int kWgradMaxBlocks = 1024;
+constexpr int kWgradRows = 16;
 
 template <int C>
 __device__ __forceinline__ bf8 gather8(const bf16* base) {  // base[s * (C + 2)], s = 0..7
@@ -227,16 +231,49 @@ __device__ __forceinline__ bf8 gather8(const bf16* base) {  // base[s * (C + 2)]
     return __builtin_bit_cast(bf8, v);
 }
 
+// One staged row of NPX pixels x C channels as 16-byte pieces, one per thread
+// of the 192-thread block (NPX * C / 8 <= 192).
+template <int C, int NPX>
+struct WRow {
+    static_assert(NPX * (C / 8) <= 192, "one piece per thread");
+    v4u v;
+};
+
+template <int C, int NPX>
+__device__ __forceinline__ void wrow_fetch(WRow<C, NPX>& f, const bf16* __restrict__ src, int bimg, int H, int W,
+                                           int yy, int xs) {
+    const int e = threadIdx.x;
+    const int cg = e % (C / 8), j = e / (C / 8);
+    const int xx = xs + j;
+    v4u v = v4u{0u, 0u, 0u, 0u};
+    if (e < NPX * (C / 8) && yy >= 0 && yy < H && xx >= 0 && xx < W)
+        v = *reinterpret_cast<const v4u*>(src + ((long long)(bimg * H + yy) * W + xx) * C + cg * 8);
+    f.v = v;
+}
+
+template <int C, int NPX>
+__device__ __forceinline__ void wrow_store(const WRow<C, NPX>& f, bf16* row) {
+    const int e = threadIdx.x;
+    const int cg = e % (C / 8), j = e / (C / 8);
+    if (e < NPX * (C / 8)) {
+        unsigned* dst = reinterpret_cast<unsigned*>(row + j * (C + 2) + cg * 8);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) dst[k] = f.v[k];
+    }
+}
+
 template <int CIN, int COUT>
 __global__ __launch_bounds__(192) void k_conv_wgrad(int B, int H, int W, const bf16* __restrict__ dy,
                                                    const bf16* __restrict__ x, float* __restrict__ part) {
+    constexpr int XR = (kSeg + 2) * (CIN + 2);  // one staged x row
     __shared__ bf16 dyL[kSeg * (COUT + 2)];
-    __shared__ bf16 xL[3 * (kSeg + 2) * (CIN + 2)];
+    __shared__ bf16 xL[3 * XR];
     constexpr int MT = COUT / 16, NT = CIN / 16;
     const int lane = threadIdx.x & 63, r = threadIdx.x >> 6;  // r: tap row (dy offset r - 1)
     const int i = lane & 15, grp = lane >> 4;
     const int segs_x = (W + kSeg - 1) / kSeg;
-    const int nseg = B * H * segs_x;
+    const int runs = (H + kWgradRows - 1) / kWgradRows;
+    const int nwork = B * runs * segs_x;
     v4f acc[3][MT][NT];
 #pragma unroll
     for (int d = 0; d < 3; ++d)
@@ -244,47 +281,43 @@ __global__ __launch_bounds__(192) void k_conv_wgrad(int B, int H, int W, const b
         for (int a = 0; a < MT; ++a)
 #pragma unroll
             for (int b = 0; b < NT; ++b) acc[d][a][b] = v4f{0.f, 0.f, 0.f, 0.f};
-    for (int seg = blockIdx.x; seg < nseg; seg += gridDim.x) {
-        const int sx = seg % segs_x, rowi = seg / segs_x;  // rowi = b * H + y
-        const int y = rowi % H, bimg = rowi / H;
-        const int x0 = sx * kSeg;
-        __syncthreads();  // the previous segment's LDS reads are done
-        // dy of the segment: 32 pixels x COUT/8 groups of 8 channels
-        for (int e = threadIdx.x; e < kSeg * (COUT / 8); e += 192) {
-            const int px = e / (COUT / 8), cg = e % (COUT / 8);
-            const int xx = x0 + px;
-            v4u v = v4u{0u, 0u, 0u, 0u};
-            if (xx < W) v = *reinterpret_cast<const v4u*>(dy + ((long long)rowi * W + xx) * COUT + cg * 8);
-            unsigned* dst = reinterpret_cast<unsigned*>(dyL + px * (COUT + 2) + cg * 8);
-#pragma unroll
-            for (int k = 0; k < 4; ++k) dst[k] = v[k];
-        }
-        // x rows y-1 .. y+1, columns x0-1 .. x0+32
-        for (int e = threadIdx.x; e < 3 * (kSeg + 2) * (CIN / 8); e += 192) {
-            const int cg = e % (CIN / 8), q = e / (CIN / 8);
-            const int j = q % (kSeg + 2), rr = q / (kSeg + 2);
-            const int yy = y + rr - 1, xx = x0 - 1 + j;
-            v4u v = v4u{0u, 0u, 0u, 0u};
-            if (yy >= 0 && yy < H && xx >= 0 && xx < W)
-                v = *reinterpret_cast<const v4u*>(x + ((long long)(bimg * H + yy) * W + xx) * CIN + cg * 8);
-            unsigned* dst = reinterpret_cast<unsigned*>(xL + (rr * (kSeg + 2) + j) * (CIN + 2) + cg * 8);
-#pragma unroll
-            for (int k = 0; k < 4; ++k) dst[k] = v[k];
-        }
-        __syncthreads();
-        // K = the segment's 32 pixels, one 32-deep MFMA step per tile
-        bf8 A[MT];
-#pragma unroll
-        for (int a = 0; a < MT; ++a) A[a] = gather8<COUT>(dyL + (8 * grp) * (COUT + 2) + a * 16 + i);
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-#pragma unroll
-            for (int b = 0; b < NT; ++b) {
-                const bf8 Bf = gather8<CIN>(xL + (r * (kSeg + 2) + 8 * grp + d) * (CIN + 2) + b * 16 + i);
-#pragma unroll
-                for (int a = 0; a < MT; ++a)
-                    acc[d][a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[a], Bf, acc[d][a][b], 0, 0, 0);
+    for (int wk = blockIdx.x; wk < nwork; wk += gridDim.x) {
+        const int sx = wk % segs_x, t = wk / segs_x;
+        const int run = t % runs, bimg = t / runs;
+        const int x0 = sx * kSeg, ya = run * kWgradRows, yb = min(H, ya + kWgradRows);
+        WRow<CIN, kSeg + 2> fx;
+        WRow<COUT, kSeg> fd;
+        __syncthreads();  // the previous item's LDS reads are done
+        wrow_fetch(fx, x, bimg, H, W, ya - 1, x0 - 1);
+        wrow_store(fx, xL + ((ya + 2) % 3) * XR);
+        wrow_fetch(fx, x, bimg, H, W, ya, x0 - 1);
+        wrow_store(fx, xL + (ya % 3) * XR);
+        wrow_fetch(fx, x, bimg, H, W, ya + 1, x0 - 1);
+        wrow_fetch(fd, dy, bimg, H, W, ya, x0);
+        for (int yy = ya; yy < yb; ++yy) {
+            wrow_store(fx, xL + ((yy + 1) % 3) * XR);  // x row yy+1 into the slot of row yy-2
+            wrow_store(fd, dyL);
+            __syncthreads();
+            if (yy + 1 < yb) {  // in flight during the products
+                wrow_fetch(fx, x, bimg, H, W, yy + 2, x0 - 1);
+                wrow_fetch(fd, dy, bimg, H, W, yy + 1, x0);
             }
+            // K = the row's 32 pixels, one 32-deep MFMA step per tile
+            bf8 A[MT];
+#pragma unroll
+            for (int a = 0; a < MT; ++a) A[a] = gather8<COUT>(dyL + (8 * grp) * (COUT + 2) + a * 16 + i);
+            const bf16* xr = xL + ((yy + r + 2) % 3) * XR;  // x row yy + r - 1
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+#pragma unroll
+                for (int b = 0; b < NT; ++b) {
+                    const bf8 Bf = gather8<CIN>(xr + (8 * grp + d) * (CIN + 2) + b * 16 + i);
+#pragma unroll
+                    for (int a = 0; a < MT; ++a)
+                        acc[d][a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[a], Bf, acc[d][a][b], 0, 0, 0);
+                }
+            }
+            __syncthreads();  // every wave is done with dyL and row yy-1's slot
         }
     }
     // lane holds D[4 grp + q][i]: co = a*16 + 4 grp + q, ci = b*16 + i; tap = 3 r + d
@@ -607,8 +640,8 @@ void gradients(aafwi_cnn* c, int B, const float* g, const float* m, const float*
                        (const double*)c->st1, (const double*)c->st2, c->dlt[3]);
     if (loss) hipLaunchKernelGGL(k_loss_total, dim3(1), dim3(64), 0, c->stream, B, n, (const double*)c->st2, loss);
     AAFWI_HIP(hipGetLastError());
-    const int nseg = B * c->H * ((c->W + kSeg - 1) / kSeg);
-    const int nchunk = std::min(nseg, kWgradMaxBlocks);
+    const int nwork = B * ((c->H + kWgradRows - 1) / kWgradRows) * ((c->W + kSeg - 1) / kSeg);
+    const int nchunk = std::min(nwork, kWgradMaxBlocks);
     // layer 4 (32 -> 1): weight gradient, then the delta at layer 3's output
     hipLaunchKernelGGL((k_conv_wgrad<32, 16>), dim3(nchunk), dim3(192), 0, c->stream, B, c->H, c->W, c->dlt[3],
                        c->act[3], c->wpart);
@@ -661,8 +694,9 @@ extern "C" int aafwi_cnn_create(int32_t nz, int32_t nx, int32_t max_batch, const
             c->st_in = calloc_dev<double>(c, (size_t)max_batch * 3);
             c->st1 = calloc_dev<double>(c, (size_t)max_batch * 2);
             c->st2 = calloc_dev<double>(c, (size_t)max_batch * 2);
-            const size_t nseg = (size_t)max_batch * nz * ((nx + aafwi::kSeg - 1) / aafwi::kSeg);
-            const size_t nchunk = std::min(nseg, (size_t)aafwi::kWgradMaxBlocks);
+            const size_t nwork = (size_t)max_batch * ((nz + aafwi::kWgradRows - 1) / aafwi::kWgradRows) *
+                                 ((nx + aafwi::kSeg - 1) / aafwi::kSeg);
+            const size_t nchunk = std::min(nwork, (size_t)aafwi::kWgradMaxBlocks);
             c->wpart = calloc_dev<float>(c, nchunk * 9 * 32 * 32);
             c->gsum = calloc_dev<double>(c, (size_t)aafwi::kRedGroups * 9 * 32 * 32);
             AAFWI_HIP(hipMemcpy(c->w, weights, sizeof(float) * AAFWI_CNN_PARAMS, hipMemcpyHostToDevice));
