@@ -142,53 +142,118 @@ __device__ __forceinline__ void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Cyclic Jacobi eigen-decomposition of the symmetric n x n matrix S (row
-// stride kAACap, n <= 31), overwritten by its diagonalisation; V receives the
-// vectors.  The row and column updates of each rotation are spread over one
-// wavefront (lane k owns row and column k of S and row k of V); the
-// rotation parameters are computed by every lane from the same values.
-// Called by all 64 lanes of a single-wave block, S and V in LDS.
+// Fixed-order sum of the kReduceBlocks partial rows (row stride `stride`
+// doubles, the first NV used) by one wavefront: lane l adds rows
+// R l .. R l + R - 1 in order (R = kReduceBlocks / 64), then a butterfly
+// combines the lanes, so every lane returns the same NV sums.
+template <int NV>
+__device__ __forceinline__ void wave_partial_sums(const double* __restrict__ part, int stride, double (&acc)[NV]) {
+    static_assert(kReduceBlocks % 64 == 0, "partial rows split evenly over the lanes");
+    constexpr int R = kReduceBlocks / 64;
+    const int l = threadIdx.x & 63;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+    for (int j = 0; j < R; ++j) {
+        const double* row = part + (long long)(l * R + j) * stride;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[v] += row[v];
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = wave_reduce(acc[v]);
+}
+
+// Jacobi eigen-decomposition of the symmetric n x n matrix S (row stride
+// kAACap, n <= 31), overwritten by its diagonalisation; V receives the
+// vectors.  Parallel ordering: the indices (plus a dummy one when n is odd)
+// are paired round-robin, so each round holds n/2 disjoint (p, q) pairs and a
+// sweep of n - 1 rounds meets every pair once.  Rotations of disjoint pairs
+// commute, so a round applies all of its rotations at once: each lane
+// computes the angle of one pair from the same matrix, then the column, row
+// and vector updates are spread over the wavefront (one element pair per
+// lane and pass).  The angle and the threshold are those of the classical
+// cyclic method.  Called by all 64 lanes of a single-wave block, S and V in
+// LDS.
+
 __device__ void jacobi_eig_wave(double* S, double* V, int n) {
+    __shared__ double rc[kAACap / 2], rs[kAACap / 2];
+    __shared__ int rp[kAACap / 2], rq[kAACap / 2];
     const int k = threadIdx.x;
     if (k < n)
         for (int i = 0; i < n; ++i) V[k * kAACap + i] = (i == k) ? 1.0 : 0.0;
     wave_sync_lds();
+    const int N = n + (n & 1);  // players, with index n as the dummy when n is odd
+    const int half = N / 2;
     for (int sweep = 0; sweep < 60; ++sweep) {
         double off = 0.0, diag = 0.0;
-        for (int i = 0; i < n; ++i) {
-            diag += S[i * kAACap + i] * S[i * kAACap + i];
-            for (int j = i + 1; j < n; ++j) off += S[i * kAACap + j] * S[i * kAACap + j];
-        }
-        if (off <= 1e-32 * diag || off == 0.0) break;
-        for (int p = 0; p < n; ++p) {
-            for (int q = p + 1; q < n; ++q) {
-                const double apq = S[p * kAACap + q];
-                if (apq == 0.0) continue;
-                const double app = S[p * kAACap + p], aqq = S[q * kAACap + q];
-                const double theta = (aqq - app) / (2.0 * apq);
-                const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-                const double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
-                wave_sync_lds();
-                if (k < n) {  // columns p, q
-                    const double skp = S[k * kAACap + p], skq = S[k * kAACap + q];
-                    S[k * kAACap + p] = c * skp - sn * skq;
-                    S[k * kAACap + q] = sn * skp + c * skq;
-                }
-                wave_sync_lds();
-                if (k < n) {  // rows p, q
-                    const double spk = S[p * kAACap + k], sqk = S[q * kAACap + k];
-                    S[p * kAACap + k] = c * spk - sn * sqk;
-                    S[q * kAACap + k] = sn * spk + c * sqk;
-                }
-                wave_sync_lds();
-                if (k == 0) S[p * kAACap + q] = S[q * kAACap + p] = 0.0;
-                if (k < n) {
-                    const double vkp = V[k * kAACap + p], vkq = V[k * kAACap + q];
-                    V[k * kAACap + p] = c * vkp - sn * vkq;
-                    V[k * kAACap + q] = sn * vkp + c * vkq;
-                }
-                wave_sync_lds();
+        if (k < n)
+            for (int j = 0; j < n; ++j) {
+                const double v = S[k * kAACap + j];
+                if (j == k)
+                    diag = v * v;
+                else
+                    off += v * v;
             }
+        // butterfly sums: every lane holds the same value, so all take the same exit
+        off = wave_reduce(off);  // both triangles
+        diag = wave_reduce(diag);
+        if (off <= 2e-32 * diag || off == 0.0) break;
+        for (int r = 0; r < N - 1; ++r) {
+            if (k < half) {
+                // circle method: position 0 holds index 0, positions 1 .. N-1 rotate by r
+                const int a = (k == 0) ? 0 : 1 + (k - 1 + r) % (N - 1);
+                const int b = 1 + (N - 2 - k + r) % (N - 1);  // position N-1-k
+                int p = min(a, b), q = max(a, b);
+                double c = 1.0, sn = 0.0;
+                if (q >= n) {
+                    p = q = -1;  // paired with the dummy: no rotation
+                } else {
+                    const double apq = S[p * kAACap + q];
+                    if (apq != 0.0) {
+                        const double app = S[p * kAACap + p], aqq = S[q * kAACap + q];
+                        const double theta = (aqq - app) / (2.0 * apq);
+                        const double t =
+                            (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                        c = 1.0 / sqrt(t * t + 1.0);
+                        sn = t * c;
+                    }
+                }
+                rp[k] = p;
+                rq[k] = q;
+                rc[k] = c;
+                rs[k] = sn;
+            }
+            wave_sync_lds();
+            for (int it = k; it < n * half; it += 64) {  // columns p, q of every pair
+                const int i = it % n, m = it / n;
+                const int p = rp[m], q = rq[m];
+                if (p < 0) continue;
+                const double c = rc[m], sn = rs[m];
+                const double sip = S[i * kAACap + p], siq = S[i * kAACap + q];
+                S[i * kAACap + p] = c * sip - sn * siq;
+                S[i * kAACap + q] = sn * sip + c * siq;
+            }
+            wave_sync_lds();
+            for (int it = k; it < n * half; it += 64) {  // rows p, q of every pair
+                const int j = it % n, m = it / n;
+                const int p = rp[m], q = rq[m];
+                if (p < 0) continue;
+                const double c = rc[m], sn = rs[m];
+                const double spj = S[p * kAACap + j], sqj = S[q * kAACap + j];
+                S[p * kAACap + j] = c * spj - sn * sqj;
+                S[q * kAACap + j] = sn * spj + c * sqj;
+            }
+            wave_sync_lds();
+            if (k < half && rp[k] >= 0) S[rp[k] * kAACap + rq[k]] = S[rq[k] * kAACap + rp[k]] = 0.0;
+            for (int it = k; it < n * half; it += 64) {  // vectors
+                const int i = it % n, m = it / n;
+                const int p = rp[m], q = rq[m];
+                if (p < 0) continue;
+                const double c = rc[m], sn = rs[m];
+                const double vip = V[i * kAACap + p], viq = V[i * kAACap + q];
+                V[i * kAACap + p] = c * vip - sn * viq;
+                V[i * kAACap + q] = sn * vip + c * viq;
+            }
+            wave_sync_lds();
         }
     }
 }
@@ -200,10 +265,12 @@ __global__ __launch_bounds__(64) void k_aa_solve(AAState* s, const double* __res
     __shared__ double S[kAACap * kAACap];
     __shared__ double V[kAACap * kAACap];
     const int t = threadIdx.x;
-    if (t < 2 * CAP) {
-        double acc = 0.0;
-        for (int b = 0; b < kReduceBlocks; ++b) acc += part[(long long)b * 2 * CAP + t];
-        sums[t] = acc;
+    {
+        double acc[2 * CAP];
+        wave_partial_sums<2 * CAP>(part, 2 * CAP, acc);
+        if (t == 0)
+#pragma unroll
+            for (int v = 0; v < 2 * CAP; ++v) sums[v] = acc[v];
     }
     __shared__ int ctl[2];  // lane 0 -> wave: columns left (ndg), done flag
     __syncthreads();
@@ -500,17 +567,19 @@ __global__ __launch_bounds__(kReduceThreads) void k_qr_scale_rhs(long long n, do
     store_partials<CAP>(v, CAP, part);
 }
 
-// Fixed-order sum of the block partials into dst[0..ncol).
-__global__ void k_qr_reduce(const double* __restrict__ part, int which, AAState* s) {
-    const int t = threadIdx.x;
-    double acc = 0.0;
-    if (t < kAACap)
-        for (int b = 0; b < kReduceBlocks; ++b) acc += part[(long long)b * 2 * kAACap + t];
-    if (t >= kAACap) return;
-    if (which == 0) s->c1[t] = acc;
-    if (which == 1) s->c2[t] = acc;
-    if (which == 2 && t == 0) s->nrm2 = acc;
-    if (which == 3) s->rhs[t] = acc;
+// Fixed-order sum of the block partials (first kAACap values of each row)
+// into c1, c2, nrm2 or rhs; one wavefront.
+__global__ __launch_bounds__(64) void k_qr_reduce(const double* __restrict__ part, int which, AAState* s) {
+    double acc[kAACap];
+    wave_partial_sums<kAACap>(part, 2 * kAACap, acc);
+    if (threadIdx.x != 0) return;
+    if (which == 2) {
+        s->nrm2 = acc[0];
+        return;
+    }
+    double* dst = which == 0 ? s->c1 : which == 1 ? s->c2 : s->rhs;
+#pragma unroll
+    for (int v = 0; v < kAACap; ++v) dst[v] = acc[v];
 }
 
 // Finish the push (new column of R), apply the drop rule, solve R gamma = Q^T g_k.
