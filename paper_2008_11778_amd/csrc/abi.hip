@@ -66,7 +66,7 @@ struct Engine {
     aafwi::Inst* dinst = nullptr;
     aafwi::TileRec* dtiles[4] = {nullptr, nullptr, nullptr, nullptr};
     int ntiles[4] = {0, 0, 0, 0};
-    // two-step tables (56 output columns per wave) of forward, recompute, adjoint
+    // two-step tables (64 output columns per wave) of forward, recompute, adjoint
     aafwi::TileRec* dtiles2[3] = {nullptr, nullptr, nullptr};
     int ntiles2[3] = {0, 0, 0};
     bool tb[3] = {false, false, false};  // forward / recompute / adjoint: two steps per launch
@@ -252,14 +252,15 @@ void add_instance(Engine* e, const aafwi_geometry& G, const aafwi_batch_io* io) 
 // region c, so every XCD holds the same share of every instance (instances
 // whose records end early leave every XCD equally); regions are padded to
 // equal length with no-op tiles (inst = -1).
-std::vector<aafwi::TileRec> tile_table(Engine* e, int kid, int width) {
+std::vector<aafwi::TileRec> tile_table(Engine* e, int kid, bool two) {
+    const int width = two ? aafwi::kTile2 : 64;
     constexpr int kX = 8, kWaves = 4;
     std::vector<std::vector<aafwi::TileRec>> region(kX);
     for (int i = 0; i < (int)e->in.size(); ++i) {
         const aafwi::WaveGrid& g = e->in[i].g;
         // one-step kernels keep a strip's receiver rows one per lane: at most 64 rows
         const int tz_set = e->tz[kid] ? e->tz[kid] : default_tz(g.nzp);
-        const int tz = std::min(width == 64 ? std::min(tz_set, 64) : tz_set, g.nzp);
+        const int tz = std::min(two ? tz_set : std::min(tz_set, 64), g.nzp);
         const int ntx = (g.nxp + width - 1) / width;
         std::vector<aafwi::TileRec> t;
         for (int s = 0; s < g.S; ++s) {
@@ -300,8 +301,8 @@ void upload_tiles(Engine* e, aafwi::TileRec*& dst, int& count, const std::vector
 }
 
 void build_tiles(Engine* e, int kid) {
-    upload_tiles(e, e->dtiles[kid], e->ntiles[kid], tile_table(e, kid, 64));
-    if (kid < 3) upload_tiles(e, e->dtiles2[kid], e->ntiles2[kid], tile_table(e, kid, aafwi::kTile2));
+    upload_tiles(e, e->dtiles[kid], e->ntiles[kid], tile_table(e, kid, false));
+    if (kid < 3) upload_tiles(e, e->dtiles2[kid], e->ntiles2[kid], tile_table(e, kid, true));
 }
 
 void finalize(Engine* e) {

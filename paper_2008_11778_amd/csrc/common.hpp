@@ -124,7 +124,7 @@ void launch_step(int kernel_id, hipStream_t st, const TileRec* tiles, int ntiles
                  const StepArgs& a);
 void launch_step2(int kernel_id, hipStream_t st, const TileRec* tiles, int ntiles, const Inst* insts,
                   const StepArgs& a);
-constexpr int kTile2 = 56;  // output columns of a two-step wave tile
+constexpr int kTile2 = 64;  // output columns of a two-step wave tile (aligned like the one-step tiles)
 // Per-instance kernels; `active`/`inst` make them no-ops for masked instances.
 void launch_fold(hipStream_t st, const WaveGrid& g, float inv_dt2, const float* gimg, float* grad,
                  const int* active, int inst);

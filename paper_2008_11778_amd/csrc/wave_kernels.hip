@@ -149,11 +149,13 @@ __device__ __forceinline__ void rows_copy(float (&dst)[U], const float (&src)[U]
 // Unscaled 8th-order Laplacian at one point: z-pairs from the register
 // column q (centred on the point), x-pairs from the LDS row r (centred on
 // the point's lane).
-__device__ __forceinline__ float lap8p(const float* q, const float* r) {
-    const float s1 = (q[-1] + q[1]) + (r[-1] + r[1]);
-    const float s2 = (q[-2] + q[2]) + (r[-2] + r[2]);
-    const float s3 = (q[-3] + q[3]) + (r[-3] + r[3]);
-    const float s4 = (q[-4] + q[4]) + (r[-4] + r[4]);
+// ZS: stride of the z-column in floats.
+template <int ZS>
+__device__ __forceinline__ float lap8g(const float* q, const float* r) {
+    const float s1 = (q[-ZS] + q[ZS]) + (r[-1] + r[1]);
+    const float s2 = (q[-2 * ZS] + q[2 * ZS]) + (r[-2] + r[2]);
+    const float s3 = (q[-3 * ZS] + q[3 * ZS]) + (r[-3] + r[3]);
+    const float s4 = (q[-4 * ZS] + q[4 * ZS]) + (r[-4] + r[4]);
     float acc = (2.0f * kC0) * q[0];
     acc = fmaf(kC1, s1, acc);
     acc = fmaf(kC2, s2, acc);
@@ -164,7 +166,7 @@ __device__ __forceinline__ float lap8p(const float* q, const float* r) {
 
 template <int U>
 __device__ __forceinline__ float lap8(const Queue<U>& c, int j, const float* row, int lane) {
-    return lap8p(c.q + j + 4, row + 4 + lane);
+    return lap8g<1>(c.q + j + 4, row + 4 + lane);
 }
 
 // Per-lane addressing of a wave tile: node offset (bytes, row z0) and halo
@@ -460,42 +462,63 @@ __global__ __launch_bounds__(256) void k_adj_step(const TileRec* __restrict__ ti
 // ---------------------------------------------------------------------------
 // Two steps per launch (forward, recompute, adjoint).
 //
-// A wave owns 56 output columns [x0, x0+56) and rows [z0, z1).  Its 64 lanes
-// cover columns x0-4 .. x0+59.  Step one (level n -> n+1) is evaluated on all
-// 64 lanes for rows z0-4 .. z1+3, which is exactly the 4-cell neighbourhood
-// that step two (n+1 -> n+2) needs for the owned columns and rows; step two
-// trails step one by one register block (4 rows) and reads the step-one
-// values from registers (z) and from an LDS row (x).  Out-of-grid rows and
-// columns of step one come out zero by themselves: their loads, Kp
-// included, read zero through the buffer range check.  Each time level is
-// read and written once per launch instead of once per step; the price is
-// the recomputed 4-cell frame (64 of 56 columns, tz+8 of tz rows).  The
-// arithmetic of every point is that of the one-step kernels, in the same
-// order, so both paths give bitwise identical fields, traces and images.
+// A wave owns the 64 columns [x0, x0+64) (x0 a multiple of 64, so every row
+// it streams is two whole cache lines) and rows [z0, z1); lane l is column
+// x0 + l.  Step two (level n+1 -> n+2) of those points needs step one
+// (n -> n+1) on the 4-cell frame around them: rows z0-4 .. z1+3 and columns
+// x0-4 .. x0+67.  The 64 lanes evaluate step one on their own columns for
+// rows z0-4 .. z1+3; the eight frame columns are evaluated in one extra pass
+// per 4-row block, packed as (row, frame column) over lanes 0-31, from side
+// loads of those columns (lanes 32-63 fetch the four columns beyond each
+// side that the frame's stencil reaches).  Step two trails step one by one
+// register block and reads the step-one values from registers (z) and from
+// an LDS row (x).  Out-of-grid rows and columns come out zero by themselves:
+// their loads, Kp included, read zero through the buffer range check.  Each
+// time level is read and written once per launch instead of once per step;
+// the price is the frame (tz+8 of tz rows, 8 side columns per 64).  Every
+// point is evaluated with the one-step arithmetic in the same order, so both
+// paths give bitwise identical fields, traces and images.
 // ---------------------------------------------------------------------------
 struct Lanes2 {
-    int xc;           // column of this lane: x0 - 4 + lane
-    bool xin;         // inside the padded grid
-    bool own;         // an output column of this tile (lanes 4..59)
-    unsigned base;    // byte offset of (row 0, xc), or out of the buffer
-    unsigned hbase;   // lanes 0-7: (row 0, x-halo column of step one)
-    int hslot;
-    bool interior_x;  // all 64 lane columns undamped
-    float sx;
+    int xc;            // main column x0 + lane
+    bool xin;          // inside the padded grid
+    unsigned base;     // byte offset of (row 0, xc), or out of the buffer
+    int sr;            // side lanes: row of the 4-row block, (lane & 31) >> 3
+    int fc;            // frame column of lane & 31
+    bool fin;          // that frame column lies inside the grid
+    unsigned sbase;    // byte offset of (row sr, side column), or out: frame column
+                       // for lanes 0-31, outer column for lanes 32-63
+    unsigned fbase;    // lanes 0-31: as sbase (u^{n-1} and Kp of the frame); 32-63: out
+    int apos;          // side value's place in the 80-column step-one row (x0-8 at 0)
+    int fpos;          // place of the frame column of lane & 31 in that row
+    int bpos;          // place of the frame column of lane & 31 in the 72-column step-two row (x0-4 at 0)
+    bool interior_x;   // the 64 main columns are all undamped
+    bool interior_f;   // columns x0-4 .. x0+67 are all undamped
+    float sx;          // sponge term of the main column
+    float fsx;         // sponge term of the frame column of lane & 31
 };
 
 __device__ __forceinline__ Lanes2 lanes2(const WaveGrid& g, const Tile& t) {
     Lanes2 L;
-    L.xc = t.x0 - 4 + t.lane;
-    L.xin = L.xc >= 0 && L.xc < g.nxp;
-    L.own = t.lane >= 4 && t.lane < 60 && L.xin;
+    const int lane = t.lane, k = lane & 7;
+    L.xc = t.x0 + lane;
+    L.xin = L.xc < g.nxp;
     L.base = L.xin ? (unsigned)L.xc * 4u : kOut;
-    const int hx = (t.lane < 4) ? (t.x0 - 8 + t.lane) : (t.x0 + 56 + t.lane);
-    const bool hok = t.lane < 8 && hx >= 0 && hx < g.nxp;
-    L.hbase = hok ? (unsigned)hx * 4u : kOut;
-    L.hslot = (t.lane < 4) ? t.lane : (64 + t.lane);
-    L.interior_x = (t.x0 - 4 >= g.nb) && (t.x0 + 60 <= g.nb + g.nx);
+    L.sr = (lane & 31) >> 3;
+    L.fc = k < 4 ? t.x0 - 4 + k : t.x0 + 60 + k;
+    L.fin = L.fc >= 0 && L.fc < g.nxp;
+    const int oc = k < 4 ? t.x0 - 8 + k : t.x0 + 64 + k;
+    const int sc = lane < 32 ? L.fc : oc;
+    const bool sin = sc >= 0 && sc < g.nxp;
+    L.sbase = sin ? (unsigned)(L.sr * g.pitch + sc) * 4u : kOut;
+    L.fbase = lane < 32 ? L.sbase : kOut;
+    L.apos = sc - (t.x0 - 8);
+    L.fpos = L.fc - (t.x0 - 8);
+    L.bpos = L.fc - (t.x0 - 4);
+    L.interior_x = (t.x0 >= g.nb) && (t.x0 + 64 <= g.nb + g.nx);
+    L.interior_f = (t.x0 - 4 >= g.nb) && (t.x0 + 68 <= g.nb + g.nx);
     L.sx = sponge_st(L.xc, g.nx, g.nb, g.inv_nb, g.scoef);
+    L.fsx = sponge_st(L.fc, g.nx, g.nb, g.inv_nb, g.scoef);
     return L;
 }
 
@@ -504,10 +527,11 @@ __device__ __forceinline__ Lanes2 lanes2(const WaveGrid& g, const Tile& t) {
 __device__ __forceinline__ unsigned row_off(int z, int pitch) { return (unsigned)(z * pitch * 4); }
 
 // Receiver-row slots of the rows z0-4 .. z0+123 a two-step tile touches
-// (strips of up to 120 rows),
-// held one per lane in two registers (loaded once per tile) and read back per
-// row with a wave-uniform lane index: no memory access inside the row loop,
-// whose prefetched loads would otherwise all be waited for.
+// (strips of up to 120 rows), held one per lane in two registers (loaded
+// once per tile) and read back with a wave-uniform lane index (readlane) or,
+// for the packed frame rows, a per-lane one (bpermute): no memory access
+// inside the row loop, whose prefetched loads would otherwise all be waited
+// for.
 struct FrameRows {
     int lo, hi;
 };
@@ -523,6 +547,14 @@ __device__ __forceinline__ FrameRows frame_rowmap(const RecMaps& rm, const WaveG
 __device__ __forceinline__ int frame_slot(const FrameRows& f, int z, int z0) {
     const int i = z - (z0 - 4);
     return i < 64 ? __builtin_amdgcn_readlane(f.lo, i) : __builtin_amdgcn_readlane(f.hi, i - 64);
+}
+
+// Per-lane row z (all lanes take part).
+__device__ __forceinline__ int frame_slot_lane(const FrameRows& f, int z, int z0) {
+    const int i = z - (z0 - 4);
+    const int a = (i & 63) * 4;
+    const int lo = __builtin_amdgcn_ds_bpermute(a, f.lo), hi = __builtin_amdgcn_ds_bpermute(a, f.hi);
+    return (i >= 0 && i < 64) ? lo : (i >= 64 && i < 128) ? hi : -1;
 }
 
 // Register rings of the two-step kernels.  The loop over 4-row blocks is
@@ -550,25 +582,36 @@ __device__ __forceinline__ void window(float (&w)[12], const float (&a)[4], cons
     }
 }
 
-// Stage rows 4..7 of a window (the block's rows) into LDS, with the x-halo
-// of lanes 0-7 when given.
-__device__ __forceinline__ void stage_w(float* rows, const float (&w)[12], const float (&hv)[4], int lane,
-                                        int hslot) {
+// LDS of a two-step wave: the step-one rows (4 x 80: columns x0-8 .. x0+71),
+// the frame columns' z-window (12 rows x 8), the step-two rows (4 x 72:
+// columns x0-4 .. x0+67).
+constexpr int kRowA = 80, kRowB = 72, kLds2 = 4 * kRowA + 12 * 8 + 4 * kRowB;
+
+// Stage the block's u^n (or lam^{n+1}) rows: main lanes' rows into the
+// step-one rows, the side values (row sr of the block) beside them, and the
+// frame columns' rows za-4 .. za+7 into the z-window.
+__device__ __forceinline__ void stage_one(float* A, float* F, const float (&q)[12], float hp, float hc, float hn,
+                                          int lane, const Lanes2& L) {
     wave_sync();
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        rows[j * 72 + 4 + lane] = w[j + 4];
-        if (lane < 8) rows[j * 72 + hslot] = hv[j];
+    for (int j = 0; j < 4; ++j) A[j * kRowA + 8 + lane] = q[j + 4];
+    A[L.sr * kRowA + L.apos] = hc;
+    if (lane < 32) {
+        const int f = lane & 7;
+        F[L.sr * 8 + f] = hp;
+        F[(4 + L.sr) * 8 + f] = hc;
+        F[(8 + L.sr) * 8 + f] = hn;
     }
     wave_sync();
 }
 
-// Step two's rows: centre values only (lanes 0-3 and 60-63 of step two are
-// not output columns, whatever they read).
-__device__ __forceinline__ void stage_c(float* rows, const float (&w)[12], int lane) {
+// Stage the step-one rows that step two reads: main lanes' values and the
+// frame values of lanes 0-31.
+__device__ __forceinline__ void stage_two(float* Bv, const float (&v)[12], float bf, int lane, const Lanes2& L) {
     wave_sync();
 #pragma unroll
-    for (int j = 0; j < 4; ++j) rows[j * 72 + 4 + lane] = w[j + 4];
+    for (int j = 0; j < 4; ++j) Bv[j * kRowB + 4 + lane] = v[j + 4];
+    if (lane < 32) Bv[L.sr * kRowB + L.bpos] = bf;
     wave_sync();
 }
 
@@ -615,7 +658,7 @@ __device__ __forceinline__ FastRows fast_rows(const WaveGrid& g, const Tile& t, 
     const int za = t.z0 - 4 + t.lane, zb = t.z0 + 60 + t.lane;
     f.lo = __builtin_amdgcn_ballot_w64(fr.lo >= 0 || za == src_row);
     f.hi = __builtin_amdgcn_ballot_w64(fr.hi >= 0 || zb == src_row);
-    f.on = on && L.interior_x;
+    f.on = on && L.interior_f;
     return f;
 }
 
@@ -623,11 +666,19 @@ __device__ __forceinline__ bool is_fast(const FastRows& f, int za, int z0) {
     return f.on && za - 4 >= f.zlo && za + 3 < f.zhi && rows_clear(f.lo, f.hi, za - z0);
 }
 
+// Sponge factors of a point off the main lanes (no interior shortcut: with
+// both sponge terms zero the reciprocal is exactly 1, as on the shortcut).
+__device__ __forceinline__ void sponge_pt(const WaveGrid& g, float sx, int z, float& A, float& B) {
+    const float st = sx + sponge_st(z, g.nz, g.nb, g.inv_nb, g.scoef);
+    A = __builtin_amdgcn_rcpf(1.0f + st);
+    B = fmaf(2.0f, A, -1.0f);
+}
+
 template <int U, bool kRecompute>
 __global__ __launch_bounds__(256) void k_fwd_step2(const TileRec* __restrict__ tiles, int ntiles,
                                                    const Inst* __restrict__ insts, StepArgs a) {
     static_assert(U == 4, "the two-step register rings hold 4-row blocks");
-    __shared__ float lds[kWaves][2 * U * 72];
+    __shared__ float lds[kWaves][kLds2];
     const Tile t = decode_tile(tiles, ntiles);
     if (!t.live) return;
     if (a.active && !a.active[t.inst]) return;
@@ -670,8 +721,9 @@ __global__ __launch_bounds__(256) void k_fwd_step2(const TileRec* __restrict__ t
     const RecMaps rm = I.rm;
     float* d = a.d_ovr ? a.d_ovr : I.d;
     const int lane = t.lane;
-    float* rowsA = &lds[threadIdx.x >> 6][0];
-    float* rowsB = rowsA + U * 72;
+    float* A_ = &lds[threadIdx.x >> 6][0];
+    float* F_ = A_ + 4 * kRowA;
+    float* B_ = F_ + 12 * 8;
     const long long off0 = (long long)t.s * g.plane;
     const Rsrc UR = view(u + off0, g.plane);
     const Rsrc UP = view(uprev + off0, g.plane);
@@ -688,7 +740,7 @@ __global__ __launch_bounds__(256) void k_fwd_step2(const TileRec* __restrict__ t
     const Lanes2 L = lanes2(g, t);
     const int2 sn = I.src.node[t.s];
     const unsigned rb = (unsigned)g.pitch * 4u;
-    const unsigned own_mask = L.own ? 0u : kOut;  // OR-ed into store offsets
+    const unsigned own_mask = L.xin ? 0u : kOut;  // OR-ed into store offsets
     FrameRows fr{-1, -1};
     if (!kRecompute) fr = frame_rowmap(rm, g, t);
     const FastRows fast = fast_rows(g, t, L, fr, sn.x, two && !ck0 && !ck1);
@@ -696,12 +748,16 @@ __global__ __launch_bounds__(256) void k_fwd_step2(const TileRec* __restrict__ t
     const int za0 = t.z0 - 4;
     const int zend = two ? t.z1 + 4 : t.z1;
     int za = za0;
-    unsigned o = L.base + row_off(za0, g.pitch), oh = L.hbase + row_off(za0, g.pitch);
+    unsigned o = L.base + row_off(za0, g.pitch);
+    unsigned os = L.sbase + row_off(za0, g.pitch);
+    unsigned of = L.fbase + row_off(za0, g.pitch);
     float c[4][4];   // u^n: blocks k-1, k, k+1 in use, k+2 arriving
     float b[4][4];   // u^{n+1} of step one: blocks k-2, k-1, k
     float kp[4][4];  // Kp: block k-1 (step two), k (step one), k+1 arriving
     float p[2][4];   // u^{n-1}: block k, k+1 arriving
-    float h[2][4];   // x-halo of u^n (lanes 0-7): block k, k+1 arriving
+    float hs[4];     // side lanes: u^n at row sr of blocks k-1, k, k+1 in use, k+2 arriving
+    float ph[2], kh[2];  // lanes 0-31: u^{n-1}, Kp at the frame column, row sr of block k, k+1 arriving
+    float bh[2];     // lanes 0-31: step one at the frame column, row sr of block k, and of block k-1
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         c[3][i] = bld(UR, o + (unsigned)(i - 4) * rb);
@@ -711,9 +767,14 @@ __global__ __launch_bounds__(256) void k_fwd_step2(const TileRec* __restrict__ t
 #pragma unroll
         for (int r = 0; r < 4; ++r) b[r][i] = 0.0f;
     }
+    hs[3] = bld(UR, os - 4u * rb);
+    hs[0] = bld(UR, os);
+    hs[1] = bld(UR, os + 4u * rb);
     rows_fetch(p[0], UP, o, rb);
     rows_fetch(kp[0], KR, o, rb);
-    rows_fetch(h[0], UR, oh, rb);
+    ph[0] = bld(UP, of);
+    kh[0] = bld(KR, of);
+    bh[0] = bh[1] = 0.0f;
 
     auto block = [&](auto KC) __attribute__((always_inline)) {
         using S = Blk<decltype(KC)::value>;
@@ -722,46 +783,56 @@ __global__ __launch_bounds__(256) void k_fwd_step2(const TileRec* __restrict__ t
         for (int i = 0; i < 4; ++i) c[S::ahead][i] = bld(UR, o + (unsigned)(8 + i) * rb);
         rows_fetch(p[S::odd], UP, o + 4 * rb, rb);
         rows_fetch(kp[S::next], KR, o + 4 * rb, rb);
-        rows_fetch(h[S::odd], UR, oh + 4 * rb, rb);
+        hs[S::ahead] = bld(UR, os + 8u * rb);
+        ph[S::odd] = bld(UP, of + 4u * rb);
+        kh[S::odd] = bld(KR, of + 4u * rb);
         float q[12];
         window(q, c[S::prev], c[S::cur], c[S::next]);
-        stage_w(rowsA, q, h[S::even], lane, L.hslot);
+        stage_one(A_, F_, q, hs[S::prev], hs[S::cur], hs[S::next], lane, L);
+        const float* fz = F_ + (4 + L.sr) * 8 + (lane & 7);  // frame z-column, centred
+        const float* fx = A_ + L.sr * kRowA + L.fpos;        // frame x-row, centred
         if (is_fast(fast, za, t.z0)) {
             // with A = B = 1 the leapfrog update would otherwise fuse Kp*acc
             // into the subtraction and skip the rounding of q-hat
 #pragma clang fp contract(off)
-            const unsigned os = o | own_mask;
+            const unsigned ow = o | own_mask;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const float acc = lap8p(q + j + 4, rowsA + j * 72 + 4 + lane);
+                const float acc = lap8g<1>(q + j + 4, A_ + j * kRowA + 8 + lane);
                 const float qh = kp[S::cur][j] * acc;
                 const float un = fmaf(2.0f, q[j + 4], fmaf(-1.0f, p[S::even][j], qh));
                 b[S::cur][j] = un;
-                bst_row(O1, os, (unsigned)j * rb, un);
-                if (kRecompute) bst_row(Q0, os, (unsigned)j * rb, qh);
+                bst_row(O1, ow, (unsigned)j * rb, un);
+                if (kRecompute) bst_row(Q0, ow, (unsigned)j * rb, qh);
+            }
+            {
+                const float acc = lap8g<8>(fz, fx);
+                const float qh = kh[S::even] * acc;
+                bh[S::even] = fmaf(2.0f, fz[0], fmaf(-1.0f, ph[S::even], qh));
             }
             float v[12];
             window(v, b[S::ahead], b[S::prev], b[S::cur]);
-            stage_c(rowsB, v, lane);
-            const unsigned os2 = os - 4u * rb;
+            stage_two(B_, v, bh[S::odd], lane, L);
+            const unsigned ow2 = ow - 4u * rb;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const float acc = lap8p(v + j + 4, rowsB + j * 72 + 4 + lane);
+                const float acc = lap8g<1>(v + j + 4, B_ + j * kRowB + 4 + lane);
                 const float qh = kp[S::prev][j] * acc;
                 const float un = fmaf(2.0f, v[j + 4], fmaf(-1.0f, q[j], qh));
-                bst_row(O2, os2, (unsigned)j * rb, un);
-                if (kRecompute) bst_row(Q1, os2, (unsigned)j * rb, qh);
+                bst_row(O2, ow2, (unsigned)j * rb, un);
+                if (kRecompute) bst_row(Q1, ow2, (unsigned)j * rb, qh);
             }
             za += 4;
             o += 4 * rb;
-            oh += 4 * rb;
+            os += 4 * rb;
+            of += 4 * rb;
             return;
         }
-        // step one at rows za .. za+3, all lanes
+        // step one at rows za .. za+3, main lanes
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int z = za + j;
-            float acc = lap8p(q + j + 4, rowsA + j * 72 + 4 + lane);
+            float acc = lap8g<1>(q + j + 4, A_ + j * kRowA + 8 + lane);
             if (z == sn.x && L.xc == sn.y) acc += w0;
             float A, B;
             sponge_ab(g, L, z, A, B);
@@ -782,20 +853,30 @@ __global__ __launch_bounds__(256) void k_fwd_step2(const TileRec* __restrict__ t
                 if (kRecompute) bst(Q0, oz, qh);
                 if (!kRecompute) {
                     const int slot = frame_slot(fr, z, t.z0);
-                    if (slot >= 0 && L.own) sample(rm, g, t.s, slot, L.xc, d, nt, n, un);
+                    if (slot >= 0 && L.xin) sample(rm, g, t.s, slot, L.xc, d, nt, n, un);
                 }
             }
+        }
+        // step one at the frame columns, row za + sr (lanes 0-31; 32-63 repeat them)
+        {
+            const int z = za + L.sr;
+            float acc = lap8g<8>(fz, fx);
+            if (z == sn.x && L.fc == sn.y) acc += w0;
+            float A, B;
+            sponge_pt(g, L.fsx, z, A, B);
+            const float qh = kh[S::even] * acc;
+            bh[S::even] = fmaf(2.0f * A, fz[0], fmaf(-B, ph[S::even], qh));
         }
         // step two at rows za-4 .. za-1
         if (two && za - 4 >= t.z0) {
             float v[12];
             window(v, b[S::ahead], b[S::prev], b[S::cur]);
-            stage_c(rowsB, v, lane);
+            stage_two(B_, v, bh[S::odd], lane, L);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int z = za - 4 + j;
                 if (z >= t.z1) break;
-                float acc = lap8p(v + j + 4, rowsB + j * 72 + 4 + lane);
+                float acc = lap8g<1>(v + j + 4, B_ + j * kRowB + 4 + lane);
                 if (z == sn.x && L.xc == sn.y) acc += w1;
                 float A, B;
                 sponge_ab(g, L, z, A, B);
@@ -806,13 +887,14 @@ __global__ __launch_bounds__(256) void k_fwd_step2(const TileRec* __restrict__ t
                 if (kRecompute) bst(Q1, oz, qh);
                 if (!kRecompute) {
                     const int slot = frame_slot(fr, z, t.z0);
-                    if (slot >= 0 && L.own) sample(rm, g, t.s, slot, L.xc, d, nt, n + 1, un);
+                    if (slot >= 0 && L.xin) sample(rm, g, t.s, slot, L.xc, d, nt, n + 1, un);
                 }
             }
         }
         za += 4;
         o += 4 * rb;
-        oh += 4 * rb;
+        os += 4 * rb;
+        of += 4 * rb;
     };
     while (za < zend) {
         block(IC<0>{});
@@ -832,7 +914,7 @@ template <int U>
 __global__ __launch_bounds__(256) void k_adj_step2(const TileRec* __restrict__ tiles, int ntiles,
                                                    const Inst* __restrict__ insts, StepArgs a) {
     static_assert(U == 4, "the two-step register rings hold 4-row blocks");
-    __shared__ float lds[kWaves][2 * U * 72];
+    __shared__ float lds[kWaves][kLds2];
     const Tile t = decode_tile(tiles, ntiles);
     if (!t.live) return;
     if (a.active && !a.active[t.inst]) return;
@@ -856,8 +938,9 @@ __global__ __launch_bounds__(256) void k_adj_step2(const TileRec* __restrict__ t
     const RecMaps rm = I.rm;
     const float h2 = I.h2;
     const int lane = t.lane;
-    float* rowsA = &lds[threadIdx.x >> 6][0];
-    float* rowsB = rowsA + U * 72;
+    float* A_ = &lds[threadIdx.x >> 6][0];
+    float* F_ = A_ + 4 * kRowA;
+    float* B_ = F_ + 12 * 8;
     const long long off0 = (long long)t.s * g.plane;
     const Rsrc UR = view(l + off0, g.plane);
     const Rsrc UP = view(lprev + off0, g.plane);
@@ -869,83 +952,103 @@ __global__ __launch_bounds__(256) void k_adj_step2(const TileRec* __restrict__ t
     const Rsrc GI = view(I.GI + off0, g.plane);
     const Lanes2 L = lanes2(g, t);
     const unsigned rb = (unsigned)g.pitch * 4u;
-    const unsigned own_mask = L.own ? 0u : kOut;
+    const unsigned own_mask = L.xin ? 0u : kOut;
     const FrameRows fr = frame_rowmap(rm, g, t);
     const FastRows fast = fast_rows(g, t, L, fr, -1, two);
 
     const int za0 = t.z0 - 4;
     const int zend = two ? t.z1 + 4 : t.z1;
     int za = za0;
-    unsigned o = L.base + row_off(za0, g.pitch), oh = L.hbase + row_off(za0, g.pitch);
+    unsigned o = L.base + row_off(za0, g.pitch);
+    unsigned os = L.sbase + row_off(za0, g.pitch);
+    unsigned of = L.fbase + row_off(za0, g.pitch);
     float c[4][4];   // lam^{n+1}: blocks k-1, k, k+1 in use, k+2 arriving
     float b[4][4];   // lam^n of step one: blocks k-2, k-1, k
     float kp[4][4];  // Kp: block k-1 (step two), k (step one), k+1 arriving
     float p[2][4];   // lam^{n+2}: block k, k+1 arriving
-    float h[2][4];   // x-halo of lam^{n+1} (lanes 0-7)
-    float ia[2][4], ib[2][4], ig[2][4];  // q^n, q^{n-1}, image at step two's rows of this block / the next
+    float hs[4];     // side lanes: lam^{n+1} at row sr of blocks k-1, k, k+1 in use, k+2 arriving
+    float ph[2], kh[2];  // lanes 0-31: lam^{n+2}, Kp at the frame column
+    float bh[2];     // lanes 0-31: step one at the frame column, blocks k and k-1
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         c[3][i] = bld(UR, o + (unsigned)(i - 4) * rb);
         c[0][i] = bld(UR, o + (unsigned)i * rb);
         c[1][i] = bld(UR, o + (unsigned)(4 + i) * rb);
         kp[3][i] = 0.0f;
-        ia[0][i] = ib[0][i] = ig[0][i] = 0.0f;
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) b[rr][i] = 0.0f;
     }
+    hs[3] = bld(UR, os - 4u * rb);
+    hs[0] = bld(UR, os);
+    hs[1] = bld(UR, os + 4u * rb);
     rows_fetch(p[0], UP, o, rb);
     rows_fetch(kp[0], KR, o, rb);
-    rows_fetch(h[0], UR, oh, rb);
+    ph[0] = bld(UP, of);
+    kh[0] = bld(KR, of);
+    bh[0] = bh[1] = 0.0f;
 
     auto block = [&](auto KC) __attribute__((always_inline)) {
         using S = Blk<decltype(KC)::value>;
+        // image operands of step two's rows za-4 .. za-1, issued before the
+        // next block's rows so that waiting for them leaves those in flight
+        float ia[4], ib[4], ig[4];
+        if (two && za - 4 >= t.z0) {
+            rows_fetch(ia, QA, o - 4 * rb, rb);
+            rows_fetch(ib, QB, o - 4 * rb, rb);
+            rows_fetch(ig, GI, o - 4 * rb, rb);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) ia[i] = ib[i] = ig[i] = 0.0f;
+        }
 #pragma unroll
         for (int i = 0; i < 4; ++i) c[S::ahead][i] = bld(UR, o + (unsigned)(8 + i) * rb);
         rows_fetch(p[S::odd], UP, o + 4 * rb, rb);
         rows_fetch(kp[S::next], KR, o + 4 * rb, rb);
-        rows_fetch(h[S::odd], UR, oh + 4 * rb, rb);
-        // image operands of rows za .. za+3 (step two's rows of the next block)
-        if (two) {
-            rows_fetch(ia[S::odd], QA, o, rb);
-            rows_fetch(ib[S::odd], QB, o, rb);
-            rows_fetch(ig[S::odd], GI, o, rb);
-        }
+        hs[S::ahead] = bld(UR, os + 8u * rb);
+        ph[S::odd] = bld(UP, of + 4u * rb);
+        kh[S::odd] = bld(KR, of + 4u * rb);
         float q[12];
         window(q, c[S::prev], c[S::cur], c[S::next]);
-        stage_w(rowsA, q, h[S::even], lane, L.hslot);
+        stage_one(A_, F_, q, hs[S::prev], hs[S::cur], hs[S::next], lane, L);
+        const float* fz = F_ + (4 + L.sr) * 8 + (lane & 7);
+        const float* fx = A_ + L.sr * kRowA + L.fpos;
         if (is_fast(fast, za, t.z0)) {
             // with A = B = 1 the leapfrog update would otherwise fuse Kp*acc
             // into the subtraction and skip the rounding of q-hat
 #pragma clang fp contract(off)
-            const unsigned os = o | own_mask;
+            const unsigned ow = o | own_mask;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const float acc = lap8p(q + j + 4, rowsA + j * 72 + 4 + lane);
+                const float acc = lap8g<1>(q + j + 4, A_ + j * kRowA + 8 + lane);
                 const float ln = fmaf(2.0f, q[j + 4], fmaf(-1.0f, p[S::even][j], kp[S::cur][j] * acc));
                 b[S::cur][j] = ln;
-                bst_row(O1, os, (unsigned)j * rb, ln);
+                bst_row(O1, ow, (unsigned)j * rb, ln);
+            }
+            {
+                const float acc = lap8g<8>(fz, fx);
+                bh[S::even] = fmaf(2.0f, fz[0], fmaf(-1.0f, ph[S::even], kh[S::even] * acc));
             }
             float v[12];
             window(v, b[S::ahead], b[S::prev], b[S::cur]);
-            stage_c(rowsB, v, lane);
-            const unsigned os2 = os - 4u * rb;
+            stage_two(B_, v, bh[S::odd], lane, L);
+            const unsigned ow2 = ow - 4u * rb;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const float acc = lap8p(v + j + 4, rowsB + j * 72 + 4 + lane);
+                const float acc = lap8g<1>(v + j + 4, B_ + j * kRowB + 4 + lane);
                 const float lm = fmaf(2.0f, v[j + 4], fmaf(-1.0f, q[j], kp[S::prev][j] * acc));
-                bst_row(O2, os2, (unsigned)j * rb, lm);
-                bst_row(GI, os2, (unsigned)j * rb,
-                        fmaf(lm, ib[S::even][j], fmaf(v[j + 4], ia[S::even][j], ig[S::even][j])));
+                bst_row(O2, ow2, (unsigned)j * rb, lm);
+                bst_row(GI, ow2, (unsigned)j * rb, fmaf(lm, ib[j], fmaf(v[j + 4], ia[j], ig[j])));
             }
             za += 4;
             o += 4 * rb;
-            oh += 4 * rb;
+            os += 4 * rb;
+            of += 4 * rb;
             return;
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int z = za + j;
-            float acc = lap8p(q + j + 4, rowsA + j * 72 + 4 + lane);
+            float acc = lap8g<1>(q + j + 4, A_ + j * kRowA + 8 + lane);
             const int slot = frame_slot(fr, z, t.z0);
             if (slot >= 0 && L.xin) acc = fmaf(-h2, injected(rm, g, t.s, slot, L.xc, r, nt, n), acc);
             float A, B;
@@ -958,15 +1061,25 @@ __global__ __launch_bounds__(256) void k_adj_step2(const TileRec* __restrict__ t
                 if (!two) bst(GI, oz, fmaf(ln, bld(QA, oz), bld(GI, oz)));
             }
         }
+        // step one at the frame columns, row za + sr (lanes 0-31; 32-63 repeat them)
+        {
+            const int z = za + L.sr;
+            float acc = lap8g<8>(fz, fx);
+            const int slot = frame_slot_lane(fr, z, t.z0);
+            if (slot >= 0 && L.fin) acc = fmaf(-h2, injected(rm, g, t.s, slot, L.fc, r, nt, n), acc);
+            float A, B;
+            sponge_pt(g, L.fsx, z, A, B);
+            bh[S::even] = fmaf(2.0f * A, fz[0], fmaf(-B, ph[S::even], kh[S::even] * acc));
+        }
         if (two && za - 4 >= t.z0) {
             float v[12];
             window(v, b[S::ahead], b[S::prev], b[S::cur]);
-            stage_c(rowsB, v, lane);
+            stage_two(B_, v, bh[S::odd], lane, L);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int z = za - 4 + j;
                 if (z >= t.z1) break;
-                float acc = lap8p(v + j + 4, rowsB + j * 72 + 4 + lane);
+                float acc = lap8g<1>(v + j + 4, B_ + j * kRowB + 4 + lane);
                 const int slot = frame_slot(fr, z, t.z0);
                 if (slot >= 0 && L.xin) acc = fmaf(-h2, injected(rm, g, t.s, slot, L.xc, r, nt, n - 1), acc);
                 float A, B;
@@ -974,12 +1087,13 @@ __global__ __launch_bounds__(256) void k_adj_step2(const TileRec* __restrict__ t
                 const float lm = fmaf(2.0f * A, v[j + 4], fmaf(-B, q[j], kp[S::prev][j] * acc));
                 const unsigned oz = (o + (unsigned)j * rb - 4u * rb) | own_mask;
                 bst(O2, oz, lm);
-                bst(GI, oz, fmaf(lm, ib[S::even][j], fmaf(v[j + 4], ia[S::even][j], ig[S::even][j])));
+                bst(GI, oz, fmaf(lm, ib[j], fmaf(v[j + 4], ia[j], ig[j])));
             }
         }
         za += 4;
         o += 4 * rb;
-        oh += 4 * rb;
+        os += 4 * rb;
+        of += 4 * rb;
     };
     while (za < zend) {
         block(IC<0>{});
