@@ -423,6 +423,57 @@ def lsrtm_workload(args):
     print(json.dumps(out), flush=True)
 
 
+def target_workload(args):
+    """Time to the misfit target on the FWI-gradient case: plain AA (M = 10)
+    for args.target_iters iterations through the C-ABI problem sets the target
+    J_K / J_0; the same run through the autograd form (torch.autograd over the
+    same forward and adjoint) is timed to the same target.  Both paths use the
+    same context, launch shapes and line search."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2008_11778_amd import Context, autotune
+    from paper_2008_11778_amd.inversion import AADescent, AutogradFWIProblem, FWIProblem
+
+    dev = torch.device("cuda", 0)
+    g, m_true, m0 = synth.config2()
+    ctx = Context(g, ckpt_every=50)
+    m0t = torch.from_numpy(m0).to(dev)
+    autotune.apply(ctx, autotune.tune(g, m0t, verbose=True))
+    d_obs = ctx.forward_model(torch.from_numpy(m_true).to(dev)).clone()
+    torch.cuda.synchronize()
+    runs = {}
+    for kind in ("c_abi", "autograd"):
+        prob = FWIProblem(ctx, d_obs) if kind == "c_abi" else AutogradFWIProblem(ctx, d_obs)
+        run = AADescent(prob, m0t, None, M=10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rec = run.first()
+        hist = [(0, rec.J, time.perf_counter() - t0, prob.n_adj, prob.n_fwd)]
+        for _ in range(args.target_iters):
+            rec = run.iterate()
+            torch.cuda.synchronize()
+            hist.append((rec.k, rec.J, time.perf_counter() - t0, prob.n_adj, prob.n_fwd))
+            log(f"{kind} k={rec.k} J={rec.J:.6e} lam={rec.lam} t={hist[-1][2]:.1f}s")
+        run.close()
+        runs[kind] = hist
+    J0 = runs["c_abi"][0][1]
+    target = runs["c_abi"][-1][1] / J0
+    paths = {}
+    for kind, hist in runs.items():
+        hit = next((h for h in hist if h[1] / J0 <= target * (1 + 1e-6)), None)
+        paths[kind] = {"time_s": round(hit[2], 2) if hit else None, "iterations": hit[0] if hit else None,
+                       "gradients": hit[3] if hit else None, "forward_runs": hit[4] if hit else None,
+                       "final_ratio": round(hist[-1][1] / J0, 6)}
+    out = {"metric": "time to misfit target (plain AA, M = 10)", "value": paths["c_abi"]["time_s"], "unit": "s",
+           "n_gpus": 1, "higher_is_better": False, "target_ratio": round(target, 6),
+           "config": {"workload": f"FWI-gradient case 768x256, 64 shots, 4000 steps; target J_{args.target_iters}/J_0 "
+                                  "of plain AA(10) through the C-ABI problem"},
+           "paths": paths, "dtype": "f32", "data": "synthetic"}
+    print(json.dumps(out), flush=True)
+
+
 def cnn_workload(args):
     """Speed of the learned-direction network alone: forward and Adam training
     step on 8 images of 384 x 1024 (random inputs), HIP-event timed; reports
@@ -583,7 +634,8 @@ def main():
                     help="launch shape instead of autotuning: steps per launch of the forward, recompute and "
                          "adjoint kernels, rows per wave of the forward, recompute, adjoint and Born steps, and "
                          "optionally their tile orders, e.g. 1,1,2:8,64,20,64:1,0,0,0")
-    ap.add_argument("--workload", default="fwi", choices=["fwi", "batched", "learned", "cnn", "noisy", "lsrtm"])
+    ap.add_argument("--workload", default="fwi", choices=["fwi", "batched", "learned", "cnn", "noisy", "lsrtm", "target"])
+    ap.add_argument("--target-iters", type=int, default=30, help="target workload: plain AA iterations")
     ap.add_argument("--budget", type=float, default=20, help="noisy workload: gradient evaluations per optimiser")
     ap.add_argument("--instances", type=int, default=32, help="batched workload: number of instances")
     ap.add_argument("--iters", type=int, default=10, help="batched workload: AA iterations per instance")
@@ -610,6 +662,8 @@ def main():
         return noisy_workload(args)
     if args.workload == "lsrtm":
         return lsrtm_workload(args)
+    if args.workload == "target":
+        return target_workload(args)
     # the oracle runs first, in child processes started before this process
     # touches the GPU
     cpu = None

@@ -64,6 +64,44 @@ class FWIProblem:
         return J
 
 
+class AutogradFWIProblem:
+    """The same J(m) and gradient through the autograd form: f(m) is
+    ``seismic_forward`` (a torch.autograd.Function over the HIP forward and
+    adjoint), the residual r = f(m) - d_obs stays FP32 and J = 1/2 sum r^2 is
+    accumulated in FP64 by torch; ``J.backward()`` hands r to the adjoint.
+    The graph of the last misfit evaluation is kept, so the gradient at the
+    accepted line-search trial reuses its forward run (its checkpoints)."""
+
+    def __init__(self, ctx: Context, d_obs: torch.Tensor):
+        self.ctx = ctx
+        self.d_obs = d_obs
+        self.kept = None
+        self.kept_J = None
+        self.kept_leaf = None
+        self.n_fwd = 0
+        self.n_adj = 0
+
+    def misfit_keep(self, m: torch.Tensor) -> float:
+        from .autograd import seismic_forward
+        leaf = m.detach().view(self.ctx.nz, self.ctx.nx).requires_grad_(True)
+        d = seismic_forward(leaf, self.ctx)
+        r = d - self.d_obs
+        J = 0.5 * torch.sum(r.double() ** 2)
+        self.kept, self.kept_J, self.kept_leaf = m, J, leaf
+        self.n_fwd += 1
+        return float(J.item())
+
+    def gradient(self, m: torch.Tensor, grad: torch.Tensor):
+        if self.kept is not m:
+            self.misfit_keep(m)
+        J, leaf = self.kept_J, self.kept_leaf
+        J.backward()
+        grad.copy_(leaf.grad.reshape(grad.shape))
+        self.kept, self.kept_J, self.kept_leaf = None, None, None
+        self.n_adj += 1
+        return float(J.item())
+
+
 class LSRTMProblem:
     """J(x) = 1/2 ||L x - d_r||^2 at a fixed background m0 (eq. LSRTM)."""
 

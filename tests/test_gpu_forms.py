@@ -233,3 +233,31 @@ def test_filtered_rtm_and_scaled_start_match_oracle(lsrtm_small):
     assert rel(f, f_ref) <= 1e-3
     assert abs(alpha - a_ref) / abs(a_ref) <= 1e-3
     assert rel(x0, x_ref) <= 1e-3
+
+
+def test_autograd_problem_matches_c_abi_problem(fwi_small):
+    """The autograd form of J and its gradient (torch.autograd over the same
+    forward and adjoint) hands the adjoint the same FP32 residual as the C-ABI
+    problem: identical gradients, J equal to FP64 rounding, and the same
+    Algorithm 2 iterates over a few iterations."""
+    import torch
+    from paper_2008_11778_amd import Context
+    from paper_2008_11778_amd.inversion import AADescent, AutogradFWIProblem, FWIProblem
+    g, m, d_obs = fwi_small
+    with Context(g, ckpt_every=32) as ctx:
+        do = T(d_obs)
+        mt = T(m).reshape(-1)
+        g1, g2 = torch.empty_like(mt), torch.empty_like(mt)
+        J1 = FWIProblem(ctx, do).gradient(mt, g1)
+        J2 = AutogradFWIProblem(ctx, do).gradient(mt, g2)
+        assert torch.equal(g1, g2)
+        assert abs(J1 - J2) <= 1e-12 * J1
+        ps = []
+        for prob in (FWIProblem(ctx, do), AutogradFWIProblem(ctx, do)):
+            run = AADescent(prob, T(m), None, M=5)
+            run.first()
+            lams = [run.iterate().lam for _ in range(3)]
+            ps.append((run.p.clone(), lams))
+            run.close()
+    assert ps[0][1] == ps[1][1]
+    assert float(torch.linalg.norm(ps[0][0] - ps[1][0]) / torch.linalg.norm(ps[0][0])) <= 1e-6
