@@ -154,9 +154,9 @@ int aafwi_aa_destroy(aafwi_aa* aa);
 int aafwi_aa_step(aafwi_aa* aa, const float* p_k, const float* g_k, float eta, float* p_bar,
                   float* p_tilde, double* gamma, int32_t* mk);
 
-/* Condition number of A_k found by the last step (device double), for logs. */
 /* Least-squares solver of Step 2.  AAFWI_AA_GRAM (default): FP64 normal
- * equations of the exact gradient differences, cyclic Jacobi.  AAFWI_AA_QR:
+ * equations of the exact gradient differences, solved by a Jacobi
+ * eigen-decomposition (parallel ordering).  AAFWI_AA_QR:
  * the rank-updated QR factorisation of the paper's Step 2 (columns appended
  * by Gram-Schmidt with reorthogonalisation, the oldest removed by Givens
  * rotations; Q is n x M doubles on the device, allocated on first use);
@@ -178,6 +178,7 @@ int aafwi_aa_set_damping(aafwi_aa* aa, float beta);
  * cond_2(W^(1/2) A_k).  Clears the history.  Synchronises the stream. */
 int aafwi_aa_set_weights(aafwi_aa* aa, const float* w);
 
+/* Condition number of A_k found by the last step (device double), for logs. */
 int aafwi_aa_last_cond(aafwi_aa* aa, double* cond_dev);
 
 /* out = lambda*p_tilde + (1-lambda)*p_bar (Algorithm 2, Step 5), formed in
