@@ -60,9 +60,10 @@ enum ConvMode { kHidden = 0, kLast = 1, kInputGrad = 2 };
 // one image over a run of rows and walks down it: a 3-row LDS ring holds
 // input rows y-1 .. y+1 (columns x0-1 .. x0+64, zeros outside the image),
 // each output row adds one new input row, and the row after that is fetched
-// into registers while the current row runs on the matrix cores.  Wave w
-// takes pixels x0+16w .. x0+16w+15 and reads each A fragment as one 16-byte
-// LDS load.
+// into registers while the current row runs on the matrix cores.  The ring
+// has four slots, so the row being written is never one of the three being
+// read and one barrier per row orders the two.  Wave w takes pixels x0+16w
+// .. x0+16w+15 and reads each A fragment as one 16-byte LDS load.
 constexpr int kCSeg = 64;
 
 template <int C>
@@ -110,7 +111,7 @@ __global__ __launch_bounds__(256) void k_conv_mm(int B, int H, int W, int rows, 
     constexpr int RW = (kCSeg + 2) * CS;     // one staged row
     static_assert(MODE == kLast || NOUT == 32, "hidden and input-gradient layers have 32 outputs");
     constexpr int TS = NOUT + 8;             // transpose tile pixel stride
-    __shared__ __align__(16) bf16 xL[3 * RW];
+    __shared__ __align__(16) bf16 xL[4 * RW];
     __shared__ __align__(16) bf16 tL[4][16 * TS];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int i = lane & 15, grp = lane >> 4;
@@ -141,15 +142,16 @@ __global__ __launch_bounds__(256) void k_conv_mm(int B, int H, int W, int rows, 
         RowFetch<C> f;
         __syncthreads();  // the ring's previous contents are no longer read
         row_fetch<C>(f, x, bimg, H, W, ya - 1, x0);
-        row_store<C, CS>(f, xL + ((ya + 2) % 3) * RW);
+        row_store<C, CS>(f, xL + ((ya + 3) & 3) * RW);
         row_fetch<C>(f, x, bimg, H, W, ya, x0);
-        row_store<C, CS>(f, xL + (ya % 3) * RW);
+        row_store<C, CS>(f, xL + (ya & 3) * RW);
         row_fetch<C>(f, x, bimg, H, W, ya + 1, x0);
         for (int yy = ya; yy < yb; ++yy) {
-            row_store<C, CS>(f, xL + ((yy + 1) % 3) * RW);  // input row yy+1 into the slot of row yy-2
+            // input row yy+1 into the slot of row yy-3, last read two rows ago
+            row_store<C, CS>(f, xL + ((yy + 1) & 3) * RW);
             __syncthreads();
             if (yy + 1 < yb) row_fetch<C>(f, x, bimg, H, W, yy + 2, x0);  // in flight during the products
-            const int base[3] = {((yy + 2) % 3) * RW, (yy % 3) * RW, ((yy + 1) % 3) * RW};
+            const int base[3] = {((yy + 3) & 3) * RW, (yy & 3) * RW, ((yy + 1) & 3) * RW};
             v4f acc[NT];
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) acc[nt] = v4f{0.f, 0.f, 0.f, 0.f};
@@ -199,8 +201,11 @@ __global__ __launch_bounds__(256) void k_conv_mm(int B, int H, int W, int rows, 
                     }
                     *reinterpret_cast<v4u*>(y + o) = v;
                 }
+                // the wave reads its transpose tile before the next row rewrites it
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             }
-            __syncthreads();  // every wave is done with row yy-1's slot and its transpose tile
         }
     }
 }
@@ -216,8 +221,10 @@ __global__ __launch_bounds__(256) void k_conv_mm(int B, int H, int W, int rows, 
 // pixels on v_mfma_f32_16x16x32_bf16: A = dy^T (co x pixels), B = x shifted
 // by the tap (pixels x ci).  A fragment takes 8 consecutive pixels of one
 // channel: the LDS pixel stride is padded by two channels so that those
-// gathers do not collide in the LDS banks.  Blocks take (image, row run,
-// segment) items with a grid stride and keep accumulating across them.
+// gathers do not collide in the LDS banks.  The x ring has four slots and dy
+// two, so the rows being written are never the ones being read and one
+// barrier per row orders the two.  Blocks take (image, row run, segment)
+// items with a grid stride and keep accumulating across them.
 constexpr int kSeg = 32;
 constexpr int kWgradMaxBlocks = 1024;
 constexpr int kWgradRows = 16;
@@ -266,8 +273,9 @@ template <int CIN, int COUT>
 __global__ __launch_bounds__(192) void k_conv_wgrad(int B, int H, int W, const bf16* __restrict__ dy,
                                                    const bf16* __restrict__ x, float* __restrict__ part) {
     constexpr int XR = (kSeg + 2) * (CIN + 2);  // one staged x row
-    __shared__ bf16 dyL[kSeg * (COUT + 2)];
-    __shared__ bf16 xL[3 * XR];
+    constexpr int DR = kSeg * (COUT + 2);        // one staged dy row
+    __shared__ bf16 dyL[2 * DR];
+    __shared__ bf16 xL[4 * XR];
     constexpr int MT = COUT / 16, NT = CIN / 16;
     const int lane = threadIdx.x & 63, r = threadIdx.x >> 6;  // r: tap row (dy offset r - 1)
     const int i = lane & 15, grp = lane >> 4;
@@ -289,14 +297,16 @@ __global__ __launch_bounds__(192) void k_conv_wgrad(int B, int H, int W, const b
         WRow<COUT, kSeg> fd;
         __syncthreads();  // the previous item's LDS reads are done
         wrow_fetch(fx, x, bimg, H, W, ya - 1, x0 - 1);
-        wrow_store(fx, xL + ((ya + 2) % 3) * XR);
+        wrow_store(fx, xL + ((ya + 3) & 3) * XR);
         wrow_fetch(fx, x, bimg, H, W, ya, x0 - 1);
-        wrow_store(fx, xL + (ya % 3) * XR);
+        wrow_store(fx, xL + (ya & 3) * XR);
         wrow_fetch(fx, x, bimg, H, W, ya + 1, x0 - 1);
         wrow_fetch(fd, dy, bimg, H, W, ya, x0);
         for (int yy = ya; yy < yb; ++yy) {
-            wrow_store(fx, xL + ((yy + 1) % 3) * XR);  // x row yy+1 into the slot of row yy-2
-            wrow_store(fd, dyL);
+            // x row yy+1 into the slot of row yy-3, dy row yy into the slot of row yy-2
+            wrow_store(fx, xL + ((yy + 1) & 3) * XR);
+            bf16* dyr = dyL + (yy & 1) * DR;
+            wrow_store(fd, dyr);
             __syncthreads();
             if (yy + 1 < yb) {  // in flight during the products
                 wrow_fetch(fx, x, bimg, H, W, yy + 2, x0 - 1);
@@ -305,8 +315,8 @@ __global__ __launch_bounds__(192) void k_conv_wgrad(int B, int H, int W, const b
             // K = the row's 32 pixels, one 32-deep MFMA step per tile
             bf8 A[MT];
 #pragma unroll
-            for (int a = 0; a < MT; ++a) A[a] = gather8<COUT>(dyL + (8 * grp) * (COUT + 2) + a * 16 + i);
-            const bf16* xr = xL + ((yy + r + 2) % 3) * XR;  // x row yy + r - 1
+            for (int a = 0; a < MT; ++a) A[a] = gather8<COUT>(dyr + (8 * grp) * (COUT + 2) + a * 16 + i);
+            const bf16* xr = xL + ((yy + r + 3) & 3) * XR;  // x row yy + r - 1
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
 #pragma unroll
@@ -317,7 +327,6 @@ __global__ __launch_bounds__(192) void k_conv_wgrad(int B, int H, int W, const b
                         acc[d][a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[a], Bf, acc[d][a][b], 0, 0, 0);
                 }
             }
-            __syncthreads();  // every wave is done with dyL and row yy-1's slot
         }
     }
     // lane holds D[4 grp + q][i]: co = a*16 + 4 grp + q, ci = b*16 + i; tap = 3 r + d
