@@ -463,7 +463,7 @@ __device__ __forceinline__ void store_partials(double (&v)[CAP], int ncol, doubl
         if (lane == 0) sh[wv][i] = a;
     }
     __syncthreads();
-    if (threadIdx.x < ncol) {
+    if ((int)threadIdx.x < ncol) {
         double t = 0.0;
         for (int w = 0; w < kReduceThreads / 64; ++w) t += sh[w][threadIdx.x];
         part[(long long)blockIdx.x * 2 * kAACap + threadIdx.x] = t;

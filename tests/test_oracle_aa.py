@@ -9,7 +9,6 @@ equals the Krylov least-squares definition; the two-loop recursion equals
 dense BFGS.
 """
 import numpy as np
-import pytest
 
 from oracle import aa, krylov
 

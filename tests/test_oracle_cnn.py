@@ -3,7 +3,6 @@ correlate2d, hand-written backward against central differences, the fixed
 point and descent properties of d_theta, Adam against its closed form for a
 constant gradient, and bfloat16 rounding against known bit patterns."""
 import numpy as np
-import pytest
 from scipy.signal import correlate2d
 
 from oracle import cnn

@@ -9,7 +9,6 @@ Taylor remainder and the conserved discrete energy.
 import math
 
 import numpy as np
-import pytest
 
 import synth
 from oracle import fd
