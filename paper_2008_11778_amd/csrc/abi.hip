@@ -502,10 +502,13 @@ int timing_enable(Engine* e, int every) {
     for (auto& l : e->launches) l = 0;
     e->time_every = every;
     if (every > 0) {
+        // timing-only events: no system-scope fence at record (its cache
+        // writeback would be timed with the kernel); timing_read synchronises
+        // the stream before it reads them
         while (e->ev_pool.size() < 8192) {
             hipEvent_t a, b;
-            AAFWI_HIP(hipEventCreate(&a));
-            AAFWI_HIP(hipEventCreate(&b));
+            AAFWI_HIP(hipEventCreateWithFlags(&a, hipEventDisableSystemFence));
+            AAFWI_HIP(hipEventCreateWithFlags(&b, hipEventDisableSystemFence));
             e->ev_pool.emplace_back(a, b);
         }
     }
