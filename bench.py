@@ -88,7 +88,15 @@ def cpu_baseline(target_s: float = 15.0):
     wall = time.perf_counter() - t0
     g, _, _ = synth.config2(nshots=64, nt=nt)
     updates = 2.0 * g.nz_p * g.nx_p * nt * cores
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
     return dict(value=updates / wall / 1e9, unit="Gpt-updates/s", cores=cores, kind="oracle",
+                per_core=round(2.0 * g.nz_p * g.nx_p * nt / (sum(times) / len(times)) / 1e9, 4),
+                host_cpus=os.cpu_count(), host_cpu_model=model,
                 sample=f"{cores} of 64 shots (one per process), {nt} of 4000 steps each, forward + adjoint "
                        f"gradient in FP64 NumPy; wall {wall:.1f} s, per-shot {min(times):.1f}-{max(times):.1f} s")
 
