@@ -57,12 +57,12 @@ enum ConvMode { kHidden = 0, kLast = 1, kInputGrad = 2 };
 // k = 32 ch + 8 g .. 8 g + 7, i.e. 8 consecutive channels of one tap.  w is
 // [tap][NOUT][C] bf16; every wave keeps all its weight fragments in
 // registers.  A block of four waves owns a 64-pixel-wide column segment of
-// one image over a run of rows and walks down it: a 3-row LDS ring holds
-// input rows y-1 .. y+1 (columns x0-1 .. x0+64, zeros outside the image),
-// each output row adds one new input row, and the row after that is fetched
-// into registers while the current row runs on the matrix cores.  The ring
-// has four slots, so the row being written is never one of the three being
-// read and one barrier per row orders the two.  Wave w takes pixels x0+16w
+// one image over a run of rows and walks down it: an LDS ring of four row
+// slots holds input rows y-1 .. y+1 (columns x0-1 .. x0+64, zeros outside the
+// image), each output row adds one new input row, and the row after that is
+// fetched into registers while the current row runs on the matrix cores.  The
+// row being written is never one of the three being read, so one barrier per
+// row orders the two.  Wave w takes pixels x0+16w
 // .. x0+16w+15 and reads each A fragment as one 16-byte LDS load.
 constexpr int kCSeg = 64;
 
@@ -213,10 +213,11 @@ __global__ __launch_bounds__(256) void k_conv_mm(int B, int H, int W, int rows, 
 // Weight gradient: part[block][tap][co][ci] = sum over the block's pixels p of
 // dy[p][co] x[p + off(tap)][ci] (FP32 partials, summed over blocks in a fixed
 // order by the reduction below).  A block of three waves owns a 32-pixel
-// column segment of one image over a run of rows and walks down it: a 3-row
-// LDS ring holds input rows y-1 .. y+1 (columns x0-1 .. x0+32, zeros outside
-// the image), dy of row y sits beside it, and the next rows of x and dy are
-// fetched into registers while the current row runs on the matrix cores.
+// column segment of one image over a run of rows and walks down it: an LDS
+// ring of four row slots holds input rows y-1 .. y+1 (columns x0-1 .. x0+32,
+// zeros outside the image), dy of row y sits beside it, and the next rows of
+// x and dy are fetched into registers while the current row runs on the
+// matrix cores.
 // Wave r accumulates the three taps of tap row r as GEMMs over the row's
 // pixels on v_mfma_f32_16x16x32_bf16: A = dy^T (co x pixels), B = x shifted
 // by the tap (pixels x ci).  A fragment takes 8 consecutive pixels of one
