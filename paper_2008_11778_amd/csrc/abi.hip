@@ -75,6 +75,7 @@ struct Engine {
     int* active = nullptr;  // device [N], batches only
     std::vector<int> active_host;
     double* J = nullptr;    // device [N]
+    double* fold_tmp = nullptr;  // device: one FP64 plane of the largest instance (shot sum before the fold)
     double* part = nullptr;
     int* flag = nullptr;
     int* same = nullptr;
@@ -336,6 +337,9 @@ void finalize(Engine* e) {
     for (const InstHost& I : e->in) pair_bytes += 2LL * I.field * (long long)sizeof(float);
     for (bool& t : e->tb) t = pair_bytes > (256LL << 20);
     e->J = dalloc<double>(e, N);
+    long long max_plane = 0;
+    for (const InstHost& I : e->in) max_plane = std::max(max_plane, (long long)I.g.plane);
+    e->fold_tmp = dalloc<double>(e, (size_t)max_plane);
     e->part = dalloc<double>(e, aafwi::kReduceBlocks);
     e->flag = dalloc<int>(e, 1);
     e->same = dalloc<int>(e, 1);
@@ -469,7 +473,7 @@ void run_backward(Engine* e, const float* r_ovr, const std::vector<float*>& grad
     for (int i = 0; i < N; ++i) {
         const InstHost& I = e->in[i];
         const double inv_dt2 = 1.0 / ((double)I.dt * (double)I.dt);
-        aafwi::launch_fold(e->stream, I.g, (float)inv_dt2, I.GI, grad[i], e->active, i);
+        aafwi::launch_fold(e->stream, I.g, (float)inv_dt2, I.GI, e->fold_tmp, grad[i], e->active, i);
     }
 }
 

@@ -126,7 +126,7 @@ void launch_step2(int kernel_id, hipStream_t st, const TileRec* tiles, int ntile
                   const StepArgs& a);
 constexpr int kTile2 = 64;  // output columns of a two-step wave tile (aligned like the one-step tiles)
 // Per-instance kernels; `active`/`inst` make them no-ops for masked instances.
-void launch_fold(hipStream_t st, const WaveGrid& g, float inv_dt2, const float* gimg, float* grad,
+void launch_fold(hipStream_t st, const WaveGrid& g, float inv_dt2, const float* gimg, double* ssum, float* grad,
                  const int* active, int inst);
 void launch_residual_misfit(hipStream_t st, long long n, const float* d, const float* dobs,
                             float* r, double* partials, double* J, const int* active, int inst);

@@ -1251,10 +1251,23 @@ __global__ void k_zero(float* __restrict__ p, long long n) {
     for (; i < n; i += stride) p[i] = 0.0f;
 }
 
-// grad[iz][ix] = sum_s sum over the padded cells copied from (iz, ix) of
-// gimg_s * (1 + st) / dt^2  (the image holds lam * A dt^2 q; 1/A = 1 + st).
-__global__ void k_fold(WaveGrid g, float inv_dt2, const float* __restrict__ gimg,
-                       float* __restrict__ grad, const int* __restrict__ active, int inst) {
+// grad[iz][ix] = sum over the padded cells copied from (iz, ix) of
+// (sum_s gimg_s) * (1 + st) / dt^2  (the image holds lam * A dt^2 q; 1/A = 1 + st).
+// Two passes in FP64, each in a fixed order: the shot sum at every padded
+// cell (one coalesced sweep over the S planes), then the fold of the sponge
+// cells onto the interior edge cells they copy (at most (nb+1)^2 cells for a
+// corner, read from the small summed plane).
+__global__ void k_shot_sum(WaveGrid g, const float* __restrict__ gimg, double* __restrict__ ssum,
+                           const int* __restrict__ active, int inst) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.plane || (active && !active[inst])) return;
+    double acc = 0.0;
+    for (int s = 0; s < g.S; ++s) acc += (double)gimg[(long long)s * g.plane + i];
+    ssum[i] = acc;
+}
+
+__global__ void k_fold(WaveGrid g, float inv_dt2, const double* __restrict__ ssum, float* __restrict__ grad,
+                       const int* __restrict__ active, int inst) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= g.nz * g.nx || (active && !active[inst])) return;
     const int iz = i / g.nx, ix = i % g.nx;
@@ -1263,14 +1276,11 @@ __global__ void k_fold(WaveGrid g, float inv_dt2, const float* __restrict__ gimg
     const int xa = (ix == 0) ? 0 : ix + g.nb;
     const int xb = (ix == g.nx - 1) ? g.nxp - 1 : ix + g.nb;
     double acc = 0.0;
-    for (int s = 0; s < g.S; ++s) {
-        const float* G = gimg + (long long)s * g.plane;
-        for (int zp = za; zp <= zb; ++zp) {
-            const float sz = sponge_st(zp, g.nz, g.nb, g.inv_nb, g.scoef);
-            for (int xp = xa; xp <= xb; ++xp) {
-                const double ia = 1.0 + (double)sz + (double)sponge_st(xp, g.nx, g.nb, g.inv_nb, g.scoef);
-                acc += (double)G[(long long)zp * g.pitch + xp] * ia;
-            }
+    for (int zp = za; zp <= zb; ++zp) {
+        const float sz = sponge_st(zp, g.nz, g.nb, g.inv_nb, g.scoef);
+        for (int xp = xa; xp <= xb; ++xp) {
+            const double ia = 1.0 + (double)sz + (double)sponge_st(xp, g.nx, g.nb, g.inv_nb, g.scoef);
+            acc += ssum[(long long)zp * g.pitch + xp] * ia;
         }
     }
     grad[i] = (float)(acc * (double)inv_dt2);
@@ -1403,10 +1413,14 @@ void launch_step2(int kernel_id, hipStream_t st, const TileRec* tiles, int ntile
     AAFWI_HIP(hipGetLastError());
 }
 
-void launch_fold(hipStream_t st, const WaveGrid& g, float inv_dt2, const float* gimg, float* grad,
+void launch_fold(hipStream_t st, const WaveGrid& g, float inv_dt2, const float* gimg, double* ssum, float* grad,
                  const int* active, int inst) {
+    hipLaunchKernelGGL(k_shot_sum, dim3((unsigned)((g.plane + 255) / 256)), dim3(256), 0, st, g, gimg, ssum, active,
+                       inst);
+    AAFWI_HIP(hipGetLastError());
     const int n = g.nz * g.nx;
-    hipLaunchKernelGGL(k_fold, dim3((n + 255) / 256), dim3(256), 0, st, g, inv_dt2, gimg, grad, active, inst);
+    hipLaunchKernelGGL(k_fold, dim3((n + 255) / 256), dim3(256), 0, st, g, inv_dt2, (const double*)ssum, grad,
+                       active, inst);
     AAFWI_HIP(hipGetLastError());
 }
 
