@@ -117,6 +117,21 @@ int aafwi_adjoint_gradient(aafwi_ctx* ctx, const float* m, const float* d_obs, f
  * context holds a copy of it).  AAFWI_E_STATE if no checkpoints are kept. */
 int aafwi_adjoint_from_residual(aafwi_ctx* ctx, const float* r, float* grad);
 
+/* Storage layout of the forward wavefield the backward pass images against
+ * (eq. adj_grad1 needs the forward field of every step).  Off (the layout at
+ * creation): checkpoints every ckpt_every steps, and the backward pass
+ * recomputes each segment's forward steps from its checkpoint.  On (full
+ * storage): a forward run with kept checkpoints writes q-hat of every step
+ * (nt field planes of all shots, nt * nshots * (nz+2nb) * pitch floats, pitch
+ * = nx+2nb rounded up to 64) and the backward pass reads them, recomputing
+ * nothing.  Gradients, images and traces are bitwise the same in both.  The
+ * switch drops kept state (aafwi_adjoint_from_residual needs a new forward
+ * run with keep_ckpt=1) and synchronises the stream.  AAFWI_E_NOMEM if the
+ * device cannot hold the full layout; the previous layout is kept then. */
+int aafwi_set_full_storage(aafwi_ctx* ctx, int enable);
+/* enabled: 1 with full storage, 0 with checkpoints. */
+int aafwi_get_full_storage(const aafwi_ctx* ctx, int* enabled);
+
 /* ---- Born modelling and its adjoint (eq. Born, eq. LSRTM) ------------------ */
 
 /* d_scat = L dm at background m0 (device [nz][nx] each; d_scat [S][nt][R]). */

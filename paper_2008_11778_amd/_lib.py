@@ -90,6 +90,8 @@ _sig("aafwi_set_time_blocking", _vp, ctypes.c_int)
 _sig("aafwi_set_time_blocking_kernel", _vp, _i32, ctypes.c_int)
 _sig("aafwi_set_tile_order", _vp, _i32, _i32)
 _sig("aafwi_get_time_blocking", _vp, ctypes.POINTER(ctypes.c_int))
+_sig("aafwi_set_full_storage", _vp, ctypes.c_int)
+_sig("aafwi_get_full_storage", _vp, ctypes.POINTER(ctypes.c_int))
 _sig("aafwi_batch_set_time_blocking", _vp, ctypes.c_int)
 _sig("aafwi_batch_destroy", _vp)
 _sig("aafwi_batch_misfits", _vp, _vp)
@@ -160,6 +162,7 @@ class Context:
         with torch.cuda.device(self.device):
             self.stream = stream if stream is not None else torch.cuda.current_stream()
             self.nz, self.nx, self.nt = int(geom.nz), int(geom.nx), int(geom.nt)
+            self.nb = int(geom.nb)
             self.nshots = int(np.asarray(geom.src_iz).size)
             self.nrec = int(np.asarray(geom.rec_iz).size // self.nshots)
             s, self._keep = make_geometry_struct(geom, ckpt_every)
@@ -277,6 +280,24 @@ class Context:
         v = ctypes.c_int()
         _check(_lib.aafwi_get_time_blocking(self._h, ctypes.byref(v)))
         return int(v.value)
+
+    def set_full_storage(self, enable: bool):
+        """Keep q-hat of every forward step in device memory (no recompute in
+        the backward pass) or checkpoints; results are bitwise equal.  Drops
+        kept state; raises AafwiError (out of memory) and keeps the previous
+        layout when the device cannot hold the full one."""
+        self.generation += 1
+        _check(_lib.aafwi_set_full_storage(self._h, int(bool(enable))))
+
+    def full_storage(self) -> bool:
+        v = ctypes.c_int()
+        _check(_lib.aafwi_get_full_storage(self._h, ctypes.byref(v)))
+        return bool(v.value)
+
+    def full_storage_bytes(self) -> int:
+        """Device bytes of the q planes of every step (the full layout's main buffer)."""
+        pitch = (self.nx + 2 * self.nb + 63) // 64 * 64
+        return 4 * self.nt * self.nshots * (self.nz + 2 * self.nb) * pitch
 
     def get_tile(self, kernel_id: int) -> int:
         v = _i32()

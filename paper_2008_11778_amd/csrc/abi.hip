@@ -61,6 +61,8 @@ struct InstHost {
 struct Engine {
     hipStream_t stream = nullptr;
     int k = 0;
+    int k_ckpt = 0;       // checkpoint interval of the checkpointed layout
+    bool keep_q = false;  // full storage: the kept forward writes q-hat of every step, no recompute
     bool is_batch = false;  // per-instance masks, caller buffers fixed at creation
     std::vector<InstHost> in;
     aafwi::Inst* dinst = nullptr;
@@ -81,6 +83,7 @@ struct Engine {
     int* same = nullptr;
     long long bytes = 0;
     std::vector<void*> allocs;
+    std::map<void*, size_t> alloc_bytes;
     // timing
     int time_every = 0;
     long long launches[4] = {0, 0, 0, 0};
@@ -117,8 +120,23 @@ T* dalloc(Engine* e, size_t count) {
         throw Error{AAFWI_E_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed"};
     }
     e->allocs.push_back(p);
+    e->alloc_bytes[p] = bytes;
     e->bytes += (long long)bytes;
     return (T*)p;
+}
+
+template <typename T>
+void dfree(Engine* e, T*& p) {
+    if (!p) return;
+    void* v = (void*)p;
+    (void)hipFree(v);
+    e->allocs.erase(std::remove(e->allocs.begin(), e->allocs.end(), v), e->allocs.end());
+    auto it = e->alloc_bytes.find(v);
+    if (it != e->alloc_bytes.end()) {
+        e->bytes -= (long long)it->second;
+        e->alloc_bytes.erase(it);
+    }
+    p = nullptr;
 }
 
 void free_engine(Engine* e) {
@@ -292,10 +310,7 @@ std::vector<aafwi::TileRec> tile_table(Engine* e, int kid, bool two) {
 }
 
 void upload_tiles(Engine* e, aafwi::TileRec*& dst, int& count, const std::vector<aafwi::TileRec>& all) {
-    if (dst) {
-        (void)hipFree(dst);
-        e->allocs.erase(std::remove(e->allocs.begin(), e->allocs.end(), (void*)dst), e->allocs.end());
-    }
+    dfree(e, dst);
     dst = dalloc<aafwi::TileRec>(e, all.size());
     AAFWI_HIP(hipMemcpy(dst, all.data(), sizeof(aafwi::TileRec) * all.size(), hipMemcpyHostToDevice));
     count = (int)all.size();
@@ -306,7 +321,8 @@ void build_tiles(Engine* e, int kid) {
     if (kid < 3) upload_tiles(e, e->dtiles2[kid], e->ntiles2[kid], tile_table(e, kid, true));
 }
 
-void finalize(Engine* e) {
+// Device descriptors of the instances (buffers, sizes, segment layout).
+void upload_insts(Engine* e) {
     const int N = (int)e->in.size();
     std::vector<aafwi::Inst> tab(N);
     for (int i = 0; i < N; ++i) {
@@ -326,8 +342,14 @@ void finalize(Engine* e) {
         D.h2 = I.h * I.h;
         D.field = I.field;
     }
-    e->dinst = dalloc<aafwi::Inst>(e, N);
     AAFWI_HIP(hipMemcpy(e->dinst, tab.data(), sizeof(aafwi::Inst) * N, hipMemcpyHostToDevice));
+}
+
+void finalize(Engine* e) {
+    const int N = (int)e->in.size();
+    e->k_ckpt = e->k;
+    e->dinst = dalloc<aafwi::Inst>(e, N);
+    upload_insts(e);
     for (int kid = 0; kid < 4; ++kid) build_tiles(e, kid);
     // Default launch mode: two steps per launch once one time level pair of
     // every instance (the one-step working set) outgrows the 256 MB
@@ -384,6 +406,18 @@ void step2(Engine* e, int kid, const aafwi::StepArgs& a) {
     aafwi::launch_step2(kid, e->stream, e->dtiles2[kid], e->ntiles2[kid], e->dinst, a);
 }
 
+// Forward launch of the full-storage layout: it writes q-hat beside u^{n+1},
+// the traffic of a recompute launch, so it takes the recompute kernel's launch
+// mode, tile table and timing slot (the recompute pass itself never runs).
+void step_keep_q(Engine* e, const aafwi::StepArgs& a) {
+    constexpr int kid = AAFWI_K_REC_STEP;
+    Timed t(e, kid);
+    if (e->tb[kid])
+        aafwi::launch_step2(AAFWI_K_FWD_STEP, e->stream, e->dtiles2[kid], e->ntiles2[kid], e->dinst, a);
+    else
+        aafwi::launch_step(AAFWI_K_FWD_STEP, e->stream, e->dtiles[kid], e->ntiles[kid], e->dinst, a);
+}
+
 void model_prep(Engine* e, int i, const float* m) {
     const InstHost& I = e->in[i];
     const double c2 = ((double)I.dt / (double)I.h) * ((double)I.dt / (double)I.h);
@@ -398,7 +432,15 @@ int max_nt(const Engine* e) {
 
 // Forward pass of every (active) instance; models m[i], samples into d_ovr (if
 // set) or the instances' own data buffers.
+// Every instance holds its checkpoint and q-plane buffers (a failed layout
+// switch that could not restore the previous layout leaves them unset).
+void require_layout(const Engine* e) {
+    for (const InstHost& I : e->in)
+        if (!I.ckpt || !I.qseg) throw Error{AAFWI_E_STATE, "storage layout lost after a failed set_full_storage"};
+}
+
 void run_forward(Engine* e, const std::vector<const float*>& m, float* d_ovr, bool keep) {
+    require_layout(e);
     const int N = (int)e->in.size();
     for (int i = 0; i < N; ++i) {
         model_prep(e, i, m[i]);
@@ -406,10 +448,14 @@ void run_forward(Engine* e, const std::vector<const float*>& m, float* d_ovr, bo
     }
     aafwi::StepArgs a{0, 0, keep ? 1 : 0, d_ovr, nullptr, e->active};
     const int T = max_nt(e);
-    const bool two = e->tb[AAFWI_K_FWD_STEP];
+    const bool keep_q = keep && e->keep_q;
+    a.keep_q = keep_q ? 1 : 0;
+    const bool two = e->tb[keep_q ? AAFWI_K_REC_STEP : AAFWI_K_FWD_STEP];
     for (int n = 0; n < T; n += two ? 2 : 1) {
         a.n = n;
-        if (two)
+        if (keep_q)
+            step_keep_q(e, a);
+        else if (two)
             step2(e, AAFWI_K_FWD_STEP, a);
         else
             step(e, AAFWI_K_FWD_STEP, a);
@@ -430,6 +476,7 @@ int seg_len(const Engine* e, const InstHost& I, int J) {
 // Backward pass of every (active) instance from its kept checkpoints; the
 // adjoint source is r_ovr (if set) or the instances' own residual buffers.
 void run_backward(Engine* e, const float* r_ovr, const std::vector<float*>& grad) {
+    require_layout(e);
     const int N = (int)e->in.size();
     int maxseg = 0;
     for (int i = 0; i < N; ++i) {
@@ -446,16 +493,16 @@ void run_backward(Engine* e, const float* r_ovr, const std::vector<float*>& grad
         a.seg = J;
         // recompute and adjoint choose their launch mode independently: the
         // segment's q planes do not depend on it, and the adjoint keeps one
-        // mode (one buffer convention) for the whole pass
-        if (e->tb[AAFWI_K_REC_STEP]) {
-            for (int tt = 0; tt < len; tt += 2) {
+        // mode (one buffer convention) for the whole pass.  Full storage: the
+        // kept forward already wrote the q planes of its one segment.
+        if (!e->keep_q) {
+            const bool two = e->tb[AAFWI_K_REC_STEP];
+            for (int tt = 0; tt < len; tt += two ? 2 : 1) {
                 a.n = tt;
-                step2(e, AAFWI_K_REC_STEP, a);
-            }
-        } else {
-            for (int tt = 0; tt < len; ++tt) {
-                a.n = tt;
-                step(e, AAFWI_K_REC_STEP, a);
+                if (two)
+                    step2(e, AAFWI_K_REC_STEP, a);
+                else
+                    step(e, AAFWI_K_REC_STEP, a);
             }
         }
         if (e->tb[AAFWI_K_ADJ_STEP]) {
@@ -568,6 +615,43 @@ int set_time_blocking(Engine* e, int kernel_id, int enable) {
         if (kernel_id == -1 || kernel_id == k) e->tb[k] = enable != 0;
     for (auto& kv : e->graphs) (void)hipGraphExecDestroy(kv.second);
     e->graphs.clear();
+    return AAFWI_OK;
+}
+
+// Switch between the checkpointed layout (checkpoints every k_ckpt steps, one
+// segment of q planes, recomputed per segment) and full storage (q planes of
+// every step, written by the kept forward).  Kept state is dropped either way.
+// On an allocation failure the previous layout is restored and the error
+// (AAFWI_E_NOMEM) rethrown.
+int set_full_storage(Engine* e, bool on) {
+    AAFWI_HIP(hipStreamSynchronize(e->stream));
+    if (on == e->keep_q) return AAFWI_OK;
+    auto release = [&]() {
+        for (InstHost& I : e->in) {
+            dfree(e, I.ckpt);
+            dfree(e, I.qseg);
+            I.have_ckpt = false;
+        }
+    };
+    auto layout = [&](bool full) {
+        e->k = full ? max_nt(e) : e->k_ckpt;
+        for (InstHost& I : e->in) {
+            I.nseg = (I.nt + e->k - 1) / e->k;
+            I.ckpt = dalloc<float>(e, (size_t)I.field * 2 * I.nseg);
+            I.qseg = dalloc<float>(e, (size_t)I.field * (full ? I.nt : e->k));
+        }
+    };
+    release();
+    try {
+        layout(on);
+    } catch (const Error&) {
+        release();
+        layout(e->keep_q);  // the memory just released holds it again
+        upload_insts(e);
+        throw;
+    }
+    e->keep_q = on;
+    upload_insts(e);
     return AAFWI_OK;
 }
 
@@ -777,6 +861,21 @@ extern "C" int aafwi_set_time_blocking_kernel(aafwi_ctx* c, int32_t kernel_id, i
     return guarded([&]() -> int {
         AAFWI_REQUIRE(c, "set_time_blocking_kernel: NULL context");
         return set_time_blocking(c->e, kernel_id, enable);
+    });
+}
+
+extern "C" int aafwi_set_full_storage(aafwi_ctx* c, int enable) {
+    return guarded([&]() -> int {
+        AAFWI_REQUIRE(c, "set_full_storage: NULL context");
+        return set_full_storage(c->e, enable != 0);
+    });
+}
+
+extern "C" int aafwi_get_full_storage(const aafwi_ctx* c, int* enabled) {
+    return guarded([&]() -> int {
+        AAFWI_REQUIRE(c && enabled, "get_full_storage: NULL argument");
+        *enabled = c->e->keep_q ? 1 : 0;
+        return AAFWI_OK;
     });
 }
 

@@ -110,7 +110,13 @@ struct StepArgs {
     float* d_ovr;          // if set: sampling target for every instance (single context)
     const float* r_ovr;    // if set: adjoint source for every instance (single context)
     const int* active;     // per-instance mask (NULL = all active)
+    int keep_q = 0;        // forward: write q-hat of step n to plane n of qseg (full storage, one segment)
 };
+
+// Forward-kernel modes: plain forward (sampling, checkpoint copies),
+// recompute of a segment from its checkpoint (q-hat out, no sampling), and
+// forward keeping q-hat of every step (sampling, no checkpoint copies).
+constexpr int kModeFwd = 0, kModeRec = 1, kModeFwdQ = 2;
 
 // Launchers (wave_kernels.hip).
 void launch_model_prep(hipStream_t st, const WaveGrid& g, float c2, const float* m, float* K,

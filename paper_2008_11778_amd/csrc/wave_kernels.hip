@@ -270,15 +270,17 @@ __device__ __forceinline__ int strip_rowmap(const RecMaps& rm, const WaveGrid& g
 }
 
 // ---------------------------------------------------------------------------
-// forward step (sampling, optional checkpoint copy) and recompute step (q out)
+// forward step (sampling, optional checkpoint copy), recompute step (q out),
+// and forward step that samples and keeps q-hat of every step (full storage)
 // ---------------------------------------------------------------------------
-template <int U, bool kRecompute>
+template <int U, int kMode>
 __global__ __launch_bounds__(256) void k_fwd_step(const TileRec* __restrict__ tiles, int ntiles,
                                                   const Inst* __restrict__ insts, StepArgs a) {
     __shared__ float lds[kWaves][U * 72];
     const Tile t = decode_tile(tiles, ntiles);
     if (!t.live) return;
     if (a.active && !a.active[t.inst]) return;
+    constexpr bool kRecompute = kMode == kModeRec, kKeepQ = kMode != kModeFwd, kSample = kMode != kModeRec;
     const Inst& I = insts[t.inst];
     const WaveGrid g = I.g;
     // step index, buffers and checkpoint slot of this instance
@@ -294,7 +296,8 @@ __global__ __launch_bounds__(256) void k_fwd_step(const TileRec* __restrict__ ti
         u = I.F[n & 1];  // u^n
         out = I.F[(n + 1) & 1];  // u^{n-1}, overwritten by u^{n+1}
         uprev = out;
-        if (a.keep && n % I.k == 0) ck_u = I.ckpt + (long long)(n / I.k) * 2 * I.field;
+        if (kMode == kModeFwd && a.keep && n % I.k == 0) ck_u = I.ckpt + (long long)(n / I.k) * 2 * I.field;
+        if (kKeepQ) q = I.qseg + (long long)n * I.field;  // one segment: its step index is n
     } else {
         const int j = I.nseg - 1 - a.seg;  // segment being recomputed
         const int tt = a.n;
@@ -330,10 +333,10 @@ __global__ __launch_bounds__(256) void k_fwd_step(const TileRec* __restrict__ ti
     const bool ck = ck_u != nullptr;
     const Rsrc CU = view(ck ? ck_u + off0 : u, g.plane);
     const Rsrc CUM = view(ck ? ck_u + I.field + off0 : u, g.plane);
-    const Rsrc QR = view(kRecompute ? q + off0 : u, g.plane);
+    const Rsrc QR = view(kKeepQ ? q + off0 : u, g.plane);
     const Lanes L = lanes(g, t);
     const int2 sn = I.src.node[t.s];
-    const int my_rm = kRecompute ? -1 : strip_rowmap(rm, g, t);
+    const int my_rm = kSample ? strip_rowmap(rm, g, t) : -1;
     const unsigned rb = L.rb;
 
     unsigned o = L.o, oh = L.oh;
@@ -366,8 +369,8 @@ __global__ __launch_bounds__(256) void k_fwd_step(const TileRec* __restrict__ ti
                 bst(CUM, oz, pv[j]);
             }
             bst(O, oz, un);
-            if (kRecompute) bst(QR, oz, qh);
-            if (!kRecompute) {
+            if (kKeepQ) bst(QR, oz, qh);
+            if (kSample) {
                 const int slot = __builtin_amdgcn_readlane(my_rm, z - t.z0);
                 if (slot >= 0 && L.xin) sample(rm, g, t.s, slot, L.x, d, nt, n, un);
             }
@@ -674,7 +677,7 @@ __device__ __forceinline__ void sponge_pt(const WaveGrid& g, float sx, int z, fl
     B = fmaf(2.0f, A, -1.0f);
 }
 
-template <int U, bool kRecompute>
+template <int U, int kMode>
 __global__ __launch_bounds__(256) void k_fwd_step2(const TileRec* __restrict__ tiles, int ntiles,
                                                    const Inst* __restrict__ insts, StepArgs a) {
     static_assert(U == 4, "the two-step register rings hold 4-row blocks");
@@ -682,6 +685,7 @@ __global__ __launch_bounds__(256) void k_fwd_step2(const TileRec* __restrict__ t
     const Tile t = decode_tile(tiles, ntiles);
     if (!t.live) return;
     if (a.active && !a.active[t.inst]) return;
+    constexpr bool kRecompute = kMode == kModeRec, kKeepQ = kMode != kModeFwd, kSample = kMode != kModeRec;
     const Inst& I = insts[t.inst];
     const WaveGrid g = I.g;
     int n, tt = 0, cnt;
@@ -711,7 +715,7 @@ __global__ __launch_bounds__(256) void k_fwd_step2(const TileRec* __restrict__ t
     // checkpoint slots reached by this launch: (u^n, u^{n-1}) and (u^{n+1}, u^n)
     float* ck0 = nullptr;
     float* ck1 = nullptr;
-    if (!kRecompute && a.keep) {
+    if (kMode == kModeFwd && a.keep) {
         if (n % I.k == 0) ck0 = I.ckpt + (long long)(n / I.k) * 2 * I.field;
         if (two && (n + 1) % I.k == 0) ck1 = I.ckpt + (long long)((n + 1) / I.k) * 2 * I.field;
     }
@@ -734,15 +738,16 @@ __global__ __launch_bounds__(256) void k_fwd_step2(const TileRec* __restrict__ t
     const Rsrc C0P = view(ck0 ? ck0 + I.field + off0 : u, g.plane);
     const Rsrc C1U = view(ck1 ? ck1 + off0 : u, g.plane);
     const Rsrc C1P = view(ck1 ? ck1 + I.field + off0 : u, g.plane);
-    float* q0 = kRecompute ? I.qseg + (long long)tt * I.field + off0 : out1;
+    // q-hat planes: the segment's step tt (recompute) or step n (full storage, one segment)
+    float* q0 = kKeepQ ? I.qseg + (long long)(kRecompute ? tt : n) * I.field + off0 : out1;
     const Rsrc Q0 = view(q0, g.plane);
-    const Rsrc Q1 = view(kRecompute && two ? q0 + I.field : out1, g.plane);
+    const Rsrc Q1 = view(kKeepQ && two ? q0 + I.field : out1, g.plane);
     const Lanes2 L = lanes2(g, t);
     const int2 sn = I.src.node[t.s];
     const unsigned rb = (unsigned)g.pitch * 4u;
     const unsigned own_mask = L.xin ? 0u : kOut;  // OR-ed into store offsets
     FrameRows fr{-1, -1};
-    if (!kRecompute) fr = frame_rowmap(rm, g, t);
+    if (kSample) fr = frame_rowmap(rm, g, t);
     const FastRows fast = fast_rows(g, t, L, fr, sn.x, two && !ck0 && !ck1);
 
     const int za0 = t.z0 - 4;
@@ -803,7 +808,7 @@ __global__ __launch_bounds__(256) void k_fwd_step2(const TileRec* __restrict__ t
                 const float un = fmaf(2.0f, q[j + 4], fmaf(-1.0f, p[S::even][j], qh));
                 b[S::cur][j] = un;
                 bst_row(O1, ow, (unsigned)j * rb, un);
-                if (kRecompute) bst_row(Q0, ow, (unsigned)j * rb, qh);
+                if (kKeepQ) bst_row(Q0, ow, (unsigned)j * rb, qh);
             }
             {
                 const float acc = lap8g<8>(fz, fx);
@@ -820,7 +825,7 @@ __global__ __launch_bounds__(256) void k_fwd_step2(const TileRec* __restrict__ t
                 const float qh = kp[S::prev][j] * acc;
                 const float un = fmaf(2.0f, v[j + 4], fmaf(-1.0f, q[j], qh));
                 bst_row(O2, ow2, (unsigned)j * rb, un);
-                if (kRecompute) bst_row(Q1, ow2, (unsigned)j * rb, qh);
+                if (kKeepQ) bst_row(Q1, ow2, (unsigned)j * rb, qh);
             }
             za += 4;
             o += 4 * rb;
@@ -850,8 +855,8 @@ __global__ __launch_bounds__(256) void k_fwd_step2(const TileRec* __restrict__ t
                     bst(C1P, oz, q[j + 4]);
                 }
                 bst(O1, oz, un);
-                if (kRecompute) bst(Q0, oz, qh);
-                if (!kRecompute) {
+                if (kKeepQ) bst(Q0, oz, qh);
+                if (kSample) {
                     const int slot = frame_slot(fr, z, t.z0);
                     if (slot >= 0 && L.xin) sample(rm, g, t.s, slot, L.xc, d, nt, n, un);
                 }
@@ -884,8 +889,8 @@ __global__ __launch_bounds__(256) void k_fwd_step2(const TileRec* __restrict__ t
                 const float un = fmaf(2.0f * A, v[j + 4], fmaf(-B, q[j], qh));
                 const unsigned oz = (o + (unsigned)j * rb - 4u * rb) | own_mask;
                 bst(O2, oz, un);
-                if (kRecompute) bst(Q1, oz, qh);
-                if (!kRecompute) {
+                if (kKeepQ) bst(Q1, oz, qh);
+                if (kSample) {
                     const int slot = frame_slot(fr, z, t.z0);
                     if (slot >= 0 && L.xin) sample(rm, g, t.s, slot, L.xc, d, nt, n + 1, un);
                 }
@@ -1379,10 +1384,13 @@ void launch_step(int kernel_id, hipStream_t st, const TileRec* tiles, int ntiles
     const dim3 grid((ntiles + kWaves - 1) / kWaves), block(64 * kWaves);
     switch (kernel_id) {
         case AAFWI_K_FWD_STEP:
-            hipLaunchKernelGGL((k_fwd_step<kUFwd, false>), grid, block, 0, st, tiles, ntiles, insts, a);
+            if (a.keep_q)
+                hipLaunchKernelGGL((k_fwd_step<kUFwd, kModeFwdQ>), grid, block, 0, st, tiles, ntiles, insts, a);
+            else
+                hipLaunchKernelGGL((k_fwd_step<kUFwd, kModeFwd>), grid, block, 0, st, tiles, ntiles, insts, a);
             break;
         case AAFWI_K_REC_STEP:
-            hipLaunchKernelGGL((k_fwd_step<kUFwd, true>), grid, block, 0, st, tiles, ntiles, insts, a);
+            hipLaunchKernelGGL((k_fwd_step<kUFwd, kModeRec>), grid, block, 0, st, tiles, ntiles, insts, a);
             break;
         case AAFWI_K_ADJ_STEP:
             hipLaunchKernelGGL(k_adj_step<kUAdj>, grid, block, 0, st, tiles, ntiles, insts, a);
@@ -1399,10 +1407,13 @@ void launch_step2(int kernel_id, hipStream_t st, const TileRec* tiles, int ntile
     const dim3 grid((ntiles + kWaves - 1) / kWaves), block(64 * kWaves);
     switch (kernel_id) {
         case AAFWI_K_FWD_STEP:
-            hipLaunchKernelGGL((k_fwd_step2<kUFwd, false>), grid, block, 0, st, tiles, ntiles, insts, a);
+            if (a.keep_q)
+                hipLaunchKernelGGL((k_fwd_step2<kUFwd, kModeFwdQ>), grid, block, 0, st, tiles, ntiles, insts, a);
+            else
+                hipLaunchKernelGGL((k_fwd_step2<kUFwd, kModeFwd>), grid, block, 0, st, tiles, ntiles, insts, a);
             break;
         case AAFWI_K_REC_STEP:
-            hipLaunchKernelGGL((k_fwd_step2<kUFwd, true>), grid, block, 0, st, tiles, ntiles, insts, a);
+            hipLaunchKernelGGL((k_fwd_step2<kUFwd, kModeRec>), grid, block, 0, st, tiles, ntiles, insts, a);
             break;
         case AAFWI_K_ADJ_STEP:
             hipLaunchKernelGGL(k_adj_step2<kUAdj>, grid, block, 0, st, tiles, ntiles, insts, a);
