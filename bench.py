@@ -4,13 +4,13 @@
 A step is one iteration of Algorithm 2 on the full FWI-gradient workload:
 768 x 256 interior grid (nx x nz), dx = 12.5 m, 20-cell sponge, dt = 1 ms,
 4000 time steps, 64 shots batched in every launch, 384 receivers per shot,
-AA depth M = 10.  The forward field the imaging condition needs is kept in
-full (q-hat of all 4000 steps, 228 GiB of HBM) when the device holds it, else
-as checkpoints every 50 steps with segments recomputed in the backward pass
-(--checkpoints forces this).  Each iteration runs the backward pass of the
-gradient (adjoint + imaging + fold, after the recompute with checkpoints) on
+wavefield checkpoints every 50 steps, AA depth M = 10.  Each iteration runs
+the backward pass of the gradient (recompute + adjoint + imaging + fold) on
 the forward run kept from the accepted line-search trial, the Anderson step,
-and the line-search forward run(s), each of which keeps its run.
+and the line-search forward run(s).  When the device holds q-hat of all 4000
+steps (235 GiB), the same iterations are timed a second time with that full
+storage instead of checkpoints (no recompute) and reported beside the
+headline as "full_storage".
 
 value = (forward + adjoint point-updates of one gradient, per iteration) /
 wall time, in G point-updates/s; a point-update advances one padded cell one
@@ -113,27 +113,114 @@ def source_digest():
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def measured_traffic(kernel: str, steps_per_launch: int, tiles: dict, section: str = "kernels"):
+def measured_traffic(kernel: str, steps_per_launch: int, tiles: dict, section: str = "kernels",
+                     full: bool = False):
     """HBM bytes per launch of ``kernel`` from the committed counter summary
     (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), or None
-    when it is missing or was taken on other kernel sources or another launch
-    shape (steps per launch, rows per wave, tile order).  ``section`` selects
-    the workload: "kernels" for the FWI-gradient grid, "large_kernels" for
-    the 1024 x 384, 96-shot grid."""
+    when it is missing or was taken on other kernel sources, another launch
+    shape (steps per launch, rows per wave, tile order) or the other storage
+    layout (with full storage the recompute slot holds the forward kernel
+    that keeps q-hat).  ``section`` selects the workload: "kernels" for the
+    FWI-gradient grid, "large_kernels" for the 1024 x 384, 96-shot grid."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as f:
             tr = json.load(f)
     except (OSError, ValueError):
         return None
-    if tr.get("source_sha256") != source_digest() or kernel not in tr.get(section, {}):
+    key = "kept_forward" if (kernel == "rec_step" and full) else kernel
+    if tr.get("source_sha256") != source_digest() or key not in tr.get(section, {}):
         return None
-    k = tr[section][kernel]
+    k = tr[section][key]
     kid = {v: i for i, v in NAMES.items()}[kernel]
     if (k.get("steps_per_launch") != steps_per_launch or k.get("rows") != tiles.get(kid)
             or k.get("order") != tiles.get(f"order{kid}", 0)):
         return None
     return round((k["fetch_kib"] * tr["fetch_factor"] + k["write_kib"] * tr["write_factor"]) * 1024.0)
+
+
+def timed_iterations(ctx, m0t, d_obs, args):
+    """Algorithm 2 from m0 on FWIProblem(ctx, d_obs): the first gradient and
+    args.warmup iterations untimed, then args.steps iterations timed (wall
+    clock, device synchronised on both sides) with HIP-event sampling of every
+    args.time_every-th stepping launch."""
+    import torch
+
+    from paper_2008_11778_amd.inversion import AADescent, FWIProblem
+
+    prob = FWIProblem(ctx, d_obs)
+    run = AADescent(prob, m0t, None, M=10)
+    rec = run.first()
+    log(f"k=0 J={rec.J:.6e} eta={run.eta:.3e}")
+    for _ in range(args.warmup):
+        rec = run.iterate()
+        log(f"warmup k={rec.k} J={rec.J:.6e} lam={rec.lam} mk={rec.mk}")
+    ctx.kernel_timing(args.time_every)
+    torch.cuda.synchronize()
+    n_adj0, n_fwd0 = prob.n_adj, prob.n_fwd
+    t0 = time.perf_counter()
+    recs = []
+    for _ in range(args.steps):
+        rec = run.iterate()
+        recs.append(rec)
+        log(f"step k={rec.k} J={rec.J:.6e} lam={rec.lam} mk={rec.mk} fwd={rec.n_fwd} t={rec.wall:.2f}s")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kt = {kid: ctx.kernel_timing_read(kid) for kid in (0, 1, 2)}
+    ctx.kernel_timing(0)
+    run.close()
+    return {"elapsed": elapsed, "n_adj": prob.n_adj - n_adj0, "n_fwd": prob.n_fwd - n_fwd0, "recs": recs, "kt": kt}
+
+
+def try_full_storage(ctx, dev) -> bool:
+    """Switch ctx to full storage when q-hat of every step fits in free device
+    memory with 8 GiB to spare."""
+    import torch
+
+    free, _ = torch.cuda.mem_get_info(dev)
+    need = ctx.full_storage_bytes()
+    ok = need + (8 << 30) < free
+    if ok:
+        ctx.set_full_storage(True)
+    log(f"full storage: {ok} (q-hat of every step {need / 2**30:.1f} GiB, device free {free / 2**30:.1f} GiB)")
+    return ok
+
+
+def full_storage_run(g, tiles, mt, m0t, dev, args, recs, upd_fwd, cells, sp):
+    """The timed iterations again on a context that keeps q-hat of every step
+    (the kept forward writes it, no segment is recomputed): same launch
+    shapes, same observed data, same iterates (gradients are bitwise those of
+    the checkpointed layout).  Not the configured workload (checkpoints every
+    50 steps); reported beside it."""
+    import torch
+
+    from paper_2008_11778_amd import Context, autotune
+
+    with Context(g, ckpt_every=50) as ctx:
+        autotune.apply(ctx, tiles)
+        if not try_full_storage(ctx, dev):
+            return None
+        gib = ctx.device_bytes() / 2**30
+        d_obs = ctx.forward_model(mt)
+        torch.cuda.synchronize()
+        it = timed_iterations(ctx, m0t, d_obs, args)
+        del d_obs
+    value = 2.0 * upd_fwd * it["n_adj"] / it["elapsed"] / 1e9
+    kern = {}
+    for kid, name in ((1, "kept_forward"), (2, "adj_step")):
+        mean_ms, cnt = it["kt"][kid]
+        if cnt:
+            b = (BYTES2[kid] if sp[kid] == 2 else BYTES[kid]) * cells * g.nshots
+            kern[name] = {"mean_us": round(mean_ms * 1e3, 2), "timed": cnt, "steps_per_launch": sp[kid],
+                          "bytes_per_launch": b, "gbs": round(b / (mean_ms / 1e3) / 1e9, 1)}
+    same = [r.J for r in it["recs"]] == [r.J for r in recs]
+    log(f"full storage: {value:.2f} G point-updates/s, same iterates: {same}")
+    return {"value": round(value, 2), "unit": "Gpt-updates/s",
+            "ms_per_step": round(it["elapsed"] / args.steps * 1e3, 2), "same_misfits": same,
+            "device_gib": round(gib, 1), "kernels": kern,
+            "note": "the same timed iterations with q-hat of all steps kept in HBM instead of checkpoints "
+                    "every 50 steps: the kept forward runs the recompute kernel's launch shape and writes "
+                    "q-hat as it steps, and the backward pass recomputes nothing"}
 
 
 def aa_step_timing(n, M=10, steps=30):
@@ -645,9 +732,11 @@ def main():
                     help="launch shape instead of autotuning: steps per launch of the forward, recompute and "
                          "adjoint kernels, rows per wave of the forward, recompute, adjoint and Born steps, and "
                          "optionally their tile orders, e.g. 1,1,2:8,64,20,64:1,0,0,0")
-    ap.add_argument("--checkpoints", action="store_true",
-                    help="keep the checkpointed layout (recompute in the backward pass) even where q-hat of "
-                         "every step fits in device memory")
+    ap.add_argument("--full-storage", action="store_true",
+                    help="time the headline iterations with q-hat of every step kept in device memory instead "
+                         "of the configured checkpoints every 50 steps")
+    ap.add_argument("--no-full-storage-run", action="store_true",
+                    help="skip the second timed run with full storage")
     ap.add_argument("--workload", default="fwi", choices=["fwi", "batched", "learned", "cnn", "noisy", "lsrtm", "target"])
     ap.add_argument("--target-iters", type=int, default=30, help="target workload: plain AA iterations")
     ap.add_argument("--budget", type=float, default=20, help="noisy workload: gradient evaluations per optimiser")
@@ -691,7 +780,6 @@ def main():
 
     import synth
     from paper_2008_11778_amd import Context
-    from paper_2008_11778_amd.inversion import AADescent, FWIProblem
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
@@ -720,13 +808,8 @@ def main():
         ctx.set_time_blocking(False)
     log(f"launch shape: {tiles}")
     full = False
-    if not args.checkpoints:
-        free, _ = torch.cuda.mem_get_info(dev)
-        need = ctx.full_storage_bytes()
-        if need + (8 << 30) < free:  # leave 8 GiB for everything else
-            ctx.set_full_storage(True)
-            full = True
-        log(f"full storage: {full} (q-hat of every step {need / 2**30:.1f} GiB, device free {free / 2**30:.1f} GiB)")
+    if args.full_storage:
+        full = try_full_storage(ctx, dev)
     log(f"device memory held by the context: {ctx.device_bytes() / 2**30:.1f} GiB")
     cells = g.nz_p * g.nx_p
     upd_fwd = float(cells) * g.nt * g.nshots
@@ -734,35 +817,10 @@ def main():
     mt = torch.from_numpy(m_true).to(dev)
     d_obs = ctx.forward_model(mt)  # synthetic observed data from the true model
     torch.cuda.synchronize()
-    prob = FWIProblem(ctx, d_obs)
-    run = AADescent(prob, m0t, None, M=10)
-    rec = run.first()
-    log(f"k=0 J={rec.J:.6e} eta={run.eta:.3e}")
-    for _ in range(args.warmup):
-        rec = run.iterate()
-        log(f"warmup k={rec.k} J={rec.J:.6e} lam={rec.lam} mk={rec.mk}")
-
-    ctx.kernel_timing(args.time_every)
-    torch.cuda.synchronize()
-    n_adj0, n_fwd0 = prob.n_adj, prob.n_fwd
-    t0 = time.perf_counter()
-    recs = []
-    for _ in range(args.steps):
-        rec = run.iterate()
-        recs.append(rec)
-        log(f"step k={rec.k} J={rec.J:.6e} lam={rec.lam} mk={rec.mk} fwd={rec.n_fwd} t={rec.wall:.2f}s")
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    elapsed = t1 - t0
-    n_adj, n_fwd = prob.n_adj - n_adj0, prob.n_fwd - n_fwd0
+    it = timed_iterations(ctx, m0t, d_obs, args)
+    elapsed, n_adj, n_fwd, recs, kt = it["elapsed"], it["n_adj"], it["n_fwd"], it["recs"], it["kt"]
     credited = 2.0 * upd_fwd * n_adj  # one forward and one adjoint per gradient
     value = credited / elapsed / 1e9
-
-    # kernel timing
-    kt = {}
-    for kid in (0, 1, 2):
-        mean_ms, cnt = ctx.kernel_timing_read(kid)
-        kt[kid] = (mean_ms, cnt)
     mask = ctx.time_blocking()
     sp = {k: 2 if mask >> k & 1 else 1 for k in range(3)}  # steps per launch
     k_ck = g.nt if full else 50
@@ -781,7 +839,8 @@ def main():
     per_launch_bytes = launch_bytes[dom]
     achieved = per_launch_bytes / mean_s / 1e9
     roofline = dict(kernel=NAMES[dom], bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
-                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(NAMES[dom], sp[dom], tiles),
+                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
+                    traffic=measured_traffic(NAMES[dom], sp[dom], tiles, full=full and dom == 1),
                     mean_launch_us=round(kt[dom][0] * 1e3, 2), timed_launches=kt[dom][1],
                     bytes_per_launch=per_launch_bytes, steps_per_launch=sp[dom])
     kernels = {NAMES[k]: dict(mean_us=round(kt[k][0] * 1e3, 2), timed=kt[k][1], steps_per_launch=sp[k],
@@ -833,6 +892,9 @@ def main():
         log(f"copy probe: {args.copy_probe} MiB x5, {gbs:.1f} GB/s (read + write)")
         del a, b
     ctx.close()
+    del d_obs
+    if not full and not args.no_full_storage_run:
+        out["full_storage"] = full_storage_run(g, tiles, mt, m0t, dev, args, recs, upd_fwd, cells, sp)
     out["aa_step"] = aa_step_timing(g.nz * g.nx)
     log(f"Anderson step: {out['aa_step']}")
     if not args.no_large:
