@@ -525,8 +525,9 @@ def target_workload(args):
     """Time to the misfit target on the FWI-gradient case: plain AA (M = 10)
     for args.target_iters iterations through the C-ABI problem sets the target
     J_K / J_0; the same run through the autograd form (torch.autograd over the
-    same forward and adjoint) is timed to the same target.  Both paths use the
-    same context, launch shapes and line search."""
+    same forward and adjoint) is timed to the same target, and so is the C-ABI
+    run with full storage of the forward field (no recompute) when the device
+    holds it.  All paths use the same context, launch shapes and line search."""
     import numpy as np
     import torch
 
@@ -542,8 +543,10 @@ def target_workload(args):
     d_obs = ctx.forward_model(torch.from_numpy(m_true).to(dev)).clone()
     torch.cuda.synchronize()
     runs = {}
-    for kind in ("c_abi", "autograd"):
-        prob = FWIProblem(ctx, d_obs) if kind == "c_abi" else AutogradFWIProblem(ctx, d_obs)
+    for kind in ("c_abi", "autograd", "c_abi_full_storage"):
+        if kind == "c_abi_full_storage" and not try_full_storage(ctx, dev):
+            continue
+        prob = AutogradFWIProblem(ctx, d_obs) if kind == "autograd" else FWIProblem(ctx, d_obs)
         run = AADescent(prob, m0t, None, M=10)
         torch.cuda.synchronize()
         t0 = time.perf_counter()

@@ -124,3 +124,22 @@ def test_full_storage_too_large_keeps_checkpoints():
         d = ctx.forward_model(T(m), keep_ckpt=True)
         torch.cuda.synchronize()
         assert torch.isfinite(d).all()
+
+
+def test_autograd_form_with_full_storage():
+    """The autograd form's backward runs on whatever the kept forward left:
+    with full storage its gradient is bitwise the checkpointed one."""
+    import torch
+    from paper_2008_11778_amd import Context
+    from paper_2008_11778_amd.inversion import AutogradFWIProblem
+    g, m = ragged_case(nshots=2, nt=97)
+    d_obs = np.zeros((g.nshots, g.nt, g.nrec), np.float32) + 0.25
+    grads = []
+    for full in (False, True):
+        with Context(g, ckpt_every=10) as ctx:
+            ctx.set_full_storage(full)
+            mt = T(m).reshape(-1)
+            gr = torch.empty_like(mt)
+            J = AutogradFWIProblem(ctx, T(d_obs)).gradient(mt, gr)
+            grads.append((gr.cpu().numpy(), J))
+    assert np.array_equal(grads[0][0], grads[1][0]) and grads[0][1] == grads[1][1]
