@@ -755,8 +755,8 @@ def main():
                     help="learned workload: held-out 1024x384, 96-shot, 4000-step models")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the shot-sharded multi-GPU "
-              "design is described in DESIGN.md and not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); sharding the shots over "
+              "several GPUs is not built", file=sys.stderr)
         sys.exit(2)
     if args.workload == "batched":
         return batched_workload(args)
