@@ -9,9 +9,9 @@
 // consecutive gradient differences (each difference formed exactly in FP64
 // from two FP32 values) and the right-hand side dG^T g_k.  Each step adds
 // one Gram row/column in a single pass over the window, then one workgroup
-// decomposes the Gram matrix (cyclic Jacobi, FP64): the oldest columns are
-// dropped while cond_2(A_k) = sqrt(lmax/lmin) exceeds cond_max, and
-// gamma = V diag(1/l) V^T rhs.  The mixing pass forms, per element in FP64,
+// decomposes the Gram matrix (Jacobi in parallel ordering, FP64): the oldest
+// columns are dropped while cond_2(A_k) = sqrt(lmax/lmin) exceeds cond_max,
+// and gamma = V diag(1/l) V^T rhs.  The mixing pass forms, per element in FP64,
 //   p_bar   = p_k - eta g_k
 //   p_tilde = p_bar - sum_i gamma_i [(p_{i+1} - p_i) - eta (g_{i+1} - g_i)].
 //
