@@ -57,14 +57,16 @@ enum ConvMode { kHidden = 0, kLast = 1, kInputGrad = 2 };
 // k = 32 ch + 8 g .. 8 g + 7, i.e. 8 consecutive channels of one tap.  w is
 // [tap][NOUT][C] bf16; every wave keeps all its weight fragments in
 // registers.  A block of four waves owns a 64-pixel-wide column segment of
-// one image over a run of rows and walks down it: an LDS ring of four row
-// slots holds input rows y-1 .. y+1 (columns x0-1 .. x0+64, zeros outside the
-// image), each output row adds one new input row, and the row after that is
-// fetched into registers while the current row runs on the matrix cores.  The
-// row being written is never one of the three being read, so one barrier per
-// row orders the two.  Wave w takes pixels x0+16w
-// .. x0+16w+15 and reads each A fragment as one 16-byte LDS load.
+// one image over a run of rows and walks down it two output rows per pass:
+// an LDS ring of six row slots holds input rows y-1 .. y+2 (columns x0-1 ..
+// x0+64, zeros outside the image), each pass adds two new input rows, and the
+// two after those are fetched into registers while the current pair runs on
+// the matrix cores (four independent accumulation chains per wave).  The
+// rows being written are never among the four being read, so one barrier per
+// pass orders the two.  Wave w takes pixels x0+16w .. x0+16w+15 and reads
+// each A fragment as one 16-byte LDS load.
 constexpr int kCSeg = 64;
+constexpr int kConvSlots = 6;  // LDS ring of staged input rows
 
 template <int C>
 struct RowFetch {
@@ -111,7 +113,7 @@ __global__ __launch_bounds__(256) void k_conv_mm(int B, int H, int W, int rows, 
     constexpr int RW = (kCSeg + 2) * CS;     // one staged row
     static_assert(MODE == kLast || NOUT == 32, "hidden and input-gradient layers have 32 outputs");
     constexpr int TS = NOUT + 8;             // transpose tile pixel stride
-    __shared__ __align__(16) bf16 xL[4 * RW];
+    __shared__ __align__(16) bf16 xL[kConvSlots * RW];
     __shared__ __align__(16) bf16 tL[4][16 * TS];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int i = lane & 15, grp = lane >> 4;
@@ -131,6 +133,7 @@ __global__ __launch_bounds__(256) void k_conv_mm(int B, int H, int W, int rows, 
         for (int nt = 0; nt < NT; ++nt)
             bw[ch][nt] = tap_ok[ch] ? ld8(w + ((tap * NOUT + nt * 16 + i) * C + c0)) : zero8();
     }
+    auto slot = [](int r) { return ((r + kConvSlots) % kConvSlots) * RW; };  // r >= -1
     const int segs_x = (W + kCSeg - 1) / kCSeg;
     const int runs = (H + rows - 1) / rows;
     const int nwork = B * runs * segs_x;
@@ -139,72 +142,91 @@ __global__ __launch_bounds__(256) void k_conv_mm(int B, int H, int W, int rows, 
         const int sx = wk % segs_x, t = wk / segs_x;
         const int run = t % runs, bimg = t / runs;
         const int x0 = sx * kCSeg, ya = run * rows, yb = min(H, ya + rows);
-        RowFetch<C> f;
+        RowFetch<C> f0, f1;
         __syncthreads();  // the ring's previous contents are no longer read
-        row_fetch<C>(f, x, bimg, H, W, ya - 1, x0);
-        row_store<C, CS>(f, xL + ((ya + 3) & 3) * RW);
-        row_fetch<C>(f, x, bimg, H, W, ya, x0);
-        row_store<C, CS>(f, xL + (ya & 3) * RW);
-        row_fetch<C>(f, x, bimg, H, W, ya + 1, x0);
-        for (int yy = ya; yy < yb; ++yy) {
-            // input row yy+1 into the slot of row yy-3, last read two rows ago
-            row_store<C, CS>(f, xL + ((yy + 1) & 3) * RW);
+        row_fetch<C>(f0, x, bimg, H, W, ya - 1, x0);
+        row_store<C, CS>(f0, xL + slot(ya - 1));
+        row_fetch<C>(f0, x, bimg, H, W, ya, x0);
+        row_store<C, CS>(f0, xL + slot(ya));
+        row_fetch<C>(f0, x, bimg, H, W, ya + 1, x0);
+        row_fetch<C>(f1, x, bimg, H, W, ya + 2, x0);
+        // two output rows (yy, yy+1) per pass: input rows yy-1 .. yy+2 are
+        // read; rows yy+1, yy+2 are stored at the start of the pass into the
+        // slots of rows yy-5, yy-4, which the previous pass no longer reads
+        for (int yy = ya; yy < yb; yy += 2) {
+            row_store<C, CS>(f0, xL + slot(yy + 1));
+            row_store<C, CS>(f1, xL + slot(yy + 2));
             __syncthreads();
-            if (yy + 1 < yb) row_fetch<C>(f, x, bimg, H, W, yy + 2, x0);  // in flight during the products
-            const int base[3] = {((yy + 3) & 3) * RW, (yy & 3) * RW, ((yy + 1) & 3) * RW};
-            v4f acc[NT];
+            if (yy + 2 < yb) {  // in flight during the products
+                row_fetch<C>(f0, x, bimg, H, W, yy + 3, x0);
+                row_fetch<C>(f1, x, bimg, H, W, yy + 4, x0);
+            }
+            const int base[4] = {slot(yy - 1), slot(yy), slot(yy + 1), slot(yy + 2)};
+            v4f acc[2][NT];
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt) acc[nt] = v4f{0.f, 0.f, 0.f, 0.f};
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) acc[h][nt] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int ch = 0; ch < NCH; ++ch) {
-                const int off = (rsel[ch] == 0 ? base[0] : rsel[ch] == 1 ? base[1] : base[2]) + cofs[ch] + px * CS;
-                const bf8 a = tap_ok[ch] ? __builtin_bit_cast(bf8, *reinterpret_cast<const v4u*>(xL + off)) : zero8();
+                const int rs = rsel[ch];
+                const int o0 = (rs == 0 ? base[0] : rs == 1 ? base[1] : base[2]) + cofs[ch] + px * CS;
+                const int o1 = (rs == 0 ? base[1] : rs == 1 ? base[2] : base[3]) + cofs[ch] + px * CS;
+                const bf8 a0 = tap_ok[ch] ? __builtin_bit_cast(bf8, *reinterpret_cast<const v4u*>(xL + o0)) : zero8();
+                const bf8 a1 = tap_ok[ch] ? __builtin_bit_cast(bf8, *reinterpret_cast<const v4u*>(xL + o1)) : zero8();
 #pragma unroll
-                for (int nt = 0; nt < NT; ++nt)
-                    acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[ch][nt], acc[nt], 0, 0, 0);
+                for (int nt = 0; nt < NT; ++nt) {
+                    acc[0][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, bw[ch][nt], acc[0][nt], 0, 0, 0);
+                    acc[1][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bw[ch][nt], acc[1][nt], 0, 0, 0);
+                }
             }
-            // lane holds D[4 grp + r][i]: pixel 16 wv + 4 grp + r of the segment, output channel nt*16 + i
-            const long long rowp = (long long)(bimg * H + yy) * W;
-            if (MODE == kLast) {
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int xx = x0 + 16 * wv + 4 * grp + r;
-                    if (xx < W && i == 0) z[rowp + xx] = acc[0][r];
-                }
-            } else {
-                // through the wave's LDS tile to one 16-byte store (8 channels of one pixel) per lane
-                bf16* tw = tL[wv];
+            for (int h = 0; h < 2; ++h) {
+                const int yo = yy + h;
+                if (yo >= yb) break;
+                // lane holds D[4 grp + r][i]: pixel 16 wv + 4 grp + r of the segment, output channel nt*16 + i
+                const long long rowp = (long long)(bimg * H + yo) * W;
+                if (MODE == kLast) {
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
-#pragma unroll
-                    for (int nt = 0; nt < NT; ++nt)
-                        tw[(4 * grp + r) * TS + nt * 16 + i] =
-                            f2bf(MODE == kHidden ? fmaxf(acc[nt][r], 0.f) : acc[nt][r]);
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                const int p = lane >> 2, cg = lane & 3;
-                const int xx = x0 + 16 * wv + p;
-                if (xx < W) {
-                    v4u v = *reinterpret_cast<const v4u*>(tw + p * TS + cg * 8);
-                    const long long o = (rowp + xx) * NOUT + cg * 8;
-                    if (MODE == kInputGrad) {
-                        // keep the gradient where the layer input (post-ReLU) is positive
-                        const v4u mk = *reinterpret_cast<const v4u*>(mask + o);
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            const unsigned lo = mk[q] & 0xffffu, hi = mk[q] >> 16;
-                            const unsigned keep = (bf2f((bf16)lo) > 0.f ? 0xffffu : 0u) |
-                                                  (bf2f((bf16)hi) > 0.f ? 0xffff0000u : 0u);
-                            v[q] &= keep;
-                        }
+                    for (int r = 0; r < 4; ++r) {
+                        const int xx = x0 + 16 * wv + 4 * grp + r;
+                        if (xx < W && i == 0) z[rowp + xx] = acc[h][0][r];
                     }
-                    *reinterpret_cast<v4u*>(y + o) = v;
+                } else {
+                    // through the wave's LDS tile to one 16-byte store (8 channels of one pixel) per lane
+                    bf16* tw = tL[wv];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+#pragma unroll
+                        for (int nt = 0; nt < NT; ++nt)
+                            tw[(4 * grp + r) * TS + nt * 16 + i] =
+                                f2bf(MODE == kHidden ? fmaxf(acc[h][nt][r], 0.f) : acc[h][nt][r]);
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    const int p = lane >> 2, cg = lane & 3;
+                    const int xx = x0 + 16 * wv + p;
+                    if (xx < W) {
+                        v4u v = *reinterpret_cast<const v4u*>(tw + p * TS + cg * 8);
+                        const long long o = (rowp + xx) * NOUT + cg * 8;
+                        if (MODE == kInputGrad) {
+                            // keep the gradient where the layer input (post-ReLU) is positive
+                            const v4u mk = *reinterpret_cast<const v4u*>(mask + o);
+#pragma unroll
+                            for (int q = 0; q < 4; ++q) {
+                                const unsigned lo = mk[q] & 0xffffu, hi = mk[q] >> 16;
+                                const unsigned keep = (bf2f((bf16)lo) > 0.f ? 0xffffu : 0u) |
+                                                      (bf2f((bf16)hi) > 0.f ? 0xffff0000u : 0u);
+                                v[q] &= keep;
+                            }
+                        }
+                        *reinterpret_cast<v4u*>(y + o) = v;
+                    }
+                    // the wave reads its transpose tile before it is rewritten
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                 }
-                // the wave reads its transpose tile before the next row rewrites it
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             }
         }
     }
