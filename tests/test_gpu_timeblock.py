@@ -1,8 +1,9 @@
 """Two time steps per launch against one step per launch: traces, misfits,
 gradients and Born-adjoint images must be bitwise equal (the two-step
 kernels evaluate every point with the one-step arithmetic in the same
-order), over ragged 56- and 64-column tilings, several strip heights, odd
-record lengths, odd and even checkpoint intervals, and uneven batches."""
+order), over a ragged 64-column tiling, several strip heights (ragged
+strips included), odd record lengths, odd and even checkpoint intervals, and
+uneven batches."""
 import numpy as np
 import pytest
 
@@ -18,8 +19,8 @@ def T(a):
 
 
 def ragged_case(nshots=3, nt=301):
-    """70 x 150 interior (90 x 170 padded: three full 56-column tiles and a
-    2-column tail; strips of more than 64 rows apply to the two-step kernels
+    """70 x 150 interior (90 x 170 padded: two full 64-column tiles and a
+    42-column tail; strips of more than 64 rows apply to the two-step kernels
     only), sources in a corner, mid-grid and the far edge,
     receivers in two rows including the edge columns and a shared node."""
     g, m = synth.small_case(nz=70, nx=150, nb=10, nt=nt, nshots=nshots, nrec=12, f0=20.0, instance=3)
