@@ -162,6 +162,18 @@ __global__ __launch_bounds__(256) void k_conv_mm(int B, int H, int W, int rows, 
                 row_fetch<C>(f1, x, bimg, H, W, yy + 4, x0);
             }
             const int base[4] = {slot(yy - 1), slot(yy), slot(yy + 1), slot(yy + 2)};
+            // input gradient: the ReLU masks of both output rows, read now so
+            // that they arrive during the products
+            const int mp = lane >> 2, mcg = lane & 3;
+            const int mxx = x0 + 16 * wv + mp;
+            v4u mk[2] = {v4u{0u, 0u, 0u, 0u}, v4u{0u, 0u, 0u, 0u}};
+            if (MODE == kInputGrad && mxx < W) {
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+                    if (yy + h < yb)
+                        mk[h] = *reinterpret_cast<const v4u*>(
+                            mask + ((long long)(bimg * H + yy + h) * W + mxx) * NOUT + mcg * 8);
+            }
             v4f acc[2][NT];
 #pragma unroll
             for (int h = 0; h < 2; ++h)
@@ -211,10 +223,9 @@ __global__ __launch_bounds__(256) void k_conv_mm(int B, int H, int W, int rows, 
                         const long long o = (rowp + xx) * NOUT + cg * 8;
                         if (MODE == kInputGrad) {
                             // keep the gradient where the layer input (post-ReLU) is positive
-                            const v4u mk = *reinterpret_cast<const v4u*>(mask + o);
 #pragma unroll
                             for (int q = 0; q < 4; ++q) {
-                                const unsigned lo = mk[q] & 0xffffu, hi = mk[q] >> 16;
+                                const unsigned lo = mk[h][q] & 0xffffu, hi = mk[h][q] >> 16;
                                 const unsigned keep = (bf2f((bf16)lo) > 0.f ? 0xffffu : 0u) |
                                                       (bf2f((bf16)hi) > 0.f ? 0xffff0000u : 0u);
                                 v[q] &= keep;
