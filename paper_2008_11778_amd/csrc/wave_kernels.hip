@@ -99,6 +99,17 @@ __device__ __forceinline__ void bst(Rsrc r, unsigned off, float v) {
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
 }
 
+// Streams touched once per pass (q-hat planes, checkpoint copies) carry the
+// non-temporal cache policy, so they do not push out of the caches the
+// planes that the next launch reads again (u^n, lam^n, the image).
+constexpr int kStream = 2;  // cache-policy operand: non-temporal
+__device__ __forceinline__ float bld_s(Rsrc r, unsigned off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, kStream));
+}
+__device__ __forceinline__ void bst_s(Rsrc r, unsigned off, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, kStream);
+}
+
 // Register blocking along z.  A lane advances U rows per block.  At the
 // start of the block for rows zb .. zb+U-1 it holds the z-queue q[0..U+8) =
 // u at rows zb-4 .. zb+U+3 and the per-row streams (u^{n-1}, Kp, halo, ...)
@@ -138,6 +149,12 @@ template <int U>
 __device__ __forceinline__ void rows_fetch(float (&v)[U], Rsrc R, unsigned o, unsigned rb) {
 #pragma unroll
     for (int i = 0; i < U; ++i) v[i] = bld(R, o + (unsigned)i * rb);
+}
+
+template <int U>
+__device__ __forceinline__ void rows_fetch_s(float (&v)[U], Rsrc R, unsigned o, unsigned rb) {
+#pragma unroll
+    for (int i = 0; i < U; ++i) v[i] = bld_s(R, o + (unsigned)i * rb);
 }
 
 template <int U>
@@ -365,11 +382,11 @@ __global__ __launch_bounds__(256) void k_fwd_step(const TileRec* __restrict__ ti
             const float qh = kv[j] * acc;
             const float un = fmaf(2.0f * A, c.q[j + 4], fmaf(-B, pv[j], qh));
             if (ck) {
-                bst(CU, oz, c.q[j + 4]);
-                bst(CUM, oz, pv[j]);
+                bst_s(CU, oz, c.q[j + 4]);
+                bst_s(CUM, oz, pv[j]);
             }
             bst(O, oz, un);
-            if (kKeepQ) bst(QR, oz, qh);
+            if (kKeepQ) bst_s(QR, oz, qh);
             if (kSample) {
                 const int slot = __builtin_amdgcn_readlane(my_rm, z - t.z0);
                 if (slot >= 0 && L.xin) sample(rm, g, t.s, slot, L.x, d, nt, n, un);
@@ -428,7 +445,7 @@ __global__ __launch_bounds__(256) void k_adj_step(const TileRec* __restrict__ ti
     rows_fetch(pv, UP, o, rb);
     rows_fetch(kv, KR, o, rb);
     rows_fetch(hv, UR, oh, rb);
-    rows_fetch(qv, QR, o, rb);
+    rows_fetch_s(qv, QR, o, rb);
     rows_fetch(gv, GI, o, rb);
     for (int zb = t.z0; zb < t.z1; zb += U, o += U * rb, oh += U * rb) {
         float nq[U], npv[U], nkv[U], nhv[U], nqv[U], ngv[U];
@@ -436,7 +453,7 @@ __global__ __launch_bounds__(256) void k_adj_step(const TileRec* __restrict__ ti
         rows_fetch(npv, UP, o + U * rb, rb);
         rows_fetch(nkv, KR, o + U * rb, rb);
         rows_fetch(nhv, UR, oh + U * rb, rb);
-        rows_fetch(nqv, QR, o + U * rb, rb);
+        rows_fetch_s(nqv, QR, o + U * rb, rb);
         rows_fetch(ngv, GI, o + U * rb, rb);
         stage(rows, c, hv, lane, L.hslot);
 #pragma unroll
@@ -629,6 +646,9 @@ struct IC {
 __device__ __forceinline__ void bst_row(Rsrc r, unsigned voff, unsigned soff, float v) {
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
 }
+__device__ __forceinline__ void bst_row_s(Rsrc r, unsigned voff, unsigned soff, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, kStream);
+}
 
 // Frame rows z0-4+i (i < 128) flagged in a two-word lane mask: whether rows
 // i0 .. i0+7 are all unflagged.
@@ -808,7 +828,7 @@ __global__ __launch_bounds__(256) void k_fwd_step2(const TileRec* __restrict__ t
                 const float un = fmaf(2.0f, q[j + 4], fmaf(-1.0f, p[S::even][j], qh));
                 b[S::cur][j] = un;
                 bst_row(O1, ow, (unsigned)j * rb, un);
-                if (kKeepQ) bst_row(Q0, ow, (unsigned)j * rb, qh);
+                if (kKeepQ) bst_row_s(Q0, ow, (unsigned)j * rb, qh);
             }
             {
                 const float acc = lap8g<8>(fz, fx);
@@ -825,7 +845,7 @@ __global__ __launch_bounds__(256) void k_fwd_step2(const TileRec* __restrict__ t
                 const float qh = kp[S::prev][j] * acc;
                 const float un = fmaf(2.0f, v[j + 4], fmaf(-1.0f, q[j], qh));
                 bst_row(O2, ow2, (unsigned)j * rb, un);
-                if (kKeepQ) bst_row(Q1, ow2, (unsigned)j * rb, qh);
+                if (kKeepQ) bst_row_s(Q1, ow2, (unsigned)j * rb, qh);
             }
             za += 4;
             o += 4 * rb;
@@ -847,15 +867,15 @@ __global__ __launch_bounds__(256) void k_fwd_step2(const TileRec* __restrict__ t
             if (z >= t.z0 && z < t.z1) {
                 const unsigned oz = (o + (unsigned)j * rb) | own_mask;
                 if (ck0) {
-                    bst(C0U, oz, q[j + 4]);
-                    bst(C0P, oz, p[S::even][j]);
+                    bst_s(C0U, oz, q[j + 4]);
+                    bst_s(C0P, oz, p[S::even][j]);
                 }
                 if (ck1) {
-                    bst(C1U, oz, un);
-                    bst(C1P, oz, q[j + 4]);
+                    bst_s(C1U, oz, un);
+                    bst_s(C1P, oz, q[j + 4]);
                 }
                 bst(O1, oz, un);
-                if (kKeepQ) bst(Q0, oz, qh);
+                if (kKeepQ) bst_s(Q0, oz, qh);
                 if (kSample) {
                     const int slot = frame_slot(fr, z, t.z0);
                     if (slot >= 0 && L.xin) sample(rm, g, t.s, slot, L.xc, d, nt, n, un);
@@ -889,7 +909,7 @@ __global__ __launch_bounds__(256) void k_fwd_step2(const TileRec* __restrict__ t
                 const float un = fmaf(2.0f * A, v[j + 4], fmaf(-B, q[j], qh));
                 const unsigned oz = (o + (unsigned)j * rb - 4u * rb) | own_mask;
                 bst(O2, oz, un);
-                if (kKeepQ) bst(Q1, oz, qh);
+                if (kKeepQ) bst_s(Q1, oz, qh);
                 if (kSample) {
                     const int slot = frame_slot(fr, z, t.z0);
                     if (slot >= 0 && L.xin) sample(rm, g, t.s, slot, L.xc, d, nt, n + 1, un);
@@ -998,8 +1018,8 @@ __global__ __launch_bounds__(256) void k_adj_step2(const TileRec* __restrict__ t
         // next block's rows so that waiting for them leaves those in flight
         float ia[4], ib[4], ig[4];
         if (two && za - 4 >= t.z0) {
-            rows_fetch(ia, QA, o - 4 * rb, rb);
-            rows_fetch(ib, QB, o - 4 * rb, rb);
+            rows_fetch_s(ia, QA, o - 4 * rb, rb);
+            rows_fetch_s(ib, QB, o - 4 * rb, rb);
             rows_fetch(ig, GI, o - 4 * rb, rb);
         } else {
 #pragma unroll
@@ -1063,7 +1083,7 @@ __global__ __launch_bounds__(256) void k_adj_step2(const TileRec* __restrict__ t
             if (z >= t.z0 && z < t.z1) {
                 const unsigned oz = (o + (unsigned)j * rb) | own_mask;
                 bst(O1, oz, ln);
-                if (!two) bst(GI, oz, fmaf(ln, bld(QA, oz), bld(GI, oz)));
+                if (!two) bst(GI, oz, fmaf(ln, bld_s(QA, oz), bld(GI, oz)));
             }
         }
         // step one at the frame columns, row za + sr (lanes 0-31; 32-63 repeat them)
