@@ -96,8 +96,9 @@ int aafwi_sync(aafwi_ctx* ctx);
 /* ---- forward modelling: f(m) = R F(m)  (eq. FWD, eq. FWI) ------------------ */
 
 /* m: device [nz][nx]; d: device [S][nt][R], overwritten.  If keep_ckpt != 0,
- * wavefield checkpoints are kept so that aafwi_adjoint_from_residual can run
- * the backward pass without a second forward. */
+ * the run is kept (wavefield checkpoints, or q-hat of every step with full
+ * storage, see aafwi_set_full_storage) so that aafwi_adjoint_from_residual
+ * can run the backward pass without a second forward. */
 int aafwi_forward_model(aafwi_ctx* ctx, const float* m, float* d, int keep_ckpt);
 
 /* r = d - d_obs (device [S][nt][R]; r may alias d) and J = 1/2 sum r^2 written
