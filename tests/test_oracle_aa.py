@@ -161,7 +161,7 @@ def test_two_loop_equals_dense_bfgs():
     np.testing.assert_allclose(H @ Y[-1], S[-1], rtol=1e-10, atol=1e-12)
 
 
-def test_lbfgs_converges_on_quadratic_and_wolfe_holds():
+def test_lbfgs_converges_on_quadratic_with_monotone_misfit():
     Amat, b = _lin_problem(n=20, seed=13, cond=100.0)
     fg = lambda p: (0.5 * np.sum((Amat @ p - b) ** 2), Amat.T @ (Amat @ p - b))
     xs = krylov.lbfgs(fg, np.zeros(20), M=5, iters=60)
