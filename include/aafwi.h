@@ -197,6 +197,43 @@ int aafwi_aa_set_weights(aafwi_aa* aa, const float* w);
 /* Condition number of A_k found by the last step (device double), for logs. */
 int aafwi_aa_last_cond(aafwi_aa* aa, double* cond_dev);
 
+/* ---- batched Anderson step (Algorithm 2, Steps 1-3, per instance) ---------- */
+
+/* Anderson state of `count` independent instances (instance i holds vectors
+ * of n[i] values; all share the depth M, 1..31, and the drop rule cond_max)
+ * whose steps run together: one launch prepares every window, one computes
+ * every new Gram row and right-hand side (kReduceBlocks partial sums per
+ * instance), one workgroup per instance solves its FP64 system, and one
+ * launch mixes every instance.  Each instance's arithmetic and summation
+ * order are those of aafwi_aa_step with the Gram solver (no damping, no
+ * weights), so its gamma, p_bar and p_tilde are bitwise the same.  The
+ * library owns the rings (2 (M+1) n[i] floats per instance), the FP64
+ * states and partial sums; all are allocated here.  Errors: AAFWI_E_INVALID
+ * for a bad count, n, M or cond_max; AAFWI_E_NOMEM. */
+typedef struct aafwi_batch_aa aafwi_batch_aa;
+int aafwi_batch_aa_create(int32_t count, const int64_t* n, int32_t M, double cond_max,
+                          aafwi_stream stream, aafwi_batch_aa** out);
+
+/* One step for every active instance i (active: host [count] mask, or NULL
+ * for all): p_bar[i] = G(p_k[i]) = p_k[i] - eta[i] g_k[i] and p_tilde[i] from
+ * the instance's window (eq. AA2_update); on an instance's first step (or
+ * after a reset) p_tilde[i] = p_bar[i].  p_k, g_k, p_bar, p_tilde: host
+ * arrays of device pointers (n[i] floats each; inactive entries may be
+ * NULL); eta: host array.  Inactive instances are left untouched. */
+int aafwi_batch_aa_step(aafwi_batch_aa* b, const float* const* p_k, const float* const* g_k,
+                        const float* eta, float* const* p_bar, float* const* p_tilde,
+                        const uint8_t* active);
+
+/* Clear the windows of the instances selected by `which` (host [count]
+ * mask, or NULL for all). */
+int aafwi_batch_aa_reset(aafwi_batch_aa* b, const uint8_t* which);
+
+/* Copy every instance's last gamma (device [count][M] doubles) and window
+ * size M_k (device [count] int32) out; either pointer may be NULL. */
+int aafwi_batch_aa_state(aafwi_batch_aa* b, double* gamma, int32_t* mk);
+
+int aafwi_batch_aa_destroy(aafwi_batch_aa* b);
+
 /* out = lambda*p_tilde + (1-lambda)*p_bar (Algorithm 2, Step 5), formed in
  * FP64 and rounded once; device [n]; out may alias either input. */
 int aafwi_blend(aafwi_stream stream, int64_t n, float lambda, const float* p_tilde,
@@ -277,6 +314,14 @@ int aafwi_batch_use_graphs(aafwi_batch* b, int enable);
 
 int aafwi_batch_device_bytes(const aafwi_batch* b, int64_t* bytes);
 int aafwi_batch_set_tile(aafwi_batch* b, int32_t kernel_id, int32_t rows_per_wave);
+
+/* Strip height of one instance for stepping kernel kernel_id (or -1 for all):
+ * rows per wave in [1, 120], or 0 to follow aafwi_batch_set_tile.  Instances
+ * of different grid classes can so take the heights the autotuner chose for
+ * their class while sharing every launch (the launch mode, one or two steps
+ * per launch, stays common to the batch).  Results do not depend on it
+ * (bitwise); captured graphs are rebuilt on their next use. */
+int aafwi_batch_set_instance_tile(aafwi_batch* b, int32_t inst, int32_t kernel_id, int32_t rows_per_wave);
 int aafwi_batch_kernel_timing(aafwi_batch* b, int every);
 int aafwi_batch_kernel_timing_read(aafwi_batch* b, int kernel_id, double* mean_ms, int64_t* count);
 
@@ -333,7 +378,10 @@ int aafwi_cnn_train_step(aafwi_cnn* c, int32_t B, const float* g, const float* m
 #define AAFWI_K_BORN_STEP  3 /* background + scattered pair step                  */
 
 /* Enable (every > 0) or disable (0) event timing of every `every`-th launch
- * of each stepping kernel on the context's stream; the counters are reset. */
+ * of each stepping kernel on the context's stream; the counters are reset.
+ * Event pairs are read back and reused once their launch has completed, so
+ * the sample covers every `every`-th launch of a run of any length (a
+ * launch is skipped only while all 4096 pairs are still in flight). */
 int aafwi_kernel_timing(aafwi_ctx* ctx, int every);
 
 /* Synchronise and return the mean duration in ms and the number of timed
@@ -348,9 +396,11 @@ int aafwi_set_tile(aafwi_ctx* ctx, int32_t kernel_id, int32_t rows_per_wave);
 
 /* Order of the wave tiles of stepping kernel kernel_id (or -1 for all) in
  * its launch: 0 = the x-tiles of one strip are adjacent (default), 1 = the
- * strips of one tile column are adjacent.  Adjacent tiles run at about the
- * same time on one XCD, so the order decides whether the x-halo or the
- * strip-overlap re-reads hit in L2.  Results do not depend on it (bitwise). */
+ * strips of one tile column are adjacent, G in 2..64 = the same tile of G
+ * consecutive shots is adjacent (x-tiles of a strip next, then strips).
+ * Adjacent tiles run at about the same time on one XCD, so the order decides
+ * whether the x-halo, the strip-overlap or the shared Kp re-reads hit in L2.
+ * Results do not depend on it (bitwise). */
 int aafwi_set_tile_order(aafwi_ctx* ctx, int32_t kernel_id, int32_t order);
 
 /* Current strip height of stepping kernel kernel_id. */
@@ -371,6 +421,8 @@ int aafwi_set_time_blocking_kernel(aafwi_ctx* ctx, int32_t kernel_id, int enable
 /* mask: bit k set when kernel k advances two steps per launch. */
 int aafwi_get_time_blocking(const aafwi_ctx* ctx, int* mask);
 int aafwi_batch_set_time_blocking(aafwi_batch* b, int enable);
+/* mask of the batch's launch modes, as for aafwi_get_time_blocking. */
+int aafwi_batch_get_time_blocking(const aafwi_batch* b, int* mask);
 
 /* Thread-local message for the last non-zero return on this thread. */
 const char* aafwi_last_error(void);

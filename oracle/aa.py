@@ -23,7 +23,11 @@ Readings taken where the paper leaves a choice (each listed in the design
 notes): the least-squares solve here is numpy's SVD-based lstsq on A_k
 itself; columns are dropped oldest first while cond_2(A_k) exceeds
 ``cond_max``; lambda is tried in {1, 1/2, 1/4, 1/8} with the Armijo test
-J(p) <= J(p_k) + c1 <g_k, p - p_k>, falling back to lambda = 0 untested.
+J(p) <= J(p_k) + c1 <g_k, p - p_k>, falling back to lambda = 0 untested;
+when such a fallback step then turns out to have decreased J, the window is
+cleared and mixing restarts from it (a restart safeguard in the manner of
+damped AA with restarts, Henderson and Varadhan 2019; the paper leaves the
+fallback's effect on the window open).
 """
 from __future__ import annotations
 
@@ -169,11 +173,17 @@ def multisecant_matrix(P: np.ndarray, D: np.ndarray) -> np.ndarray:
 # ----------------------------------------------------------------------------
 
 def alg2(grad_fn, misfit_fn, p0, eta, M, iters, cond_max=COND_MAX, lambdas=LAMBDAS,
-         c1=ARMIJO_C1, linesearch=True, beta=1.0, weights=None):
+         c1=ARMIJO_C1, linesearch=True, beta=1.0, weights=None, restart=True):
     """Run Algorithm 2 for ``iters`` AA iterations after p_1 = G(p_0).
 
     grad_fn(p) -> (J, g); misfit_fn(p) -> J.  Returns a dict with the
     accepted iterates, misfits, chosen lambdas and evaluation counts.
+    With ``restart``, when the search of iteration k fell back to
+    lambda = 0 and that plain descent step decreased the misfit
+    (J(p_{k+1}) < J(p_k), known from the gradient evaluation at p_{k+1}),
+    the window is cleared before p_{k+1} enters it: Anderson mixing
+    restarts from the descent step (M_k counts the iterations since the
+    restart).  A descent step that did not decrease J keeps the window.
     """
     hist = AAHistory(M, cond_max, beta, weights)
     p = np.asarray(p0, np.float64).ravel().copy()
@@ -184,10 +194,15 @@ def alg2(grad_fn, misfit_fn, p0, eta, M, iters, cond_max=COND_MAX, lambdas=LAMBD
     n_grad, n_fwd = 1, 0
     p = p - eta * g0
     iterates.append(p.copy())
+    fell_back = False
+    restarts = []  # iterations k whose window was cleared before p_k entered
     for _ in range(iters):
         J, g = grad_fn(p)
         g = np.asarray(g, np.float64).ravel()
         n_grad += 1
+        if restart and fell_back and J < misfits[-1]:
+            hist.reset()
+            restarts.append(len(misfits))
         misfits.append(J)
         pbar, ptilde, gamma, mk = hist.step(p, g, eta)
         gammas.append(gamma)
@@ -204,9 +219,86 @@ def alg2(grad_fn, misfit_fn, p0, eta, M, iters, cond_max=COND_MAX, lambdas=LAMBD
         else:
             lam_acc, new = 1.0, ptilde
         lams.append(lam_acc)
+        fell_back = linesearch and lam_acc == 0.0
         p = new.copy()
         iterates.append(p.copy())
     return dict(iterates=iterates, misfits=misfits, lambdas=lams, gammas=gammas,
+                n_grad=n_grad, n_fwd=n_fwd, restarts=restarts)
+
+
+def learned_alg2(grad_fn, misfit_fn, dir_fn, p0, eta, eta_theta, M, iters, cond_max=COND_MAX,
+                 lambdas=LAMBDAS, c1=ARMIJO_C1, restart=True):
+    """Algorithm 2 on the learned map G_theta(p) = p - eta_theta d(p), with
+    d = dir_fn(g, p) the network's direction at p (its gradient g), and
+    plain Anderson acceleration on G(p) = p - eta g as the fallback.
+
+    Both windows are fed at every iteration: (p_k, d_k) for G_theta and
+    (p_k, g_k) for G.  Step 4 backtracks over ``lambdas`` between
+    ptilde_theta and pbar_theta with the sufficient-decrease test on the true
+    gradient, J(p) <= J(p_k) + c1 <g_k, p - p_k>.  When no lambda passes,
+    pbar_theta is taken if J(pbar_theta) < J(p_k) (one more forward run);
+    otherwise the iteration is redone on the plain window (the fallback):
+    the same backtracking between its ptilde and pbar, and its pbar if no
+    lambda passes.  A window whose search ended on its pbar restarts at the
+    next iteration if that iteration's J is below the previous one (as in
+    ``alg2``).  Returns the accepted iterates, misfits, directions d_k,
+    lambdas, fallback flags and evaluation counts."""
+    h_t = AAHistory(M, cond_max)
+    h_p = AAHistory(M, cond_max)
+    p = np.asarray(p0, np.float64).ravel().copy()
+    J, g = grad_fn(p)
+    g = np.asarray(g, np.float64).ravel()
+    d = np.asarray(dir_fn(g, p), np.float64).ravel()
+    iterates, misfits, dirs, lams, fallbacks = [p.copy()], [J], [d], [], []
+    n_grad, n_fwd = 1, 0
+    pbar_t = h_t.step(p, d, eta_theta)[0]
+    h_p.step(p, g, eta)
+    p = pbar_t.copy()
+    iterates.append(p.copy())
+    fb_t = fb_p = False
+
+    def search(ptilde, pbar, J, g, p):
+        nonlocal n_fwd
+        for lam in lambdas:
+            trial = lam * ptilde + (1.0 - lam) * pbar
+            n_fwd += 1
+            if misfit_fn(trial) <= J + c1 * float(np.dot(g, trial - p)):
+                return lam, trial
+        return 0.0, None
+
+    for _ in range(iters):
+        J, g = grad_fn(p)
+        g = np.asarray(g, np.float64).ravel()
+        n_grad += 1
+        if restart and J < misfits[-1]:
+            if fb_t:
+                h_t.reset()
+            if fb_p:
+                h_p.reset()
+        misfits.append(J)
+        d = np.asarray(dir_fn(g, p), np.float64).ravel()
+        dirs.append(d)
+        pbar_t, ptilde_t, _, _ = h_t.step(p, d, eta_theta)
+        pbar_p, ptilde_p, _, _ = h_p.step(p, g, eta)
+        fb_t = fb_p = False
+        fell = False
+        lam, new = search(ptilde_t, pbar_t, J, g, p)
+        if new is None:
+            fb_t = True
+            n_fwd += 1
+            if misfit_fn(pbar_t) < J:
+                new = pbar_t
+            else:
+                fell = True
+                lam, new = search(ptilde_p, pbar_p, J, g, p)
+                if new is None:
+                    fb_p = True
+                    new = pbar_p
+        lams.append(lam)
+        fallbacks.append(fell)
+        p = new.copy()
+        iterates.append(p.copy())
+    return dict(iterates=iterates, misfits=misfits, dirs=dirs, lambdas=lams, fallbacks=fallbacks,
                 n_grad=n_grad, n_fwd=n_fwd)
 
 

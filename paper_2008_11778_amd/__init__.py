@@ -7,7 +7,7 @@ behind the C ABI of ``libaafwi.so`` (declared in ``include/aafwi.h``);
 its comparators on top of it.  The binding is loaded on first use, so the
 build module can be imported before the library exists.
 """
-_EXPORTS = ("AA", "AafwiError", "Batch", "CNN", "Context", "Reducer", "axpy", "blend", "scale", "K_ADJ_STEP", "K_BORN_STEP",
+_EXPORTS = ("AA", "AafwiError", "Batch", "BatchAA", "CNN", "Context", "Reducer", "axpy", "blend", "scale", "K_ADJ_STEP", "K_BORN_STEP",
             "K_FWD_STEP", "K_REC_STEP", "LIB_PATH")
 
 

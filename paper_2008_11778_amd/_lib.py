@@ -63,6 +63,13 @@ _sig("aafwi_device_bytes", _vp, ctypes.POINTER(_i64))
 _sig("aafwi_sync", _vp)
 _sig("aafwi_forward_model", _vp, _vp, _vp, ctypes.c_int)
 _sig("aafwi_residual_misfit", _vp, _vp, _vp, _vp, _vp)
+_sig("aafwi_batch_aa_create", ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.c_int32, ctypes.c_double, _vp,
+     ctypes.POINTER(_vp))
+_sig("aafwi_batch_aa_step", _vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_float),
+     ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_uint8))
+_sig("aafwi_batch_aa_reset", _vp, ctypes.POINTER(ctypes.c_uint8))
+_sig("aafwi_batch_aa_state", _vp, _vp, _vp)
+_sig("aafwi_batch_aa_destroy", _vp)
 _sig("aafwi_adjoint_gradient", _vp, _vp, _vp, _vp, _vp)
 _sig("aafwi_adjoint_from_residual", _vp, _vp, _vp)
 _sig("aafwi_born", _vp, _vp, _vp, _vp)
@@ -93,6 +100,7 @@ _sig("aafwi_get_time_blocking", _vp, ctypes.POINTER(ctypes.c_int))
 _sig("aafwi_set_full_storage", _vp, ctypes.c_int)
 _sig("aafwi_get_full_storage", _vp, ctypes.POINTER(ctypes.c_int))
 _sig("aafwi_batch_set_time_blocking", _vp, ctypes.c_int)
+_sig("aafwi_batch_get_time_blocking", _vp, ctypes.POINTER(ctypes.c_int))
 _sig("aafwi_batch_destroy", _vp)
 _sig("aafwi_batch_misfits", _vp, _vp)
 _sig("aafwi_batch_set_active", _vp, _vp)
@@ -101,6 +109,7 @@ _sig("aafwi_batch_backward", _vp)
 _sig("aafwi_batch_use_graphs", _vp, ctypes.c_int)
 _sig("aafwi_batch_device_bytes", _vp, ctypes.POINTER(_i64))
 _sig("aafwi_batch_set_tile", _vp, _i32, _i32)
+_sig("aafwi_batch_set_instance_tile", _vp, _i32, _i32, _i32)
 _sig("aafwi_batch_kernel_timing", _vp, ctypes.c_int)
 _sig("aafwi_batch_kernel_timing_read", _vp, ctypes.c_int, ctypes.POINTER(_f64), ctypes.POINTER(_i64))
 _lib.aafwi_last_error.argtypes = []
@@ -386,6 +395,16 @@ class Batch:
     def set_tile(self, rows_per_wave: int, kernel_id: int = -1):
         _check(_lib.aafwi_batch_set_tile(self._h, int(kernel_id), int(rows_per_wave)))
 
+    def set_instance_tile(self, inst: int, rows_per_wave: int, kernel_id: int = -1):
+        """Strip height of one instance (0 = the batch setting)."""
+        _check(_lib.aafwi_batch_set_instance_tile(self._h, int(inst), int(kernel_id), int(rows_per_wave)))
+
+    def time_blocking(self) -> int:
+        """Bit k set when stepping kernel k runs two steps per launch."""
+        v = ctypes.c_int(0)
+        _check(_lib.aafwi_batch_get_time_blocking(self._h, ctypes.byref(v)))
+        return int(v.value)
+
     def device_bytes(self) -> int:
         v = _i64()
         _check(_lib.aafwi_batch_device_bytes(self._h, ctypes.byref(v)))
@@ -468,6 +487,60 @@ class AA:
     def close(self):
         if getattr(self, "_h", None):
             _check(_lib.aafwi_aa_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class BatchAA:
+    """Anderson state of many instances stepped together (one launch
+    sequence for all of them); instance i holds vectors of ns[i] values."""
+
+    def __init__(self, ns, M: int, cond_max: float = 1e5, stream=None):
+        self.ns = [int(x) for x in ns]
+        self.N, self.M = len(self.ns), int(M)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        arr = (ctypes.c_int64 * self.N)(*self.ns)
+        h = _vp()
+        _check(_lib.aafwi_batch_aa_create(self.N, arr, self.M, float(cond_max), _stream_handle(self.stream),
+                                          ctypes.byref(h)))
+        self._h = h
+        self.gamma = torch.zeros(self.N, self.M, dtype=torch.float64, device=self.device)
+        self.mk = torch.zeros(self.N, dtype=torch.int32, device=self.device)
+
+    def _ptrs(self, ts, name, active):
+        out = (_vp * self.N)()
+        for i, t in enumerate(ts):
+            if active is None or active[i]:
+                out[i] = _ptr(t, numel=self.ns[i], name=f"{name}[{i}]")
+        return out
+
+    def step(self, ps, gs, etas, pbars, ptildes, active=None):
+        """pbar[i] = G(p[i]) and ptilde[i] for every active instance."""
+        act = None if active is None else (ctypes.c_uint8 * self.N)(*[1 if a else 0 for a in active])
+        eta = (ctypes.c_float * self.N)(*[float(e) for e in etas])
+        _check(_lib.aafwi_batch_aa_step(self._h, self._ptrs(ps, "p", active), self._ptrs(gs, "g", active), eta,
+                                        self._ptrs(pbars, "p_bar", active), self._ptrs(ptildes, "p_tilde", active),
+                                        act))
+
+    def reset(self, which=None):
+        w = None if which is None else (ctypes.c_uint8 * self.N)(*[1 if a else 0 for a in which])
+        _check(_lib.aafwi_batch_aa_reset(self._h, w))
+
+    def state(self):
+        """(gamma [N][M] float64, mk [N] int32) of the last step, on the device."""
+        _check(_lib.aafwi_batch_aa_state(self._h, _ptr(self.gamma, torch.float64, self.N * self.M, "gamma"),
+                                         _ptr(self.mk, torch.int32, self.N, "mk")))
+        return self.gamma, self.mk
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(_lib.aafwi_batch_aa_destroy(self._h))
             self._h = None
 
     def __del__(self):

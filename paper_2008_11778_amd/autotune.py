@@ -128,6 +128,8 @@ def tune(geom, m, candidates=CANDIDATES, nt=48, use_cache=True, verbose=False) -
         out[k], out[f"order{k}"] = rows, order
         if k < 3:
             out[f"two{k}"] = bool(two)
+            # the best height of each mode, for batches whose mode is fixed
+            out[f"rows_one{k}"], out[f"rows_two{k}"] = best[(False, k)][1], best[(True, k)][1]
         if verbose:
             print(f"autotune {key} kernel {k}: {'two' if two else 'one'}-step, rows {rows}, order {order}, "
                   f"{t * 1e3:.1f} us per step", flush=True)
@@ -152,3 +154,38 @@ def apply(ctx, tiles: dict):
             ctx.set_tile(int(tiles[k]), k)
         if f"order{k}" in tiles:
             ctx.set_tile_order(int(tiles[f"order{k}"]), k)
+
+
+def class_rows(entry: dict, k: int, two: bool) -> int:
+    """Strip height of kernel k for a launch mode from a tune() entry; 0 (the
+    library default) when the entry holds no height for that mode."""
+    if k < 3 and f"rows_{'two' if two else 'one'}{k}" in entry:
+        return int(entry[f"rows_{'two' if two else 'one'}{k}"])
+    if k == 3 or bool(entry.get(f"two{k}", False)) == two:
+        return int(entry.get(k, 0))
+    return 0
+
+
+def tune_batch(batch, geoms, models, shots: int = 8, use_cache=True, verbose=False) -> dict:
+    """Per-grid-class strip heights for a batch of uneven instances.
+
+    Instances with the same padded grid form a class; each class is tuned
+    once (tune() on its first instance with at most ``shots`` shots, from the
+    caches when they hold it) and every instance of the class takes that
+    class's height for the batch's own launch mode (one mode per kernel is
+    shared by the whole batch, since one launch covers every instance).
+    Returns {class key: {kernel: rows}}."""
+    mask = batch.time_blocking()
+    chosen = {}
+    for i, (g, m) in enumerate(zip(geoms, models)):
+        cls = (g.nz + 2 * g.nb, g.nx + 2 * g.nb)
+        if cls not in chosen:
+            S = int(np.asarray(g.src_iz).size)
+            sub = g.subset_shots(list(range(min(S, shots)))) if hasattr(g, "subset_shots") else g
+            entry = tune(sub, m, use_cache=use_cache, verbose=verbose)
+            chosen[cls] = {k: class_rows(entry, k, bool(mask >> k & 1) if k < 3 else False) for k in KERNELS}
+        for k, rows in chosen[cls].items():
+            batch.set_instance_tile(i, rows, k)
+    if verbose:
+        print(f"autotune batch: per-class heights {chosen} (modes {mask})", flush=True)
+    return {f"{a}x{b}": v for (a, b), v in chosen.items()}

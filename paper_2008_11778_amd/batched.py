@@ -9,7 +9,8 @@ is accepted keeps that forward run for its next gradient.
 
 With the same inputs this produces, instance by instance, the same iterates
 as ``inversion.AADescent`` on separate contexts (the kernels and their
-arithmetic order are identical).
+arithmetic order are identical), restarts of the Anderson window after a
+fallback step that decreased J included.
 """
 from __future__ import annotations
 
@@ -18,14 +19,15 @@ import time
 import numpy as np
 import torch
 
-from ._lib import AA, Batch, Reducer, axpy, blend
+from ._lib import Batch, BatchAA, Reducer, axpy, blend
 from .inversion import ARMIJO_C1, LAMBDAS
 
 
 class BatchedAADescent:
     def __init__(self, batch: Batch, p0, M: int, etas=None, eta_frac: float = 0.02, cond_max: float = 1e5,
-                 lambdas=LAMBDAS, c1: float = ARMIJO_C1):
+                 lambdas=LAMBDAS, c1: float = ARMIJO_C1, restart: bool = True):
         self.b = batch
+        self.restart = restart
         self.N = batch.N
         self.M, self.lambdas, self.c1, self.eta_frac = M, lambdas, c1, eta_frac
         self.etas = None if etas is None else [float(e) for e in etas]
@@ -35,9 +37,13 @@ class BatchedAADescent:
             self.pbar = [torch.empty_like(x) for x in self.p]
             self.ptilde = [torch.empty_like(x) for x in self.p]
             self.slope = torch.zeros(self.N, dtype=torch.float64, device=batch.device)
-        self.aa = [AA(x.numel(), M, cond_max, stream=s) for x in self.p]
+        # one Anderson state for all instances: every step is one launch
+        # sequence over the whole batch
+        self.aa = BatchAA([x.numel() for x in self.p], M, cond_max, stream=s) if M > 0 else None
         self.red = Reducer(stream=s)
         self.kept_ok = [False] * self.N
+        self.fell_back = [False] * self.N
+        self.J_prev = None
         self.k = 0
         self.n_forward_launches = 0
         self.n_backward_launches = 0
@@ -73,18 +79,19 @@ class BatchedAADescent:
 
     def _anderson(self):
         s = self.b.stream
+        if self.aa is not None:
+            self.aa.step(self.p, [self._g(i) for i in range(self.N)], self.etas, self.pbar, self.ptilde)
+            return
         for i in range(self.N):
-            if self.M > 0:
-                self.aa[i].step(self.p[i], self._g(i), self.etas[i], self.pbar[i], self.ptilde[i])
-            else:
-                blend(1.0, self.p[i], self.p[i], self.pbar[i], stream=s)
-                axpy(-self.etas[i], self._g(i), self.pbar[i], stream=s)
-                blend(1.0, self.pbar[i], self.pbar[i], self.ptilde[i], stream=s)
+            blend(1.0, self.p[i], self.p[i], self.pbar[i], stream=s)
+            axpy(-self.etas[i], self._g(i), self.pbar[i], stream=s)
+            blend(1.0, self.pbar[i], self.pbar[i], self.ptilde[i], stream=s)
 
     # -- Algorithm 2 -------------------------------------------------------------
     def first(self):
         """g_0 at p_0 for every instance, then p_1 = G(p_0)."""
         J = self._gradients()
+        self.J_prev = np.array(J, np.float64)
         if self.etas is None:
             self.etas = []
             with torch.cuda.stream(self.b.stream):
@@ -106,6 +113,11 @@ class BatchedAADescent:
         s = self.b.stream
         self.k += 1
         J = self._gradients()
+        # restart after a fallback step that decreased J (as in AADescent)
+        which = [self.restart and self.fell_back[i] and J[i] < self.J_prev[i] for i in range(self.N)]
+        if self.aa is not None and any(which):
+            self.aa.reset(which)
+        self.J_prev = np.array(J, np.float64)
         self._anderson()
         pending = [True] * self.N
         lam = [0.0] * self.N
@@ -129,6 +141,7 @@ class BatchedAADescent:
                     lam[i] = lv
                     J_next[i] = Jt[i]
                     pending[i] = False
+        self.fell_back = list(pending)
         for i in range(self.N):
             if pending[i]:
                 with torch.cuda.stream(s):
@@ -139,6 +152,6 @@ class BatchedAADescent:
         return J, lam, J_next
 
     def close(self):
-        for a in self.aa:
-            a.close()
-        self.aa = []
+        if self.aa is not None:
+            self.aa.close()
+            self.aa = None

@@ -207,7 +207,9 @@ class LBFGS:
             return cache[a]
 
         a = strong_wolfe(lambda a: ev(a)[0], lambda a: ev(a)[1], self.J, d0, a1=a1)
-        Jn, _, pn, gn = ev(a)
+        Jn, dn0, pn, gn = ev(a)
+        # the accepted step: J and the directional derivative at both ends
+        self.last_step = {"alpha": a, "J0": self.J, "d0": d0, "J": Jn, "slope": dn0, "c2": 0.9}
         s = torch.empty_like(self.p)
         blend(1.0, pn, pn, s)
         axpy(-1.0, self.p, s)
@@ -266,7 +268,8 @@ class NCG:
             return cache[a]
 
         a = strong_wolfe(lambda a: ev(a)[0], lambda a: ev(a)[1], self.J, d0, a1=self.a_init, c2=self.c2)
-        Jn, _, pn, gn = ev(a)
+        Jn, dn0, pn, gn = ev(a)
+        self.last_step = {"alpha": a, "J0": self.J, "d0": d0, "J": Jn, "slope": dn0, "c2": self.c2}
         gg = float(red.dot(self.g, self.g).item())
         beta = max(0.0, float(red.dot_diff(gn, gn, self.g).item()) / gg)
         dn = _scale_into(beta, d, torch.empty_like(d))

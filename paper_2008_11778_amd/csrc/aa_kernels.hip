@@ -26,7 +26,9 @@
 // of R is that of dG, so the solve is not squared as in the Gram form; the
 // drop rule is the same (cond_2(R) = sqrt(lmax/lmin) of R^T R).
 #include <cmath>
+#include <algorithm>
 #include <new>
+#include <vector>
 
 #include "common.hpp"
 
@@ -55,8 +57,7 @@ __device__ __forceinline__ double wave_reduce(double v) {
     return v;
 }
 
-__global__ void k_aa_prepare(AAState* s, int cap) {
-    if (threadIdx.x != 0) return;
+__device__ __forceinline__ void aa_prepare_body(AAState* s, int cap) {
     if (s->count == cap) {
         // drop the oldest iterate and its gradient difference
         const int ndg = s->count - 1;
@@ -68,23 +69,25 @@ __global__ void k_aa_prepare(AAState* s, int cap) {
     s->slot_new = (s->head + s->count) % cap;
 }
 
+__global__ void k_aa_prepare(AAState* s, int cap) {
+    if (threadIdx.x != 0) return;
+    aa_prepare_body(s, cap);
+}
+
 // One pass: copy (p_new, g_new) into the ring and accumulate, per block,
 //   cross[i] = dnew . dG_i (i < cnt-1), cross[cnt-1] = dnew . dnew,
 //   rhs[i]   = dG_i . g_new (i < cnt-1), rhs[cnt-1] = dnew . g_new,
 // with dnew = g_new - g_{cnt-1}.
 template <int CAP>
-__global__ __launch_bounds__(kReduceThreads) void k_aa_dots(long long n, const float* __restrict__ p_new,
-                                                            const float* __restrict__ g_new,
-                                                            float* __restrict__ ring_p,
-                                                            float* __restrict__ ring_g, int cap,
-                                                            const AAState* __restrict__ s,
-                                                            const float* __restrict__ w,
-                                                            double* __restrict__ part) {
+__device__ __forceinline__ void aa_dots_body(long long n, const float* __restrict__ p_new,
+                                             const float* __restrict__ g_new, float* __restrict__ ring_p,
+                                             float* __restrict__ ring_g, int cap, const AAState* __restrict__ s,
+                                             const float* __restrict__ w, double* __restrict__ part, int blk) {
     const int cnt = s->count, head = s->head, slot_new = s->slot_new;
     double cross[CAP], rhs[CAP];
 #pragma unroll
     for (int i = 0; i < CAP; ++i) cross[i] = rhs[i] = 0.0;
-    for (long long e = (long long)blockIdx.x * kReduceThreads + threadIdx.x; e < n;
+    for (long long e = (long long)blk * kReduceThreads + threadIdx.x; e < n;
          e += (long long)kReduceBlocks * kReduceThreads) {
         const float gn = g_new[e];
         ring_p[(long long)slot_new * n + e] = p_new[e];
@@ -132,8 +135,19 @@ __global__ __launch_bounds__(kReduceThreads) void k_aa_dots(long long n, const f
     if (threadIdx.x < 2 * CAP) {
         double t = 0.0;
         for (int w = 0; w < kReduceThreads / 64; ++w) t += sh[w][threadIdx.x];
-        part[(long long)blockIdx.x * 2 * CAP + threadIdx.x] = t;
+        part[(long long)blk * 2 * CAP + threadIdx.x] = t;
     }
+}
+
+template <int CAP>
+__global__ __launch_bounds__(kReduceThreads) void k_aa_dots(long long n, const float* __restrict__ p_new,
+                                                            const float* __restrict__ g_new,
+                                                            float* __restrict__ ring_p,
+                                                            float* __restrict__ ring_g, int cap,
+                                                            const AAState* __restrict__ s,
+                                                            const float* __restrict__ w,
+                                                            double* __restrict__ part) {
+    aa_dots_body<CAP>(n, p_new, g_new, ring_p, ring_g, cap, s, w, part, blockIdx.x);
 }
 
 __device__ __forceinline__ void wave_sync_lds() {
@@ -259,8 +273,7 @@ __device__ void jacobi_eig_wave(double* S, double* V, int n) {
 }
 
 template <int CAP>
-__global__ __launch_bounds__(64) void k_aa_solve(AAState* s, const double* __restrict__ part, int cap,
-                                                 double cond_max) {
+__device__ void aa_solve_body(AAState* s, const double* __restrict__ part, int cap, double cond_max) {
     __shared__ double sums[2 * CAP];
     __shared__ double S[kAACap * kAACap];
     __shared__ double V[kAACap * kAACap];
@@ -342,14 +355,17 @@ __global__ __launch_bounds__(64) void k_aa_solve(AAState* s, const double* __res
 }
 
 template <int CAP>
-__global__ __launch_bounds__(256) void k_aa_mix(long long n, const float* __restrict__ p_k,
-                                                const float* __restrict__ g_k, float eta, float beta,
-                                                const float* __restrict__ ring_p,
-                                                const float* __restrict__ ring_g, int cap,
-                                                const AAState* __restrict__ s, float* __restrict__ p_bar,
-                                                float* __restrict__ p_tilde) {
-    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n) return;
+__global__ __launch_bounds__(64) void k_aa_solve(AAState* s, const double* __restrict__ part, int cap,
+                                                 double cond_max) {
+    aa_solve_body<CAP>(s, part, cap, cond_max);
+}
+
+template <int CAP>
+__device__ __forceinline__ void aa_mix_body(long long e, long long n, const float* __restrict__ p_k,
+                                            const float* __restrict__ g_k, float eta, float beta,
+                                            const float* __restrict__ ring_p, const float* __restrict__ ring_g,
+                                            int cap, const AAState* __restrict__ s, float* __restrict__ p_bar,
+                                            float* __restrict__ p_tilde) {
     const int mk = s->mk, head = s->head;
     const double et = (double)eta;
     const double eb = (double)eta * (double)beta;
@@ -374,6 +390,18 @@ __global__ __launch_bounds__(256) void k_aa_mix(long long n, const float* __rest
     }
     p_bar[e] = (float)pb;
     p_tilde[e] = (float)pt;
+}
+
+template <int CAP>
+__global__ __launch_bounds__(256) void k_aa_mix(long long n, const float* __restrict__ p_k,
+                                                const float* __restrict__ g_k, float eta, float beta,
+                                                const float* __restrict__ ring_p,
+                                                const float* __restrict__ ring_g, int cap,
+                                                const AAState* __restrict__ s, float* __restrict__ p_bar,
+                                                float* __restrict__ p_tilde) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    aa_mix_body<CAP>(e, n, p_k, g_k, eta, beta, ring_p, ring_g, cap, s, p_bar, p_tilde);
 }
 
 // ---------------------------------------------------------------------------
@@ -766,6 +794,68 @@ void aa_launch(hipStream_t st, long long n, const float* p, const float* g, floa
     AAFWI_HIP(hipGetLastError());
 }
 
+// ---------------------------------------------------------------------------
+// Batched step: the Gram/mixing step of many independent instances (each its
+// own n, window and eta; one M) in four launches.  Instance i's work runs the
+// single-instance arithmetic on its own state with the same partial-sum
+// count, so its results are bitwise those of aafwi_aa_step.
+// ---------------------------------------------------------------------------
+struct BAAInst {
+    long long n;
+    const float* p;
+    const float* g;
+    float* pbar;
+    float* ptilde;
+    float* ring_p;
+    float* ring_g;
+    AAState* s;
+    double* part;
+    float eta;
+    int active;
+};
+
+__global__ void k_baa_prepare(const BAAInst* __restrict__ in, int count, int cap) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count || !in[i].active) return;
+    aa_prepare_body(in[i].s, cap);
+}
+
+template <int CAP>
+__global__ __launch_bounds__(kReduceThreads) void k_baa_dots(const BAAInst* __restrict__ in, int cap) {
+    const BAAInst& I = in[blockIdx.y];
+    if (!I.active) return;  // uniform over the block
+    aa_dots_body<CAP>(I.n, I.p, I.g, I.ring_p, I.ring_g, cap, I.s, nullptr, I.part, blockIdx.x);
+}
+
+template <int CAP>
+__global__ __launch_bounds__(64) void k_baa_solve(const BAAInst* __restrict__ in, int cap, double cond_max) {
+    const BAAInst& I = in[blockIdx.x];
+    if (!I.active) return;
+    aa_solve_body<CAP>(I.s, I.part, cap, cond_max);
+}
+
+template <int CAP>
+__global__ __launch_bounds__(256) void k_baa_mix(const BAAInst* __restrict__ in, int cap) {
+    const BAAInst& I = in[blockIdx.y];
+    if (!I.active) return;
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= I.n) return;
+    aa_mix_body<CAP>(e, I.n, I.p, I.g, I.eta, 1.0f, I.ring_p, I.ring_g, cap, I.s, I.pbar, I.ptilde);
+}
+
+template <int CAP>
+void baa_launch(hipStream_t st, const BAAInst* tab, int count, long long max_n, int cap, double cond_max) {
+    hipLaunchKernelGGL(k_baa_prepare, dim3((unsigned)((count + 63) / 64)), dim3(64), 0, st, tab, count, cap);
+    AAFWI_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_baa_dots<CAP>, dim3(kReduceBlocks, (unsigned)count), dim3(kReduceThreads), 0, st, tab, cap);
+    AAFWI_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_baa_solve<CAP>, dim3((unsigned)count), dim3(64), 0, st, tab, cap, cond_max);
+    AAFWI_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_baa_mix<CAP>, dim3((unsigned)((max_n + 255) / 256), (unsigned)count), dim3(256), 0, st,
+                       tab, cap);
+    AAFWI_HIP(hipGetLastError());
+}
+
 }  // namespace
 
 void launch_dot(hipStream_t st, long long n, const float* x, const float* y, const float* z,
@@ -1021,6 +1111,157 @@ extern "C" int aafwi_axpy(aafwi_stream stream, int64_t n, float a, const float* 
     return guarded([&]() -> int {
         AAFWI_REQUIRE(n > 0 && x && y, "axpy: bad argument");
         aafwi::launch_axpy((hipStream_t)stream, n, a, x, y);
+        return AAFWI_OK;
+    });
+}
+
+// ---------------------------------------------------------------------------
+// C ABI: batched Anderson step
+// ---------------------------------------------------------------------------
+struct aafwi_batch_aa {
+    int count, M, cap, capT;
+    double cond_max;
+    hipStream_t stream;
+    std::vector<long long> n;
+    long long max_n;
+    float* ring;  // per instance: ring_p then ring_g, n_i * cap floats each
+    std::vector<long long> ring_off;
+    aafwi::AAState* states;
+    double* part;  // per instance: kReduceBlocks * 2 * kAACap doubles
+    aafwi::BAAInst* dtab;
+    std::vector<aafwi::BAAInst> htab;
+};
+
+namespace {
+void baa_free(aafwi_batch_aa* b) {
+    if (!b) return;
+    if (b->ring) (void)hipFree(b->ring);
+    if (b->states) (void)hipFree(b->states);
+    if (b->part) (void)hipFree(b->part);
+    if (b->dtab) (void)hipFree(b->dtab);
+    delete b;
+}
+}  // namespace
+
+extern "C" int aafwi_batch_aa_create(int32_t count, const int64_t* n, int32_t M, double cond_max,
+                                     aafwi_stream stream, aafwi_batch_aa** out) {
+    return guarded([&]() -> int {
+        AAFWI_REQUIRE(out != nullptr, "batch_aa_create: out is NULL");
+        *out = nullptr;
+        AAFWI_REQUIRE(count >= 1 && count <= 65535, "batch_aa_create: count must be in [1, 65535]");
+        AAFWI_REQUIRE(n != nullptr, "batch_aa_create: n is NULL");
+        AAFWI_REQUIRE(M >= 1 && M + 1 <= aafwi::kAACap, "batch_aa_create: M must be in [1, 31]");
+        AAFWI_REQUIRE(cond_max >= 1.0, "batch_aa_create: cond_max must be >= 1");
+        aafwi_batch_aa* b = new aafwi_batch_aa{};
+        b->count = count;
+        b->M = M;
+        b->cap = M + 1;
+        b->capT = b->cap <= 4 ? 4 : b->cap <= 8 ? 8 : b->cap <= 16 ? 16 : 32;
+        b->cond_max = cond_max;
+        b->stream = (hipStream_t)stream;
+        b->max_n = 0;
+        long long total = 0;
+        for (int i = 0; i < count; ++i) {
+            if (n[i] <= 0) {
+                delete b;
+                throw aafwi::Error{AAFWI_E_INVALID, "batch_aa_create: every n must be positive"};
+            }
+            b->n.push_back(n[i]);
+            b->ring_off.push_back(total);
+            total += 2LL * n[i] * b->cap;
+            b->max_n = std::max(b->max_n, (long long)n[i]);
+        }
+        try {
+            auto alloc = [&](void** p, size_t bytes) {
+                if (hipMalloc(p, bytes) != hipSuccess) {
+                    (void)hipGetLastError();
+                    *p = nullptr;
+                    throw aafwi::Error{AAFWI_E_NOMEM, "batch_aa_create: device allocation failed"};
+                }
+            };
+            alloc((void**)&b->ring, sizeof(float) * (size_t)total);
+            alloc((void**)&b->states, sizeof(aafwi::AAState) * (size_t)count);
+            alloc((void**)&b->part, sizeof(double) * aafwi::kReduceBlocks * 2 * aafwi::kAACap * (size_t)count);
+            alloc((void**)&b->dtab, sizeof(aafwi::BAAInst) * (size_t)count);
+            AAFWI_HIP(hipMemsetAsync(b->states, 0, sizeof(aafwi::AAState) * (size_t)count, b->stream));
+        } catch (...) {
+            baa_free(b);
+            throw;
+        }
+        b->htab.resize(count);
+        *out = b;
+        return AAFWI_OK;
+    });
+}
+
+extern "C" int aafwi_batch_aa_step(aafwi_batch_aa* b, const float* const* p_k, const float* const* g_k,
+                                   const float* eta, float* const* p_bar, float* const* p_tilde,
+                                   const uint8_t* active) {
+    return guarded([&]() -> int {
+        AAFWI_REQUIRE(b != nullptr, "batch_aa_step: NULL state");
+        AAFWI_REQUIRE(p_k && g_k && eta && p_bar && p_tilde, "batch_aa_step: NULL argument array");
+        for (int i = 0; i < b->count; ++i) {
+            const bool on = active ? active[i] != 0 : true;
+            if (on) {
+                AAFWI_REQUIRE(p_k[i] && g_k[i] && p_bar[i] && p_tilde[i], "batch_aa_step: NULL vector");
+                AAFWI_REQUIRE(std::isfinite(eta[i]) && eta[i] >= 0.0f, "batch_aa_step: eta must be finite and >= 0");
+            }
+            aafwi::BAAInst& I = b->htab[i];
+            I.n = b->n[i];
+            I.p = p_k[i];
+            I.g = g_k[i];
+            I.pbar = p_bar[i];
+            I.ptilde = p_tilde[i];
+            I.ring_p = b->ring + b->ring_off[i];
+            I.ring_g = b->ring + b->ring_off[i] + b->n[i] * b->cap;
+            I.s = b->states + i;
+            I.part = b->part + (size_t)i * aafwi::kReduceBlocks * 2 * aafwi::kAACap;
+            I.eta = eta[i];
+            I.active = on ? 1 : 0;
+        }
+        // pageable source: the copy has consumed htab when the call returns
+        AAFWI_HIP(hipMemcpyAsync(b->dtab, b->htab.data(), sizeof(aafwi::BAAInst) * b->count, hipMemcpyHostToDevice,
+                                 b->stream));
+        switch (b->capT) {
+            case 4: aafwi::baa_launch<4>(b->stream, b->dtab, b->count, b->max_n, b->cap, b->cond_max); break;
+            case 8: aafwi::baa_launch<8>(b->stream, b->dtab, b->count, b->max_n, b->cap, b->cond_max); break;
+            case 16: aafwi::baa_launch<16>(b->stream, b->dtab, b->count, b->max_n, b->cap, b->cond_max); break;
+            default: aafwi::baa_launch<32>(b->stream, b->dtab, b->count, b->max_n, b->cap, b->cond_max); break;
+        }
+        return AAFWI_OK;
+    });
+}
+
+extern "C" int aafwi_batch_aa_reset(aafwi_batch_aa* b, const uint8_t* which) {
+    return guarded([&]() -> int {
+        AAFWI_REQUIRE(b != nullptr, "batch_aa_reset: NULL state");
+        for (int i = 0; i < b->count; ++i)
+            if (!which || which[i])
+                AAFWI_HIP(hipMemsetAsync(b->states + i, 0, sizeof(aafwi::AAState), b->stream));
+        return AAFWI_OK;
+    });
+}
+
+extern "C" int aafwi_batch_aa_state(aafwi_batch_aa* b, double* gamma, int32_t* mk) {
+    return guarded([&]() -> int {
+        AAFWI_REQUIRE(b != nullptr, "batch_aa_state: NULL state");
+        for (int i = 0; i < b->count; ++i) {
+            if (gamma)
+                AAFWI_HIP(hipMemcpyAsync(gamma + (size_t)i * b->M, b->states[i].gamma, sizeof(double) * b->M,
+                                         hipMemcpyDeviceToDevice, b->stream));
+            if (mk)
+                AAFWI_HIP(hipMemcpyAsync(mk + i, &b->states[i].mk, sizeof(int32_t), hipMemcpyDeviceToDevice,
+                                         b->stream));
+        }
+        return AAFWI_OK;
+    });
+}
+
+extern "C" int aafwi_batch_aa_destroy(aafwi_batch_aa* b) {
+    return guarded([&]() -> int {
+        if (!b) return AAFWI_OK;
+        (void)hipStreamSynchronize(b->stream);
+        baa_free(b);
         return AAFWI_OK;
     });
 }

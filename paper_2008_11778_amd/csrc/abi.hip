@@ -56,6 +56,7 @@ struct InstHost {
     int2* src = nullptr;
     int *rowmap = nullptr, *xmap = nullptr, *rnext = nullptr;
     bool have_ckpt = false;
+    int tz[4] = {0, 0, 0, 0};  // per-instance strip heights (0: the engine's setting)
 };
 
 struct Engine {
@@ -87,8 +88,10 @@ struct Engine {
     // timing
     int time_every = 0;
     long long launches[4] = {0, 0, 0, 0};
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[4];
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[4];  // recorded, not yet read
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
+    double ev_ms[4] = {0.0, 0.0, 0.0, 0.0};  // summed durations of the pairs already read
+    long long ev_n[4] = {0, 0, 0, 0};
     // graphs (batches)
     bool use_graphs = false;
     bool capturing = false;
@@ -278,20 +281,31 @@ std::vector<aafwi::TileRec> tile_table(Engine* e, int kid, bool two) {
     for (int i = 0; i < (int)e->in.size(); ++i) {
         const aafwi::WaveGrid& g = e->in[i].g;
         // one-step kernels keep a strip's receiver rows one per lane: at most 64 rows
-        const int tz_set = e->tz[kid] ? e->tz[kid] : default_tz(g.nzp);
+        const int tz_set = e->in[i].tz[kid] ? e->in[i].tz[kid] : (e->tz[kid] ? e->tz[kid] : default_tz(g.nzp));
         const int tz = std::min(two ? tz_set : std::min(tz_set, 64), g.nzp);
         const int ntx = (g.nxp + width - 1) / width;
         std::vector<aafwi::TileRec> t;
-        for (int s = 0; s < g.S; ++s) {
-            if (e->order[kid] == 0) {
+        const int ord = e->order[kid];
+        if (ord <= 1) {
+            for (int s = 0; s < g.S; ++s) {
+                if (ord == 0) {
+                    for (int z0 = 0; z0 < g.nzp; z0 += tz)
+                        for (int tx = 0; tx < ntx; ++tx)
+                            t.push_back({i, s, tx * width, (z0 << 16) | std::min(z0 + tz, g.nzp)});
+                } else {
+                    for (int tx = 0; tx < ntx; ++tx)
+                        for (int z0 = 0; z0 < g.nzp; z0 += tz)
+                            t.push_back({i, s, tx * width, (z0 << 16) | std::min(z0 + tz, g.nzp)});
+                }
+            }
+        } else {
+            // groups of `ord` shots innermost: the same tile of several shots
+            // runs at about the same time, so they share its Kp rows in L2
+            for (int s0 = 0; s0 < g.S; s0 += ord)
                 for (int z0 = 0; z0 < g.nzp; z0 += tz)
                     for (int tx = 0; tx < ntx; ++tx)
-                        t.push_back({i, s, tx * width, (z0 << 16) | std::min(z0 + tz, g.nzp)});
-            } else {
-                for (int tx = 0; tx < ntx; ++tx)
-                    for (int z0 = 0; z0 < g.nzp; z0 += tz)
-                        t.push_back({i, s, tx * width, (z0 << 16) | std::min(z0 + tz, g.nzp)});
-            }
+                        for (int s = s0; s < std::min(s0 + ord, g.S); ++s)
+                            t.push_back({i, s, tx * width, (z0 << 16) | std::min(z0 + tz, g.nzp)});
         }
         const size_t n = t.size();
         for (int c = 0; c < kX; ++c)
@@ -375,16 +389,45 @@ void finalize(Engine* e) {
     AAFWI_HIP(hipDeviceSynchronize());
 }
 
-// Event pair around a stepping launch when sampling is on (not inside captures).
+// Reads every recorded pair whose end event has completed (all of them when
+// ``wait``), adds its duration to the per-kernel sums and returns the pair to
+// the pool, so that a run of any length is sampled over its whole span.
+void harvest_events(Engine* e, bool wait) {
+    if (wait) AAFWI_HIP(hipStreamSynchronize(e->stream));
+    for (int id = 0; id < 4; ++id) {
+        auto& v = e->ev[id];
+        size_t keep = 0;
+        for (size_t i = 0; i < v.size(); ++i) {
+            if (!wait && hipEventQuery(v[i].second) != hipSuccess) {
+                v[keep++] = v[i];
+                continue;
+            }
+            float ms = 0.0f;
+            AAFWI_HIP(hipEventElapsedTime(&ms, v[i].first, v[i].second));
+            e->ev_ms[id] += ms;
+            e->ev_n[id] += 1;
+            e->ev_pool.push_back(v[i]);
+        }
+        v.resize(keep);
+    }
+    // a query of a pending event leaves "not ready" as the last error
+    if (!wait) (void)hipGetLastError();
+}
+
+// Event pair around a stepping launch when sampling is on (not inside
+// captures); when the pool is empty, the completed pairs are read first.
 struct Timed {
     Engine* e;
     int id;
     std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
     Timed(Engine* e_, int id_) : e(e_), id(id_) {
-        if (!e->capturing && e->time_every > 0 && (e->launches[id] % e->time_every) == 0 && !e->ev_pool.empty()) {
-            ev = e->ev_pool.back();
-            e->ev_pool.pop_back();
-            AAFWI_HIP(hipEventRecord(ev.first, e->stream));
+        if (!e->capturing && e->time_every > 0 && (e->launches[id] % e->time_every) == 0) {
+            if (e->ev_pool.empty()) harvest_events(e, false);
+            if (!e->ev_pool.empty()) {
+                ev = e->ev_pool.back();
+                e->ev_pool.pop_back();
+                AAFWI_HIP(hipEventRecord(ev.first, e->stream));
+            }
         }
         e->launches[id] += 1;
     }
@@ -545,18 +588,18 @@ bool kept_model_is(Engine* e, const float* m) {
 }
 
 int timing_enable(Engine* e, int every) {
-    AAFWI_HIP(hipStreamSynchronize(e->stream));
-    for (auto& v : e->ev) {
-        for (auto& x : v) e->ev_pool.push_back(x);
-        v.clear();
+    harvest_events(e, true);
+    for (int id = 0; id < 4; ++id) {
+        e->ev_ms[id] = 0.0;
+        e->ev_n[id] = 0;
+        e->launches[id] = 0;
     }
-    for (auto& l : e->launches) l = 0;
     e->time_every = every;
     if (every > 0) {
         // timing-only events: no system-scope fence at record (its cache
-        // writeback would be timed with the kernel); timing_read synchronises
-        // the stream before it reads them
-        while (e->ev_pool.size() < 8192) {
+        // writeback would be timed with the kernel); pairs are read once their
+        // end event has completed and then recorded again
+        while (e->ev_pool.size() < 4096) {
             hipEvent_t a, b;
             AAFWI_HIP(hipEventCreateWithFlags(&a, hipEventDisableSystemFence));
             AAFWI_HIP(hipEventCreateWithFlags(&b, hipEventDisableSystemFence));
@@ -568,15 +611,9 @@ int timing_enable(Engine* e, int every) {
 
 int timing_read(Engine* e, int id, double* mean_ms, int64_t* count) {
     AAFWI_REQUIRE(mean_ms && count && id >= 0 && id < 4, "kernel_timing_read: bad argument");
-    AAFWI_HIP(hipStreamSynchronize(e->stream));
-    double tot = 0.0;
-    for (auto& x : e->ev[id]) {
-        float ms = 0.0f;
-        AAFWI_HIP(hipEventElapsedTime(&ms, x.first, x.second));
-        tot += ms;
-    }
-    *count = (int64_t)e->ev[id].size();
-    *mean_ms = e->ev[id].empty() ? 0.0 : tot / (double)e->ev[id].size();
+    harvest_events(e, true);
+    *count = (int64_t)e->ev_n[id];
+    *mean_ms = e->ev_n[id] ? e->ev_ms[id] / (double)e->ev_n[id] : 0.0;
     return AAFWI_OK;
 }
 
@@ -595,7 +632,7 @@ int set_tile(Engine* e, int kernel_id, int rows) {
 }
 
 int set_tile_order(Engine* e, int kernel_id, int order) {
-    AAFWI_REQUIRE(order == 0 || order == 1, "set_tile_order: order must be 0 or 1");
+    AAFWI_REQUIRE(order >= 0 && order <= 64, "set_tile_order: order must be 0, 1 or a shot group size up to 64");
     AAFWI_REQUIRE(kernel_id >= -1 && kernel_id < 4, "set_tile_order: kernel_id must be -1 or a kernel id");
     AAFWI_HIP(hipStreamSynchronize(e->stream));
     for (int k = 0; k < 4; ++k)
@@ -987,6 +1024,10 @@ extern "C" int aafwi_batch_forward(aafwi_batch* b, int keep_ckpt) {
             }
             residuals(e, d, dobs, r);
         });
+        // host-side state of the kept runs: a graph replay does not run the
+        // body above, so it is set here for replays and direct calls alike
+        for (int i = 0; i < (int)e->in.size(); ++i)
+            if (e->active_host[i]) e->in[i].have_ckpt = keep_ckpt != 0;
         return AAFWI_OK;
     });
 }
@@ -1032,6 +1073,33 @@ extern "C" int aafwi_batch_set_tile(aafwi_batch* b, int32_t kernel_id, int32_t r
     });
 }
 
+extern "C" int aafwi_batch_set_instance_tile(aafwi_batch* b, int32_t inst, int32_t kernel_id, int32_t rows) {
+    return guarded([&]() -> int {
+        AAFWI_REQUIRE(b, "batch_set_instance_tile: NULL batch");
+        Engine* e = b->e;
+        AAFWI_REQUIRE(inst >= 0 && inst < (int)e->in.size(), "batch_set_instance_tile: instance out of range");
+        AAFWI_REQUIRE(rows >= 0 && rows <= 120, "batch_set_instance_tile: rows per wave must be in [0, 120]");
+        AAFWI_REQUIRE(kernel_id >= -1 && kernel_id < 4, "batch_set_instance_tile: kernel_id must be -1 or a kernel id");
+        AAFWI_HIP(hipStreamSynchronize(e->stream));
+        for (int k = 0; k < 4; ++k)
+            if (kernel_id == -1 || kernel_id == k) {
+                e->in[inst].tz[k] = rows;
+                build_tiles(e, k);
+            }
+        for (auto& kv : e->graphs) (void)hipGraphExecDestroy(kv.second);
+        e->graphs.clear();
+        return AAFWI_OK;
+    });
+}
+
+extern "C" int aafwi_batch_get_time_blocking(const aafwi_batch* b, int* mask) {
+    return guarded([&]() -> int {
+        AAFWI_REQUIRE(b && mask, "batch_get_time_blocking: NULL argument");
+        *mask = (b->e->tb[0] ? 1 : 0) | (b->e->tb[1] ? 2 : 0) | (b->e->tb[2] ? 4 : 0);
+        return AAFWI_OK;
+    });
+}
+
 extern "C" int aafwi_batch_set_time_blocking(aafwi_batch* b, int enable) {
     return guarded([&]() -> int {
         AAFWI_REQUIRE(b, "batch_set_time_blocking: NULL batch");
@@ -1052,3 +1120,4 @@ extern "C" int aafwi_batch_kernel_timing_read(aafwi_batch* b, int id, double* me
         return timing_read(b->e, id, mean_ms, count);
     });
 }
+

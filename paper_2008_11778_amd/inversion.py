@@ -15,6 +15,12 @@ Readings of the paper used here (Section "Method", Algorithm 2):
     and p_{k+1} = lambda ptilde + (1 - lambda) pbar (Step 5).
   * The accepted trial's forward run keeps its wavefield checkpoints, so the
     next gradient needs only the backward pass (no second forward).
+  * Restart (the paper leaves the fallback's effect on the window open):
+    when the search of iteration k fell back to lambda = 0 and that plain
+    descent step decreased J (J(p_{k+1}) < J(p_k), known once the gradient
+    at p_{k+1} is evaluated), the Anderson window is cleared before p_{k+1}
+    enters it, so mixing restarts from the descent step; a descent step
+    that did not decrease J keeps the window.
 """
 from __future__ import annotations
 
@@ -189,9 +195,14 @@ class AADescent:
 
     def __init__(self, problem, p0: torch.Tensor, eta: float | None, M: int, cond_max: float = 1e5,
                  lambdas=LAMBDAS, c1: float = ARMIJO_C1, linesearch: bool = True,
-                 eta_frac: float = 0.02, aa_solver: str = "gram", aa_beta: float = 1.0, aa_weights=None):
+                 eta_frac: float = 0.02, aa_solver: str = "gram", aa_beta: float = 1.0, aa_weights=None,
+                 restart: bool = True):
         self.problem, self.M, self.eta = problem, M, eta
         self.lambdas, self.c1, self.linesearch, self.eta_frac = lambdas, c1, linesearch, eta_frac
+        self.restart = restart
+        self.fell_back = False  # the last iteration's search took lambda = 0
+        self.J_prev = None      # J(p_k) of the last iteration
+        self.n_restart = 0
         self.shape = p0.shape
         self.aa = AA(p0.numel(), max(M, 1), cond_max, solver=aa_solver) if M > 0 else None
         if self.aa is not None:
@@ -217,6 +228,7 @@ class AADescent:
 
     def first(self) -> IterLog:
         J = self.problem.gradient(self.p, self.g)
+        self.J_prev = J
         if self.eta is None:
             self.eta = step_size(self.p, self.g, self.eta_frac)
         self._G()
@@ -227,6 +239,10 @@ class AADescent:
         self.k += 1
         p, g = self.p, self.g
         J = self.problem.gradient(p, g)
+        if self.restart and self.fell_back and self.aa is not None and J < self.J_prev:
+            self.aa.reset()
+            self.n_restart += 1
+        self.J_prev = J
         self._G()
         lam_acc, p_next = 0.0, None
         if self.linesearch:
@@ -242,6 +258,7 @@ class AADescent:
         else:
             lam_acc, p_next = 1.0, self.ptilde
             self.ptilde = torch.empty_like(p)
+        self.fell_back = self.linesearch and p_next is None
         if p_next is None:
             p_next = self.pbar
             self.pbar = torch.empty_like(p)
@@ -258,11 +275,13 @@ class AADescent:
 
 def aa_descent(problem, p0: torch.Tensor, eta: float | None, M: int, iters: int, cond_max: float = 1e5,
                lambdas=LAMBDAS, c1: float = ARMIJO_C1, linesearch: bool = True,
-               keep_iterates: bool = True, log_path: str | None = None, callback=None, aa_solver: str = "gram"):
+               keep_iterates: bool = True, log_path: str | None = None, callback=None, aa_solver: str = "gram",
+               restart: bool = True):
     """Run Algorithm 2 for ``iters`` iterations after p_1 = G(p_0).
     Returns (iterates p_0..p_{iters+1}, history of IterLog, final p).
-    aa_solver: "gram" (FP64 normal equations) or "qr" (rank-updated QR)."""
-    run = AADescent(problem, p0, eta, M, cond_max, lambdas, c1, linesearch, aa_solver=aa_solver)
+    aa_solver: "gram" (FP64 normal equations) or "qr" (rank-updated QR);
+    restart: clear the window after a fallback step that decreased J."""
+    run = AADescent(problem, p0, eta, M, cond_max, lambdas, c1, linesearch, aa_solver=aa_solver, restart=restart)
     iterates = [run.p.clone()] if keep_iterates else []
     hist = []
     out = open(log_path, "a") if log_path else None

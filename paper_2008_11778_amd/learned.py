@@ -8,7 +8,9 @@ eq. GD).  Algorithm 2 runs unchanged on G_theta (its history holds d_theta
 instead of g).  Fallback: when the line search accepts no lambda in
 {1, 1/2, 1/4, 1/8} and J(pbar_theta) >= J(p_k) as well, the iteration is redone
 with plain Anderson acceleration on G, whose history is fed with (p_k, g_k) at
-every iteration so that it is ready when needed.
+every iteration so that it is ready when needed.  A window whose search fell
+back to its plain descent step restarts (is cleared) at the next iteration
+when that step decreased J, as in plain Algorithm 2.
 
 Training pairs (g_k, p_k, s_k = p_{k+1} - p_k) come from plain Anderson runs
 (all instances of a batch advanced together by BatchedAADescent) and from
@@ -37,8 +39,13 @@ class LearnedAADescent:
 
     def __init__(self, problem, p0: torch.Tensor, net: CNN, M: int = 10, eta: float | None = None,
                  eta_theta: float | None = None, cond_max: float = 1e5, lambdas=LAMBDAS, c1: float = ARMIJO_C1,
-                 eta_frac: float = 0.02):
+                 eta_frac: float = 0.02, restart: bool = True):
         self.problem, self.net, self.M = problem, net, M
+        self.restart = restart
+        # which window's search fell back to its plain step in the last
+        # iteration; the window restarts if that step decreased J
+        self.fb_theta = self.fb_plain = False
+        self.J_prev = None
         self.eta, self.eta_theta, self.eta_frac = eta, eta_theta, eta_frac
         self.lambdas, self.c1 = lambdas, c1
         self.shape = tuple(p0.shape)
@@ -88,6 +95,7 @@ class LearnedAADescent:
 
     def first(self) -> LearnedLog:
         J = self.problem.gradient(self.p, self.g)
+        self.J_prev = J
         self._direction()
         if self.eta is None:
             self.eta = step_size(self.p, self.g, self.eta_frac)
@@ -101,11 +109,19 @@ class LearnedAADescent:
     def iterate(self) -> LearnedLog:
         self.k += 1
         J = self.problem.gradient(self.p, self.g)
+        if self.restart and J < self.J_prev:
+            if self.fb_theta:
+                self.aa_theta.reset()
+            if self.fb_plain:
+                self.aa_plain.reset()
+        self.J_prev = J
         self._direction()
         self._maps()
         lam, p_next = self._search(self.ptilde, J)
         fallback = False
+        self.fb_theta = self.fb_plain = False
         if p_next is None:
+            self.fb_theta = True
             if self.problem.misfit_keep(self.pbar) < J:
                 p_next = self.pbar
                 self.pbar = torch.empty_like(self.p)
@@ -114,6 +130,7 @@ class LearnedAADescent:
                 self.n_fallback += 1
                 lam, p_next = self._search(self.ptilde_plain, J)
                 if p_next is None:
+                    self.fb_plain = True
                     p_next = self.pbar_plain
                     self.pbar_plain = torch.empty_like(self.p)
         self.p = p_next

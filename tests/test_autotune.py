@@ -70,3 +70,50 @@ def test_apply_sets_every_field():
     assert sorted(calls) == sorted([("two", 0, False), ("two", 1, True), ("two", 2, True),
                                     ("rows", 0, 8), ("rows", 1, 48), ("rows", 2, 96), ("rows", 3, 64),
                                     ("order", 0, 1), ("order", 1, 0), ("order", 2, 1), ("order", 3, 0)])
+
+
+def test_class_rows_per_mode():
+    entry = {0: 48, "two0": True, "rows_one0": 8, "rows_two0": 48, 1: 64, "two1": False, 2: 20, "two2": True,
+             3: 28}
+    assert autotune.class_rows(entry, 0, True) == 48
+    assert autotune.class_rows(entry, 0, False) == 8
+    # no per-mode entry: the winner's height when the modes agree, else the default
+    assert autotune.class_rows(entry, 1, False) == 64
+    assert autotune.class_rows(entry, 1, True) == 0
+    assert autotune.class_rows(entry, 2, True) == 20
+    assert autotune.class_rows(entry, 3, False) == 28
+
+
+def test_tune_batch_sets_heights_per_grid_class(tmp_path, monkeypatch):
+    """Two grid classes (three instances, one class twice): each class is
+    looked up once (with at most 8 shots) and every instance gets its class's
+    heights for the batch's launch modes."""
+    monkeypatch.setenv("AAFWI_TUNE_CACHE", str(tmp_path))
+    ga = synth.make_geometry(64, 96, 10.0, 8, 1e-3, 12, rec_stride=2)
+    gb = synth.make_geometry(32, 200, 10.0, 8, 1e-3, 5, rec_stride=2)
+    entries = {
+        autotune.grid_key(ga.subset_shots(list(range(8)))): {"0": 16, "two0": True, "rows_one0": 12, "rows_two0": 16,
+                                                            "1": 24, "two1": False, "2": 32, "two2": True, "3": 40,
+                                                            "order0": 0, "order1": 0, "order2": 0, "order3": 0},
+        autotune.grid_key(gb): {"0": 8, "two0": False, "rows_one0": 8, "rows_two0": 64, "1": 20, "two1": True,
+                                "2": 24, "two2": True, "3": 12, "order0": 0, "order1": 0, "order2": 0, "order3": 0},
+    }
+    with open(tmp_path / "tiles.json", "w") as f:
+        json.dump(entries, f)
+    calls = []
+
+    class FakeBatch:
+        def time_blocking(self):
+            return 0b101  # forward and adjoint two steps per launch, recompute one
+
+        def set_instance_tile(self, i, rows, k):
+            calls.append((i, k, rows))
+
+    out = autotune.tune_batch(FakeBatch(), [ga, gb, ga], [None, None, None])
+    got = {(i, k): rows for i, k, rows in calls}
+    # class a: forward two-step 16, recompute one-step 24, adjoint two-step 32, Born 40
+    assert [got[(0, k)] for k in range(4)] == [16, 24, 32, 40] == [got[(2, k)] for k in range(4)]
+    # class b: forward two-step 64 (its one-step winner is not the batch's mode),
+    # recompute: its winner is two-step, no one-step height stored -> default 0
+    assert [got[(1, k)] for k in range(4)] == [64, 0, 24, 12]
+    assert len(out) == 2

@@ -78,3 +78,48 @@ def test_steepest_descent_matches_picard(problem):
         its, hist, _ = aa_descent(prob, torch.from_numpy(m0).to(dev), eta, M=0, iters=3, linesearch=False)
     for k, (a, b) in enumerate(zip(its, ref_it)):
         assert rel(a.cpu().numpy(), b) <= 1e-4, (k, rel(a.cpu().numpy(), b))
+
+
+def test_alg2_restart_after_fallback_matches_oracle():
+    """A small two-shot case with a strict sufficient-decrease constant
+    (c1 = 0.7, lambda in {1, 1/2}, M = 3), where iteration 1 falls back to
+    the descent step, that step decreases J and the window restarts at
+    iteration 2 (the oracle's own run records it): the GPU run takes the
+    same lambda decisions, restarts at the same iteration, and its iterates
+    and misfits match the oracle's.  The trial margins of this case are at
+    least 7e-3 of J, far above the FP32 misfit error."""
+    import torch
+    from paper_2008_11778_amd import Context
+    from paper_2008_11778_amd.inversion import AADescent, FWIProblem
+    g, m = synth.small_case(nz=32, nx=40, nb=8, nt=200, nshots=2, nrec=10)
+    r = np.random.default_rng(3)
+    m_true = (m.astype(np.float64) * (1 + 0.05 * synth.smooth(r.standard_normal(m.shape), 3.0) / 0.3)).astype(np.float32)
+    d_obs = fd.forward_model(g, m_true).astype(np.float32)
+    _, g0 = fd.adjoint_gradient(g, m, d_obs)
+    eta = float(0.02 * np.abs(m).max() / np.abs(g0).max())
+    shape = m.shape
+    ref = oaa.alg2(lambda p: fd.adjoint_gradient(g, p.reshape(shape), d_obs),
+                   lambda p: fd.misfit(fd.forward_model(g, p.reshape(shape)), d_obs),
+                   m.ravel(), eta, 3, 6, c1=0.7, lambdas=(1.0, 0.5))
+    assert ref["restarts"] == [2] and ref["lambdas"][0] == 0.0
+    dev = torch.device("cuda", 0)
+    with Context(g) as ctx:
+        prob = FWIProblem(ctx, torch.from_numpy(d_obs).to(dev))
+        run = AADescent(prob, torch.from_numpy(m).to(dev), eta, M=3, c1=0.7, lambdas=(1.0, 0.5))
+        logs = [run.first()]
+        its = [torch.from_numpy(m).reshape(-1).numpy(), run.p.cpu().numpy()]
+        for _ in range(6):
+            logs.append(run.iterate())
+            its.append(run.p.cpu().numpy())
+        n_restart = run.n_restart
+        run.close()
+    lams = [h.lam for h in logs[1:]]
+    print("lambdas gpu", lams, "oracle", ref["lambdas"], "window sizes", [h.mk for h in logs[1:]])
+    assert lams == ref["lambdas"]
+    assert n_restart == len(ref["restarts"])
+    assert logs[2].mk == 0  # the restarted window holds p_2 alone
+    for k, (a, b) in enumerate(zip(its, ref["iterates"])):
+        print(f"iterate {k}: rel {rel(a, b):.2e}")
+        assert rel(a, b) <= 1e-4, (k, rel(a, b))
+    for k, (h, Jr) in enumerate(zip(logs, ref["misfits"])):
+        assert abs(h.J - Jr) / Jr <= 1e-3, (k, h.J, Jr)

@@ -172,8 +172,21 @@ def test_two_loop_matches_oracle():
     assert rel(out, ref) <= 1e-5
 
 
-def test_lbfgs_fwi_decreases_and_satisfies_armijo(fwi_small):
-    import torch
+def _check_strong_wolfe(st, c1=1e-4):
+    """The strong-Wolfe conditions on an accepted step (Nocedal and Wright,
+    eq. 3.7): sufficient decrease J(p + a d) <= J(p) + c1 a g.d and the
+    curvature bound |g(p + a d).d| <= c2 |g.d|, with g.d < 0.  Several points
+    can satisfy them, so this checks validity, not the point chosen."""
+    assert st["d0"] < 0.0, st
+    assert st["alpha"] > 0.0, st
+    assert st["J"] <= st["J0"] + c1 * st["alpha"] * st["d0"], st
+    assert abs(st["slope"]) <= st["c2"] * abs(st["d0"]), st
+
+
+def test_lbfgs_fwi_steps_satisfy_strong_wolfe(fwi_small):
+    """L-BFGS (M = 5) on a small FWI problem: every accepted step satisfies
+    both strong-Wolfe conditions (c1 = 1e-4, c2 = 0.9), checked from the
+    misfits and directional derivatives the HIP path computed, and J falls."""
     from paper_2008_11778_amd import Context
     from paper_2008_11778_amd.comparators import LBFGS
     from paper_2008_11778_amd.inversion import FWIProblem
@@ -182,15 +195,18 @@ def test_lbfgs_fwi_decreases_and_satisfies_armijo(fwi_small):
         prob = FWIProblem(ctx, T(d_obs))
         opt = LBFGS(prob, T(m), M=5)
         Js = [opt.J]
-        for _ in range(3):
+        for _ in range(4):
             Js.append(opt.iterate())
+            print(opt.last_step)
+            _check_strong_wolfe(opt.last_step)
     assert all(b < a for a, b in zip(Js, Js[1:])), Js
 
 
 def test_ncg_matches_oracle_iterates(fwi_small):
     """Polak-Ribiere+ CG on the HIP path against the oracle's, from the same
     start and the same first step: same line-search outcome, iterates within
-    the gradient tolerance."""
+    the gradient tolerance; every accepted step satisfies the strong-Wolfe
+    conditions (c1 = 1e-4, c2 = 0.1) on the HIP path's own values."""
     from paper_2008_11778_amd import Context
     from paper_2008_11778_amd.comparators import NCG
     from paper_2008_11778_amd.inversion import FWIProblem
@@ -202,11 +218,15 @@ def test_ncg_matches_oracle_iterates(fwi_small):
         a1 = opt.a_init * float(np.linalg.norm(fd.adjoint_gradient(g, m, d_obs)[1]))
         its = [opt.p.cpu().numpy()]
         Js = [opt.J]
+        steps = []
         for _ in range(2):
             Js.append(opt.iterate())
             its.append(opt.p.cpu().numpy())
+            steps.append(opt.last_step)
     ref = krylov.ncg(lambda p: fd.adjoint_gradient(g, p.reshape(shape), d_obs), m.ravel(), 2, a1=a1)
     assert all(b < a for a, b in zip(Js, Js[1:])), Js
+    for st in steps:
+        _check_strong_wolfe(st)
     for k, (a, b) in enumerate(zip(its, ref)):
         assert rel(a, b) <= 1e-3, (k, rel(a, b))
 

@@ -292,3 +292,58 @@ def test_invalid_arguments_raise(torch_dev):
         with pytest.raises(AafwiError) as e:
             ctx.sync()
         assert e.value.code == -5
+
+
+def test_batched_aa_step_matches_oracle_and_single_steps(torch_dev):
+    """The batched Anderson step over three instances of different sizes
+    (n = 700, 5000, 12345; M = 4, two of the instances with nearly collinear
+    gradients so that the condition guard drops columns): every instance's
+    gamma, window size, p_bar and p_tilde against the oracle's AAHistory of
+    that instance at the tolerances of the single step, and bitwise against
+    separate single-instance steps; one instance is masked for one step
+    (left untouched) and one is reset midway."""
+    torch, dev = torch_dev
+    from paper_2008_11778_amd import AA, BatchAA
+    r = np.random.default_rng(12)
+    ns, M, etas = [700, 5000, 12345], 4, [0.37, 0.1, 0.05]
+    refs = [oaa.AAHistory(M, cond_max=1e5) for _ in ns]
+    singles = [AA(n, M, cond_max=1e5) for n in ns]
+    batch = BatchAA(ns, M, cond_max=1e5)
+    base = [r.standard_normal(n) for n in ns]
+    ps = [r.standard_normal(n).astype(np.float32) for n in ns]
+    pb_b = [torch.empty(n, device=dev) for n in ns]
+    pt_b = [torch.empty(n, device=dev) for n in ns]
+    for k in range(8):
+        gs = []
+        for i, n in enumerate(ns):
+            if i == 0:
+                g = r.standard_normal(n) + 0.3 * k
+            else:  # nearly collinear differences on the larger instances
+                g = base[i] * (1 + k) + (1e-7 if (k + i) % 2 else 1e-2) * r.standard_normal(n)
+            gs.append(g.astype(np.float32))
+        active = [True, k != 3, True]
+        if k == 5:
+            batch.reset([False, False, True])
+            singles[2].reset()
+            refs[2].reset()
+        pt_in = [T(torch, dev, p) for p in ps]
+        gt_in = [T(torch, dev, g) for g in gs]
+        batch.step(pt_in, gt_in, etas, pb_b, pt_b, active=active)
+        gam_b, mk_b = batch.state()
+        gam_b, mk_b = gam_b.cpu().numpy(), mk_b.cpu().numpy()
+        for i in range(len(ns)):
+            if not active[i]:
+                continue
+            pb_s, pt_s = singles[i].step(pt_in[i], gt_in[i], etas[i])
+            pbr, ptr_, gam, mk = refs[i].step(ps[i], gs[i], etas[i])
+            assert int(mk_b[i]) == mk == int(singles[i].mk.item()), (k, i)
+            assert torch.equal(pb_b[i], pb_s) and torch.equal(pt_b[i], pt_s), (k, i)
+            if mk:
+                assert np.array_equal(gam_b[i, :mk], singles[i].gamma.cpu().numpy()[:mk]), (k, i)
+            assert rel(pb_b[i].cpu().numpy(), pbr) <= 1e-6
+            tol = 1e-5 if i == 0 else 1e-4
+            assert rel(pt_b[i].cpu().numpy(), ptr_) <= tol, (k, i, rel(pt_b[i].cpu().numpy(), ptr_))
+            ps[i] = (ptr_ if i == 0 else ps[i] + 0.01).astype(np.float32)
+    batch.close()
+    for a in singles:
+        a.close()

@@ -105,12 +105,15 @@ def test_uneven_batch_two_step_equals_one_step():
 
 
 def test_tile_order_is_bitwise_neutral():
+    """Tile orders: x-tiles of a strip adjacent, strips of a column
+    adjacent, and shot groups of 2 (the last group ragged on 3 shots) and 4
+    (larger than the shot count) innermost."""
     from paper_2008_11778_amd import Context
-    g, m = ragged_case(nshots=2, nt=121)
+    g, m = ragged_case(nshots=3, nt=121)
     d_obs = np.zeros((g.nshots, g.nt, g.nrec), np.float32)
     outs = []
     for tb in (False, True):
-        for order in (0, 1):
+        for order in (0, 1, 2, 4):
             with Context(g, ckpt_every=16) as ctx:
                 ctx.set_time_blocking(tb)
                 ctx.set_tile_order(order)

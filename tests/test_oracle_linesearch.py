@@ -39,7 +39,7 @@ def _kinked(K, c=0.5):
     return J, grad
 
 
-def _run(K, c1, iters=1, M=1):
+def _run(K, c1, iters=1, M=1, restart=True):
     J, grad = _kinked(K)
     calls = []
 
@@ -47,7 +47,7 @@ def _run(K, c1, iters=1, M=1):
         calls.append(float(np.asarray(p).ravel()[0]))
         return J(p)
 
-    res = aa.alg2(grad, misfit, np.array([3.0]), 0.5, M=M, iters=iters, c1=c1)
+    res = aa.alg2(grad, misfit, np.array([3.0]), 0.5, M=M, iters=iters, c1=c1, restart=restart)
     return res, calls
 
 
@@ -127,6 +127,43 @@ def test_window_length_is_min_of_M_and_k():
     f_2 [0.25, 1.5] / (0.25^2 + 1.5^2) = 0.75 [0.25, 1.5] / 2.3125."""
     res, _ = _run(K=8.0, c1=1e-4, iters=2, M=2)
     np.testing.assert_allclose(res["gammas"][1], 0.75 * np.array([0.25, 1.5]) / 2.3125, rtol=1e-14)
+
+
+def test_restart_after_a_fallback_that_decreased_J():
+    """K = 4096, three iterations.  Iteration 1 falls back to p_2 = pbar =
+    1.25 (above).  At p_2: g_2 = 1 + 0.5*0.25 = 1.125 and J(p_2) = 0.5 +
+    0.25 + 0.25*0.0625 = 0.765625 < J(p_1) = 1.75, so the fallback step
+    decreased J and the window restarts from p_2: no difference column,
+    gamma empty, ptilde = pbar = G(p_2) = 1.25 - 0.5625 = 0.6875, and all
+    four trials sit at 0.6875, where J = 0.5 - 0.3125 + 2048*0.09765625 =
+    200.1875 fails; p_3 = 0.6875.  At p_3: g_3 = 1 + 4096*(-0.3125) = -1279
+    and J(p_3) = 200.1875 > J(p_2), so this fallback keeps the window
+    (p_2, p_3): f_2 = -0.5625, f_3 = 639.5, A = 640.0625 and
+    gamma = 639.5 / 640.0625.
+    Without the restart, iteration 2 would use the window (p_1, p_2):
+    A = -0.5625 + 0.75 = 0.1875, gamma = -3, ptilde = 0.6875 - (-0.5625)(-3)
+    = -1, so its first trial would be at -1."""
+    res, calls = _run(K=4096.0, c1=1e-4, iters=3)
+    assert res["lambdas"] == [0.0, 0.0, res["lambdas"][2]]
+    assert res["restarts"] == [2]
+    assert res["gammas"][1].size == 0
+    np.testing.assert_allclose(calls[4:8], [0.6875] * 4, rtol=1e-14)
+    np.testing.assert_allclose(res["iterates"][3], [0.6875], rtol=1e-14)
+    np.testing.assert_allclose(res["misfits"][2:4], [0.765625, 200.1875], rtol=1e-14)
+    np.testing.assert_allclose(res["gammas"][2], [639.5 / 640.0625], rtol=1e-14)
+    res0, calls0 = _run(K=4096.0, c1=1e-4, iters=2, restart=False)
+    assert res0["restarts"] == []
+    np.testing.assert_allclose(res0["gammas"][1], [-3.0], rtol=1e-14)
+    assert calls0[4] == -1.0
+
+
+def test_no_restart_without_a_fallback():
+    """The K = 8 case accepts lambda = 1/4 in iteration 1 (no fallback), so
+    iteration 2 keeps the window (p_1, p_2) whatever the misfits do:
+    gamma = 0.5 as worked above."""
+    res, _ = _run(K=8.0, c1=1e-4, iters=2)
+    assert res["restarts"] == []
+    np.testing.assert_allclose(res["gammas"][1], [0.5], rtol=1e-14)
 
 
 # ----------------------------------------------------------------------------
