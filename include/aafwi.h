@@ -106,6 +106,22 @@ int aafwi_forward_model(aafwi_ctx* ctx, const float* m, float* d, int keep_ckpt)
 int aafwi_residual_misfit(aafwi_ctx* ctx, const float* d, const float* d_obs, float* r,
                           double* J);
 
+/* The same residual and misfit for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc), with no context: r = d - d_obs over n device floats (r
+ * may alias d) and J = 1/2 sum r^2 as one device double, with the same
+ * kernels and summation order as aafwi_residual_misfit (bitwise equal
+ * results for the same n).  The FP64 partial sums live in a static device
+ * array of 1024 doubles (8 KiB), one per GPU, held until the process ends;
+ * its device address is looked up on the first call on each device.  Nothing
+ * is allocated and nothing needs to start at zero.  Work is enqueued on
+ * `stream`, which must belong to the current device.  Calls that overlap on
+ * one GPU (on different streams, or from different threads) share the array
+ * and race.  Errors: AAFWI_E_INVALID for NULL pointers or n outside
+ * [1, 2^40]; AAFWI_E_HIP if the array's address cannot be found. */
+int aafwi_residual_misfit_noalloc(aafwi_stream stream, int64_t n, const float* d, const float* d_obs,
+                                  float* r, double* J);
+
 /* ---- adjoint-state gradient (eq. FWI_adj, eq. adj_grad1) ------------------- */
 
 /* Forward (with checkpoints) + residual + adjoint + zero-lag imaging + fold.

@@ -63,6 +63,7 @@ _sig("aafwi_device_bytes", _vp, ctypes.POINTER(_i64))
 _sig("aafwi_sync", _vp)
 _sig("aafwi_forward_model", _vp, _vp, _vp, ctypes.c_int)
 _sig("aafwi_residual_misfit", _vp, _vp, _vp, _vp, _vp)
+_sig("aafwi_residual_misfit_noalloc", _vp, ctypes.c_int64, _vp, _vp, _vp, _vp)
 _sig("aafwi_batch_aa_create", ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.c_int32, ctypes.c_double, _vp,
      ctypes.POINTER(_vp))
 _sig("aafwi_batch_aa_step", _vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_float),
@@ -574,6 +575,16 @@ class Reducer:
                                    _ptr(out, torch.float64, 1, "out"),
                                    _ptr(self.ws, torch.float64, DOT_WORKSPACE, "workspace")))
         return out
+
+
+def residual_misfit_noalloc(d, d_obs, r, J, stream=None):
+    """r = d - d_obs and J = 1/2 sum r^2 (one device double) through the
+    entry point that allocates nothing; r and J are caller tensors."""
+    n = d.numel()
+    _check(_lib.aafwi_residual_misfit_noalloc(_stream_handle(stream), n, _ptr(d, numel=n, name="d"),
+                                              _ptr(d_obs, numel=n, name="d_obs"), _ptr(r, numel=n, name="r"),
+                                              _ptr(J, torch.float64, 1, "J")))
+    return r, J
 
 
 def blend(lam, p_tilde, p_bar, out=None, stream=None):

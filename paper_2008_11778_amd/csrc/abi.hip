@@ -21,6 +21,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1121,3 +1122,50 @@ extern "C" int aafwi_batch_kernel_timing_read(aafwi_batch* b, int id, double* me
     });
 }
 
+// ---------------------------------------------------------------------------
+// residual and misfit without any allocation
+// ---------------------------------------------------------------------------
+namespace {
+
+// FP64 partial sums of the misfit reduction (one per reduction block), shared
+// by every call on a device.  In host code this name is only a stand-in for
+// the device array: its device address comes from hipGetSymbolAddress.
+constexpr int kScratchDoubles = aafwi::kReduceBlocks;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+constexpr long long kMaxMisfitElems = 1LL << 40;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch array, looked up once per device
+// (with that device current) and kept.
+double* scratch_on_current_device() {
+    int dev = -1;
+    AAFWI_HIP(hipGetDevice(&dev));
+    AAFWI_REQUIRE(dev >= 0 && dev < kMaxDevices, "residual_misfit_noalloc: device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        AAFWI_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        AAFWI_REQUIRE(p != nullptr, "residual_misfit_noalloc: no device address for the scratch array");
+        g_scratch_ptr[dev] = (double*)p;
+    }
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
+extern "C" int aafwi_residual_misfit_noalloc(aafwi_stream stream, int64_t n, const float* d, const float* d_obs,
+                                             float* r, double* J) {
+    return guarded([&]() -> int {
+        AAFWI_REQUIRE(d && d_obs && r && J, "residual_misfit_noalloc: NULL argument");
+        AAFWI_REQUIRE(n >= 1, "residual_misfit_noalloc: n must be at least 1");
+        AAFWI_REQUIRE(n <= kMaxMisfitElems, "residual_misfit_noalloc: n exceeds the 2^40-element limit");
+        double* part = scratch_on_current_device();
+        // the reduction writes every one of its kReduceBlocks partials before
+        // the final sum reads them, so nothing left by an earlier call is read
+        aafwi::launch_residual_misfit((hipStream_t)stream, (long long)n, d, d_obs, r, part, J, nullptr, 0);
+        return AAFWI_OK;
+    });
+}
