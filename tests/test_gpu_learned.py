@@ -202,33 +202,33 @@ def test_learned_aa_matches_oracle_with_trained_weights(learned_case):
         assert abs(h.J - Jr) <= 1e-2 * Jr, (k, h.J, Jr)
 
 
-@pytest.mark.skip(reason="training-set size for a reliable held-out gain is being measured; "
-                         "32 models of 64 x 160 gave a geometric-mean ratio of 1.27")
 def test_trained_network_gains_over_plain_aa():
     """What the learned direction gains: the network is trained on the GPU
-    (Adam, 20 epochs) on pairs from plain AA runs on 32 seeded layered models
-    of the learned-direction family (64 x 160 grids, 8 shots, 1 s records),
-    then plain Algorithm 2 and Algorithm 2 on G_theta (M = 10, 6
-    iterations each, the plain-AA fallback on) run from the smoothed start
-    of 4 held-out models of the same family.  The learned runs end at a
-    lower misfit on average (geometric mean of J_learned / J_plain below 1)
-    and on at least 3 of the 4 models."""
+    (Adam, 20 epochs) on the 512 (g_k, p_k, s_k) pairs of plain AA runs
+    (M = 10, 8 iterations) on 64 seeded layered models of the
+    learned-direction family (320 x 128 grids, 16 shots, 2 s records), then
+    plain Algorithm 2 and Algorithm 2 on G_theta (M = 10, 8 iterations each,
+    the plain-AA fallback on) run from the smoothed start of 6 held-out
+    models of the same family.  The learned runs end at a lower misfit: the
+    geometric mean of J_learned / J_plain is below 0.9 and at least 4 of the
+    6 models end lower.  (Measured with this recipe: 0.74, 5 of 6; with 32
+    training models 0.76, with 128 models 0.56.)"""
     import torch
     from paper_2008_11778_amd import CNN, Context
     from paper_2008_11778_amd.inversion import AADescent, FWIProblem
     from paper_2008_11778_amd.learned import LearnedAADescent, aa_pairs, init_weights, train
-    size = dict(nz=64, nx=160, nshots=8, nt=1000)
-    cases = [synth.learned_instance(i, **size) for i in range(32)]
-    pairs = aa_pairs(cases, M=10, iters=6, ckpt_every=50)
-    net = CNN(size["nz"], size["nx"], 8, init_weights(5005))
+    cases = [synth.learned_instance(i) for i in range(64)]
+    pairs = aa_pairs(cases, M=10, iters=8, ckpt_every=50)
+    nz, nx = cases[0][2].shape
+    net = CNN(nz, nx, 8, init_weights(5005))
     hist = train(net, pairs, epochs=20, batch=8, lr=1e-3)
     print(f"{len(pairs)} pairs, epoch losses {hist[0]:.4f} -> {hist[-1]:.4f}")
-    assert hist[-1] < hist[0]
-    net1 = CNN(size["nz"], size["nx"], 1, net.get_weights())
+    assert len(pairs) == 512 and hist[-1] < hist[0]
+    net1 = CNN(nz, nx, 1, net.get_weights())
     net.close()
     ratios = []
-    for j in range(4):
-        g, mt, m0 = synth.learned_instance(500 + j, **size)
+    for j in range(6):
+        g, mt, m0 = synth.learned_instance(500 + j)
         final = {}
         with Context(g) as ctx:
             d_obs = ctx.forward_model(torch.from_numpy(mt).cuda()).clone()
@@ -237,7 +237,7 @@ def test_trained_network_gains_over_plain_aa():
                 p0 = torch.from_numpy(m0).cuda()
                 run = AADescent(prob, p0, None, M=10) if kind == "plain" else LearnedAADescent(prob, p0, net1, M=10)
                 run.first()
-                for _ in range(6):
+                for _ in range(8):
                     run.iterate()
                 final[kind] = prob.misfit_keep(run.p)
                 run.close()
@@ -246,5 +246,5 @@ def test_trained_network_gains_over_plain_aa():
     net1.close()
     gm = float(np.exp(np.mean(np.log(ratios))))
     print(f"geometric mean J_learned / J_plain = {gm:.3f}")
-    assert gm < 1.0
-    assert sum(r < 1.0 for r in ratios) >= 3
+    assert gm < 0.9
+    assert sum(r < 1.0 for r in ratios) >= 4
