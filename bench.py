@@ -669,18 +669,22 @@ def learned_workload(args):
     import synth
     from paper_2008_11778_amd import CNN, Context
     from paper_2008_11778_amd.inversion import AADescent, FWIProblem
-    from paper_2008_11778_amd.learned import LearnedAADescent, aa_pairs, init_weights, lbfgs_pairs, merge, train
+    from paper_2008_11778_amd.learned import (LearnedAADescent, aa_pairs, flip_x, init_weights, lbfgs_pairs, merge,
+                                              train)
 
     dev = torch.device("cuda", 0)
     t_all = time.perf_counter()
-    train_cases = [synth.learned_instance(i) for i in range(args.train_instances)]
+    size = dict(nz=args.train_nz, nx=args.train_nx, nshots=args.train_shots, nt=args.train_nt)
+    train_cases = [synth.learned_instance(i, **size) for i in range(args.train_instances)]
     t0 = time.perf_counter()
     pa = aa_pairs(train_cases, M=10, iters=args.train_iters)
     log(f"AA pairs: {len(pa)} in {time.perf_counter() - t0:.1f}s")
     t0 = time.perf_counter()
-    pl = lbfgs_pairs(train_cases[: args.lbfgs_instances], M=10, iters=6)
+    pl = lbfgs_pairs(train_cases[: args.lbfgs_instances], M=10, iters=args.lbfgs_iters)
     log(f"L-BFGS pairs: {len(pl)} in {time.perf_counter() - t0:.1f}s")
     pairs = merge(pa, pl)
+    if args.flip:
+        pairs = merge(pairs, flip_x(pairs))
     t_data = time.perf_counter() - t_all
     nz, nx = train_cases[0][2].shape
     net = CNN(nz, nx, 8, init_weights(5005))
@@ -733,7 +737,7 @@ def learned_workload(args):
 
     rows = []
     for j in range(args.test_instances):
-        g, mt, m0 = synth.learned_instance(500 + j)
+        g, mt, m0 = synth.learned_instance(500 + j, **size)
         rows.append(compare(500 + j, g, mt, m0, net))
     large = []
     if args.large_test:
@@ -769,6 +773,46 @@ def learned_workload(args):
     print(json.dumps(out), flush=True)
 
 
+def tune_workload(args):
+    """Launch shapes of the FWI-gradient (768 x 256, 64 shots) and large-grid
+    (1024 x 384, 96 shots) workloads timed in place (autotune.tune_in_place:
+    the workload's own context with checkpoints every 50 steps, its start
+    model and its residual against observed data from the true model) and
+    written into the tuning table shipped with the package, keeping each
+    entry's Born-kernel shape.  Prints one JSON line with the new entries."""
+    import torch
+
+    import synth
+    from paper_2008_11778_amd import Context, autotune
+
+    dev = torch.device("cuda", 0)
+    with open(autotune.SHIPPED) as f:
+        shipped = json.load(f)
+    out = {}
+    for make in (synth.config2, synth.config5):
+        g, m_true, m0 = make()
+        key = autotune.grid_key(g)
+        with Context(g, ckpt_every=50) as ctx:
+            m0t = torch.from_numpy(m0).to(dev)
+            d_obs = ctx.forward_model(torch.from_numpy(m_true).to(dev)).clone()
+            t0 = time.perf_counter()
+            entry = autotune.tune_in_place(ctx, m0t, d_obs, verbose=True)
+            log(f"{key}: tuned in place in {time.perf_counter() - t0:.1f} s: {entry}")
+        old = shipped.get(key, {})
+        for fld in ("3", "order3"):
+            if fld in old:
+                entry[int(fld) if fld.isdigit() else fld] = old[fld]
+        shipped[key] = {str(k): v for k, v in entry.items()}
+        out[key] = shipped[key]
+    shipped["_about"] = ("launch shapes chosen on MI355X: the FWI-gradient (296x808x64) and large-grid (424x1064x96) "
+                         "classes timed in place by autotune.tune_in_place on their own workloads (full 4000-step "
+                         "records, checkpoints every 50, real residuals; bench.py --workload tune), the other classes "
+                         "by autotune.tune on short records; key: padded rows x padded columns x shots")
+    with open(autotune.SHIPPED, "w") as f:
+        json.dump(shipped, f, indent=1)
+    print(json.dumps({"metric": "launch shapes tuned in place", "entries": out}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -794,7 +838,8 @@ def main():
                          "of the configured checkpoints every 50 steps")
     ap.add_argument("--no-full-storage-run", action="store_true",
                     help="skip the second timed run with full storage")
-    ap.add_argument("--workload", default="fwi", choices=["fwi", "batched", "learned", "cnn", "noisy", "lsrtm", "target"])
+    ap.add_argument("--workload", default="fwi",
+                    choices=["fwi", "batched", "learned", "cnn", "noisy", "lsrtm", "target", "tune"])
     ap.add_argument("--target-iters", type=int, default=30, help="target workload: plain AA iterations")
     ap.add_argument("--budget", type=float, default=20, help="noisy workload: gradient evaluations per optimiser")
     ap.add_argument("--instances", type=int, default=32, help="batched workload: number of instances")
@@ -803,6 +848,12 @@ def main():
     ap.add_argument("--train-instances", type=int, default=200, help="learned workload: training models")
     ap.add_argument("--train-iters", type=int, default=8, help="learned workload: AA iterations per training model")
     ap.add_argument("--lbfgs-instances", type=int, default=8, help="learned workload: L-BFGS training runs")
+    ap.add_argument("--lbfgs-iters", type=int, default=6, help="learned workload: iterations per L-BFGS run")
+    ap.add_argument("--train-nz", type=int, default=128, help="learned workload: training grid rows")
+    ap.add_argument("--train-nx", type=int, default=320, help="learned workload: training grid columns")
+    ap.add_argument("--train-shots", type=int, default=16, help="learned workload: shots per training model")
+    ap.add_argument("--train-nt", type=int, default=2000, help="learned workload: training record length")
+    ap.add_argument("--flip", action="store_true", help="learned workload: add the x-mirrored pairs")
     ap.add_argument("--test-instances", type=int, default=16, help="learned workload: held-out models")
     ap.add_argument("--epochs", type=int, default=20, help="learned workload: training epochs")
     ap.add_argument("--large-test", type=int, default=2,
@@ -824,6 +875,8 @@ def main():
         return lsrtm_workload(args)
     if args.workload == "target":
         return target_workload(args)
+    if args.workload == "tune":
+        return tune_workload(args)
     # the oracle runs first, in child processes started before this process
     # touches the GPU
     cpu = None

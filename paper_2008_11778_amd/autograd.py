@@ -41,3 +41,27 @@ class SeismicForward(torch.autograd.Function):
 def seismic_forward(m: torch.Tensor, context: Context) -> torch.Tensor:
     """Differentiable f(m): [S][nt][R] seismograms from the model m [nz][nx]."""
     return SeismicForward.apply(m, context)
+
+
+class Misfit(torch.autograd.Function):
+    """J = 1/2 ||d - d_obs||^2 (eq. FWI) through the library's residual
+    kernel (r = d - d_obs in FP32, J in FP64 in a fixed order, the same
+    arithmetic as the C-ABI problem); the gradient with respect to d is r,
+    scaled by the incoming gradient of J."""
+
+    @staticmethod
+    def forward(fctx, d: torch.Tensor, d_obs: torch.Tensor, context: Context):
+        r, J = context.residual_misfit(d.detach().contiguous(), d_obs.contiguous())
+        fctx.save_for_backward(r)
+        return J.view(())
+
+    @staticmethod
+    def backward(fctx, grad_J: torch.Tensor):
+        from ._lib import scale
+        (r,) = fctx.saved_tensors
+        return scale(float(grad_J.item()), r), None, None
+
+
+def misfit(d: torch.Tensor, d_obs: torch.Tensor, context: Context) -> torch.Tensor:
+    """Differentiable J(d) = 1/2 ||d - d_obs||^2 as a device FP64 scalar."""
+    return Misfit.apply(d, d_obs, context)

@@ -189,3 +189,66 @@ def tune_batch(batch, geoms, models, shots: int = 8, use_cache=True, verbose=Fal
     if verbose:
         print(f"autotune batch: per-class heights {chosen} (modes {mask})", flush=True)
     return {f"{a}x{b}": v for (a, b), v in chosen.items()}
+
+
+def tune_in_place(ctx, m, d_obs=None, rows_one=(8, 16, 32, 64), rows_two=(16, 24, 48, 96), orders=(0, 1),
+                  verbose=False) -> dict:
+    """Launch shapes timed where the run happens: on the caller's own context
+    (its grid, shots, record length and checkpoint layout), its model and,
+    with ``d_obs``, its own residual, so that the planes the kernels stream
+    hold the values of the real run (a short record from rest holds mostly
+    zeros).  Every candidate (steps per launch, tile order, strip height) is
+    applied to the forward, recompute and adjoint kernels at once and timed
+    over one forward run with kept checkpoints and one backward pass of the
+    whole record; per kernel the fastest per-step time wins (ties within 2 %
+    to the taller strip).  The Born kernel keeps the context's setting.
+    Returns a tune()-style entry for the three kernels (apply() takes it) and
+    leaves the context in that shape."""
+    import torch
+    d = ctx._new(ctx.data_shape)
+    r = ctx._new(ctx.data_shape)
+    J = ctx._new((1,), torch.float64)
+    table = {}
+    shapes = [(False, o, h) for o in orders for h in rows_one] + [(True, o, h) for o in orders for h in rows_two]
+    for tb, order, rows in shapes:
+        if rows > ctx.nz + 2 * ctx.nb and rows != min(rows_one + rows_two):
+            continue
+        for k in range(3):
+            ctx.set_time_blocking(tb, k)
+            ctx.set_tile_order(order, k)
+            ctx.set_tile(rows, k)
+        ctx.kernel_timing(1)
+        ctx.forward_model(m, d, keep_ckpt=True)
+        if d_obs is not None:
+            ctx.residual_misfit(d, d_obs, r, J)
+        else:
+            r.copy_(d)
+        ctx.adjoint_from_residual(r)
+        for k in range(3):
+            ms, cnt = ctx.kernel_timing_read(k)
+            if cnt:
+                table[(tb, order, rows, k)] = ms / (2 if tb else 1)
+        ctx.kernel_timing(0)
+        if verbose:
+            print(f"autotune in place: {'two' if tb else 'one'}-step order {order} rows {rows}: "
+                  + ", ".join(f"k{k} {table.get((tb, order, rows, k), float('nan')) * 1e3:.1f} us/step"
+                              for k in range(3)), flush=True)
+    out = {}
+    for k in range(3):
+        cand = {key: t for key, t in table.items() if key[3] == k}
+        best = min(cand.values())
+        near = [(key[2], -key[1], key) for key, t in cand.items() if t <= best * (1 + TIE)]
+        # the best mode first, then within that mode the tallest strip inside the tie band
+        mode = min(cand, key=cand.get)[0]
+        near = [x for x in near if x[2][0] == mode] or near
+        tb, order, rows, _ = max(near)[2]
+        out[k], out[f"order{k}"], out[f"two{k}"] = rows, order, bool(tb)
+        for mm in (False, True):
+            mc = {key: t for key, t in cand.items() if key[0] == mm}
+            if mc:
+                out[f"rows_{'two' if mm else 'one'}{k}"] = min(mc, key=mc.get)[2]
+        if verbose:
+            print(f"autotune in place: kernel {k}: {'two' if tb else 'one'}-step, rows {rows}, order {order}, "
+                  f"{cand[(tb, order, rows, k)] * 1e3:.1f} us per step", flush=True)
+    apply(ctx, out)
+    return out

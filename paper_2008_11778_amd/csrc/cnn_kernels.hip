@@ -9,10 +9,10 @@
 // Training target for a step s taken by an optimiser: t = -s / rms(s); loss
 // per image mean((d / rms(d) - t)^2), averaged over the batch.
 //
-// Convolutions are implicit GEMMs on v_mfma_f32_16x16x16_bf16: one wave owns
+// Convolutions are implicit GEMMs on v_mfma_f32_16x16x32_bf16: one wave owns
 // 16 consecutive pixels (rows of the 16x16 tile) and all output channels
-// (16-column tiles); the reduction runs over (tap, 16-channel chunk).
-// Activations are NHWC with the channel count padded to a multiple of 16.
+// (16-column tiles); the reduction runs over (tap, channel) in chunks of 32.
+// Activations are NHWC with the channel count padded to 16 or 32.
 // Weight copies: Wf[tap][co][ci] (forward), Wd[tap][ci][co] (input gradient).
 #include <algorithm>
 #include <cmath>

@@ -73,10 +73,11 @@ class FWIProblem:
 class AutogradFWIProblem:
     """The same J(m) and gradient through the autograd form: f(m) is
     ``seismic_forward`` (a torch.autograd.Function over the HIP forward and
-    adjoint), the residual r = f(m) - d_obs stays FP32 and J = 1/2 sum r^2 is
-    accumulated in FP64 by torch; ``J.backward()`` hands r to the adjoint.
-    The graph of the last misfit evaluation is kept, so the gradient at the
-    accepted line-search trial reuses its forward run (its checkpoints)."""
+    adjoint) and J = ``misfit`` (a torch.autograd.Function over the library's
+    residual kernel: r = f(m) - d_obs in FP32, J in FP64 in the same order as
+    the C-ABI problem); ``J.backward()`` hands r to the adjoint.  The graph of
+    the last misfit evaluation is kept, so the gradient at the accepted
+    line-search trial reuses its forward run (its checkpoints)."""
 
     def __init__(self, ctx: Context, d_obs: torch.Tensor):
         self.ctx = ctx
@@ -88,11 +89,10 @@ class AutogradFWIProblem:
         self.n_adj = 0
 
     def misfit_keep(self, m: torch.Tensor) -> float:
-        from .autograd import seismic_forward
+        from .autograd import misfit, seismic_forward
         leaf = m.detach().view(self.ctx.nz, self.ctx.nx).requires_grad_(True)
         d = seismic_forward(leaf, self.ctx)
-        r = d - self.d_obs
-        J = 0.5 * torch.sum(r.double() ** 2)
+        J = misfit(d, self.d_obs, self.ctx)
         self.kept, self.kept_J, self.kept_leaf = m, J, leaf
         self.n_fwd += 1
         return float(J.item())

@@ -227,6 +227,13 @@ def merge(*ps: Pairs) -> Pairs:
                  sum((p.source for p in ps), []))
 
 
+def flip_x(p: Pairs) -> Pairs:
+    """The pairs mirrored along x (augmentation: the layered family and the
+    evenly spread shots look alike under the mirror, the network does not)."""
+    return Pairs(torch.flip(p.g, dims=[2]).contiguous(), torch.flip(p.m, dims=[2]).contiguous(),
+                 torch.flip(p.s, dims=[2]).contiguous(), [f"{x}-flip" for x in p.source])
+
+
 def train(net: CNN, pairs: Pairs, epochs: int = 20, batch: int = 8, lr: float = 1e-3, seed: int = 5006):
     """Adam over shuffled mini-batches; returns the mean loss of each epoch."""
     rng = np.random.default_rng(seed)
