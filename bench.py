@@ -633,20 +633,28 @@ def cnn_workload(args):
     step on 8 images of 384 x 1024 (random inputs), HIP-event timed; reports
     algorithmic TFLOP/s and, since the 3 x 3 layers of 16-32 channels carry
     about 90 flop per byte (below the bf16 ridge of 2500 / 8 = 312), the
-    forward pass against the HBM roofline: each layer reads its bf16 input
-    and writes its output once, 420 bytes per pixel over the four layers
-    (16-channel padded input 32 + 3 x 64 read, 3 x 64 bf16 + 4 FP32 written)."""
+    forward pass against the HBM roofline.  With the second and third layers
+    fused, inference reads the padded 16-channel input (32 bytes a pixel)
+    and the 32-channel bf16 activations h1 and h3 (64 each) once and writes
+    h1, h3 and the FP32 output z: 292 bytes per pixel (420 with four separate
+    layers, which also write and re-read h2).  Both variants are timed."""
     from paper_2008_11778_amd import CNN
     from paper_2008_11778_amd.learned import init_weights
     B, H, W = 8, 384, 1024
-    speed = cnn_timing(CNN(H, W, B, init_weights(5005)), B, H, W, reps=args.steps * 10)
+    net = CNN(H, W, B, init_weights(5005))
+    net.set_fused(False)
+    separate = cnn_timing(net, B, H, W, reps=args.steps * 10)
+    net.set_fused(True)
+    speed = cnn_timing(net, B, H, W, reps=args.steps * 10)
     flops = 2.0 * B * H * W * 19296
-    hbm = 420.0 * B * H * W
+    hbm = 292.0 * B * H * W
     gbs = hbm / (speed["forward"] / 1e3) / 1e9
     out = {"metric": "learned-direction network speed (bf16 matrix cores)", "value": round(
         flops / speed["forward"] / 1e9, 1), "unit": "TFLOP/s (forward, algorithmic)", "n_gpus": 1,
            "higher_is_better": True, "forward_ms": round(speed["forward"], 3),
            "train_step_ms": round(speed["train_step"], 3),
+           "separate_layers": {"forward_ms": round(separate["forward"], 3),
+                               "train_step_ms": round(separate["train_step"], 3)},
            "train_tflops": round(3 * flops / speed["train_step"] / 1e9, 1),
            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "bytes_per_forward": hbm},

@@ -375,6 +375,12 @@ int aafwi_cnn_get_weights(aafwi_cnn* c, float* weights);
  * network output, d (optional) the direction softplus(z) * g. */
 int aafwi_cnn_forward(aafwi_cnn* c, int32_t B, const float* g, const float* m, float* z, float* d);
 
+/* Evaluate the second and third convolutions in one kernel (on, the
+ * default: their intermediate activation stays in on-chip memory during
+ * inference and is written once for the backward pass during training) or
+ * as two kernels (off).  The results are bitwise the same either way. */
+int aafwi_cnn_set_fused(aafwi_cnn* c, int32_t on);
+
 /* Weight gradient (device, AAFWI_CNN_PARAMS floats, host weight layout) of
  * the batch loss; loss: device double, optional.  Weights are unchanged. */
 int aafwi_cnn_gradients(aafwi_cnn* c, int32_t B, const float* g, const float* m, const float* s, float* grad,

@@ -629,6 +629,7 @@ _sig("aafwi_cnn_get_weights", _vp, _vp)
 _sig("aafwi_cnn_forward", _vp, _i32, _vp, _vp, _vp, _vp)
 _sig("aafwi_cnn_gradients", _vp, _i32, _vp, _vp, _vp, _vp, _vp)
 _sig("aafwi_cnn_train_step", _vp, _i32, _vp, _vp, _vp, _f32, _vp)
+_sig("aafwi_cnn_set_fused", _vp, _i32)
 CNN_PARAMS = 19296
 CNN_SHAPES = ((32, 2, 3, 3), (32, 32, 3, 3), (32, 32, 3, 3), (1, 32, 3, 3))
 
@@ -678,6 +679,10 @@ class CNN:
     def set_weights(self, weights):
         w = cnn_flatten(weights) if isinstance(weights, (list, tuple)) else np.ascontiguousarray(weights, np.float32)
         _check(_lib.aafwi_cnn_set_weights(self._h, w.ctypes.data))
+
+    def set_fused(self, on: bool):
+        """Second and third convolutions in one kernel (default) or two."""
+        _check(_lib.aafwi_cnn_set_fused(self._h, int(bool(on))))
 
     def get_weights(self) -> np.ndarray:
         w = np.empty(CNN_PARAMS, np.float32)

@@ -10,8 +10,8 @@
 // per image mean((d / rms(d) - t)^2), averaged over the batch.
 //
 // Convolutions are implicit GEMMs on v_mfma_f32_16x16x32_bf16: one wave owns
-// 16 consecutive pixels (rows of the 16x16 tile) and all output channels
-// (16-column tiles); the reduction runs over (tap, channel) in chunks of 32.
+// 16 consecutive pixels and all output channels (16-channel tiles); the
+// reduction runs over (tap, channel) in chunks of 32.
 // Activations are NHWC with the channel count padded to 16 or 32.
 // Weight copies: Wf[tap][co][ci] (forward), Wd[tap][ci][co] (input gradient).
 #include <algorithm>
@@ -64,7 +64,11 @@ enum ConvMode { kHidden = 0, kLast = 1, kInputGrad = 2 };
 // the matrix cores (four independent accumulation chains per wave).  The
 // rows being written are never among the four being read, so one barrier per
 // pass orders the two.  Wave w takes pixels x0+16w .. x0+16w+15 and reads
-// each A fragment as one 16-byte LDS load.
+// each activation fragment as one 16-byte LDS load.  For the 32-channel
+// outputs the weights are the A operand and the activations the B operand,
+// so a lane's accumulators hold four consecutive channels of one pixel and
+// go to HBM as 8-byte stores; the 16-channel last layer keeps the pixels in
+// the A operand (its single useful channel is then one lane group).
 constexpr int kCSeg = 64;
 constexpr int kConvSlots = 6;  // LDS ring of staged input rows
 
@@ -75,19 +79,33 @@ struct RowFetch {
     v4u v[kPer];
 };
 
-// Global -> registers: input row yy over columns x0-1 .. x0+64 (zeros outside).
+// One image of an NHWC bf16 tensor as a raw buffer resource (base in SGPRs,
+// 32-bit byte offsets); the hardware range check returns zeros for loads at
+// offsets at or beyond the image, which is how pieces outside the image are
+// read (offset kOut).
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+constexpr unsigned kOut = 0x80000000u;
 template <int C>
-__device__ __forceinline__ void row_fetch(RowFetch<C>& f, const bf16* __restrict__ x, int bimg, int H, int W,
-                                          int yy, int x0) {
+__device__ __forceinline__ Rsrc image_view(const bf16* x, int bimg, int H, int W) {
+    const long long n = (long long)H * W * C;
+    return __builtin_amdgcn_make_buffer_rsrc((void*)(x + bimg * n), (short)0, (int)(n * 2), 0x00020000);
+}
+
+// Global -> registers: input row yy over columns x0-1 .. x0+64 (zeros outside;
+// a row the caller will not store, need = false, reads zeros too).  No
+// branch surrounds a load and the data goes to LDS unchanged, so the
+// compiler can wait for each row by count while the rows fetched after it
+// stay in flight.
+template <int C>
+__device__ __forceinline__ void row_fetch(RowFetch<C>& f, Rsrc r, int H, int W, int yy, int x0, bool need = true) {
 #pragma unroll
     for (int k = 0; k < RowFetch<C>::kPer; ++k) {
         const int e = threadIdx.x + 256 * k;
         const int cg = e % (C / 8), j = e / (C / 8);
         const int xx = x0 - 1 + j;
-        v4u v = v4u{0u, 0u, 0u, 0u};
-        if (e < RowFetch<C>::kChunks && yy >= 0 && yy < H && xx >= 0 && xx < W)
-            v = *reinterpret_cast<const v4u*>(x + ((long long)(bimg * H + yy) * W + xx) * C + cg * 8);
-        f.v[k] = v;
+        const bool in = need && e < RowFetch<C>::kChunks && yy >= 0 && yy < H && xx >= 0 && xx < W;
+        const unsigned off = in ? (unsigned)(((yy * W + xx) * C + cg * 8) * 2) : kOut;
+        f.v[k] = __builtin_bit_cast(v4u, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
     }
 }
 
@@ -102,8 +120,71 @@ __device__ __forceinline__ void row_store(const RowFetch<C>& f, bf16* row) {
     }
 }
 
+// The weight fragments are loaded before a kernel's main loop.  An empty asm
+// statement that takes all of them as operands makes the compiler wait for
+// those loads there, once, so that the loop's own waits count only the
+// loads the loop issues (otherwise the first use of each fragment inside the
+// loop carries a wait that also drains the rows prefetched for later passes).
+template <int N, int NT>
+__device__ __forceinline__ void settle(const bf8 (&bw)[N][NT]) {
+#pragma unroll
+    for (int a = 0; a < N; ++a)
+#pragma unroll
+        for (int b = 0; b < NT; ++b) asm volatile("" ::"v"(bw[a][b]));
+}
+
+// Products of one pass for 32 input channels (one tap per 32-wide chunk):
+// two output rows from the four staged rows at base[0..3] (input rows y-1 ..
+// y+2 of the first output row y).  Each (input row, column shift) fragment
+// is read from LDS once and feeds both output rows that use it; every
+// accumulator still takes its nine taps in ascending tap order, so the sums
+// are those of a plain per-row loop over the taps.  SGN = -1 mirrors the
+// taps (input gradient).  TR puts the weights in the A operand: the
+// accumulators then hold four consecutive output channels of one pixel.
+template <int CS, int NT, int SGN, bool TR>
+__device__ __forceinline__ void conv_pass32(const bf16* L, const int (&base)[4], int aofs, const bf8 (&bw)[9][NT],
+                                            v4f (&acc)[2][NT]) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int s = SGN > 0 ? u : 3 - u;
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+            const int cx = SGN > 0 ? v : 2 - v;
+            const bf8 a = __builtin_bit_cast(bf8, *reinterpret_cast<const v4u*>(L + base[s] + cx * CS + aofs));
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int r = s - h;  // input row of this output row, relative to the row above it
+                if (r < 0 || r > 2) continue;
+                const int t = SGN > 0 ? 3 * r + cx : 3 * (2 - r) + (2 - cx);
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+                    acc[h][nt] = TR ? __builtin_amdgcn_mfma_f32_16x16x32_bf16(bw[t][nt], a, acc[h][nt], 0, 0, 0)
+                                    : __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[t][nt], acc[h][nt], 0, 0, 0);
+            }
+        }
+    }
+}
+
+// Four FP32 values -> four packed bf16 (8 bytes), ReLU first when asked.
+__device__ __forceinline__ uint2 pack4(const v4f& a, bool relu) {
+    unsigned h[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) h[q] = f2bf(relu ? fmaxf(a[q], 0.f) : a[q]);
+    return uint2{h[0] | (h[1] << 16), h[2] | (h[3] << 16)};
+}
+
+// Keep each bf16 of v where the matching bf16 of the ReLU output m is > 0.
+__device__ __forceinline__ uint2 relu_mask(uint2 v, uint2 m) {
+    const unsigned mm[2] = {m.x, m.y};
+    unsigned keep[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+        keep[q] = (bf2f((bf16)(mm[q] & 0xffffu)) > 0.f ? 0xffffu : 0u) | (bf2f((bf16)(mm[q] >> 16)) > 0.f ? 0xffff0000u : 0u);
+    return uint2{v.x & keep[0], v.y & keep[1]};
+}
+
 template <int C, int NOUT, int MODE>
-__global__ __launch_bounds__(256) void k_conv_mm(int B, int H, int W, int rows, const bf16* __restrict__ x,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_conv_mm(int B, int H, int W, int rows, const bf16* __restrict__ x,
                                                  const bf16* __restrict__ w, const bf16* __restrict__ mask,
                                                  bf16* __restrict__ y, float* __restrict__ z) {
     constexpr int NCH = (9 * C + 31) / 32;
@@ -112,9 +193,10 @@ __global__ __launch_bounds__(256) void k_conv_mm(int B, int H, int W, int rows, 
     constexpr int CS = C + 8;                // LDS pixel stride: 16-byte aligned rows of channels
     constexpr int RW = (kCSeg + 2) * CS;     // one staged row
     static_assert(MODE == kLast || NOUT == 32, "hidden and input-gradient layers have 32 outputs");
-    constexpr int TS = NOUT + 8;             // transpose tile pixel stride
+    // 32-channel outputs: weights in the A operand, so that a lane ends with
+    // four consecutive channels of its own pixel (one 8-byte store per tile)
+    constexpr bool TR = MODE != kLast;
     __shared__ __align__(16) bf16 xL[kConvSlots * RW];
-    __shared__ __align__(16) bf16 tL[4][16 * TS];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int i = lane & 15, grp = lane >> 4;
     bf8 bw[NCH][NT];
@@ -133,112 +215,112 @@ __global__ __launch_bounds__(256) void k_conv_mm(int B, int H, int W, int rows, 
         for (int nt = 0; nt < NT; ++nt)
             bw[ch][nt] = tap_ok[ch] ? ld8(w + ((tap * NOUT + nt * 16 + i) * C + c0)) : zero8();
     }
+    settle(bw);
     auto slot = [](int r) { return ((r + kConvSlots) % kConvSlots) * RW; };  // r >= -1
     const int segs_x = (W + kCSeg - 1) / kCSeg;
     const int runs = (H + rows - 1) / rows;
     const int nwork = B * runs * segs_x;
-    const int px = 16 * wv + i;  // this lane's pixel in the segment (A rows)
+    const int px = 16 * wv + i;  // this lane's pixel in the segment (A rows, or B columns with TR)
     for (int wk = blockIdx.x; wk < nwork; wk += gridDim.x) {
         const int sx = wk % segs_x, t = wk / segs_x;
         const int run = t % runs, bimg = t / runs;
         const int x0 = sx * kCSeg, ya = run * rows, yb = min(H, ya + rows);
-        RowFetch<C> f0, f1;
+        // the rows of the next two passes are in flight in registers: the
+        // passes alternate between two buffer pairs; a pass stores its pair
+        // (rows yy+1, yy+2) into the ring and refills it with the rows of the
+        // pass after next
+        const Rsrc xr = image_view<C>(x, bimg, H, W);
+        RowFetch<C> fa0, fa1, fc0, fc1;
         __syncthreads();  // the ring's previous contents are no longer read
-        row_fetch<C>(f0, x, bimg, H, W, ya - 1, x0);
-        row_store<C, CS>(f0, xL + slot(ya - 1));
-        row_fetch<C>(f0, x, bimg, H, W, ya, x0);
-        row_store<C, CS>(f0, xL + slot(ya));
-        row_fetch<C>(f0, x, bimg, H, W, ya + 1, x0);
-        row_fetch<C>(f1, x, bimg, H, W, ya + 2, x0);
+        row_fetch<C>(fc0, xr, H, W, ya - 1, x0);
+        row_fetch<C>(fc1, xr, H, W, ya, x0);
+        row_fetch<C>(fa0, xr, H, W, ya + 1, x0);
+        row_fetch<C>(fa1, xr, H, W, ya + 2, x0);
+        row_store<C, CS>(fc0, xL + slot(ya - 1));
+        row_store<C, CS>(fc1, xL + slot(ya));
+        row_fetch<C>(fc0, xr, H, W, ya + 3, x0, ya + 2 < yb);
+        row_fetch<C>(fc1, xr, H, W, ya + 4, x0, ya + 2 < yb);
         // two output rows (yy, yy+1) per pass: input rows yy-1 .. yy+2 are
         // read; rows yy+1, yy+2 are stored at the start of the pass into the
         // slots of rows yy-5, yy-4, which the previous pass no longer reads
-        for (int yy = ya; yy < yb; yy += 2) {
+        auto pass = [&](int yy, RowFetch<C>& f0, RowFetch<C>& f1) {
             row_store<C, CS>(f0, xL + slot(yy + 1));
             row_store<C, CS>(f1, xL + slot(yy + 2));
             __syncthreads();
-            if (yy + 2 < yb) {  // in flight during the products
-                row_fetch<C>(f0, x, bimg, H, W, yy + 3, x0);
-                row_fetch<C>(f1, x, bimg, H, W, yy + 4, x0);
-            }
             const int base[4] = {slot(yy - 1), slot(yy), slot(yy + 1), slot(yy + 2)};
-            // input gradient: the ReLU masks of both output rows, read now so
-            // that they arrive during the products
-            const int mp = lane >> 2, mcg = lane & 3;
-            const int mxx = x0 + 16 * wv + mp;
-            v4u mk[2] = {v4u{0u, 0u, 0u, 0u}, v4u{0u, 0u, 0u, 0u}};
-            if (MODE == kInputGrad && mxx < W) {
+            const int xx = x0 + px;
+            // input gradient: the ReLU masks of this lane's outputs, read now
+            // so that they arrive during the products (and before the rows
+            // fetched below, since loads complete in order)
+            uint2 mk[2][NT] = {};
+            if (MODE == kInputGrad && xx < W) {
 #pragma unroll
                 for (int h = 0; h < 2; ++h)
                     if (yy + h < yb)
-                        mk[h] = *reinterpret_cast<const v4u*>(
-                            mask + ((long long)(bimg * H + yy + h) * W + mxx) * NOUT + mcg * 8);
+#pragma unroll
+                        for (int nt = 0; nt < NT; ++nt)
+                            mk[h][nt] = *reinterpret_cast<const uint2*>(
+                                mask + ((long long)(bimg * H + yy + h) * W + xx) * NOUT + nt * 16 + 4 * grp);
             }
+            // in flight during the next two passes (issued in every pass, so
+            // that the waits stay counted; rows past the run read nothing new)
+            row_fetch<C>(f0, xr, H, W, yy + 5, x0, yy + 4 < yb);
+            row_fetch<C>(f1, xr, H, W, yy + 6, x0, yy + 4 < yb);
             v4f acc[2][NT];
 #pragma unroll
             for (int h = 0; h < 2; ++h)
 #pragma unroll
                 for (int nt = 0; nt < NT; ++nt) acc[h][nt] = v4f{0.f, 0.f, 0.f, 0.f};
+            if constexpr (C == 32) {
+                conv_pass32<CS, NT, sgn, TR>(xL, base, px * CS + 8 * grp, bw, acc);
+            } else {
 #pragma unroll
-            for (int ch = 0; ch < NCH; ++ch) {
-                const int rs = rsel[ch];
-                const int o0 = (rs == 0 ? base[0] : rs == 1 ? base[1] : base[2]) + cofs[ch] + px * CS;
-                const int o1 = (rs == 0 ? base[1] : rs == 1 ? base[2] : base[3]) + cofs[ch] + px * CS;
-                const bf8 a0 = tap_ok[ch] ? __builtin_bit_cast(bf8, *reinterpret_cast<const v4u*>(xL + o0)) : zero8();
-                const bf8 a1 = tap_ok[ch] ? __builtin_bit_cast(bf8, *reinterpret_cast<const v4u*>(xL + o1)) : zero8();
+                for (int ch = 0; ch < NCH; ++ch) {
+                    const int rs = rsel[ch];
+                    const int o0 = (rs == 0 ? base[0] : rs == 1 ? base[1] : base[2]) + cofs[ch] + px * CS;
+                    const int o1 = (rs == 0 ? base[1] : rs == 1 ? base[2] : base[3]) + cofs[ch] + px * CS;
+                    const bf8 a0 = tap_ok[ch] ? __builtin_bit_cast(bf8, *reinterpret_cast<const v4u*>(xL + o0)) : zero8();
+                    const bf8 a1 = tap_ok[ch] ? __builtin_bit_cast(bf8, *reinterpret_cast<const v4u*>(xL + o1)) : zero8();
 #pragma unroll
-                for (int nt = 0; nt < NT; ++nt) {
-                    acc[0][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, bw[ch][nt], acc[0][nt], 0, 0, 0);
-                    acc[1][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bw[ch][nt], acc[1][nt], 0, 0, 0);
+                    for (int nt = 0; nt < NT; ++nt) {
+                        if (TR) {
+                            acc[0][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bw[ch][nt], a0, acc[0][nt], 0, 0, 0);
+                            acc[1][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bw[ch][nt], a1, acc[1][nt], 0, 0, 0);
+                        } else {
+                            acc[0][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, bw[ch][nt], acc[0][nt], 0, 0, 0);
+                            acc[1][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bw[ch][nt], acc[1][nt], 0, 0, 0);
+                        }
+                    }
                 }
             }
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const int yo = yy + h;
                 if (yo >= yb) break;
-                // lane holds D[4 grp + r][i]: pixel 16 wv + 4 grp + r of the segment, output channel nt*16 + i
                 const long long rowp = (long long)(bimg * H + yo) * W;
                 if (MODE == kLast) {
+                    // lane holds D[4 grp + r][i]: pixel 16 wv + 4 grp + r, output channel i (z is channel 0)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const int xx = x0 + 16 * wv + 4 * grp + r;
-                        if (xx < W && i == 0) z[rowp + xx] = acc[h][0][r];
+                        const int xz = x0 + 16 * wv + 4 * grp + r;
+                        if (xz < W && i == 0) z[rowp + xz] = acc[h][0][r];
                     }
-                } else {
-                    // through the wave's LDS tile to one 16-byte store (8 channels of one pixel) per lane
-                    bf16* tw = tL[wv];
+                } else if (xx < W) {
+                    // lane holds D[4 grp + r][i]: output channels nt*16 + 4 grp + r of pixel px
 #pragma unroll
-                    for (int r = 0; r < 4; ++r)
-#pragma unroll
-                        for (int nt = 0; nt < NT; ++nt)
-                            tw[(4 * grp + r) * TS + nt * 16 + i] =
-                                f2bf(MODE == kHidden ? fmaxf(acc[h][nt][r], 0.f) : acc[h][nt][r]);
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                    __builtin_amdgcn_wave_barrier();
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                    const int p = lane >> 2, cg = lane & 3;
-                    const int xx = x0 + 16 * wv + p;
-                    if (xx < W) {
-                        v4u v = *reinterpret_cast<const v4u*>(tw + p * TS + cg * 8);
-                        const long long o = (rowp + xx) * NOUT + cg * 8;
-                        if (MODE == kInputGrad) {
-                            // keep the gradient where the layer input (post-ReLU) is positive
-#pragma unroll
-                            for (int q = 0; q < 4; ++q) {
-                                const unsigned lo = mk[h][q] & 0xffffu, hi = mk[h][q] >> 16;
-                                const unsigned keep = (bf2f((bf16)lo) > 0.f ? 0xffffu : 0u) |
-                                                      (bf2f((bf16)hi) > 0.f ? 0xffff0000u : 0u);
-                                v[q] &= keep;
-                            }
-                        }
-                        *reinterpret_cast<v4u*>(y + o) = v;
+                    for (int nt = 0; nt < NT; ++nt) {
+                        uint2 v = pack4(acc[h][nt], MODE == kHidden);
+                        // input gradient: kept where the layer input (post-ReLU) is positive
+                        if (MODE == kInputGrad) v = relu_mask(v, mk[h][nt]);
+                        *reinterpret_cast<uint2*>(y + (rowp + xx) * NOUT + nt * 16 + 4 * grp) = v;
                     }
-                    // the wave reads its transpose tile before it is rewritten
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                    __builtin_amdgcn_wave_barrier();
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                 }
             }
+        };
+        for (int yy = ya; yy < yb; yy += 4) {
+            pass(yy, fa0, fa1);
+            if (yy + 2 >= yb) break;
+            pass(yy + 2, fc0, fc1);
         }
     }
 }
@@ -546,6 +628,144 @@ __global__ void k_adam(int n, float lr, float b1, float b2, float eps, float c1,
     w[i] -= lr * (m / c1) / (sqrtf(v / c2) + eps);
 }
 
+// Layers 2 and 3 in one pass (32 -> 32 -> 32, ReLU after each): layer 3's
+// input, h2 = ReLU(conv(h1, W2)), is computed into an LDS ring of rows and
+// consumed there, so it never goes to HBM unless the caller keeps it (the
+// training forward keeps it for the backward pass).  A block of four waves
+// owns layer 3's outputs on kFSeg = 62 columns [x0, x0+62) of one image over
+// a run of rows; it evaluates h2 on the 64 columns [x0-1, x0+63) (one
+// 16-pixel MFMA tile per wave) from h1 on [x0-2, x0+64), and h2 is set to
+// zero outside the image, which is the zero padding layer 3 sees when h2
+// comes from HBM.  Per pass, h2 rows yy+1 and yy+2 are added to the h2 ring
+// (6 slots) from h1 rows yy .. yy+3 (6-slot ring, the next two fetched into
+// registers during the products), then layer 3's rows yy and yy+1 are
+// produced from h2 rows yy-1 .. yy+2.  Both layers' weight fragments stay in
+// registers.  Every product runs in the order of the single-layer kernel on
+// the same bf16 values, so the outputs are bitwise those of two separate
+// layers.
+constexpr int kFSeg = 62;
+
+template <bool KEEP>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_conv_fused23(int B, int H, int W, int rows, const bf16* __restrict__ x,
+                                                      const bf16* __restrict__ w2, const bf16* __restrict__ w3,
+                                                      bf16* __restrict__ h2out, bf16* __restrict__ y) {
+    constexpr int C = 32, NOUT = 32, NT = NOUT / 16;
+    constexpr int CS = C + 8;             // LDS pixel stride of both rings
+    constexpr int RW = (kCSeg + 2) * CS;  // h1 row: columns x0-2 .. x0+63; h2 row: x0-1 .. x0+62, two zero pixels after
+    __shared__ __align__(16) bf16 xL[kConvSlots * RW];
+    __shared__ __align__(16) bf16 hL[kConvSlots * RW];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int i = lane & 15, grp = lane >> 4;
+    bf8 bw2[9][NT], bw3[9][NT];
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            bw2[t][nt] = ld8(w2 + ((t * NOUT + nt * 16 + i) * C + 8 * grp));
+            bw3[t][nt] = ld8(w3 + ((t * NOUT + nt * 16 + i) * C + 8 * grp));
+        }
+    settle(bw2);
+    settle(bw3);
+    // the two pixels after the 64 h2 columns are read (and discarded) by
+    // layer 3's last two output pixels: keep them zero in every slot
+    for (int e = threadIdx.x; e < kConvSlots * 2 * CS; e += 256) {
+        const int sl = e / (2 * CS), r = e % (2 * CS);
+        hL[sl * RW + kCSeg * CS + r] = (bf16)0;
+    }
+    auto slot = [](int r) { return ((r + 2 * kConvSlots) % kConvSlots) * RW; };  // r >= -2
+    const int segs_x = (W + kFSeg - 1) / kFSeg;
+    const int runs = (H + rows - 1) / rows;
+    const int nwork = B * runs * segs_x;
+    const int px = 16 * wv + i;  // this lane's pixel (B columns) in both layers' 64-pixel tiles
+    const int aofs = px * CS + 8 * grp;
+    for (int wk = blockIdx.x; wk < nwork; wk += gridDim.x) {
+        const int sx = wk % segs_x, t = wk / segs_x;
+        const int run = t % runs, bimg = t / runs;
+        const int x0 = sx * kFSeg, ya = run * rows, yb = min(H, ya + rows);
+        // layer 2 on h2 rows r, r+1 (h1 rows r-1 .. r+2 in the ring): ReLU,
+        // zero outside the image, bf16 into the h2 ring (and, when kept, the
+        // rows and columns this block owns to HBM)
+        auto layer2 = [&](int r) {
+            const int base[4] = {slot(r - 1), slot(r), slot(r + 1), slot(r + 2)};
+            v4f acc[2][NT];
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) acc[h][nt] = v4f{0.f, 0.f, 0.f, 0.f};
+            conv_pass32<CS, NT, 1, true>(xL, base, aofs, bw2, acc);
+            const int xx = x0 - 1 + px;  // h2 pixel px is column x0 - 1 + px
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int yo = r + h;
+                const bool in = yo >= 0 && yo < H && xx >= 0 && xx < W;
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) {
+                    const uint2 v = in ? pack4(acc[h][nt], true) : uint2{0u, 0u};
+                    *reinterpret_cast<uint2*>(hL + slot(yo) + px * CS + nt * 16 + 4 * grp) = v;
+                    if (KEEP && in && yo >= ya && yo < yb && px >= 1 && px <= kFSeg)
+                        *reinterpret_cast<uint2*>(h2out + ((long long)(bimg * H + yo) * W + xx) * C + nt * 16 + 4 * grp) = v;
+                }
+            }
+        };
+        // h1 rows of the next two passes are in flight in registers (two
+        // buffer pairs, alternating between passes)
+        const Rsrc xr = image_view<C>(x, bimg, H, W);
+        RowFetch<C> fa0, fa1, fc0, fc1;
+        __syncthreads();  // the rings' previous contents are no longer read
+        // h1 rows ya-2 .. ya+1 (columns x0-2 .. x0+63) for h2 rows ya-1, ya
+        row_fetch<C>(fa0, xr, H, W, ya - 2, x0 - 1);
+        row_fetch<C>(fa1, xr, H, W, ya - 1, x0 - 1);
+        row_fetch<C>(fc0, xr, H, W, ya, x0 - 1);
+        row_fetch<C>(fc1, xr, H, W, ya + 1, x0 - 1);
+        row_store<C, CS>(fa0, xL + slot(ya - 2));
+        row_store<C, CS>(fa1, xL + slot(ya - 1));
+        row_store<C, CS>(fc0, xL + slot(ya));
+        row_store<C, CS>(fc1, xL + slot(ya + 1));
+        row_fetch<C>(fa0, xr, H, W, ya + 2, x0 - 1);
+        row_fetch<C>(fa1, xr, H, W, ya + 3, x0 - 1);
+        row_fetch<C>(fc0, xr, H, W, ya + 4, x0 - 1, ya + 2 < yb);
+        row_fetch<C>(fc1, xr, H, W, ya + 5, x0 - 1, ya + 2 < yb);
+        __syncthreads();
+        layer2(ya - 1);
+        auto pass = [&](int yy, RowFetch<C>& f0, RowFetch<C>& f1) {
+            // h1 rows yy+2, yy+3 go to the slots of rows yy-4, yy-3
+            row_store<C, CS>(f0, xL + slot(yy + 2));
+            row_store<C, CS>(f1, xL + slot(yy + 3));
+            __syncthreads();
+            // rows of the pass after next (issued in every pass, so that the
+            // waits stay counted; rows past the run read nothing new)
+            row_fetch<C>(f0, xr, H, W, yy + 6, x0 - 1, yy + 4 < yb);
+            row_fetch<C>(f1, xr, H, W, yy + 7, x0 - 1, yy + 4 < yb);
+            layer2(yy + 1);  // h2 rows yy+1, yy+2 into the slots of rows yy-5, yy-4
+            __syncthreads();
+            const int base[4] = {slot(yy - 1), slot(yy), slot(yy + 1), slot(yy + 2)};
+            v4f acc[2][NT];
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) acc[h][nt] = v4f{0.f, 0.f, 0.f, 0.f};
+            conv_pass32<CS, NT, 1, true>(hL, base, aofs, bw3, acc);
+            const int xx = x0 + px;  // output pixel px is column x0 + px
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int yo = yy + h;
+                if (yo >= yb) break;
+                if (px < kFSeg && xx < W) {
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt)
+                        *reinterpret_cast<uint2*>(y + ((long long)(bimg * H + yo) * W + xx) * NOUT + nt * 16 + 4 * grp) =
+                            pack4(acc[h][nt], true);
+                }
+            }
+        };
+        for (int yy = ya; yy < yb; yy += 4) {
+            pass(yy, fa0, fa1);
+            if (yy + 2 >= yb) break;
+            pass(yy + 2, fc0, fc1);
+        }
+    }
+}
+
 // bf16 copies: Wf[tap][co][ci] and Wd[tap][ci][co] (padded with zeros)
 __global__ void k_pack_weights(int cout, int cin, int coutp, int cinp, const float* __restrict__ w,
                                bf16* __restrict__ wf, bf16* __restrict__ wd) {
@@ -586,6 +806,7 @@ struct aafwi_cnn {
     double* st2 = nullptr;
     float* wpart = nullptr;
     double* gsum = nullptr;
+    bool fused = true;  // layers 2 and 3 in one kernel (bitwise the same outputs)
 };
 
 namespace {
@@ -655,7 +876,22 @@ void weight_reduce(aafwi_cnn* c, int nchunk, int coutp, int cinp, int layer) {
                        m, coutp, cinp, kCout[layer], kCin[layer], (const double*)c->gsum, c->grad + layer_offset(layer));
 }
 
-void forward(aafwi_cnn* c, int B, const float* g, const float* m) {
+// Layers 2 and 3 fused (h2 kept in HBM only when the backward pass needs it).
+void conv_fused23(aafwi_cnn* c, int B, bool keep) {
+    const int segs = B * ((c->W + aafwi::kFSeg - 1) / aafwi::kFSeg);
+    int rows = 16;
+    while (rows > 4 && segs * ((c->H + rows - 1) / rows) < 512) rows /= 2;
+    const int nwork = segs * ((c->H + rows - 1) / rows);
+    const int blocks = std::min(nwork, 2048);
+    if (keep)
+        hipLaunchKernelGGL((aafwi::k_conv_fused23<true>), dim3(blocks), dim3(256), 0, c->stream, B, c->H, c->W, rows,
+                           c->act[1], c->wf[1], c->wf[2], c->act[2], c->act[3]);
+    else
+        hipLaunchKernelGGL((aafwi::k_conv_fused23<false>), dim3(blocks), dim3(256), 0, c->stream, B, c->H, c->W, rows,
+                           c->act[1], c->wf[1], c->wf[2], nullptr, c->act[3]);
+}
+
+void forward(aafwi_cnn* c, int B, const float* g, const float* m, bool keep = true) {
     using namespace aafwi;
     const int n = c->H * c->W, P = B * n;
     hipLaunchKernelGGL(k_input_stats, dim3(kRedBlocks, B), dim3(256), 0, c->stream, n, g, m, c->part);
@@ -663,8 +899,12 @@ void forward(aafwi_cnn* c, int B, const float* g, const float* m) {
     hipLaunchKernelGGL(k_pack_input, dim3((P + 255) / 256), dim3(256), 0, c->stream, B, n, g, m,
                        (const double*)c->st_in, c->act[0]);
     conv<16, 32, kHidden>(c, B, c->act[0], c->wf[0], nullptr, c->act[1], nullptr);
-    conv<32, 32, kHidden>(c, B, c->act[1], c->wf[1], nullptr, c->act[2], nullptr);
-    conv<32, 32, kHidden>(c, B, c->act[2], c->wf[2], nullptr, c->act[3], nullptr);
+    if (c->fused) {
+        conv_fused23(c, B, keep);
+    } else {
+        conv<32, 32, kHidden>(c, B, c->act[1], c->wf[1], nullptr, c->act[2], nullptr);
+        conv<32, 32, kHidden>(c, B, c->act[2], c->wf[2], nullptr, c->act[3], nullptr);
+    }
     conv<32, 16, kLast>(c, B, c->act[3], c->wf[3], nullptr, nullptr, c->z);
     AAFWI_HIP(hipGetLastError());
 }
@@ -791,7 +1031,7 @@ extern "C" int aafwi_cnn_forward(aafwi_cnn* c, int32_t B, const float* g, const 
     return guarded([&]() -> int {
         AAFWI_REQUIRE(c && g && m, "cnn_forward: NULL argument");
         check_batch(c, B);
-        forward(c, B, g, m);
+        forward(c, B, g, m, /*keep=*/false);
         const long long N = (long long)B * c->H * c->W;
         if (z) AAFWI_HIP(hipMemcpyAsync(z, c->z, sizeof(float) * N, hipMemcpyDeviceToDevice, c->stream));
         if (d) {
@@ -799,6 +1039,14 @@ extern "C" int aafwi_cnn_forward(aafwi_cnn* c, int32_t B, const float* g, const 
                                (const float*)c->z, g, d);
             AAFWI_HIP(hipGetLastError());
         }
+        return AAFWI_OK;
+    });
+}
+
+extern "C" int aafwi_cnn_set_fused(aafwi_cnn* c, int32_t on) {
+    return guarded([&]() -> int {
+        AAFWI_REQUIRE(c, "cnn_set_fused: NULL handle");
+        c->fused = on != 0;
         return AAFWI_OK;
     });
 }

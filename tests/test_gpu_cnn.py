@@ -1,7 +1,8 @@
 """Learned-direction network on the matrix cores against the FP64 oracle:
 inference, loss and weight gradients (bf16 activations and weights, FP32
 accumulation; relative L2 within 2e-2), the Adam update, the fixed point
-d(0, m) = 0, sampled windows of a full-size image, and argument errors."""
+d(0, m) = 0, sampled windows of a full-size image, the fused second and third
+layers against separate ones (bitwise), and argument errors."""
 import ctypes
 
 import numpy as np
@@ -150,6 +151,29 @@ def test_full_size_sampled_windows():
                     h = np.maximum(h, 0.0)
             z_ref = h[0, y0 - ya:y1 - ya, x0 - xa:x1 - xa]
             assert rel(z[b, y0:y1, x0:x1], z_ref) <= TOL, (b, y0, x0)
+
+
+@pytest.mark.parametrize("B,H,W", [(3, 37, 131), (2, 384, 1024)])
+def test_fused_layers_bitwise(B, H, W):
+    """Layers 2 and 3 in one kernel give bitwise the outputs of two separate
+    kernels: the inference output z, and the weight gradient, which reads the
+    second layer's activation that the fused training forward writes out.
+    131 columns are two 62-column fused segments and a 7-column tail."""
+    from paper_2008_11778_amd import CNN
+    ws = weights(9)
+    g, m, s = images(B, H, W, 13)
+    out = {}
+    with CNN(H, W, B, ws) as net:
+        gd, md, sd = to_dev(g), to_dev(m), to_dev(s)
+        for fused in (True, False):
+            net.set_fused(fused)
+            z, _ = net.forward(gd, md, d=False)
+            grad, loss = net.gradients(gd, md, sd)
+            out[fused] = (z.cpu().numpy(), grad.cpu().numpy(), float(loss.item()))
+    assert np.std(out[True][0]) > 0.1
+    assert np.array_equal(out[True][0], out[False][0])
+    assert np.array_equal(out[True][1], out[False][1])
+    assert out[True][2] == out[False][2]
 
 
 def test_argument_errors(case):
