@@ -677,30 +677,59 @@ def learned_workload(args):
     import synth
     from paper_2008_11778_amd import CNN, Context
     from paper_2008_11778_amd.inversion import AADescent, FWIProblem
-    from paper_2008_11778_amd.learned import (LearnedAADescent, aa_pairs, flip_x, init_weights, lbfgs_pairs, merge,
-                                              train)
+    from paper_2008_11778_amd.learned import (LearnedAADescent, aa_pairs, drop_degenerate, flip_x, init_weights,
+                                              lbfgs_pairs, merge, train)
 
     dev = torch.device("cuda", 0)
     t_all = time.perf_counter()
     size = dict(nz=args.train_nz, nx=args.train_nx, nshots=args.train_shots, nt=args.train_nt)
-    train_cases = [synth.learned_instance(i, **size) for i in range(args.train_instances)]
-    t0 = time.perf_counter()
-    pa = aa_pairs(train_cases, M=10, iters=args.train_iters)
-    log(f"AA pairs: {len(pa)} in {time.perf_counter() - t0:.1f}s")
-    t0 = time.perf_counter()
-    pl = lbfgs_pairs(train_cases[: args.lbfgs_instances], M=10, iters=args.lbfgs_iters)
-    log(f"L-BFGS pairs: {len(pl)} in {time.perf_counter() - t0:.1f}s")
-    pairs = merge(pa, pl)
-    if args.flip:
-        pairs = merge(pairs, flip_x(pairs))
-    t_data = time.perf_counter() - t_all
-    nz, nx = train_cases[0][2].shape
-    net = CNN(nz, nx, 8, init_weights(5005))
-    t0 = time.perf_counter()
-    hist = train(net, pairs, epochs=args.epochs, batch=8, lr=1e-3)
-    torch.cuda.synchronize()
-    t_train = time.perf_counter() - t0
-    log(f"training: {t_train:.1f}s, epoch losses {[round(x, 4) for x in hist]}")
+    training = {}
+    if args.load_weights:
+        # a network trained by an earlier run of this workload (--save-weights)
+        net = CNN(args.train_nz, args.train_nx, 8, np.load(args.load_weights).astype(np.float32))
+        training = {"loaded": args.load_weights}
+        log(f"weights loaded from {args.load_weights}")
+    else:
+        train_cases = [synth.learned_instance(i, **size) for i in range(args.train_instances)]
+        t0 = time.perf_counter()
+        # plain-AA pairs in batches of at most --aa-batch instances (HBM: about
+        # 1 GB per 384 x 128, 24-shot, 2000-step instance)
+        chunks = []
+        for i in range(0, len(train_cases), args.aa_batch):
+            chunks.append(aa_pairs(train_cases[i:i + args.aa_batch], M=10, iters=args.train_iters))
+            log(f"AA pairs of models {i} .. {i + len(train_cases[i:i + args.aa_batch]) - 1}: "
+                f"{time.perf_counter() - t0:.1f}s")
+        pa = merge(*chunks)
+        del chunks
+        log(f"AA pairs: {len(pa)} in {time.perf_counter() - t0:.1f}s")
+        t0 = time.perf_counter()
+        pl = lbfgs_pairs(train_cases[: args.lbfgs_instances], M=10, iters=args.lbfgs_iters,
+                         progress=lambda i: (i + 1) % 10 == 0 and log(
+                             f"L-BFGS runs: {i + 1} of {args.lbfgs_instances}, {time.perf_counter() - t0:.1f}s"))
+        log(f"L-BFGS pairs: {len(pl)} in {time.perf_counter() - t0:.1f}s")
+        pairs, dropped = drop_degenerate(merge(pa, pl))
+        log(f"pairs kept: {len(pairs)} ({dropped} with a zero step or gradient, or non-finite, dropped)")
+        if args.flip:
+            pairs = merge(pairs, flip_x(pairs))
+        t_data = time.perf_counter() - t_all
+        nz, nx = train_cases[0][2].shape
+        net = CNN(nz, nx, 8, init_weights(5005))
+        t0 = time.perf_counter()
+        hist = train(net, pairs, epochs=args.epochs, batch=8, lr=1e-3)
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t0
+        log(f"training: {t_train:.1f}s, epoch losses {[round(x, 4) for x in hist]}")
+        training = {"pairs": len(pairs), "aa_pairs": len(pa), "lbfgs_pairs": len(pl), "dropped": dropped,
+                    "epochs": args.epochs,
+                    "models": args.train_instances, "aa_iters": args.train_iters,
+                    "lbfgs_models": args.lbfgs_instances, "lbfgs_iters": args.lbfgs_iters,
+                    "grid": f"{args.train_nx}x{args.train_nz}, {args.train_shots} shots, {args.train_nt} steps",
+                    "data_s": round(t_data, 1), "train_s": round(t_train, 1),
+                    "epoch_loss": [round(x, 4) for x in hist]}
+        del pairs, pa, pl
+        if args.save_weights:
+            np.save(args.save_weights, net.get_weights())
+            log(f"weights saved to {args.save_weights}")
 
     def compare(instance, geom, mt, m0, net_j, tune=False):
         """Plain AA and learned AA (M = 10) from m0 for args.iters iterations."""
@@ -754,14 +783,15 @@ def learned_workload(args):
             g, mt, m0 = synth.learned_instance(700 + j, nz=384, nx=1024, nshots=96, nt=4000)
             large.append(compare(700 + j, g, mt, m0, net_l, tune=True))
         net_l.close()
-    ratio = [r["learned_final"] / r["plain_final"] for r in rows]
+    ratio = [r["learned_final"] / r["plain_final"] for r in rows] or [float("nan")]
     reached = [r for r in rows if r["learned_s_to_plain_final"] is not None]
     speed = cnn_timing(CNN(384, 1024, 8, init_weights(5005)), 8, 384, 1024)
     flops = 2.0 * 8 * 384 * 1024 * 19296
     out = {"metric": "final misfit after k AA iterations, learned G_theta vs plain G (held-out instances)",
            "value": round(float(np.exp(np.mean(np.log(ratio)))), 4), "unit": "geomean J_learned / J_plain",
            "higher_is_better": False, "n_gpus": 1, "iters": args.iters, "instances": rows,
-           "fallback_rate": round(sum(r["learned_fallbacks"] for r in rows) / (args.iters * len(rows)), 3),
+           "fallback_rate": (round(sum(r["learned_fallbacks"] for r in rows) / (args.iters * len(rows)), 3)
+                             if rows else None),
            "reached_plain_final": sum(r["learned_s_to_plain_final"] is not None for r in rows),
            "full_size": {"workload": "1024x384 grid, 96 shots, 4000 steps, receivers every 2nd column",
                          "instances": large,
@@ -770,9 +800,7 @@ def learned_workload(args):
            "time_to_plain_final_speedup": (round(sum(r["plain_s"] for r in reached)
                                                  / sum(r["learned_s_to_plain_final"] for r in reached), 3)
                                            if reached else None),
-           "training": {"pairs": len(pairs), "aa_pairs": len(pa), "lbfgs_pairs": len(pl), "epochs": args.epochs,
-                        "data_s": round(t_data, 1), "train_s": round(t_train, 1),
-                        "epoch_loss": [round(x, 4) for x in hist]},
+           "training": training,
            "cnn_8x384x1024": {"forward_ms": round(speed["forward"], 3), "train_step_ms": round(speed["train_step"], 3),
                               "forward_tflops": round(flops / speed["forward"] / 1e9, 1),
                               "train_tflops": round(3 * flops / speed["train_step"] / 1e9, 1),
@@ -854,17 +882,21 @@ def main():
     ap.add_argument("--iters", type=int, default=10, help="batched workload: AA iterations per instance")
     ap.add_argument("--ckpt", type=int, default=70, help="batched workload: checkpoint interval")
     ap.add_argument("--train-instances", type=int, default=200, help="learned workload: training models")
-    ap.add_argument("--train-iters", type=int, default=8, help="learned workload: AA iterations per training model")
-    ap.add_argument("--lbfgs-instances", type=int, default=8, help="learned workload: L-BFGS training runs")
-    ap.add_argument("--lbfgs-iters", type=int, default=6, help="learned workload: iterations per L-BFGS run")
+    ap.add_argument("--train-iters", type=int, default=10, help="learned workload: AA iterations per training model")
+    ap.add_argument("--lbfgs-instances", type=int, default=200, help="learned workload: L-BFGS training runs")
+    ap.add_argument("--lbfgs-iters", type=int, default=10, help="learned workload: iterations per L-BFGS run")
     ap.add_argument("--train-nz", type=int, default=128, help="learned workload: training grid rows")
-    ap.add_argument("--train-nx", type=int, default=320, help="learned workload: training grid columns")
-    ap.add_argument("--train-shots", type=int, default=16, help="learned workload: shots per training model")
+    ap.add_argument("--train-nx", type=int, default=384, help="learned workload: training grid columns")
+    ap.add_argument("--train-shots", type=int, default=24, help="learned workload: shots per training model")
+    ap.add_argument("--aa-batch", type=int, default=100, help="learned workload: instances per AA-pair batch")
+    ap.add_argument("--save-weights", default="", help="learned workload: write the trained weights (.npy)")
+    ap.add_argument("--load-weights", default="",
+                    help="learned workload: skip data and training, take the weights from a .npy file")
     ap.add_argument("--train-nt", type=int, default=2000, help="learned workload: training record length")
     ap.add_argument("--flip", action="store_true", help="learned workload: add the x-mirrored pairs")
     ap.add_argument("--test-instances", type=int, default=16, help="learned workload: held-out models")
     ap.add_argument("--epochs", type=int, default=20, help="learned workload: training epochs")
-    ap.add_argument("--large-test", type=int, default=2,
+    ap.add_argument("--large-test", type=int, default=4,
                     help="learned workload: held-out 1024x384, 96-shot, 4000-step models")
     args = ap.parse_args()
     if args.gpus != 1:

@@ -203,12 +203,13 @@ def aa_pairs(cases, M: int = 10, iters: int = 8, ckpt_every: int = 50):
     return Pairs(st(gs), st(ms), st(ss), ["aa"] * len(gs))
 
 
-def lbfgs_pairs(cases, M: int = 10, iters: int = 6, ckpt_every: int = 50):
-    """Pairs from L-BFGS(M) runs (one context per instance)."""
+def lbfgs_pairs(cases, M: int = 10, iters: int = 6, ckpt_every: int = 50, progress=None):
+    """Pairs from L-BFGS(M) runs (one context per instance); progress(i), if
+    given, is called after instance i."""
     from .comparators import LBFGS
     gs, ms, ss = [], [], []
     shape = cases[0][2].shape
-    for geom, mt, m0 in cases:
+    for ci, (geom, mt, m0) in enumerate(cases):
         with Context(geom, ckpt_every=ckpt_every) as ctx:
             d_obs = ctx.forward_model(torch.from_numpy(np.ascontiguousarray(mt)).cuda()).clone()
             prob = FWIProblem(ctx, d_obs)
@@ -219,7 +220,30 @@ def lbfgs_pairs(cases, M: int = 10, iters: int = 6, ckpt_every: int = 50):
                 gs.append(gk.view(shape))
                 ms.append(pk.view(shape))
                 ss.append((run.p - pk).view(shape))
+        if progress:
+            progress(ci)
     return Pairs(torch.stack(gs), torch.stack(ms), torch.stack(ss), ["lbfgs"] * len(gs))
+
+
+def drop_degenerate(p: Pairs):
+    """The pairs that carry a direction: a step of zero (a line search that
+    did not move) or a zero gradient makes the scale-free target or input
+    0/0, and a non-finite entry poisons every later Adam step; those pairs
+    are removed.  Squared norms come from the library's FP64 dot product.
+    Returns (pairs kept, number dropped)."""
+    red = Reducer()
+    n = len(p)
+    sq = torch.empty(3, n, dtype=torch.float64, device=p.g.device)
+    for i in range(n):
+        for k, x in enumerate((p.g[i], p.m[i], p.s[i])):
+            red.dot(x, x, sq[k, i:i + 1])
+    sq = sq.cpu().numpy()
+    keep = np.flatnonzero(np.isfinite(sq).all(axis=0) & (sq[0] > 0) & (sq[2] > 0))
+    if len(keep) == n:
+        return p, 0
+    idx = torch.from_numpy(keep).to(p.g.device)
+    return Pairs(p.g.index_select(0, idx), p.m.index_select(0, idx), p.s.index_select(0, idx),
+                 [p.source[i] for i in keep]), n - len(keep)
 
 
 def merge(*ps: Pairs) -> Pairs:

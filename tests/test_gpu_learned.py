@@ -161,6 +161,26 @@ def learned_case():
     return g, m, d_obs, wb, eta, eta_t, ref, plain
 
 
+def test_drop_degenerate_pairs():
+    """Pairs with a zero step, a zero gradient or a non-finite entry are
+    removed before training (their scale-free loss is 0/0 or NaN); the rest
+    are kept in order."""
+    import torch
+    from paper_2008_11778_amd.learned import Pairs, drop_degenerate
+    r = np.random.default_rng(3)
+    g, m, s = (torch.from_numpy(r.standard_normal((6, 5, 7)).astype(np.float32)).cuda() for _ in range(3))
+    s[1] = 0.0            # line search that did not move
+    g[2] = 0.0            # fixed point
+    m[3, 2, 4] = float("nan")
+    s[4, 0, 0] = float("inf")
+    p = Pairs(g, m, s, [f"p{i}" for i in range(6)])
+    kept, dropped = drop_degenerate(p)
+    assert dropped == 4 and kept.source == ["p0", "p5"]
+    assert torch.equal(kept.g[1], g[5]) and torch.equal(kept.s[0], s[0])
+    same, none = drop_degenerate(kept)
+    assert none == 0 and same is kept
+
+
 def test_learned_aa_matches_oracle_with_trained_weights(learned_case):
     """Algorithm 2 on G_theta through the HIP path (network on the matrix
     cores, AA steps, line search) against the oracle's learned_alg2 with the
