@@ -809,6 +809,48 @@ def learned_workload(args):
     print(json.dumps(out), flush=True)
 
 
+def stream_probe_rates(gib=4, bpcs=(4, 8, 16), reps=10):
+    """Rates (TB/s) of the library's plain stream kernels (read, write, copy,
+    two reads and one write) over buffers of `gib` GiB, HIP-event timed, for
+    each workgroup count per compute unit; returns (rates, best per kind)."""
+    import torch
+
+    from paper_2008_11778_amd._lib import stream_probe
+    dev = torch.device("cuda", 0)
+    n = (gib << 30) // 4
+    a = torch.ones(n, device=dev)
+    b = torch.zeros(n, device=dev)
+    c = torch.ones(n, device=dev)
+    st = torch.cuda.current_stream()
+    rates = {}
+    for bpc in bpcs:
+        for kind, name, moved in ((0, "read", 1), (1, "write", 1), (2, "copy", 2), (3, "mix_2r1w", 3)):
+            run = lambda: stream_probe(kind, a if kind != 1 else None, b, c if kind == 3 else None, bpc, st)
+            run()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            for _ in range(reps):
+                run()
+            e1.record(st)
+            e1.synchronize()
+            rates[f"{name}/{bpc}"] = round(moved * 4 * n * reps / (e0.elapsed_time(e1) * 1e-3) / 1e12, 3)
+    del a, b, c
+    best = {k: max(v for kk, v in rates.items() if kk.startswith(k + "/")) for k in ("read", "write", "copy", "mix_2r1w")}
+    return rates, best
+
+
+def stream_workload(args):
+    """HBM stream probe: the library's plain read, write, copy and
+    two-read/one-write kernels over 4 GiB buffers at 4, 8 and 16 workgroups
+    per compute unit, HIP-event timed (10 launches each), against which the
+    stepping kernels' own rates can be read."""
+    rates, best = stream_probe_rates()
+    print(json.dumps({"metric": "HBM stream probe", "unit": "TB/s", "best": best, "rates": rates,
+                      "config": {"workload": "4 GiB buffers, 256-thread workgroups, 4/8/16 per CU"},
+                      "peak_published": HBM_PEAK_GBS / 1000.0}), flush=True)
+
+
 def tune_workload(args):
     """Launch shapes of the FWI-gradient (768 x 256, 64 shots) and large-grid
     (1024 x 384, 96 shots) workloads timed in place (autotune.tune_in_place:
@@ -875,7 +917,7 @@ def main():
     ap.add_argument("--no-full-storage-run", action="store_true",
                     help="skip the second timed run with full storage")
     ap.add_argument("--workload", default="fwi",
-                    choices=["fwi", "batched", "learned", "cnn", "noisy", "lsrtm", "target", "tune"])
+                    choices=["fwi", "batched", "learned", "cnn", "noisy", "lsrtm", "target", "tune", "stream"])
     ap.add_argument("--target-iters", type=int, default=30, help="target workload: plain AA iterations")
     ap.add_argument("--budget", type=float, default=20, help="noisy workload: gradient evaluations per optimiser")
     ap.add_argument("--instances", type=int, default=32, help="batched workload: number of instances")
@@ -917,6 +959,8 @@ def main():
         return target_workload(args)
     if args.workload == "tune":
         return tune_workload(args)
+    if args.workload == "stream":
+        return stream_workload(args)
     # the oracle runs first, in child processes started before this process
     # touches the GPU
     cpu = None
@@ -1061,6 +1105,13 @@ def main():
                                frac=round(achieved5 / HBM_PEAK_GBS, 4), traffic=k5["traffic"],
                                mean_launch_us=k5["mean_us"], timed_launches=cnt5, bytes_per_launch=bytes5,
                                steps_per_launch=sp5, rows_per_wave=k5["rows_per_wave"])
+        # what plain streams with a similar read/write mix reach on this
+        # device (the better of copy and two-reads-one-write), beside the
+        # dominant kernel's algorithmic rate
+        _, best = stream_probe_rates(gib=1, bpcs=(4, 8), reps=10)
+        out["hbm_stream_probe_tbs"] = best
+        out["roofline"]["frac_of_stream_probe"] = round(achieved5 / 1e3 / max(best["copy"], best["mix_2r1w"]), 4)
+        log(f"stream probe: {best}")
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)

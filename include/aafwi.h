@@ -393,6 +393,18 @@ int aafwi_cnn_train_step(aafwi_cnn* c, int32_t B, const float* g, const float* m
 
 /* ---- instrumentation ------------------------------------------------------- */
 
+/* HBM stream probe: one launch of a plain streaming kernel over device
+ * buffers of `bytes` bytes each (a positive multiple of 16), 256-thread
+ * workgroups, blocks_per_cu (1..64) per compute unit of 256.  kind 0 reads a
+ * (b receives nothing for finite data but must be a device buffer of 16
+ * bytes or more), 1 writes b, 2 copies a to b, 3 writes b = a + 2 c (two
+ * reads, one write: the read/write ratio of the two-step adjoint).  Not part
+ * of the method: it sets the rates of simple streams beside those of the
+ * stepping kernels.  Enqueued on stream, no synchronisation; the caller
+ * times it.  Buffers belong to the caller. */
+int aafwi_stream_probe(aafwi_stream stream, int32_t kind, int64_t bytes, int32_t blocks_per_cu, const void* a,
+                       void* b, const void* c);
+
 /* Kernel ids for aafwi_kernel_timing. */
 #define AAFWI_K_FWD_STEP   0 /* forward time step (with injection and sampling)   */
 #define AAFWI_K_REC_STEP   1 /* recompute step that stores q for imaging          */

@@ -622,6 +622,21 @@ def axpy(a, x, y, stream=None):
     return y
 
 
+_sig("aafwi_stream_probe", _vp, _i32, _i64, _i32, _vp, _vp, _vp)
+
+
+def stream_probe(kind, a, b, c=None, blocks_per_cu=4, stream=None):
+    """One launch of the HBM stream probe over equal-size device buffers:
+    kind 0 read a, 1 write b, 2 copy a -> b, 3 b = a + 2c."""
+    nbytes = b.numel() * b.element_size()
+    for name, t in (("a", a), ("c", c)):
+        if t is not None and t.numel() * t.element_size() != nbytes:
+            raise ValueError(f"{name} must have the size of b")
+    _check(_lib.aafwi_stream_probe(_stream_handle(stream), int(kind), nbytes, int(blocks_per_cu),
+                                   None if a is None else a.data_ptr(), b.data_ptr(),
+                                   None if c is None else c.data_ptr()))
+
+
 _sig("aafwi_cnn_create", _i32, _i32, _i32, _vp, _vp, ctypes.POINTER(_vp))
 _sig("aafwi_cnn_destroy", _vp)
 _sig("aafwi_cnn_set_weights", _vp, _vp)

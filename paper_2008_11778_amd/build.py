@@ -8,7 +8,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["wave_kernels.hip", "aa_kernels.hip", "cnn_kernels.hip", "abi.hip"]
+SOURCES = ["wave_kernels.hip", "aa_kernels.hip", "cnn_kernels.hip", "probe.hip", "abi.hip"]
 LIB = os.path.join(HERE, "libaafwi.so")
 
 FLAGS = [

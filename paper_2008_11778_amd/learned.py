@@ -25,7 +25,7 @@ import time
 import numpy as np
 import torch
 
-from ._lib import AA, CNN, Batch, Context, Reducer, blend
+from ._lib import AA, CNN, Batch, Context, Reducer, axpy, blend
 from .inversion import ARMIJO_C1, LAMBDAS, FWIProblem, IterLog, step_size
 
 
@@ -195,7 +195,7 @@ def aa_pairs(cases, M: int = 10, iters: int = 8, ckpt_every: int = 50):
                 for i in range(b.N):
                     gs.append(b.grad[i].clone())
                     ms.append(pk[i])
-                    ss.append(run.p[i] - pk[i])
+                    ss.append(axpy(-1.0, pk[i], run.p[i].clone()))  # p_{k+1} - p_k
         run.close()
         b.stream.synchronize()
     shape = cases[0][2].shape
@@ -219,7 +219,7 @@ def lbfgs_pairs(cases, M: int = 10, iters: int = 6, ckpt_every: int = 50, progre
                 run.iterate()
                 gs.append(gk.view(shape))
                 ms.append(pk.view(shape))
-                ss.append((run.p - pk).view(shape))
+                ss.append(axpy(-1.0, pk, run.p.clone()).view(shape))  # p_{k+1} - p_k
         if progress:
             progress(ci)
     return Pairs(torch.stack(gs), torch.stack(ms), torch.stack(ss), ["lbfgs"] * len(gs))
