@@ -361,7 +361,7 @@ int aafwi_batch_kernel_timing_read(aafwi_batch* b, int kernel_id, double* mean_m
 typedef struct aafwi_cnn aafwi_cnn;
 
 /* weights: host, AAFWI_CNN_PARAMS floats (copied).  max_batch * nz * nx must
- * stay below 2^31. */
+ * stay below 2^31 and nz * nx below 2^25 (AAFWI_E_INVALID otherwise). */
 int aafwi_cnn_create(int32_t nz, int32_t nx, int32_t max_batch, const float* weights, aafwi_stream stream,
                      aafwi_cnn** out);
 int aafwi_cnn_destroy(aafwi_cnn* c);

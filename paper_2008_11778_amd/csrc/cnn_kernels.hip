@@ -954,6 +954,8 @@ extern "C" int aafwi_cnn_create(int32_t nz, int32_t nx, int32_t max_batch, const
         AAFWI_REQUIRE(out && weights, "cnn_create: NULL argument");
         AAFWI_REQUIRE(nz >= 1 && nx >= 1 && max_batch >= 1, "cnn_create: bad size");
         AAFWI_REQUIRE((long long)nz * nx * max_batch < (1LL << 31), "cnn_create: too many pixels");
+        // one image's 32-channel bf16 activations are addressed with 32-bit byte offsets
+        AAFWI_REQUIRE((long long)nz * nx * 64 < (1LL << 31), "cnn_create: an image of more than 2^25 pixels");
         *out = nullptr;
         aafwi_cnn* c = new aafwi_cnn{};
         try {

@@ -191,3 +191,8 @@ def test_argument_errors(case):
         assert _lib.aafwi_cnn_forward(net._h, 3, gd.data_ptr(), md.data_ptr(), None, out.data_ptr()) == -1
         assert _lib.aafwi_cnn_train_step(net._h, 1, gd.data_ptr(), md.data_ptr(), gd.data_ptr(),
                                          ctypes.c_float(-1.0), None) == -1
+    # one image above 2^25 pixels (its activations need 64-bit byte offsets) is refused before allocating
+    from paper_2008_11778_amd._lib import cnn_flatten
+    w = cnn_flatten(ws)
+    h = ctypes.c_void_p()
+    assert _lib.aafwi_cnn_create(8192, 4097, 1, w.ctypes.data, None, ctypes.byref(h)) == -1 and not h.value
