@@ -151,6 +151,21 @@ class BatchedAADescent:
         self.p = new_p
         return J, lam, J_next
 
+    def current_misfits(self):
+        """J at the current iterates of all instances: a (masked) forward run
+        for those whose last step was a fallback to pbar, whose misfit the
+        line search did not compute; the others keep their accepted trial's."""
+        s = self.b.stream
+        need = [not ok for ok in self.kept_ok]
+        if any(need):
+            for i in range(self.N):
+                if need[i]:
+                    blend(1.0, self.p[i], self.p[i], self._m(i), stream=s)
+            self._forward(need)
+            self.kept_ok = [True] * self.N
+        self.b.set_active(np.ones(self.N, np.uint8))
+        return self.b.misfits()
+
     def close(self):
         if self.aa is not None:
             self.aa.close()
