@@ -785,6 +785,15 @@ def learned_workload(args):
             g, mt, m0 = synth.learned_instance(700 + j, nz=384, nx=1024, nshots=96, nt=4000)
             large.append(compare(700 + j, g, mt, m0, net_l, tune=True))
         net_l.close()
+    c5 = []
+    if args.c5_target:
+        # time to plain AA's J_K / J_0 on held-out full-size models (instances 700, ...)
+        net_l = CNN(384, 1024, 1, net.get_weights())
+        train_cost = (training.get("data_s", 0.0) + training.get("train_s", 0.0)) or args.train_cost_s
+        for j in range(args.c5_models):
+            g, mt, m0 = synth.learned_instance(700 + j, nz=384, nx=1024, nshots=96, nt=4000)
+            c5.append(c5_time_to_target(700 + j, g, mt, m0, net_l, args.c5_target, train_cost, dev))
+        net_l.close()
     ratio = [r["learned_final"] / r["plain_final"] for r in rows] or [float("nan")]
     reached = [r for r in rows if r["learned_s_to_plain_final"] is not None]
     speed = cnn_timing(CNN(384, 1024, 8, init_weights(5005)), 8, 384, 1024)
@@ -803,6 +812,7 @@ def learned_workload(args):
                                                  / sum(r["learned_s_to_plain_final"] for r in reached), 3)
                                            if reached else None),
            "training": training,
+           "c5_time_to_target": c5,
            "cnn_8x384x1024": {"forward_ms": round(speed["forward"], 3), "train_step_ms": round(speed["train_step"], 3),
                               "forward_tflops": round(flops / speed["forward"] / 1e9, 1),
                               "train_tflops": round(3 * flops / speed["train_step"] / 1e9, 1),
@@ -851,6 +861,64 @@ def stream_workload(args):
     print(json.dumps({"metric": "HBM stream probe", "unit": "TB/s", "best": best, "rates": rates,
                       "config": {"workload": "4 GiB buffers, 256-thread workgroups, 4/8/16 per CU"},
                       "peak_published": HBM_PEAK_GBS / 1000.0}), flush=True)
+
+
+def c5_time_to_target(instance, geom, mt, m0, net, K, train_cost_s, dev):
+    """On one held-out full-size model: plain AA (M = 10) for K iterations
+    sets the target J_K / J_0; learned AA (M = 10, plain-AA fallback) runs
+    until it reaches the target or K iterations.  Reports wall times and
+    gradient counts to the target, the fallback rate, the learned step's
+    relative departure from the plain descent step, and the number of runs
+    after which training pays for itself (training cost / time saved)."""
+    import numpy as np
+    import torch
+
+    from paper_2008_11778_amd import Context, autotune
+    from paper_2008_11778_amd.inversion import AADescent, FWIProblem
+    from paper_2008_11778_amd.learned import LearnedAADescent
+    with Context(geom) as ctx:
+        m0t = torch.from_numpy(m0).to(dev)
+        autotune.apply(ctx, autotune.tune(geom, m0t))
+        d_obs = ctx.forward_model(torch.from_numpy(mt).to(dev)).clone()
+        hist = {}
+        for kind in ("plain", "learned"):
+            prob = FWIProblem(ctx, d_obs)
+            run = (AADescent(prob, m0t.reshape(-1), None, M=10) if kind == "plain"
+                   else LearnedAADescent(prob, m0t, net, M=10, track_step_error=True))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rec = run.first()
+            J0 = rec.J
+            h = [dict(k=0, J=rec.J, t=0.0, grads=prob.n_adj, fwd=prob.n_fwd)]
+            target = hist["plain"][-1]["J"] / hist["plain"][0]["J"] if kind == "learned" else None
+            for _ in range(K):
+                rec = run.iterate()
+                torch.cuda.synchronize()
+                h.append(dict(k=rec.k, J=rec.J, t=time.perf_counter() - t0, grads=prob.n_adj, fwd=prob.n_fwd,
+                              fallback=bool(getattr(rec, "fallback", False)),
+                              step_err=getattr(rec, "step_rel_err", None)))
+                if target is not None and rec.J / J0 <= target * (1 + 1e-6):
+                    break
+            run.close()
+            hist[kind] = h
+            log(f"c5 {instance} {kind}: J_{h[-1]['k']}/J_0 = {h[-1]['J'] / J0:.4f} after {h[-1]['t']:.1f} s, "
+                f"{h[-1]['grads']} gradients")
+    plain, learned = hist["plain"], hist["learned"]
+    target = plain[-1]["J"] / plain[0]["J"]
+    hit = learned[-1] if learned[-1]["J"] / learned[0]["J"] <= target * (1 + 1e-6) else None
+    errs = [x["step_err"] for x in learned[1:] if x.get("step_err") is not None]
+    saved = plain[-1]["t"] - hit["t"] if hit else None
+    return {"instance": instance, "target_ratio": round(target, 6), "K": K,
+            "plain": {"time_s": round(plain[-1]["t"], 2), "gradients": plain[-1]["grads"],
+                      "forward_runs": plain[-1]["fwd"]},
+            "learned": {"time_s": round(hit["t"], 2) if hit else None, "iterations": hit["k"] if hit else None,
+                        "gradients": hit["grads"] if hit else None, "forward_runs": hit["fwd"] if hit else None,
+                        "final_ratio": round(learned[-1]["J"] / learned[0]["J"], 6),
+                        "fallback_rate": round(sum(x.get("fallback", False) for x in learned[1:])
+                                               / max(1, len(learned) - 1), 3),
+                        "step_rel_err_median": round(float(np.median(errs)), 4) if errs else None},
+            "training_cost_s": round(train_cost_s, 1) if train_cost_s else None,
+            "break_even_runs": (round(train_cost_s / saved, 1) if (saved and saved > 0 and train_cost_s) else None)}
 
 
 def tune_workload(args):
@@ -934,6 +1002,11 @@ def main():
     ap.add_argument("--train-shots", type=int, default=24, help="learned workload: shots per training model")
     ap.add_argument("--aa-batch", type=int, default=100, help="learned workload: instances per AA-pair batch")
     ap.add_argument("--save-weights", default="", help="learned workload: write the trained weights (.npy)")
+    ap.add_argument("--c5-target", type=int, default=0,
+                    help="learned workload: time to plain AA's J_K/J_0 (K = this) on full-size held-out models")
+    ap.add_argument("--c5-models", type=int, default=1, help="learned workload: models for --c5-target")
+    ap.add_argument("--train-cost-s", type=float, default=0.0,
+                    help="learned workload: training cost (s) for the break-even count when weights are loaded")
     ap.add_argument("--load-weights", default="",
                     help="learned workload: skip data and training, take the weights from a .npy file")
     ap.add_argument("--train-nt", type=int, default=2000, help="learned workload: training record length")

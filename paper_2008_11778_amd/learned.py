@@ -32,6 +32,9 @@ from .inversion import ARMIJO_C1, LAMBDAS, FWIProblem, IterLog, step_size
 @dataclasses.dataclass
 class LearnedLog(IterLog):
     fallback: bool = False
+    # |eta_theta d_theta - eta g| / |eta g| at p_k: how far the learned map's
+    # step departs from the plain descent step (None unless tracked)
+    step_rel_err: float | None = None
 
 
 class LearnedAADescent:
@@ -39,9 +42,10 @@ class LearnedAADescent:
 
     def __init__(self, problem, p0: torch.Tensor, net: CNN, M: int = 10, eta: float | None = None,
                  eta_theta: float | None = None, cond_max: float = 1e5, lambdas=LAMBDAS, c1: float = ARMIJO_C1,
-                 eta_frac: float = 0.02, restart: bool = True):
+                 eta_frac: float = 0.02, restart: bool = True, track_step_error: bool = False):
         self.problem, self.net, self.M = problem, net, M
         self.restart = restart
+        self.track_step_error = track_step_error
         # which window's search fell back to its plain step in the last
         # iteration; the window restarts if that step decreased J
         self.fb_theta = self.fb_plain = False
@@ -89,9 +93,20 @@ class LearnedAADescent:
                 return lam, trial
         return 0.0, None
 
-    def _log(self, J, lam, fallback):
+    def _step_error(self):
+        """|eta_theta d - eta g| / |eta g| from three FP64 dot products."""
+        if not self.track_step_error:
+            return None
+        dd = float(self.red.dot(self.d, self.d).item())
+        dg = float(self.red.dot(self.d, self.g).item())
+        gg = float(self.red.dot(self.g, self.g).item())
+        a, b = self.eta_theta, self.eta
+        num = max(a * a * dd - 2.0 * a * b * dg + b * b * gg, 0.0)
+        return float(np.sqrt(num) / (b * np.sqrt(gg))) if gg > 0 else None
+
+    def _log(self, J, lam, fallback, err=None):
         return LearnedLog(self.k, J, lam, int(self.aa_theta.mk.item()), self.problem.n_adj, self.problem.n_fwd,
-                          time.perf_counter() - self.t0, fallback)
+                          time.perf_counter() - self.t0, fallback, err)
 
     def first(self) -> LearnedLog:
         J = self.problem.gradient(self.p, self.g)
@@ -116,6 +131,7 @@ class LearnedAADescent:
                 self.aa_plain.reset()
         self.J_prev = J
         self._direction()
+        err = self._step_error()
         self._maps()
         lam, p_next = self._search(self.ptilde, J)
         fallback = False
@@ -134,7 +150,7 @@ class LearnedAADescent:
                     p_next = self.pbar_plain
                     self.pbar_plain = torch.empty_like(self.p)
         self.p = p_next
-        return self._log(J, lam, fallback)
+        return self._log(J, lam, fallback, err)
 
     def close(self):
         for a in (self.aa_theta, self.aa_plain):

@@ -109,6 +109,7 @@ def test_batched_algorithm2_equals_per_instance_runs(insts):
     from paper_2008_11778_amd.inversion import AADescent, FWIProblem
     etas = []
     singles = []
+    finals = []
     for g, m, d_obs in insts:
         with Context(g, ckpt_every=20) as ctx:
             prob = FWIProblem(ctx, torch.from_numpy(d_obs).cuda())
@@ -119,6 +120,7 @@ def test_batched_algorithm2_equals_per_instance_runs(insts):
             for _ in range(3):
                 run.iterate()
                 its.append(run.p.clone())
+            finals.append(prob.misfit_keep(run.p))
             run.close()
             singles.append([x.cpu().numpy() for x in its])
     with Batch([g for g, _, _ in insts], [d for _, _, d in insts], ckpt_every=20, use_graphs=True) as b:
@@ -128,7 +130,10 @@ def test_batched_algorithm2_equals_per_instance_runs(insts):
         for _ in range(3):
             br.iterate()
             bits.append([x.cpu().numpy() for x in br.p])
+        # misfits of the final iterates (a forward run where the last step fell back)
+        J_end = list(br.current_misfits())
         br.close()
     for k in range(4):
         for i in range(len(insts)):
             assert np.array_equal(bits[k][i], singles[i][k]), (k, i)
+    assert J_end == finals, (J_end, finals)
