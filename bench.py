@@ -863,6 +863,35 @@ def stream_workload(args):
                       "peak_published": HBM_PEAK_GBS / 1000.0}), flush=True)
 
 
+def fwi_case_time_to_target(dev, K=30):
+    """Plain AA (M = 10) on the FWI-gradient case (768 x 256, 64 shots, 4000
+    steps, checkpoints every 50) for K iterations through the C-ABI problem:
+    the target J_K / J_0 and the wall time and gradient count to reach it."""
+    import torch
+
+    import synth
+    from paper_2008_11778_amd import Context, autotune
+    from paper_2008_11778_amd.inversion import AADescent, FWIProblem
+    g, m_true, m0 = synth.config2()
+    with Context(g, ckpt_every=50) as ctx:
+        m0t = torch.from_numpy(m0).to(dev)
+        autotune.apply(ctx, autotune.tune(g, m0t))
+        d_obs = ctx.forward_model(torch.from_numpy(m_true).to(dev)).clone()
+        prob = FWIProblem(ctx, d_obs)
+        run = AADescent(prob, m0t, None, M=10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        J0 = run.first().J
+        for _ in range(K):
+            rec = run.iterate()
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        run.close()
+    return {"workload": "FWI-gradient case 768x256, 64 shots, 4000 steps, checkpoints every 50; plain AA(10)",
+            "target": f"J_{K}/J_0", "target_ratio": round(rec.J / J0, 6), "time_s": round(t, 2),
+            "gradients": prob.n_adj, "forward_runs": prob.n_fwd}
+
+
 def c5_time_to_target(instance, geom, mt, m0, net, K, train_cost_s, dev):
     """On one held-out full-size model: plain AA (M = 10) for K iterations
     sets the target J_K / J_0; learned AA (M = 10, plain-AA fallback) runs
@@ -1002,6 +1031,8 @@ def main():
     ap.add_argument("--train-shots", type=int, default=24, help="learned workload: shots per training model")
     ap.add_argument("--aa-batch", type=int, default=100, help="learned workload: instances per AA-pair batch")
     ap.add_argument("--save-weights", default="", help="learned workload: write the trained weights (.npy)")
+    ap.add_argument("--no-target", action="store_true",
+                    help="fwi workload: skip the time-to-misfit-target legs (about 2 minutes)")
     ap.add_argument("--c5-target", type=int, default=0,
                     help="learned workload: time to plain AA's J_K/J_0 (K = this) on full-size held-out models")
     ap.add_argument("--c5-models", type=int, default=1, help="learned workload: models for --c5-target")
@@ -1187,6 +1218,32 @@ def main():
         out["hbm_stream_probe_tbs"] = best
         out["roofline"]["frac_of_stream_probe"] = round(achieved5 / 1e3 / max(best["copy"], best["mix_2r1w"]), 4)
         log(f"stream probe: {best}")
+    if not args.no_target:
+        # time to the misfit target: plain AA on the bench case, then learned
+        # versus plain AA on the first held-out full-size model with the
+        # network that ships with the package; a failure here is reported in
+        # the line and leaves the measurements above as they are
+        ttt = {}
+        try:
+            ttt["plain_aa_fwi_case"] = fwi_case_time_to_target(dev, args.target_iters)
+            log(f"time to target, plain AA: {ttt['plain_aa_fwi_case']}")
+        except Exception as e:  # noqa: BLE001
+            ttt["plain_aa_fwi_case"] = {"error": f"{type(e).__name__}: {e}"}
+        try:
+            import synth
+            from paper_2008_11778_amd import CNN
+            from paper_2008_11778_amd.learned import shipped_weights
+            w, meta = shipped_weights()
+            g5, mt5, m05 = synth.learned_instance(700, nz=384, nx=1024, nshots=96, nt=4000)
+            with CNN(384, 1024, 1, w) as net5:
+                r5 = c5_time_to_target(700, g5, mt5, m05, net5, args.target_iters, meta.get("training_cost_s"), dev)
+            r5["workload"] = ("held-out model 700 (the first held-out full-size model), 1024x384, 96 shots, "
+                              "4000 steps; network trained at the stated recipe (shipped weights)")
+            ttt["learned_vs_plain_full_size"] = r5
+            log(f"time to target, learned vs plain: {r5}")
+        except Exception as e:  # noqa: BLE001
+            ttt["learned_vs_plain_full_size"] = {"error": f"{type(e).__name__}: {e}"}
+        out["time_to_target"] = ttt
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)

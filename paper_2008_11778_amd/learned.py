@@ -20,6 +20,8 @@ took, up to scale.
 from __future__ import annotations
 
 import dataclasses
+import json
+import os
 import time
 
 import numpy as np
@@ -27,6 +29,17 @@ import torch
 
 from ._lib import AA, CNN, Batch, Context, Reducer, axpy, blend
 from .inversion import ARMIJO_C1, LAMBDAS, FWIProblem, IterLog, step_size
+
+
+SHIPPED_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "learned_mi355x.npy")
+
+
+def shipped_weights():
+    """(weights, provenance) of the network trained at the stated recipe that
+    ships with the package (a training run of the learned workload)."""
+    w = np.load(SHIPPED_WEIGHTS).astype(np.float32)
+    with open(os.path.splitext(SHIPPED_WEIGHTS)[0] + ".json") as f:
+        return w, json.load(f)
 
 
 @dataclasses.dataclass

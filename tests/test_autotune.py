@@ -117,3 +117,17 @@ def test_tune_batch_sets_heights_per_grid_class(tmp_path, monkeypatch):
     # recompute: its winner is two-step, no one-step height stored -> default 0
     assert [got[(1, k)] for k in range(4)] == [64, 0, 24, 12]
     assert len(out) == 2
+
+
+def test_shipped_network_weights():
+    """The network weights that ship with the package load without pickles,
+    have the network's parameter count, are finite and carry their training
+    provenance (the learned workload's recipe and cost)."""
+    import numpy as np
+    from paper_2008_11778_amd.learned import SHIPPED_WEIGHTS, shipped_weights
+    from paper_2008_11778_amd._lib import CNN_PARAMS
+    w, meta = shipped_weights()
+    assert w.dtype == np.float32 and w.shape == (CNN_PARAMS,)
+    assert np.isfinite(w).all() and np.abs(w).max() > 0
+    assert meta["training_cost_s"] > 0 and "bench.py --workload learned" in meta["_about"]
+    assert np.array_equal(np.load(SHIPPED_WEIGHTS, allow_pickle=False), w)
