@@ -28,7 +28,14 @@ Here the problem is discretised and then differentiated exactly
 * exact discrete adjoint: lam^n = 2A lam^{n+1} - B lam^{n+2}
   + K (Lap lam^{n+1} - R^T r^n), lam^nt = lam^{nt+1} = 0, r = d - d_obs;
 * gradient: g_pad = sum_n lam^n * q^n with q^n = (Lap u^n + s^n)/m_pad
-  (q is u_tt by the equation, lam is -v of eq. FWI_adj up to scaling).
+  (q is u_tt by the equation, lam is -v of eq. FWI_adj up to scaling);
+* stable domain: the leapfrog scheme is stable only for velocities up to the
+  bound that comes with the geometry (vmax_bound, the CFL condition), so the
+  scheme sees m_eff = max(m, 1/vmax_bound^2) everywhere (the misfit is then
+  finite for every positive model), and the gradient is that of
+  J(m_eff(m)): the folded gradient times the mask [m > 1/vmax_bound^2];
+  Born modelling linearises the same map (dm masked the same way).  For
+  models inside the bound nothing changes.
 """
 from __future__ import annotations
 
@@ -64,6 +71,19 @@ def sponge(geom):
     xx = sponge_xi(geom.nx, geom.nb)[None, :]
     st = smax * (xz ** 2 + xx ** 2) * geom.dt / 2.0
     return 1.0 / (1.0 + st), (1.0 - st) / (1.0 + st)
+
+
+def model_floor(geom) -> float:
+    """Smallest m for which the scheme is stable: 1 / vmax_bound^2."""
+    return 1.0 / float(geom.vmax_bound) ** 2
+
+
+def effective_model(geom, m):
+    """(m_eff, mask): the model the scheme uses, max(m, floor), and the
+    derivative of that map, 1 where m > floor and 0 where the floor is taken."""
+    m = np.asarray(m, np.float64)
+    f = model_floor(geom)
+    return np.maximum(m, f), (m > f).astype(np.float64)
 
 
 def pad_model(m: np.ndarray, nb: int) -> np.ndarray:
@@ -115,7 +135,7 @@ def laplacian(u: np.ndarray, h: float, periodic: bool = False) -> np.ndarray:
 # ----------------------------------------------------------------------------
 
 def _pads(geom, m):
-    m_pad = pad_model(m, geom.nb)
+    m_pad = pad_model(effective_model(geom, m)[0], geom.nb)
     A, B = sponge(geom)
     K = A * geom.dt ** 2 / m_pad
     return m_pad, A, B, K
@@ -200,7 +220,7 @@ def adjoint_gradient(geom, m, d_obs):
         r = d - np.asarray(d_obs[s], np.float64)
         J += 0.5 * float(np.sum(r * r))
         g_pad += adjoint_shot(geom, m, s, r, qs)
-    return J, fold(g_pad, geom.nz, geom.nx, geom.nb)
+    return J, fold(g_pad, geom.nz, geom.nx, geom.nb) * effective_model(geom, m)[1]
 
 
 def adjoint_from_residual(geom, m, r):
@@ -209,7 +229,7 @@ def adjoint_from_residual(geom, m, r):
     for s in range(geom.nshots):
         _, qs, _ = forward_shot(geom, m, s, keep_q=True)
         g_pad += adjoint_shot(geom, m, s, r[s], qs)
-    return fold(g_pad, geom.nz, geom.nx, geom.nb)
+    return fold(g_pad, geom.nz, geom.nx, geom.nb) * effective_model(geom, m)[1]
 
 
 # ----------------------------------------------------------------------------
@@ -220,7 +240,7 @@ def born_shot(geom, m0, dm, s):
     """Scattered data L dm for one shot: du solves the forward scheme with the
     source -(P dm) * q0^n, where q0^n = (Lap u0^n + s^n)/m0_pad."""
     m_pad, A, B, K = _pads(geom, m0)
-    dm_pad = pad_model(dm, geom.nb)
+    dm_pad = pad_model(np.asarray(dm, np.float64) * effective_model(geom, m0)[1], geom.nb)
     sz, sx = _src_node(geom, s)
     rz, rx = _rec_nodes(geom, s)
     w = np.asarray(geom.wavelet, np.float64)

@@ -222,3 +222,81 @@ def test_scaled_rtm_start_minimises_the_data_misfit():
     J = lambda a: float(np.sum((fd.born(g, m, x0 * (a / alpha)) - d_r) ** 2))
     assert alpha > 0 and J(alpha) < J(alpha * 1.01) and J(alpha) < J(alpha * 0.99)
     assert J(alpha) < float(np.sum(d_r ** 2))
+
+
+def _above_bound_model(instance=0):
+    """The small case with a few cells whose velocity exceeds the geometry's
+    bound vmax_bound (m below the floor 1/vmax_bound^2): a 2x2 patch at 1.4
+    times the bound, one edge cell at 3 times it."""
+    g, m = synth.small_case(nt=120, instance=instance)
+    m = m.astype(np.float64)
+    floor = fd.model_floor(g)
+    bad = m.copy()
+    bad[8:10, 11:13] = floor / 1.4 ** 2
+    bad[0, 5] = floor / 9.0
+    return g, m, bad, floor
+
+
+def test_model_floor_is_the_velocity_bound():
+    g, _, bad, floor = _above_bound_model()
+    assert floor == 1.0 / g.vmax_bound ** 2
+    m_eff, mask = fd.effective_model(g, bad)
+    assert np.array_equal(m_eff, np.maximum(bad, floor))
+    assert mask.sum() == bad.size - 5 and mask[0, 5] == 0 and mask[8, 11] == 0
+
+
+def test_velocities_above_the_bound_are_seen_at_the_bound():
+    """The scheme runs on m_eff: data are bitwise those of the model clamped
+    by hand, and stay bounded (the cell at three times the CFL velocity would
+    otherwise grow without limit)."""
+    g, m, bad, floor = _above_bound_model()
+    d_bad = fd.forward_model(g, bad)
+    assert np.array_equal(d_bad, fd.forward_model(g, np.maximum(bad, floor)))
+    assert np.isfinite(d_bad).all()
+    assert np.abs(d_bad).max() < 10.0 * np.abs(fd.forward_model(g, m)).max()
+
+
+def test_gradient_is_zero_where_the_floor_is_taken_and_exact_elsewhere():
+    """Central differences of J(m_eff(m)) along a direction that moves both
+    clamped cells (which stay below the floor) and free cells match <g, dm>:
+    a gradient without the mask would count the clamped cells, on which J
+    does not depend."""
+    g, m, bad, floor = _above_bound_model()
+    r = np.random.default_rng(5)
+    d_obs = fd.forward_model(g, m * (1 + 0.03 * r.standard_normal(m.shape)))
+    J, grad = fd.adjoint_gradient(g, bad, d_obs)
+    _, mask = fd.effective_model(g, bad)
+    assert np.all(grad[mask == 0] == 0.0) and np.abs(grad[mask == 1]).max() > 0
+    # just above the floor the same cells carry a gradient: the mask is what zeroes it
+    _, grad_up = fd.adjoint_gradient(g, np.where(mask == 0, floor * 1.01, bad), d_obs)
+    assert np.all(grad_up[mask == 0] != 0.0)
+    dm = r.standard_normal(m.shape) * m
+    exact = float(np.sum(grad * dm))
+    errs = []
+    for eps in (1e-4, 1e-5):
+        # clamped cells sit at most at floor / 1.96; eps * |dm| keeps them below the floor
+        jp = fd.misfit(fd.forward_model(g, bad + eps * dm), d_obs)
+        jm = fd.misfit(fd.forward_model(g, bad - eps * dm), d_obs)
+        errs.append(abs((jp - jm) / (2 * eps) - exact) / abs(exact))
+    assert errs[1] < 1e-7, errs
+    assert errs[1] < errs[0] / 50, errs
+
+
+def test_born_linearises_the_clamped_map():
+    """Born modelling at a background with clamped cells ignores dm there (J
+    does not move with them), is the Jacobian of the clamped forward map, and
+    its adjoint passes the dot test."""
+    g, m, bad, floor = _above_bound_model(instance=1)
+    _, mask = fd.effective_model(g, bad)
+    r = np.random.default_rng(6)
+    only_clamped = np.where(mask == 0, r.standard_normal(m.shape) * floor, 0.0)
+    assert np.all(fd.born(g, bad, only_clamped) == 0.0)
+    dm = r.standard_normal(m.shape) * m
+    F0 = fd.forward_model(g, bad)
+    Ld = fd.born(g, bad, dm)
+    rem = [np.linalg.norm(fd.forward_model(g, bad + eps * dm * mask) - F0 - eps * Ld) for eps in (1e-2, 5e-3)]
+    assert 3.6 < rem[0] / rem[1] < 4.4, rem
+    y = r.standard_normal((g.nshots, g.nt, g.nrec))
+    lhs = float(np.sum(Ld * y))
+    rhs = float(np.sum(dm * fd.born_adjoint(g, bad, y)))
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
