@@ -64,7 +64,8 @@ typedef struct aafwi_geometry {
     int32_t nt;            /* number of time steps = samples per trace            */
     float vref;            /* velocity used for the sponge strength [m/s]         */
     float refl;            /* nominal sponge reflection coefficient; >= 1 = off   */
-    float vmax_bound;      /* largest velocity the model may take (CFL check)     */
+    float vmax_bound;      /* largest velocity the scheme runs (CFL check); see   */
+                           /* the stable domain below                             */
     int32_t nshots;        /* S                                                   */
     int32_t nrec;          /* R receivers per shot                                */
     const int32_t* src_iz; /* [S] interior row of each shot's source node         */
@@ -74,6 +75,14 @@ typedef struct aafwi_geometry {
     const float* wavelet;  /* [nt] source time function sampled at n*dt           */
     int32_t ckpt_every;    /* checkpoint interval in steps; 0 = library default   */
 } aafwi_geometry;
+
+/* Stable domain.  The leapfrog scheme is stable only for velocities up to
+ * vmax_bound, so every call runs it on m_eff = max(m, 1/vmax_bound^2): a model
+ * with faster cells is modelled with those cells at the bound, and the
+ * misfit stays finite for every positive model.  Gradients (and the Born
+ * adjoint image) are those of the map m -> m_eff -> data: zero at cells where
+ * m <= 1/vmax_bound^2; Born modelling ignores dm there.  Inside the bound
+ * nothing changes. */
 
 /* ---- context -------------------------------------------------------------- */
 

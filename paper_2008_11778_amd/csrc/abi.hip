@@ -43,6 +43,7 @@ namespace {
 struct InstHost {
     int nz = 0, nx = 0, nb = 0, nt = 0, S = 0, R = 0, nseg = 0;
     float h = 0, dt = 0;
+    float mmin = 0;  // 1 / vmax_bound^2: the smallest m the scheme uses
     aafwi::WaveGrid g{};
     long long field = 0;
     int nrr = 0;
@@ -194,6 +195,7 @@ void add_instance(Engine* e, const aafwi_geometry& G, const aafwi_batch_io* io) 
     InstHost I;
     I.nz = G.nz; I.nx = G.nx; I.nb = G.nb; I.nt = G.nt; I.S = G.nshots; I.R = G.nrec;
     I.h = G.h; I.dt = G.dt;
+    I.mmin = (float)(1.0 / ((double)G.vmax_bound * (double)G.vmax_bound));
     I.nseg = (G.nt + e->k - 1) / e->k;
     I.wavelet.assign(G.wavelet, G.wavelet + G.nt);
     aafwi::WaveGrid& g = I.g;
@@ -465,7 +467,7 @@ void step_keep_q(Engine* e, const aafwi::StepArgs& a) {
 void model_prep(Engine* e, int i, const float* m) {
     const InstHost& I = e->in[i];
     const double c2 = ((double)I.dt / (double)I.h) * ((double)I.dt / (double)I.h);
-    aafwi::launch_model_prep(e->stream, I.g, (float)c2, m, I.K, e->flag, e->active, i);
+    aafwi::launch_model_prep(e->stream, I.g, (float)c2, I.mmin, m, I.K, e->flag, e->active, i);
 }
 
 int max_nt(const Engine* e) {
@@ -564,7 +566,7 @@ void run_backward(Engine* e, const float* r_ovr, const std::vector<float*>& grad
     for (int i = 0; i < N; ++i) {
         const InstHost& I = e->in[i];
         const double inv_dt2 = 1.0 / ((double)I.dt * (double)I.dt);
-        aafwi::launch_fold(e->stream, I.g, (float)inv_dt2, I.GI, e->fold_tmp, grad[i], e->active, i);
+        aafwi::launch_fold(e->stream, I.g, (float)inv_dt2, I.GI, e->fold_tmp, I.mkeep, I.mmin, grad[i], e->active, i);
     }
 }
 
@@ -836,7 +838,7 @@ extern "C" int aafwi_born(aafwi_ctx* c, const float* m0, const float* dm, float*
         InstHost& I = e->in[0];
         // the kept checkpoints are untouched; Kp is rebuilt before any backward pass
         model_prep(e, 0, m0);
-        aafwi::launch_born_prep(e->stream, I.g, m0, dm, I.E);
+        aafwi::launch_born_prep(e->stream, I.g, I.mmin, m0, dm, I.E);
         for (int j = 0; j < 2; ++j) {
             aafwi::launch_zero(e->stream, I.F[j], I.field);
             aafwi::launch_zero(e->stream, I.L[j], I.field);

@@ -119,9 +119,10 @@ struct StepArgs {
 constexpr int kModeFwd = 0, kModeRec = 1, kModeFwdQ = 2;
 
 // Launchers (wave_kernels.hip).
-void launch_model_prep(hipStream_t st, const WaveGrid& g, float c2, const float* m, float* K,
+// mmin = 1 / vmax_bound^2: the scheme runs on max(m, mmin) (its stable domain)
+void launch_model_prep(hipStream_t st, const WaveGrid& g, float c2, float mmin, const float* m, float* K,
                        int* flag, const int* active, int inst);
-void launch_born_prep(hipStream_t st, const WaveGrid& g, const float* m0, const float* dm,
+void launch_born_prep(hipStream_t st, const WaveGrid& g, float mmin, const float* m0, const float* dm,
                       float* E);
 void launch_zero(hipStream_t st, float* p, long long n);
 void launch_compare(hipStream_t st, long long n, const float* a, const float* b, int* same);
@@ -132,8 +133,8 @@ void launch_step2(int kernel_id, hipStream_t st, const TileRec* tiles, int ntile
                   const StepArgs& a);
 constexpr int kTile2 = 64;  // output columns of a two-step wave tile (aligned like the one-step tiles)
 // Per-instance kernels; `active`/`inst` make them no-ops for masked instances.
-void launch_fold(hipStream_t st, const WaveGrid& g, float inv_dt2, const float* gimg, double* ssum, float* grad,
-                 const int* active, int inst);
+void launch_fold(hipStream_t st, const WaveGrid& g, float inv_dt2, const float* gimg, double* ssum, const float* m,
+                 float mmin, float* grad, const int* active, int inst);
 void launch_residual_misfit(hipStream_t st, long long n, const float* d, const float* dobs,
                             float* r, double* partials, double* J, const int* active, int inst);
 void launch_copy(hipStream_t st, long long n, const float* src, float* dst, const int* active, int inst);

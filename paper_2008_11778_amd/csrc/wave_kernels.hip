@@ -1231,7 +1231,10 @@ __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? l
 
 // Kp = A c2 / m_pad on every padded cell, 0 in the pitch padding; raises flag
 // for a non-positive or non-finite m.
-__global__ void k_model_prep(WaveGrid g, float c2, const float* __restrict__ m, float* __restrict__ K,
+// The scheme is stable only for velocities up to the geometry's bound, so it
+// runs on m_eff = max(m, mmin), mmin = 1 / vmax_bound^2; the gradient and Born
+// modelling take the derivative of that map (zero where the floor is taken).
+__global__ void k_model_prep(WaveGrid g, float c2, float mmin, const float* __restrict__ m, float* __restrict__ K,
                              int* __restrict__ flag, const int* __restrict__ active, int inst) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= g.plane || (active && !active[inst])) return;
@@ -1246,10 +1249,10 @@ __global__ void k_model_prep(WaveGrid g, float c2, const float* __restrict__ m, 
     const float st = sponge_st(zp, g.nz, g.nb, g.inv_nb, g.scoef) +
                      sponge_st(xp, g.nx, g.nb, g.inv_nb, g.scoef);
     const float A = __builtin_amdgcn_rcpf(1.0f + st);
-    K[i] = A * c2 / mv;
+    K[i] = A * c2 / fmaxf(mv, mmin);
 }
 
-__global__ void k_born_prep(WaveGrid g, const float* __restrict__ m0, const float* __restrict__ dm,
+__global__ void k_born_prep(WaveGrid g, float mmin, const float* __restrict__ m0, const float* __restrict__ dm,
                             float* __restrict__ E) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= g.plane) return;
@@ -1259,7 +1262,7 @@ __global__ void k_born_prep(WaveGrid g, const float* __restrict__ m0, const floa
         return;
     }
     const long long j = (long long)clampi(zp - g.nb, 0, g.nz - 1) * g.nx + clampi(xp - g.nb, 0, g.nx - 1);
-    E[i] = dm[j] / m0[j];
+    E[i] = m0[j] > mmin ? dm[j] / m0[j] : 0.0f;  // dm moves m_eff only above the floor
 }
 
 __global__ void k_copy(long long n, const float* __restrict__ src, float* __restrict__ dst,
@@ -1291,8 +1294,8 @@ __global__ void k_shot_sum(WaveGrid g, const float* __restrict__ gimg, double* _
     ssum[i] = acc;
 }
 
-__global__ void k_fold(WaveGrid g, float inv_dt2, const double* __restrict__ ssum, float* __restrict__ grad,
-                       const int* __restrict__ active, int inst) {
+__global__ void k_fold(WaveGrid g, float inv_dt2, const double* __restrict__ ssum, const float* __restrict__ m,
+                       float mmin, float* __restrict__ grad, const int* __restrict__ active, int inst) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= g.nz * g.nx || (active && !active[inst])) return;
     const int iz = i / g.nx, ix = i % g.nx;
@@ -1308,7 +1311,8 @@ __global__ void k_fold(WaveGrid g, float inv_dt2, const double* __restrict__ ssu
             acc += ssum[(long long)zp * g.pitch + xp] * ia;
         }
     }
-    grad[i] = (float)(acc * (double)inv_dt2);
+    // chain rule through m_eff = max(m, mmin): no gradient where the floor is taken
+    grad[i] = m[i] > mmin ? (float)(acc * (double)inv_dt2) : 0.0f;
 }
 
 __device__ __forceinline__ double block_sum(double v, double* sh) {
@@ -1366,16 +1370,16 @@ __global__ void k_compare(long long n, const float* __restrict__ a, const float*
 
 }  // namespace
 
-void launch_model_prep(hipStream_t st, const WaveGrid& g, float c2, const float* m, float* K, int* flag,
+void launch_model_prep(hipStream_t st, const WaveGrid& g, float c2, float mmin, const float* m, float* K, int* flag,
                        const int* active, int inst) {
     const int blocks = (int)((g.plane + 255) / 256);
-    hipLaunchKernelGGL(k_model_prep, dim3(blocks), dim3(256), 0, st, g, c2, m, K, flag, active, inst);
+    hipLaunchKernelGGL(k_model_prep, dim3(blocks), dim3(256), 0, st, g, c2, mmin, m, K, flag, active, inst);
     AAFWI_HIP(hipGetLastError());
 }
 
-void launch_born_prep(hipStream_t st, const WaveGrid& g, const float* m0, const float* dm, float* E) {
+void launch_born_prep(hipStream_t st, const WaveGrid& g, float mmin, const float* m0, const float* dm, float* E) {
     const int blocks = (int)((g.plane + 255) / 256);
-    hipLaunchKernelGGL(k_born_prep, dim3(blocks), dim3(256), 0, st, g, m0, dm, E);
+    hipLaunchKernelGGL(k_born_prep, dim3(blocks), dim3(256), 0, st, g, mmin, m0, dm, E);
     AAFWI_HIP(hipGetLastError());
 }
 
@@ -1444,14 +1448,14 @@ void launch_step2(int kernel_id, hipStream_t st, const TileRec* tiles, int ntile
     AAFWI_HIP(hipGetLastError());
 }
 
-void launch_fold(hipStream_t st, const WaveGrid& g, float inv_dt2, const float* gimg, double* ssum, float* grad,
-                 const int* active, int inst) {
+void launch_fold(hipStream_t st, const WaveGrid& g, float inv_dt2, const float* gimg, double* ssum, const float* m,
+                 float mmin, float* grad, const int* active, int inst) {
     hipLaunchKernelGGL(k_shot_sum, dim3((unsigned)((g.plane + 255) / 256)), dim3(256), 0, st, g, gimg, ssum, active,
                        inst);
     AAFWI_HIP(hipGetLastError());
     const int n = g.nz * g.nx;
-    hipLaunchKernelGGL(k_fold, dim3((n + 255) / 256), dim3(256), 0, st, g, inv_dt2, (const double*)ssum, grad,
-                       active, inst);
+    hipLaunchKernelGGL(k_fold, dim3((n + 255) / 256), dim3(256), 0, st, g, inv_dt2, (const double*)ssum, m, mmin,
+                       grad, active, inst);
     AAFWI_HIP(hipGetLastError());
 }
 
