@@ -172,8 +172,14 @@ def multisecant_matrix(P: np.ndarray, D: np.ndarray) -> np.ndarray:
 # Algorithm 2 driver
 # ----------------------------------------------------------------------------
 
+def project(p, floor):
+    """Keep an iterate in the model's stable domain: max(p, floor) (no-op
+    when floor is None)."""
+    return p if floor is None else np.maximum(p, floor)
+
+
 def alg2(grad_fn, misfit_fn, p0, eta, M, iters, cond_max=COND_MAX, lambdas=LAMBDAS,
-         c1=ARMIJO_C1, linesearch=True, beta=1.0, weights=None, restart=True):
+         c1=ARMIJO_C1, linesearch=True, beta=1.0, weights=None, restart=True, floor=None):
     """Run Algorithm 2 for ``iters`` AA iterations after p_1 = G(p_0).
 
     grad_fn(p) -> (J, g); misfit_fn(p) -> J.  Returns a dict with the
@@ -184,6 +190,9 @@ def alg2(grad_fn, misfit_fn, p0, eta, M, iters, cond_max=COND_MAX, lambdas=LAMBD
     the window is cleared before p_{k+1} enters it: Anderson mixing
     restarts from the descent step (M_k counts the iterations since the
     restart).  A descent step that did not decrease J keeps the window.
+    With ``floor`` (the smallest model value the forward scheme is stable
+    for), pbar = G(p_k) and ptilde are projected onto p >= floor before the
+    search; every blend of the two is then in the domain too.
     """
     hist = AAHistory(M, cond_max, beta, weights)
     p = np.asarray(p0, np.float64).ravel().copy()
@@ -192,7 +201,7 @@ def alg2(grad_fn, misfit_fn, p0, eta, M, iters, cond_max=COND_MAX, lambdas=LAMBD
     hist.step(p, g0, eta)
     iterates, misfits, lams, gammas = [p.copy()], [J0], [], []
     n_grad, n_fwd = 1, 0
-    p = p - eta * g0
+    p = project(p - eta * g0, floor)
     iterates.append(p.copy())
     fell_back = False
     restarts = []  # iterations k whose window was cleared before p_k entered
@@ -205,6 +214,7 @@ def alg2(grad_fn, misfit_fn, p0, eta, M, iters, cond_max=COND_MAX, lambdas=LAMBD
             restarts.append(len(misfits))
         misfits.append(J)
         pbar, ptilde, gamma, mk = hist.step(p, g, eta)
+        pbar, ptilde = project(pbar, floor), project(ptilde, floor)
         gammas.append(gamma)
         lam_acc = 0.0
         new = pbar
@@ -227,7 +237,7 @@ def alg2(grad_fn, misfit_fn, p0, eta, M, iters, cond_max=COND_MAX, lambdas=LAMBD
 
 
 def learned_alg2(grad_fn, misfit_fn, dir_fn, p0, eta, eta_theta, M, iters, cond_max=COND_MAX,
-                 lambdas=LAMBDAS, c1=ARMIJO_C1, restart=True):
+                 lambdas=LAMBDAS, c1=ARMIJO_C1, restart=True, floor=None):
     """Algorithm 2 on the learned map G_theta(p) = p - eta_theta d(p), with
     d = dir_fn(g, p) the network's direction at p (its gradient g), and
     plain Anderson acceleration on G(p) = p - eta g as the fallback.
@@ -241,8 +251,9 @@ def learned_alg2(grad_fn, misfit_fn, dir_fn, p0, eta, eta_theta, M, iters, cond_
     the same backtracking between its ptilde and pbar, and its pbar if no
     lambda passes.  A window whose search ended on its pbar restarts at the
     next iteration if that iteration's J is below the previous one (as in
-    ``alg2``).  Returns the accepted iterates, misfits, directions d_k,
-    lambdas, fallback flags and evaluation counts."""
+    ``alg2``).  With ``floor``, every pbar and ptilde is projected onto
+    p >= floor (as in ``alg2``).  Returns the accepted iterates, misfits,
+    directions d_k, lambdas, fallback flags and evaluation counts."""
     h_t = AAHistory(M, cond_max)
     h_p = AAHistory(M, cond_max)
     p = np.asarray(p0, np.float64).ravel().copy()
@@ -251,7 +262,7 @@ def learned_alg2(grad_fn, misfit_fn, dir_fn, p0, eta, eta_theta, M, iters, cond_
     d = np.asarray(dir_fn(g, p), np.float64).ravel()
     iterates, misfits, dirs, lams, fallbacks = [p.copy()], [J], [d], [], []
     n_grad, n_fwd = 1, 0
-    pbar_t = h_t.step(p, d, eta_theta)[0]
+    pbar_t = project(h_t.step(p, d, eta_theta)[0], floor)
     h_p.step(p, g, eta)
     p = pbar_t.copy()
     iterates.append(p.copy())
@@ -280,6 +291,8 @@ def learned_alg2(grad_fn, misfit_fn, dir_fn, p0, eta, eta_theta, M, iters, cond_
         dirs.append(d)
         pbar_t, ptilde_t, _, _ = h_t.step(p, d, eta_theta)
         pbar_p, ptilde_p, _, _ = h_p.step(p, g, eta)
+        pbar_t, ptilde_t = project(pbar_t, floor), project(ptilde_t, floor)
+        pbar_p, ptilde_p = project(pbar_p, floor), project(ptilde_p, floor)
         fb_t = fb_p = False
         fell = False
         lam, new = search(ptilde_t, pbar_t, J, g, p)

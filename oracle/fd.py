@@ -33,7 +33,8 @@ Here the problem is discretised and then differentiated exactly
   bound that comes with the geometry (vmax_bound, the CFL condition), so the
   scheme sees m_eff = max(m, 1/vmax_bound^2) everywhere (the misfit is then
   finite for every positive model), and the gradient is that of
-  J(m_eff(m)): the folded gradient times the mask [m > 1/vmax_bound^2];
+  J(m_eff(m)): the folded gradient times the mask [m >= 1/vmax_bound^2]
+  (the derivative from above at the floor, where projected iterates sit);
   Born modelling linearises the same map (dm masked the same way).  For
   models inside the bound nothing changes.
 """
@@ -80,10 +81,11 @@ def model_floor(geom) -> float:
 
 def effective_model(geom, m):
     """(m_eff, mask): the model the scheme uses, max(m, floor), and the
-    derivative of that map, 1 where m > floor and 0 where the floor is taken."""
+    derivative of that map, 1 where m >= floor (from above at the floor
+    itself, where projected iterates sit) and 0 below it."""
     m = np.asarray(m, np.float64)
     f = model_floor(geom)
-    return np.maximum(m, f), (m > f).astype(np.float64)
+    return np.maximum(m, f), (m >= f).astype(np.float64)
 
 
 def pad_model(m: np.ndarray, nb: int) -> np.ndarray:

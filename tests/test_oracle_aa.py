@@ -243,3 +243,41 @@ def test_weighted_gamma_solves_weighted_normal_equations():
     np.testing.assert_allclose(gw, ref, rtol=1e-10)
     np.testing.assert_allclose(gc, g1, rtol=1e-10)   # a constant weight changes nothing
     assert np.abs(gw - g1).max() > 1e-3               # a varying one does
+
+
+def test_alg2_projects_onto_the_stable_domain():
+    """With a floor (the smallest model value the scheme is stable for),
+    Algorithm 2 keeps every iterate at or above it.  Hand-worked: on
+    J(p) = 1/2 (p + 1)^2 with floor 0, steepest descent with eta = 1/2 from
+    p = 2 (M = 0, no search) goes 2 -> 0.5 -> max(-0.25, 0) = 0 -> 0;
+    without the floor it goes to -0.25.  With M = 2 and the search on
+    J(p) = 1/2 |p - (-1, 3)|^2 the iterates stay at or above 0 and converge
+    to the constrained minimiser (0, 3)."""
+    from oracle.aa import alg2
+    q = lambda p: (0.5 * float(np.sum((np.asarray(p) + 1.0) ** 2)), np.asarray(p) + 1.0)
+    out = alg2(q, lambda p: q(p)[0], [2.0], 0.5, M=0, iters=3, linesearch=False, floor=0.0)
+    assert [float(x[0]) for x in out["iterates"]] == [2.0, 0.5, 0.0, 0.0, 0.0]
+    free = alg2(q, lambda p: q(p)[0], [2.0], 0.5, M=0, iters=1, linesearch=False)
+    assert float(free["iterates"][-1][0]) == -0.25
+    a = np.array([-1.0, 3.0])
+    f = lambda p: (0.5 * float(np.sum((np.asarray(p) - a) ** 2)), np.asarray(p) - a)
+    out = alg2(f, lambda p: f(p)[0], [2.0, 0.0], 0.5, M=2, iters=12, floor=0.0)
+    assert all(np.all(x >= 0.0) for x in out["iterates"])
+    assert np.allclose(out["iterates"][1], [0.5, 1.5])  # G(p_0) = (0.5, 1.5), already feasible
+    assert np.allclose(out["iterates"][-1], [0.0, 3.0], atol=1e-8)
+    free = alg2(f, lambda p: f(p)[0], [2.0, 0.0], 0.5, M=2, iters=12)
+    assert min(float(x[0]) for x in free["iterates"]) < -0.5
+
+
+def test_learned_alg2_projects_both_windows():
+    """The learned form with a floor: with a direction that overshoots (d = 3 g)
+    the learned window's steps would leave the domain; every accepted iterate
+    stays at or above the floor and the run reaches the constrained
+    minimiser of J(p) = 1/2 |p - (-1, 3)|^2."""
+    from oracle.aa import learned_alg2
+    a = np.array([-1.0, 3.0])
+    f = lambda p: (0.5 * float(np.sum((np.asarray(p) - a) ** 2)), np.asarray(p) - a)
+    out = learned_alg2(f, lambda p: f(p)[0], lambda g, p: 3.0 * g, [2.0, 0.0], 0.5, 0.5, M=2, iters=15,
+                       floor=0.0)
+    assert all(np.all(x >= 0.0) for x in out["iterates"])
+    assert np.allclose(out["iterates"][-1], [0.0, 3.0], atol=1e-6)
