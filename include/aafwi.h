@@ -81,8 +81,9 @@ typedef struct aafwi_geometry {
  * with faster cells is modelled with those cells at the bound, and the
  * misfit stays finite for every positive model.  Gradients (and the Born
  * adjoint image) are those of the map m -> m_eff -> data: zero at cells where
- * m <= 1/vmax_bound^2; Born modelling ignores dm there.  Inside the bound
- * nothing changes. */
+ * m < 1/vmax_bound^2 (taken from above at the floor itself); Born modelling
+ * ignores dm there.  Inside the bound nothing changes.  The Algorithm 2
+ * drivers keep their iterates at or above the floor (aafwi_floor). */
 
 /* ---- context -------------------------------------------------------------- */
 
@@ -287,6 +288,10 @@ int aafwi_dot_diff(aafwi_stream stream, int64_t n, const float* g, const float* 
 int aafwi_laplacian_filter(aafwi_stream stream, int32_t nz, int32_t nx, float h, const float* image, float* out);
 
 int aafwi_axpy(aafwi_stream stream, int64_t n, float a, const float* x, float* y);
+
+/* x = max(x, floor) in place (device [n]): keeps an iterate in the model's
+ * stable domain (floor = 1/vmax_bound^2; see the stable domain above). */
+int aafwi_floor(aafwi_stream stream, int64_t n, float floor, float* x);
 
 /* out = a*x in FP32 (device [n]); out may alias x. */
 int aafwi_scale(aafwi_stream stream, int64_t n, float a, const float* x, float* out);

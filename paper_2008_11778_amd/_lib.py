@@ -88,6 +88,7 @@ _sig("aafwi_blend", _vp, _i64, _f32, _vp, _vp, _vp)
 _sig("aafwi_dot", _vp, _i64, _vp, _vp, _vp, _vp)
 _sig("aafwi_dot_diff", _vp, _i64, _vp, _vp, _vp, _vp, _vp)
 _sig("aafwi_axpy", _vp, _i64, _f32, _vp, _vp)
+_sig("aafwi_floor", _vp, _i64, _f32, _vp)
 _sig("aafwi_laplacian_filter", _vp, _i32, _i32, _f32, _vp, _vp)
 _sig("aafwi_scale", _vp, _i64, _f32, _vp, _vp)
 _sig("aafwi_kernel_timing", _vp, ctypes.c_int)
@@ -173,6 +174,8 @@ class Context:
             self.stream = stream if stream is not None else torch.cuda.current_stream()
             self.nz, self.nx, self.nt = int(geom.nz), int(geom.nx), int(geom.nt)
             self.nb = int(geom.nb)
+            # the smallest m the scheme runs (1 / vmax_bound^2, as the library rounds it)
+            self.floor = float(np.float32(1.0 / (float(geom.vmax_bound) ** 2)))
             self.nshots = int(np.asarray(geom.src_iz).size)
             self.nrec = int(np.asarray(geom.rec_iz).size // self.nshots)
             s, self._keep = make_geometry_struct(geom, ckpt_every)
@@ -338,6 +341,7 @@ class Batch:
         self.stream = stream if stream is not None else torch.cuda.Stream()
         self.N = len(geoms)
         self.geoms = list(geoms)
+        self.floors = [float(np.float32(1.0 / (float(g.vmax_bound) ** 2))) for g in self.geoms]
         self.shapes, self.data_shapes = [], []
         structs, self._keep = [], []
         for g in geoms:
@@ -613,6 +617,13 @@ def laplacian_filter(image, h, out=None, stream=None):
     _check(_lib.aafwi_laplacian_filter(_stream_handle(stream), nz, nx, float(h), _ptr(image, name="image"),
                                        _ptr(out, numel=nz * nx, name="out")))
     return out
+
+
+def floor_(x, floor, stream=None):
+    """x = max(x, floor) in place (an iterate kept in the stable domain)."""
+    n = x.numel()
+    _check(_lib.aafwi_floor(_stream_handle(stream), n, float(floor), _ptr(x, numel=n, name="x")))
+    return x
 
 
 def axpy(a, x, y, stream=None):

@@ -19,14 +19,17 @@ import time
 import numpy as np
 import torch
 
-from ._lib import Batch, BatchAA, Reducer, axpy, blend
+from ._lib import Batch, BatchAA, Reducer, axpy, blend, floor_
 from .inversion import ARMIJO_C1, LAMBDAS
 
 
 class BatchedAADescent:
     def __init__(self, batch: Batch, p0, M: int, etas=None, eta_frac: float = 0.02, cond_max: float = 1e5,
-                 lambdas=LAMBDAS, c1: float = ARMIJO_C1, restart: bool = True):
+                 lambdas=LAMBDAS, c1: float = ARMIJO_C1, restart: bool = True, project: bool = True):
         self.b = batch
+        # each instance's pbar and ptilde are kept at or above its floor (the
+        # stable domain of its geometry), as in the single-instance driver
+        self.floors = list(batch.floors) if project else None
         self.restart = restart
         self.N = batch.N
         self.M, self.lambdas, self.c1, self.eta_frac = M, lambdas, c1, eta_frac
@@ -81,11 +84,15 @@ class BatchedAADescent:
         s = self.b.stream
         if self.aa is not None:
             self.aa.step(self.p, [self._g(i) for i in range(self.N)], self.etas, self.pbar, self.ptilde)
-            return
-        for i in range(self.N):
-            blend(1.0, self.p[i], self.p[i], self.pbar[i], stream=s)
-            axpy(-self.etas[i], self._g(i), self.pbar[i], stream=s)
-            blend(1.0, self.pbar[i], self.pbar[i], self.ptilde[i], stream=s)
+        else:
+            for i in range(self.N):
+                blend(1.0, self.p[i], self.p[i], self.pbar[i], stream=s)
+                axpy(-self.etas[i], self._g(i), self.pbar[i], stream=s)
+                blend(1.0, self.pbar[i], self.pbar[i], self.ptilde[i], stream=s)
+        if self.floors is not None:
+            for i in range(self.N):
+                floor_(self.pbar[i], self.floors[i], stream=s)
+                floor_(self.ptilde[i], self.floors[i], stream=s)
 
     # -- Algorithm 2 -------------------------------------------------------------
     def first(self):

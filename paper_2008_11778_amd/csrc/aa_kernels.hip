@@ -752,6 +752,13 @@ __global__ void k_scale(long long n, float a, const float* x, float* out) {
     out[i] = a * x[i];
 }
 
+// x = max(x, floor) in place: an iterate kept in the model's stable domain.
+__global__ void k_floor(long long n, float floor, float* x) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    x[i] = fmaxf(x[i], floor);
+}
+
 // out = -Lap_h img on an nz x nx image (8th-order second differences, zero
 // outside the image): the Laplacian-filtered RTM image.
 __global__ void k_laplacian_filter(int nz, int nx, float inv_h2, const float* __restrict__ img,
@@ -873,6 +880,11 @@ void launch_blend(hipStream_t st, long long n, float lam, const float* pt, const
 
 void launch_scale(hipStream_t st, long long n, float a, const float* x, float* out) {
     hipLaunchKernelGGL(k_scale, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, a, x, out);
+    AAFWI_HIP(hipGetLastError());
+}
+
+void launch_floor(hipStream_t st, long long n, float floor, float* x) {
+    hipLaunchKernelGGL(k_floor, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, floor, x);
     AAFWI_HIP(hipGetLastError());
 }
 
@@ -1089,6 +1101,15 @@ extern "C" int aafwi_scale(aafwi_stream stream, int64_t n, float a, const float*
     return guarded([&]() -> int {
         AAFWI_REQUIRE(n > 0 && x && out, "scale: bad argument");
         aafwi::launch_scale((hipStream_t)stream, n, a, x, out);
+        return AAFWI_OK;
+    });
+}
+
+extern "C" int aafwi_floor(aafwi_stream stream, int64_t n, float floor, float* x) {
+    return guarded([&]() -> int {
+        AAFWI_REQUIRE(n > 0 && x, "floor: bad argument");
+        AAFWI_REQUIRE(std::isfinite(floor), "floor: floor must be finite");
+        aafwi::launch_floor((hipStream_t)stream, n, floor, x);
         return AAFWI_OK;
     });
 }

@@ -146,6 +146,7 @@ void launch_blend(hipStream_t st, long long n, float lam, const float* pt, const
                   float* out);
 void launch_axpy(hipStream_t st, long long n, float a, const float* x, float* y);
 void launch_scale(hipStream_t st, long long n, float a, const float* x, float* out);
+void launch_floor(hipStream_t st, long long n, float floor, float* x);
 
 constexpr int kReduceBlocks = 1024;  // fixed partial count: deterministic reductions
 constexpr int kReduceThreads = 256;

@@ -1233,7 +1233,7 @@ __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? l
 // for a non-positive or non-finite m.
 // The scheme is stable only for velocities up to the geometry's bound, so it
 // runs on m_eff = max(m, mmin), mmin = 1 / vmax_bound^2; the gradient and Born
-// modelling take the derivative of that map (zero where the floor is taken).
+// modelling take the derivative of that map (zero below the floor).
 __global__ void k_model_prep(WaveGrid g, float c2, float mmin, const float* __restrict__ m, float* __restrict__ K,
                              int* __restrict__ flag, const int* __restrict__ active, int inst) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1262,7 +1262,7 @@ __global__ void k_born_prep(WaveGrid g, float mmin, const float* __restrict__ m0
         return;
     }
     const long long j = (long long)clampi(zp - g.nb, 0, g.nz - 1) * g.nx + clampi(xp - g.nb, 0, g.nx - 1);
-    E[i] = m0[j] > mmin ? dm[j] / m0[j] : 0.0f;  // dm moves m_eff only above the floor
+    E[i] = m0[j] >= mmin ? dm[j] / m0[j] : 0.0f;  // dm moves m_eff only at or above the floor
 }
 
 __global__ void k_copy(long long n, const float* __restrict__ src, float* __restrict__ dst,
@@ -1311,8 +1311,9 @@ __global__ void k_fold(WaveGrid g, float inv_dt2, const double* __restrict__ ssu
             acc += ssum[(long long)zp * g.pitch + xp] * ia;
         }
     }
-    // chain rule through m_eff = max(m, mmin): no gradient where the floor is taken
-    grad[i] = m[i] > mmin ? (float)(acc * (double)inv_dt2) : 0.0f;
+    // chain rule through m_eff = max(m, mmin): no gradient below the floor (the
+    // derivative from above at the floor itself, where projected iterates sit)
+    grad[i] = m[i] >= mmin ? (float)(acc * (double)inv_dt2) : 0.0f;
 }
 
 __device__ __forceinline__ double block_sum(double v, double* sh) {

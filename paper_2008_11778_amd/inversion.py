@@ -30,7 +30,7 @@ import time
 
 import torch
 
-from ._lib import AA, Context, Reducer, axpy, blend, laplacian_filter, scale
+from ._lib import AA, Context, Reducer, axpy, blend, floor_, laplacian_filter, scale
 
 LAMBDAS = (1.0, 0.5, 0.25, 0.125)
 ARMIJO_C1 = 1e-4
@@ -42,6 +42,7 @@ class FWIProblem:
     def __init__(self, ctx: Context, d_obs: torch.Tensor):
         self.ctx = ctx
         self.d_obs = d_obs
+        self.floor = ctx.floor  # the model's stable domain: m >= floor
         self.d = ctx._new(ctx.data_shape)
         self.r = ctx._new(ctx.data_shape)
         self.J = ctx._new((1,), torch.float64)
@@ -82,6 +83,7 @@ class AutogradFWIProblem:
     def __init__(self, ctx: Context, d_obs: torch.Tensor):
         self.ctx = ctx
         self.d_obs = d_obs
+        self.floor = ctx.floor  # the model's stable domain: m >= floor
         self.kept = None
         self.kept_J = None
         self.kept_leaf = None
@@ -188,6 +190,9 @@ class AADescent:
     M = 0 is steepest descent with the fixed step (the Picard iteration of G).
     aa_solver selects the least-squares solver ("gram" or "qr"), aa_beta the
     damping of the mixed step and aa_weights a weighted l2 norm for Step 2.
+    floor: pbar and ptilde are kept at or above it (the model's stable
+    domain); by default the problem's own floor (FWI), none for problems
+    without one (LSRTM's reflectivity).
     The problem sees flat tensors; the accepted trial buffer becomes the new
     iterate itself, so the problem recognises (by object identity) that its
     kept forward run is at that iterate.
@@ -196,8 +201,9 @@ class AADescent:
     def __init__(self, problem, p0: torch.Tensor, eta: float | None, M: int, cond_max: float = 1e5,
                  lambdas=LAMBDAS, c1: float = ARMIJO_C1, linesearch: bool = True,
                  eta_frac: float = 0.02, aa_solver: str = "gram", aa_beta: float = 1.0, aa_weights=None,
-                 restart: bool = True):
+                 restart: bool = True, floor="problem"):
         self.problem, self.M, self.eta = problem, M, eta
+        self.floor = getattr(problem, "floor", None) if floor == "problem" else floor
         self.lambdas, self.c1, self.linesearch, self.eta_frac = lambdas, c1, linesearch, eta_frac
         self.restart = restart
         self.fell_back = False  # the last iteration's search took lambda = 0
@@ -225,6 +231,9 @@ class AADescent:
         else:
             _gd_step(self.p, self.g, self.eta, self.pbar)
             self.ptilde.copy_(self.pbar)
+        if self.floor is not None:
+            floor_(self.pbar, self.floor)
+            floor_(self.ptilde, self.floor)
 
     def first(self) -> IterLog:
         J = self.problem.gradient(self.p, self.g)

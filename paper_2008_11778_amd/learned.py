@@ -27,7 +27,7 @@ import time
 import numpy as np
 import torch
 
-from ._lib import AA, CNN, Batch, Context, Reducer, axpy, blend
+from ._lib import AA, CNN, Batch, Context, Reducer, axpy, blend, floor_
 from .inversion import ARMIJO_C1, LAMBDAS, FWIProblem, IterLog, step_size
 
 
@@ -55,8 +55,12 @@ class LearnedAADescent:
 
     def __init__(self, problem, p0: torch.Tensor, net: CNN, M: int = 10, eta: float | None = None,
                  eta_theta: float | None = None, cond_max: float = 1e5, lambdas=LAMBDAS, c1: float = ARMIJO_C1,
-                 eta_frac: float = 0.02, restart: bool = True, track_step_error: bool = False):
+                 eta_frac: float = 0.02, restart: bool = True, track_step_error: bool = False,
+                 floor="problem"):
         self.problem, self.net, self.M = problem, net, M
+        # pbar and ptilde of both windows are kept at or above the floor (the
+        # model's stable domain); by default the problem's own
+        self.floor = getattr(problem, "floor", None) if floor == "problem" else floor
         self.restart = restart
         self.track_step_error = track_step_error
         # which window's search fell back to its plain step in the last
@@ -91,6 +95,9 @@ class LearnedAADescent:
     def _maps(self):
         self.aa_theta.step(self.p, self.d, self.eta_theta, self.pbar, self.ptilde)
         self.aa_plain.step(self.p, self.g, self.eta, self.pbar_plain, self.ptilde_plain)
+        if self.floor is not None:
+            for x in (self.pbar, self.ptilde, self.pbar_plain, self.ptilde_plain):
+                floor_(x, self.floor)
 
     def _search(self, ptilde, J):
         """Backtracking search of Algorithm 2 (Step 4) between ptilde and the
