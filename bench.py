@@ -746,6 +746,41 @@ def learned_workload(args):
             np.save(args.save_weights, net.get_weights())
             log(f"weights saved to {args.save_weights}")
 
+    if args.finetune_models:
+        # fine-tuning at the full size (beyond the stated recipe): pairs from
+        # plain-AA and L-BFGS runs on models 800, 801, ... (disjoint from the
+        # held-out 700-703), then Adam from the current weights
+        t0 = time.perf_counter()
+        full = dict(nz=384, nx=1024, nshots=96, nt=4000)
+        ft_cases = [synth.learned_instance(800 + i, **full) for i in range(args.finetune_models)]
+        chunks = []
+        for i in range(0, len(ft_cases), 2):
+            chunks.append(aa_pairs(ft_cases[i:i + 2], M=10, iters=args.train_iters))
+            log(f"fine-tuning AA pairs of models {800 + i}, {801 + i}: {time.perf_counter() - t0:.1f}s")
+        pl_ft = lbfgs_pairs(ft_cases, M=10, iters=args.lbfgs_iters,
+                            progress=lambda i: log(f"fine-tuning L-BFGS run {i + 1}: {time.perf_counter() - t0:.1f}s"))
+        ft_pairs, ft_dropped = drop_degenerate(merge(*chunks, pl_ft))
+        del chunks, pl_ft
+        if args.flip:
+            ft_pairs = merge(ft_pairs, flip_x(ft_pairs))
+        t_ft_data = time.perf_counter() - t0
+        net_ft = CNN(384, 1024, 8, net.get_weights())
+        t0 = time.perf_counter()
+        hist_ft = train(net_ft, ft_pairs, epochs=args.finetune_epochs, batch=8, lr=args.finetune_lr)
+        torch.cuda.synchronize()
+        training["finetune"] = {"models": args.finetune_models, "pairs": len(ft_pairs), "dropped": ft_dropped,
+                                "data_s": round(t_ft_data, 1), "train_s": round(time.perf_counter() - t0, 1),
+                                "epochs": args.finetune_epochs, "lr": args.finetune_lr,
+                                "epoch_loss": [round(x, 4) for x in hist_ft]}
+        log(f"fine-tuning: {training['finetune']}")
+        del ft_pairs
+        if args.save_weights:
+            np.save(os.path.splitext(args.save_weights)[0] + "_finetuned.npy", net_ft.get_weights())
+        full_weights = net_ft.get_weights()
+        net_ft.close()
+    else:
+        full_weights = None
+
     def compare(instance, geom, mt, m0, net_j, tune=False):
         """Plain AA and learned AA (M = 10) from m0 for args.iters iterations."""
         res = {}
@@ -793,7 +828,7 @@ def learned_workload(args):
         rows.append(compare(500 + j, g, mt, m0, net))
     large = []
     if args.large_test:
-        net_l = CNN(384, 1024, 1, net.get_weights())
+        net_l = CNN(384, 1024, 1, net.get_weights() if full_weights is None else full_weights)
         for j in range(args.large_test):
             g, mt, m0 = synth.learned_instance(700 + j, nz=384, nx=1024, nshots=96, nt=4000)
             large.append(compare(700 + j, g, mt, m0, net_l, tune=True))
@@ -801,11 +836,13 @@ def learned_workload(args):
     c5 = []
     if args.c5_target:
         # time to plain AA's J_K / J_0 on held-out full-size models (instances 700, ...)
-        net_l = CNN(384, 1024, 1, net.get_weights())
+        net_l = CNN(384, 1024, 1, net.get_weights() if full_weights is None else full_weights)
         train_cost = (training.get("data_s", 0.0) + training.get("train_s", 0.0)) or args.train_cost_s
-        for j in range(args.c5_models):
-            g, mt, m0 = synth.learned_instance(700 + j, nz=384, nx=1024, nshots=96, nt=4000)
-            c5.append(c5_time_to_target(700 + j, g, mt, m0, net_l, args.c5_target, train_cost, dev))
+        if "finetune" in training:
+            train_cost += training["finetune"]["data_s"] + training["finetune"]["train_s"]
+        for j in range(args.c5_first, args.c5_first + args.c5_models):
+            g, mt, m0 = synth.learned_instance(j, nz=384, nx=1024, nshots=96, nt=4000)
+            c5.append(c5_time_to_target(j, g, mt, m0, net_l, args.c5_target, train_cost, dev))
         net_l.close()
     ratio = [r["learned_final"] / r["plain_final"] for r in rows] or [float("nan")]
     reached = [r for r in rows if r["learned_s_to_plain_final"] is not None]
@@ -1046,9 +1083,14 @@ def main():
     ap.add_argument("--save-weights", default="", help="learned workload: write the trained weights (.npy)")
     ap.add_argument("--no-target", action="store_true",
                     help="fwi workload: skip the time-to-misfit-target legs (about 2 minutes)")
+    ap.add_argument("--finetune-models", type=int, default=0,
+                    help="learned workload: fine-tune at 1024x384 on this many models (800, 801, ...)")
+    ap.add_argument("--finetune-epochs", type=int, default=20, help="learned workload: fine-tuning epochs")
+    ap.add_argument("--finetune-lr", type=float, default=3e-4, help="learned workload: fine-tuning learning rate")
     ap.add_argument("--c5-target", type=int, default=0,
                     help="learned workload: time to plain AA's J_K/J_0 (K = this) on full-size held-out models")
     ap.add_argument("--c5-models", type=int, default=1, help="learned workload: models for --c5-target")
+    ap.add_argument("--c5-first", type=int, default=700, help="learned workload: first model for --c5-target")
     ap.add_argument("--train-cost-s", type=float, default=0.0,
                     help="learned workload: training cost (s) for the break-even count when weights are loaded")
     ap.add_argument("--load-weights", default="",
