@@ -352,6 +352,13 @@ def batched_workload(args):
     Both take the autotuned strip heights of each grid class (the
     sequential contexts also its launch modes; the batch shares one mode per
     kernel).  Prints one JSON line with both wall times.
+
+    With ``--learned`` the same batch then runs the learned form
+    (BatchedLearnedAADescent with the shipped network, the same etas, M = 10)
+    for the same number of iterations: per instance the batch wall time at
+    which it first reaches plain AA's final misfit, and the final misfits.
+    ``--no-sequential`` skips the per-instance runs (the plain batch's final
+    misfits, the same numbers, are then the targets).
     """
     import numpy as np
     import torch
@@ -369,6 +376,11 @@ def batched_workload(args):
     shapes = {}  # launch shapes per grid class (padded rows x columns), tuned on at most 8 shots
     for i, (g, mt, m0) in enumerate(insts):
         cls = (g.nz + 2 * g.nb, g.nx + 2 * g.nb)
+        if args.no_sequential:
+            with Context(g, ckpt_every=k) as ctx:
+                d_obs.append(ctx.forward_model(torch.from_numpy(mt).to(dev)).cpu())
+            upd += 2.0 * g.nz_p * g.nx_p * g.nshots * g.nt * (args.iters + 1)
+            continue
         if cls not in shapes:
             sub = g.subset_shots(list(range(min(g.nshots, 8))))
             shapes[cls] = autotune.tune(sub, torch.from_numpy(m0).to(dev), use_cache=True)
@@ -396,7 +408,7 @@ def batched_workload(args):
         # the same per-class strip heights, for the batch's shared launch modes
         per_class = autotune.tune_batch(b, geoms, [torch.from_numpy(m0).to(dev) for _, _, m0 in insts])
         log(f"batch launch modes {b.time_blocking()}, per-class strip heights {per_class}")
-        br = BatchedAADescent(b, [torch.from_numpy(m0).to(dev) for _, _, m0 in insts], M=10, etas=etas)
+        br = BatchedAADescent(b, [torch.from_numpy(m0).to(dev) for _, _, m0 in insts], M=10, etas=etas or None)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         br.first()
@@ -408,20 +420,75 @@ def batched_workload(args):
         t_batch = time.perf_counter() - t0
         # untimed, as for the sequential runs: the misfit of each final iterate
         finals = np.array(br.current_misfits(), np.float64)
+        etas = list(br.etas)
         br.close()
+        if args.no_sequential:
+            targets = list(finals)
+        learned = None
+        if args.learned:
+            learned = batched_learned_leg(args, b, insts, etas, np.array(targets, np.float64), dev)
     targets = np.array(targets, np.float64)
     reached = int(np.sum(finals <= targets * (1 + 1e-9)))
     rel = float(np.max(np.abs(finals - targets) / targets))
     log(f"batched: {t_batch:.2f}s for {args.iters} iterations; {reached}/{len(insts)} instances at their "
         f"sequential misfit (max relative difference {rel:.1e})")
     out = {"metric": "time to misfit target, batched vs sequential AA (uneven instances)",
-           "value": round(sum(seq_times) / t_batch, 3), "unit": "x speedup", "n_gpus": 1,
-           "batched_s": round(t_batch, 2), "sequential_s": round(sum(seq_times), 2),
+           "value": round(sum(seq_times) / t_batch, 3) if seq_times else None, "unit": "x speedup", "n_gpus": 1,
+           "batched_s": round(t_batch, 2), "sequential_s": round(sum(seq_times), 2) if seq_times else None,
            "iterations": args.iters, "reached_targets": reached, "max_rel_diff_final_misfit": rel,
            "instances": len(insts), "ckpt_every": k,
            "credited_gpt_updates_per_s_batched": round(upd / t_batch / 1e9, 1),
            "higher_is_better": True, "dtype": "f32", "data": "synthetic"}
+    if learned is not None:
+        out["learned_batched"] = learned
     print(json.dumps(out), flush=True)
+
+
+def batched_learned_leg(args, b, insts, etas, targets, dev):
+    """The learned form on the same batch (shipped network, the plain runs'
+    etas, M = 10), timed over the same iterations; per instance the batch
+    wall time of the first iteration at whose gradient J is at or below the
+    plain run's final misfit (J(p_k) is known once the gradient at p_k is
+    evaluated), else, after the timed region, whether the final iterate
+    reaches it."""
+    import numpy as np
+    import torch
+
+    from paper_2008_11778_amd.learned import BatchedLearnedAADescent, shipped_weights
+
+    w, prov = shipped_weights()
+    bl = BatchedLearnedAADescent(b, [torch.from_numpy(m0).to(dev) for _, _, m0 in insts], w, M=10, etas=etas)
+    N = len(insts)
+    t_reach = [None] * N
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bl.first()
+    for it in range(1, args.iters + 1):
+        J, _, _ = bl.iterate()
+        t = time.perf_counter() - t0
+        for i in range(N):
+            if t_reach[i] is None and J[i] <= targets[i]:
+                t_reach[i] = t
+        log(f"batched learned iteration {it}: {t:.2f}s, {sum(x is not None for x in t_reach)} instances "
+            f"at plain AA's final misfit")
+    torch.cuda.synchronize()
+    t_learned = time.perf_counter() - t0
+    finals = np.array(bl.current_misfits(), np.float64)
+    fallbacks = list(bl.n_fallback)
+    bl.close()
+    reached_end = [t_reach[i] is not None or finals[i] <= targets[i] for i in range(N)]
+    ratio = finals / targets
+    reach_t = [x for x in t_reach if x is not None]
+    log(f"batched learned: {t_learned:.2f}s for {args.iters} iterations; {sum(reached_end)}/{N} instances at or "
+        f"below plain AA's final misfit (geomean final ratio {float(np.exp(np.mean(np.log(ratio)))):.3f})")
+    return {"network": "shipped (stated recipe)", "training_cost_s": prov.get("training_cost_s"),
+            "learned_batched_s": round(t_learned, 2), "iterations": args.iters,
+            "reached_plain_final": int(sum(reached_end)),
+            "reached_during_timed_iterations": len(reach_t),
+            "batch_s_when_reached": [None if x is None else round(x, 2) for x in t_reach],
+            "geomean_final_ratio_learned_vs_plain": round(float(np.exp(np.mean(np.log(ratio)))), 4),
+            "final_ratio_per_instance": [round(float(x), 4) for x in ratio],
+            "fallbacks": fallbacks}
 
 
 def cnn_timing(net, B, H, W, reps=20):
@@ -1091,6 +1158,10 @@ def main():
                     help="learned workload: time to plain AA's J_K/J_0 (K = this) on full-size held-out models")
     ap.add_argument("--c5-models", type=int, default=1, help="learned workload: models for --c5-target")
     ap.add_argument("--c5-first", type=int, default=700, help="learned workload: first model for --c5-target")
+    ap.add_argument("--learned", action="store_true",
+                    help="batched workload: also run the learned form on the same batch (shipped network)")
+    ap.add_argument("--no-sequential", action="store_true",
+                    help="batched workload: skip the per-instance sequential runs")
     ap.add_argument("--train-cost-s", type=float, default=0.0,
                     help="learned workload: training cost (s) for the break-even count when weights are loaded")
     ap.add_argument("--load-weights", default="",

@@ -27,7 +27,8 @@ import time
 import numpy as np
 import torch
 
-from ._lib import AA, CNN, Batch, Context, Reducer, axpy, blend, floor_
+from ._lib import AA, CNN, Batch, BatchAA, Context, Reducer, axpy, blend, floor_
+from .batched import BatchedAADescent
 from .inversion import ARMIJO_C1, LAMBDAS, FWIProblem, IterLog, step_size
 
 
@@ -175,6 +176,162 @@ class LearnedAADescent:
     def close(self):
         for a in (self.aa_theta, self.aa_plain):
             a.close()
+
+
+class BatchedLearnedAADescent(BatchedAADescent):
+    """The learned form on many uneven instances at once: every instance runs
+    its own Algorithm 2 on G_theta with the plain-AA fallback (its own eta,
+    eta_theta, both Anderson windows, restarts and search), while all
+    instances share every wave-equation launch of a Batch, one Anderson
+    launch sequence per window and map for the whole batch, and one network
+    per grid shape.
+
+    A search round runs one masked batched forward for the instances still
+    searching, each at its next trial: lambda in {1, 1/2, 1/4, 1/8} between
+    ptilde_theta and pbar_theta (Armijo), then pbar_theta itself (accepted
+    if it decreases J), then the plain window's lambdas (Armijo), then the
+    plain pbar.  Instance by instance this is LearnedAADescent on a separate
+    context: the same kernels in the same arithmetic order, so the same
+    iterates."""
+
+    def __init__(self, batch: Batch, p0, weights, M: int = 10, etas=None, eta_thetas=None,
+                 eta_frac: float = 0.02, cond_max: float = 1e5, lambdas=LAMBDAS, c1: float = ARMIJO_C1,
+                 restart: bool = True, project: bool = True):
+        if M < 1:
+            raise ValueError("the learned form needs an Anderson window (M >= 1)")
+        super().__init__(batch, p0, M, etas=etas, eta_frac=eta_frac, cond_max=cond_max, lambdas=lambdas,
+                         c1=c1, restart=restart, project=project)
+        s = batch.stream
+        self.shapes = [tuple(batch.m[i].shape) for i in range(self.N)]
+        self.eta_thetas = None if eta_thetas is None else [float(e) for e in eta_thetas]
+        # self.aa (the base class's window) is the plain window on G; the
+        # theta window holds d_theta
+        self.aa_theta = BatchAA([x.numel() for x in self.p], M, cond_max, stream=s)
+        self.nets = {sh: CNN(sh[0], sh[1], 1, weights, stream=s) for sh in sorted(set(self.shapes))}
+        with torch.cuda.stream(s):
+            self.d = [torch.empty_like(x) for x in self.p]
+            self.pbar_plain = [torch.empty_like(x) for x in self.p]
+            self.ptilde_plain = [torch.empty_like(x) for x in self.p]
+        self.fb_theta = [False] * self.N
+        self.fb_plain = [False] * self.N
+        self.n_fallback = [0] * self.N
+
+    def _directions(self):
+        for i in range(self.N):
+            sh = self.shapes[i]
+            self.nets[sh].forward(self._g(i).view(1, *sh), self.p[i].view(1, *sh), z=False,
+                                  d=self.d[i].view(1, *sh))
+
+    def _maps(self):
+        self.aa_theta.step(self.p, self.d, self.eta_thetas, self.pbar, self.ptilde)
+        self.aa.step(self.p, [self._g(i) for i in range(self.N)], self.etas, self.pbar_plain, self.ptilde_plain)
+        if self.floors is not None:
+            s = self.b.stream
+            for i in range(self.N):
+                for x in (self.pbar, self.ptilde, self.pbar_plain, self.ptilde_plain):
+                    floor_(x[i], self.floors[i], stream=s)
+
+    def first(self):
+        """g_0 and d_theta at p_0 for every instance, then p_1 = G_theta(p_0)."""
+        J = self._gradients()
+        self.J_prev = np.array(J, np.float64)
+        self._directions()
+        with torch.cuda.stream(self.b.stream):
+            if self.etas is None:
+                self.etas = [step_size(self.p[i], self._g(i), self.eta_frac) for i in range(self.N)]
+            if self.eta_thetas is None:
+                self.eta_thetas = [step_size(self.p[i], self.d[i], self.eta_frac) for i in range(self.N)]
+        self._maps()
+        with torch.cuda.stream(self.b.stream):
+            self.p = [x.clone() for x in self.pbar]
+        self.kept_ok = [False] * self.N
+        return J
+
+    def _trial(self, i, stage):
+        """Write instance i's trial of this search stage into its model
+        buffer; returns the acceptance rule ("armijo" or "decrease")."""
+        L = len(self.lambdas)
+        s = self.b.stream
+        if stage < L:
+            blend(self.lambdas[stage], self.ptilde[i], self.pbar[i], self._m(i), stream=s)
+            return "armijo"
+        if stage == L:
+            blend(1.0, self.pbar[i], self.pbar[i], self._m(i), stream=s)
+            return "decrease"
+        blend(self.lambdas[stage - L - 1], self.ptilde_plain[i], self.pbar_plain[i], self._m(i), stream=s)
+        return "armijo"
+
+    def iterate(self):
+        """One iteration k >= 1 for every instance.
+
+        Returns (J(p_k), lambdas, fallbacks): lambda is 0 where the
+        instance took pbar_theta or the plain pbar; fallback marks the
+        instances that redid the iteration with plain AA."""
+        s = self.b.stream
+        L = len(self.lambdas)
+        self.k += 1
+        J = self._gradients()
+        if self.restart:
+            th = [self.fb_theta[i] and J[i] < self.J_prev[i] for i in range(self.N)]
+            pl = [self.fb_plain[i] and J[i] < self.J_prev[i] for i in range(self.N)]
+            if any(th):
+                self.aa_theta.reset(th)
+            if any(pl):
+                self.aa.reset(pl)
+        self.J_prev = np.array(J, np.float64)
+        self._directions()
+        self._maps()
+        stage = [0] * self.N
+        pending = [True] * self.N
+        lam = [0.0] * self.N
+        fallback = [False] * self.N
+        new_p = [None] * self.N
+        self.fb_theta = [False] * self.N
+        self.fb_plain = [False] * self.N
+        while any(pending):
+            idx = [i for i in range(self.N) if pending[i]]
+            rule = {i: self._trial(i, stage[i]) for i in idx}
+            Jt = self._forward(pending)
+            for i in idx:
+                if rule[i] == "armijo":
+                    self.red.dot_diff(self._g(i), self._m(i), self.p[i], out=self.slope[i:i + 1])
+            with torch.cuda.stream(s):
+                slope = self.slope.cpu().numpy()
+            for i in idx:
+                st = stage[i]
+                ok = Jt[i] <= J[i] + self.c1 * slope[i] if rule[i] == "armijo" else Jt[i] < J[i]
+                if ok:
+                    with torch.cuda.stream(s):
+                        new_p[i] = self._m(i).clone()
+                    lam[i] = self.lambdas[st] if st < L else (0.0 if st == L else self.lambdas[st - L - 1])
+                    pending[i] = False
+                    self.fb_theta[i] = st >= L
+                    continue
+                if st == L:
+                    # pbar_theta does not decrease J either: redo with plain AA
+                    fallback[i] = True
+                    self.n_fallback[i] += 1
+                stage[i] = st + 1
+                if stage[i] == 2 * L + 1:
+                    # no plain trial accepted: the plain descent step
+                    self.fb_theta[i] = self.fb_plain[i] = True
+                    with torch.cuda.stream(s):
+                        new_p[i] = self.pbar_plain[i].clone()
+                    self.kept_ok[i] = False
+                    pending[i] = False
+        self.fell_back = [self.fb_theta[i] or self.fb_plain[i] for i in range(self.N)]
+        self.b.set_active(np.ones(self.N, np.uint8))
+        self.p = new_p
+        return J, lam, fallback
+
+    def close(self):
+        super().close()
+        if self.aa_theta is not None:
+            self.aa_theta.close()
+            self.aa_theta = None
+        for net in self.nets.values():
+            net.close()
+        self.nets = {}
 
 
 def init_weights(seed: int):

@@ -137,3 +137,68 @@ def test_batched_algorithm2_equals_per_instance_runs(insts):
         for i in range(len(insts)):
             assert np.array_equal(bits[k][i], singles[i][k]), (k, i)
     assert J_end == finals, (J_end, finals)
+
+
+def _learned_singles(insts, w, scale=None, lambdas=None, iters=3):
+    """LearnedAADescent on a separate context per instance (eta_theta times
+    ``scale`` after the first step, if given): iterates, etas, eta_thetas,
+    fallback counts and the final misfit."""
+    import torch
+    from paper_2008_11778_amd import CNN, Context
+    from paper_2008_11778_amd.inversion import LAMBDAS, FWIProblem
+    from paper_2008_11778_amd.learned import LearnedAADescent
+    out = []
+    for g, m, d_obs in insts:
+        with Context(g, ckpt_every=20) as ctx, CNN(g.nz, g.nx, 1, w) as net:
+            prob = FWIProblem(ctx, torch.from_numpy(d_obs).cuda())
+            run = LearnedAADescent(prob, torch.from_numpy(m).cuda(), net, M=3,
+                                   lambdas=LAMBDAS if lambdas is None else lambdas)
+            run.first()
+            if scale is not None:
+                run.eta_theta *= scale
+            its = [run.p.cpu().numpy()]
+            for _ in range(iters):
+                run.iterate()
+                its.append(run.p.cpu().numpy())
+            out.append(dict(its=its, eta=run.eta, eta_theta=run.eta_theta, fallbacks=run.n_fallback,
+                            J_end=prob.misfit_keep(run.p)))
+            run.close()
+    return out
+
+
+@pytest.mark.parametrize("scale,lambdas", [(None, None), (30.0, ()), (30.0, None)],
+                         ids=["own-eta", "overshoot-no-trials", "overshoot"])
+def test_batched_learned_equals_per_instance_runs(insts, scale, lambdas):
+    """The batched learned form against LearnedAADescent per instance with
+    the shipped network: at its own eta_theta, and with eta_theta 30 times
+    larger from the second step on, which overshoots so that pbar_theta
+    raises J and the iteration falls back to plain AA (with no line-search
+    trials such an iteration takes the plain pbar; with the usual four, the
+    searches run in whatever order the misfits dictate)."""
+    import torch
+    from paper_2008_11778_amd import Batch
+    from paper_2008_11778_amd.inversion import LAMBDAS
+    from paper_2008_11778_amd.learned import BatchedLearnedAADescent, shipped_weights
+    w, _ = shipped_weights()
+    ref = _learned_singles(insts, w, scale, lambdas)
+    if lambdas == ():
+        assert sum(r["fallbacks"] for r in ref) > 0, [r["fallbacks"] for r in ref]
+    with Batch([g for g, _, _ in insts], [d for _, _, d in insts], ckpt_every=20, use_graphs=True) as b:
+        br = BatchedLearnedAADescent(b, [torch.from_numpy(m).cuda() for _, m, _ in insts], w, M=3,
+                                     lambdas=LAMBDAS if lambdas is None else lambdas)
+        br.first()
+        if scale is not None:
+            br.eta_thetas = [e * scale for e in br.eta_thetas]
+        bits = [[x.cpu().numpy() for x in br.p]]
+        for _ in range(3):
+            br.iterate()
+            bits.append([x.cpu().numpy() for x in br.p])
+        J_end = list(br.current_misfits())
+        etas, eta_thetas, fallbacks = list(br.etas), list(br.eta_thetas), list(br.n_fallback)
+        br.close()
+    for i, r in enumerate(ref):
+        assert etas[i] == r["eta"] and eta_thetas[i] == r["eta_theta"], i
+        assert fallbacks[i] == r["fallbacks"], (i, fallbacks, [x["fallbacks"] for x in ref])
+        for k in range(4):
+            assert np.array_equal(bits[k][i], r["its"][k]), (k, i)
+        assert J_end[i] == r["J_end"], (i, J_end[i], r["J_end"])
