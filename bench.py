@@ -444,6 +444,70 @@ def batched_workload(args):
     print(json.dumps(out), flush=True)
 
 
+def learned_batched_heldout(args, weights, size, rows, dev):
+    """Plain and learned Algorithm 2 (M = 10) on the held-out models of the
+    training size (instances 500, ...), each as one batch of all of them,
+    timed over the same iterations; the plain batch's final misfits (those of
+    the per-instance plain runs: the batch is bitwise the single path) are
+    the targets.  Reports both batch wall times, per instance the learned
+    batch's wall time when it first reaches its target, and the per-instance
+    sequential times of the same plain and learned runs for context."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2008_11778_amd import Batch, Context
+    from paper_2008_11778_amd.batched import BatchedAADescent
+    from paper_2008_11778_amd.learned import BatchedLearnedAADescent
+
+    insts = [synth.learned_instance(500 + j, **size) for j in range(args.test_instances)]
+    d_obs = []
+    for g, mt, _ in insts:
+        with Context(g) as ctx:
+            d_obs.append(ctx.forward_model(torch.from_numpy(mt).to(dev)).cpu())
+    N = len(insts)
+    res = {}
+    with Batch([g for g, _, _ in insts], d_obs, use_graphs=True) as b:
+        for kind in ("plain", "learned"):
+            p0 = [torch.from_numpy(m0).to(dev) for _, _, m0 in insts]
+            run = (BatchedAADescent(b, p0, M=10) if kind == "plain"
+                   else BatchedLearnedAADescent(b, p0, weights, M=10))
+            t_reach = [None] * N
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            run.first()
+            for _ in range(args.iters):
+                J = run.iterate()[0]
+                if kind == "learned":
+                    t = time.perf_counter() - t0
+                    for i in range(N):
+                        if t_reach[i] is None and J[i] <= res["plain"]["finals"][i]:
+                            t_reach[i] = t
+            torch.cuda.synchronize()
+            t_run = time.perf_counter() - t0
+            finals = np.array(run.current_misfits(), np.float64)
+            res[kind] = dict(s=t_run, finals=finals, t_reach=t_reach,
+                             fallbacks=sum(getattr(run, "n_fallback", [0])))
+            run.close()
+            log(f"batched held-out {kind}: {t_run:.2f}s for {args.iters} iterations")
+    targets = res["plain"]["finals"]
+    lf = res["learned"]["finals"]
+    reach = res["learned"]["t_reach"]
+    reached = [i for i in range(N) if reach[i] is not None or lf[i] <= targets[i]]
+    seq_match = all(abs(r["plain_final"] - targets[i]) <= 1e-12 * targets[i] for i, r in enumerate(rows))
+    out = {"instances": N, "iterations": args.iters,
+           "plain_batched_s": round(res["plain"]["s"], 2), "learned_batched_s": round(res["learned"]["s"], 2),
+           "plain_sequential_s": round(sum(r["plain_s"] for r in rows), 2),
+           "targets_equal_sequential_plain_finals": seq_match,
+           "reached_plain_final": len(reached),
+           "learned_batch_s_when_reached": [None if x is None else round(x, 2) for x in reach],
+           "geomean_final_ratio_learned_vs_plain": round(float(np.exp(np.mean(np.log(lf / targets)))), 4),
+           "learned_fallbacks": res["learned"]["fallbacks"]}
+    log(f"batched held-out: plain {out['plain_batched_s']} s, learned {out['learned_batched_s']} s; "
+        f"{len(reached)}/{N} reach the plain final misfit (geomean ratio {out['geomean_final_ratio_learned_vs_plain']})")
+    return out
+
+
 def batched_learned_leg(args, b, insts, etas, targets, dev):
     """The learned form on the same batch (shipped network, the plain runs'
     etas, M = 10), timed over the same iterations; per instance the batch
@@ -893,6 +957,9 @@ def learned_workload(args):
     for j in range(args.test_instances):
         g, mt, m0 = synth.learned_instance(500 + j, **size)
         rows.append(compare(500 + j, g, mt, m0, net))
+    batched_eval = None
+    if args.batched_eval and args.test_instances:
+        batched_eval = learned_batched_heldout(args, net.get_weights(), size, rows, dev)
     large = []
     if args.large_test:
         net_l = CNN(384, 1024, 1, net.get_weights() if full_weights is None else full_weights)
@@ -930,6 +997,7 @@ def learned_workload(args):
                                            if reached else None),
            "training": training,
            "c5_time_to_target": c5,
+           "batched_held_out": batched_eval,
            "cnn_8x384x1024": {"forward_ms": round(speed["forward"], 3), "train_step_ms": round(speed["train_step"], 3),
                               "forward_tflops": round(flops / speed["forward"] / 1e9, 1),
                               "train_tflops": round(3 * flops / speed["train_step"] / 1e9, 1),
@@ -1158,6 +1226,8 @@ def main():
                     help="learned workload: time to plain AA's J_K/J_0 (K = this) on full-size held-out models")
     ap.add_argument("--c5-models", type=int, default=1, help="learned workload: models for --c5-target")
     ap.add_argument("--c5-first", type=int, default=700, help="learned workload: first model for --c5-target")
+    ap.add_argument("--batched-eval", action="store_true",
+                    help="learned workload: also run plain and learned AA on the held-out models as batches")
     ap.add_argument("--learned", action="store_true",
                     help="batched workload: also run the learned form on the same batch (shipped network)")
     ap.add_argument("--no-sequential", action="store_true",
