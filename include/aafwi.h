@@ -289,8 +289,10 @@ int aafwi_laplacian_filter(aafwi_stream stream, int32_t nz, int32_t nx, float h,
 
 int aafwi_axpy(aafwi_stream stream, int64_t n, float a, const float* x, float* y);
 
-/* x = max(x, floor) in place (device [n]): keeps an iterate in the model's
- * stable domain (floor = 1/vmax_bound^2; see the stable domain above). */
+/* x = max(x, floor) in place (device [n], caller-owned), asynchronous on
+ * stream: keeps an iterate in the model's stable domain (floor =
+ * 1/vmax_bound^2; see the stable domain above).  A NaN entry becomes floor.
+ * AAFWI_E_INVALID for n <= 0, a NULL x or a non-finite floor. */
 int aafwi_floor(aafwi_stream stream, int64_t n, float floor, float* x);
 
 /* out = a*x in FP32 (device [n]); out may alias x. */
