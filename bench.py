@@ -358,7 +358,10 @@ def batched_workload(args):
     for the same number of iterations: per instance the batch wall time at
     which it first reaches plain AA's final misfit, and the final misfits.
     ``--no-sequential`` skips the per-instance runs (the plain batch's final
-    misfits, the same numbers, are then the targets).
+    misfits, the same numbers, are then the targets).  ``--family-train N``
+    first fine-tunes the shipped network on plain-AA pairs of N further
+    instances of the same family (instances 100, ...) and runs the learned
+    form with those weights.
     """
     import numpy as np
     import torch
@@ -371,6 +374,7 @@ def batched_workload(args):
     dev = torch.device("cuda", 0)
     insts = synth.config4_instances()[: args.instances]
     k = args.ckpt
+    family = family_weights(args) if args.learned and args.family_train else None
     d_obs, etas, targets, seq_times, upd = [], [], [], [], 0.0
     from paper_2008_11778_amd import autotune
     shapes = {}  # launch shapes per grid class (padded rows x columns), tuned on at most 8 shots
@@ -426,7 +430,8 @@ def batched_workload(args):
             targets = list(finals)
         learned = None
         if args.learned:
-            learned = batched_learned_leg(args, b, insts, etas, np.array(targets, np.float64), dev)
+            learned = batched_learned_leg(args, b, insts, etas, np.array(targets, np.float64), dev,
+                                          family=family)
     targets = np.array(targets, np.float64)
     reached = int(np.sum(finals <= targets * (1 + 1e-9)))
     rel = float(np.max(np.abs(finals - targets) / targets))
@@ -508,7 +513,59 @@ def learned_batched_heldout(args, weights, size, rows, dev):
     return out
 
 
-def batched_learned_leg(args, b, insts, etas, targets, dev):
+def family_weights(args):
+    """The shipped network fine-tuned on the batched workload's family: plain
+    Algorithm 2 (M = 10, the workload's iterations) on ``--family-train``
+    further instances (100, 101, ..., disjoint from the measured ones), one
+    batch per grid shape; pairs with a zero step or gradient dropped,
+    x-mirrored copies added; then ``--family-epochs`` passes of Adam (lr
+    ``--family-lr``, batch 8), each pass one epoch on every grid shape in
+    turn with the weights carried over.  Returns (weights, record)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2008_11778_amd import CNN
+    from paper_2008_11778_amd.learned import aa_pairs, drop_degenerate, flip_x, merge, shipped_weights, train
+
+    w, _ = shipped_weights()
+    t0 = time.perf_counter()
+    groups = {}
+    for c in synth.config4_instances(args.family_train, first=100):
+        groups.setdefault(tuple(c[2].shape), []).append(c)
+    pairs, dropped = {}, 0
+    for sh in sorted(groups):
+        p, dr = drop_degenerate(aa_pairs(groups[sh], M=10, iters=args.iters, ckpt_every=args.ckpt))
+        dropped += dr
+        pairs[sh] = merge(p, flip_x(p))
+        log(f"family pairs {sh[1]}x{sh[0]}: {len(groups[sh])} instances, {len(pairs[sh])} pairs "
+            f"({time.perf_counter() - t0:.1f}s)")
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    hist = []
+    for ep in range(args.family_epochs):
+        num = den = 0.0
+        for sh in sorted(pairs):
+            if len(pairs[sh]) < 8:
+                continue
+            net = CNN(sh[0], sh[1], 8, w)
+            loss = train(net, pairs[sh], epochs=1, batch=8, lr=args.family_lr, seed=5006 + ep)[0]
+            w = net.get_weights()
+            net.close()
+            num += loss * len(pairs[sh])
+            den += len(pairs[sh])
+        hist.append(round(num / den, 4))
+    torch.cuda.synchronize()
+    rec = {"instances": args.family_train, "first_instance": 100, "shapes": len(pairs),
+           "pairs": int(sum(len(p) for p in pairs.values())), "dropped": dropped, "data_s": round(t_data, 1),
+           "train_s": round(time.perf_counter() - t0, 1), "epochs": args.family_epochs, "lr": args.family_lr,
+           "epoch_loss": hist}
+    log(f"family fine-tuning: {rec}")
+    return np.asarray(w, np.float32), rec
+
+
+def batched_learned_leg(args, b, insts, etas, targets, dev, family=None):
     """The learned form on the same batch (shipped network, the plain runs'
     etas, M = 10), timed over the same iterations; per instance the batch
     wall time of the first iteration at whose gradient J is at or below the
@@ -521,6 +578,8 @@ def batched_learned_leg(args, b, insts, etas, targets, dev):
     from paper_2008_11778_amd.learned import BatchedLearnedAADescent, shipped_weights
 
     w, prov = shipped_weights()
+    if family is not None:
+        w = family[0]
     bl = BatchedLearnedAADescent(b, [torch.from_numpy(m0).to(dev) for _, _, m0 in insts], w, M=10, etas=etas)
     N = len(insts)
     t_reach = [None] * N
@@ -545,7 +604,12 @@ def batched_learned_leg(args, b, insts, etas, targets, dev):
     reach_t = [x for x in t_reach if x is not None]
     log(f"batched learned: {t_learned:.2f}s for {args.iters} iterations; {sum(reached_end)}/{N} instances at or "
         f"below plain AA's final misfit (geomean final ratio {float(np.exp(np.mean(np.log(ratio)))):.3f})")
-    return {"network": "shipped (stated recipe)", "training_cost_s": prov.get("training_cost_s"),
+    if family is not None:
+        net_name, cost = "shipped, fine-tuned on the family (instances 100, ...)", \
+            prov.get("training_cost_s", 0.0) + family[1]["data_s"] + family[1]["train_s"]
+    else:
+        net_name, cost = "shipped (stated recipe)", prov.get("training_cost_s")
+    return {"network": net_name, "training_cost_s": cost, "family_training": family[1] if family else None,
             "learned_batched_s": round(t_learned, 2), "iterations": args.iters,
             "reached_plain_final": int(sum(reached_end)),
             "reached_during_timed_iterations": len(reach_t),
@@ -1230,6 +1294,10 @@ def main():
                     help="learned workload: also run plain and learned AA on the held-out models as batches")
     ap.add_argument("--learned", action="store_true",
                     help="batched workload: also run the learned form on the same batch (shipped network)")
+    ap.add_argument("--family-train", type=int, default=0,
+                    help="batched workload with --learned: fine-tune on this many further instances of the family")
+    ap.add_argument("--family-epochs", type=int, default=10, help="batched workload: fine-tuning passes")
+    ap.add_argument("--family-lr", type=float, default=3e-4, help="batched workload: fine-tuning learning rate")
     ap.add_argument("--no-sequential", action="store_true",
                     help="batched workload: skip the per-instance sequential runs")
     ap.add_argument("--train-cost-s", type=float, default=0.0,

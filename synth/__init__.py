@@ -230,12 +230,14 @@ def config3(nshots=64, nt=4000):
     return g, m0, dm
 
 
-def config4_instances(ninst=32):
-    """Uneven batch: grid, spacing, record length and shot count drawn per instance."""
+def config4_instances(ninst=32, first=0):
+    """Uneven batch: grid, spacing, record length and shot count drawn per
+    instance; instances first, first + 1, ... (the batched workload uses
+    0 .. 31; further instances of the same family start at 100)."""
     grids = [(128, 128), (256, 128), (384, 128), (512, 256), (768, 256), (1024, 384), (1024, 512)]
     hs = [10.0, 12.5, 15.0, 20.0]
     out = []
-    for i in range(ninst):
+    for i in range(first, first + ninst):
         r = seed(4, i, PURPOSE_LAYERS)
         nx, nz = grids[r.integers(len(grids))]
         h = hs[r.integers(len(hs))]
