@@ -3,6 +3,7 @@ table covers the workloads' grid classes with valid shapes, lookups prefer
 the user cache, and apply() hands every field to the context."""
 import json
 
+import numpy as np
 import pytest
 
 import synth
@@ -131,3 +132,19 @@ def test_shipped_network_weights():
     assert np.isfinite(w).all() and np.abs(w).max() > 0
     assert meta["training_cost_s"] > 0 and "bench.py --workload learned" in meta["_about"]
     assert np.array_equal(np.load(SHIPPED_WEIGHTS, allow_pickle=False), w)
+
+
+def test_family_instances_continue_the_batched_family():
+    """Instances drawn from a later index are new members of the same family
+    (the grids, spacings and shot counts of the batched workload's table),
+    and the batched workload's own 32 are unchanged by the offset."""
+    base = synth.config4_instances(32)
+    again = synth.config4_instances(4, first=0)
+    later = synth.config4_instances(8, first=100)
+    for (g0, mt0, m00), (g1, mt1, m01) in zip(base[:4], again):
+        assert (g0.nx, g0.nz, g0.h, g0.nt, g0.dt, g0.nshots) == (g1.nx, g1.nz, g1.h, g1.nt, g1.dt, g1.nshots)
+        assert np.array_equal(mt0, mt1) and np.array_equal(m00, m01)
+    grids = {(128, 128), (256, 128), (384, 128), (512, 256), (768, 256), (1024, 384), (1024, 512)}
+    for g, mt, m0 in later:
+        assert (g.nx, g.nz) in grids and g.h in (10.0, 12.5, 15.0, 20.0) and 4 <= g.nshots <= 96
+        assert not any(mt.shape == b[1].shape and np.array_equal(mt, b[1]) for b in base)
