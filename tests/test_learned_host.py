@@ -11,6 +11,7 @@ import pytest
 import torch
 
 from paper_2008_11778_amd import batched as batched_mod
+from paper_2008_11778_amd import inversion as inversion_mod
 from paper_2008_11778_amd import learned as learned_mod
 
 
@@ -51,21 +52,25 @@ class MixState:
         self.k += 1
         self.mk.fill_(min(self.k, 10))
 
+    resets = 0
+
     def reset(self):
         self.k = 0
         self.mk.zero_()
+        MixState.resets += 1
 
 
 SCHEDULES = {}  # (instance, window) -> schedule, set per test case
 
 
 class FakeAA:
-    """Stand-in for the single-instance Anderson state (created in the order
-    theta window, plain window by LearnedAADescent)."""
+    """Stand-in for the single-instance Anderson state (LearnedAADescent
+    creates the theta window, then the plain one; AADescent one plain)."""
     made = []
+    order = ("theta", "plain")
 
     def __init__(self, n, M, cond_max=1e5, stream=None, solver="gram"):
-        inst, which = FakeAA.made[0], ("theta", "plain")[len(FakeAA.made) - 1]
+        inst, which = FakeAA.made[0], FakeAA.order[len(FakeAA.made) - 1]
         FakeAA.made.append(which)
         self.s = MixState(SCHEDULES[(inst, which)])
         self.mk = self.s.mk
@@ -195,6 +200,10 @@ def fakes(monkeypatch):
         monkeypatch.setattr(mod, "blend", fake_blend)
         monkeypatch.setattr(mod, "floor_", fake_floor)
     monkeypatch.setattr(learned_mod, "AA", FakeAA)
+    monkeypatch.setattr(inversion_mod, "AA", FakeAA)
+    monkeypatch.setattr(inversion_mod, "Reducer", FakeReducer)
+    monkeypatch.setattr(inversion_mod, "blend", fake_blend)
+    monkeypatch.setattr(inversion_mod, "floor_", fake_floor)
     monkeypatch.setattr(learned_mod, "BatchAA", FakeBatchAA)
     monkeypatch.setattr(batched_mod, "BatchAA", FakeBatchAA)
     monkeypatch.setattr(learned_mod, "CNN", FakeCNN)
@@ -226,6 +235,8 @@ def test_batched_search_rounds_take_the_single_decisions(fakes, seed):
     iters = 8
 
     singles = []
+    MixState.resets = 0
+    FakeAA.order = ("theta", "plain")
     for i, f in enumerate(fs):
         FakeAA.made = [i]
         prob = Problem(f, floors[i])
@@ -264,6 +275,53 @@ def test_batched_search_rounds_take_the_single_decisions(fakes, seed):
         assert all(float(x.min()) >= np.float32(floors[i]) for x in s["its"][1:])  # p_1, ... in the domain
         for lam, fb in zip(s["lams"], s["fbs"]):
             outcomes.add(("plain" if fb else "theta", lam > 0))
+    assert MixState.resets > 0  # windows restarted after fallbacks that decreased J
     # every way out of the search is taken somewhere: a theta trial, pbar_theta,
     # a plain trial, the plain pbar
     assert outcomes == {("theta", True), ("theta", False), ("plain", True), ("plain", False)}, outcomes
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_batched_plain_search_rounds_take_the_single_decisions(fakes, seed):
+    """The same for plain Algorithm 2: BatchedAADescent against AADescent
+    (trials, the fallback to pbar, the restart after a fallback that
+    decreased J)."""
+    shapes = [(6, 9), (4, 4), (7, 5), (5, 8), (3, 11)]
+    fs = [Misfit(sh, 50 + 100 * seed + i) for i, sh in enumerate(shapes)]
+    floors = [0.9, 0.5, 1.2, 0.0, 1.05]
+    p0 = [torch.from_numpy(f.t + np.random.default_rng(3 + i + seed).uniform(-1.5, 1.5, f.shape)).float()
+          for i, f in enumerate(fs)]
+    etas = [c["eta"] / f.w.max() for c, f in zip(CASES, fs)]
+    for i, c in enumerate(CASES):
+        SCHEDULES[(i, "plain")] = c["theta"]  # the overshooting schedules
+    iters = 8
+    singles = []
+    MixState.resets = 0
+    FakeAA.order = ("plain",)
+    for i, f in enumerate(fs):
+        FakeAA.made = [i]
+        prob = Problem(f, floors[i])
+        run = inversion_mod.AADescent(prob, p0[i].clone().reshape(-1), etas[i], M=10)
+        run.first()
+        its, lams = [run.p.clone()], []
+        for _ in range(iters):
+            lams.append(run.iterate().lam)
+            its.append(run.p.clone())
+        singles.append(dict(its=its, lams=lams, J_end=f.J(run.p)))
+    FakeBatchAA.made = 0
+    br = batched_mod.BatchedAADescent(Batch(fs, floors), [x.clone() for x in p0], M=10, etas=etas)
+    br.first()
+    its, lams = [[x.clone() for x in br.p]], []
+    for _ in range(iters):
+        lams.append(br.iterate()[1])
+        its.append([x.clone() for x in br.p])
+    J_end = br.current_misfits()
+    taken = set()
+    for i, s in enumerate(singles):
+        for k in range(iters + 1):
+            assert torch.equal(its[k][i].view(-1), s["its"][k].view(-1)), (seed, i, k)
+        assert [lams[k][i] for k in range(iters)] == s["lams"], (seed, i)
+        assert J_end[i] == s["J_end"]
+        taken.update(s["lams"])
+    assert 0.0 in taken and 1.0 in taken and len(taken) >= 3, taken
+    assert MixState.resets > 0
